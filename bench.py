@@ -1,0 +1,199 @@
+#!/usr/bin/env python3
+"""Throughput of the CDVS front half on one MI355X.
+
+One step = the whole hot path over one batch already resident in HBM:
+cdvs_pyramid -> cdvs_alp_detect -> cdvs_orient -> cdvs_describe on a batch of
+256 seeded synthetic 640x480 u8 images (top 1000 keypoints described per
+image).  Prints one JSON line.
+
+    python bench.py [--steps K] [--warmup W] [--batch B] [--no-cpu-baseline]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import platform
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_HBM_GBS = 8000.0        # MI355X HBM3E
+PEAK_FP32_TFLOPS = 157.3     # MI355X FP32 vector (256 CU x 2.4 GHz x 256 FLOP/clk)
+
+# Minimum arithmetic per pixel, from the filter lengths: each of the four
+# scale images costs (2r+1) multiply-adds per pass and two passes, r = 5, 7, 9, 12.
+SCALES_FLOP_PER_PX = 2 * 2 * sum(2 * r + 1 for r in (5, 7, 9, 12))   # 280
+PREBLUR_FLOP_PER_PX = 2 * 2 * (2 * 7 + 1)                            # 60
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def octave_pixels(sizes, min_side=32):
+    """Per octave: total pixels over the batch."""
+    tot = {}
+    for (w, h) in sizes:
+        o = 0
+        while True:
+            tot[o] = tot.get(o, 0) + w * h
+            if min(w, h) < min_side:
+                break
+            w, h = (w + 1) // 2, (h + 1) // 2
+            o += 1
+    return [tot[o] for o in sorted(tot)]
+
+
+def algorithmic(sizes, n_kp, n_ori):
+    """Algorithmic bytes and flops of one step, per kernel."""
+    npx = octave_pixels(sizes)
+    n0 = npx[0]
+    nxt = sum(npx[1:])
+    allpx = sum(npx)
+    return {
+        "preblur": {"bytes": n0 * (1 + 4), "flop": n0 * PREBLUR_FLOP_PER_PX},
+        # read G_{o,0}, write G_{o,1..4}, write G_{o+1,0}
+        "scales": {"bytes": allpx * (4 + 16) + nxt * 4, "flop": allpx * SCALES_FLOP_PER_PX},
+        # read five planes
+        "detect": {"bytes": allpx * 20, "flop": allpx * 70},
+        "finalize": {"bytes": None, "flop": None},
+        "orient": {"bytes": n_kp * 48 + n_ori * 48, "flop": None},
+        "orient_compact": {"bytes": None, "flop": None},
+        "describe": {"bytes": n_ori * (48 + 512), "flop": None},
+        "clear": {"bytes": None, "flop": None},
+    }
+
+
+def cpu_baseline(imgs, seconds: float):
+    """The oracle (fp64 build) over a bounded sample of the same images, one
+    image per thread on the host's cores."""
+    import oracle
+    from concurrent.futures import ThreadPoolExecutor
+    O = oracle.Oracle("f64")
+    cores = os.cpu_count() or 1
+    cores = min(cores, 16)
+    t0 = time.perf_counter()
+    O.run(imgs[0], image=0)                # probe one image
+    per = time.perf_counter() - t0
+    n = max(cores, min(len(imgs), int(seconds * cores / max(per, 1e-3))))
+    n = min(n, len(imgs))
+    t0 = time.perf_counter()
+    with ThreadPoolExecutor(cores) as ex:
+        list(ex.map(lambda i: O.run(imgs[i], image=i), range(n)))
+    dt = time.perf_counter() - t0
+    return {"value": round(n / dt, 3), "unit": "images/s", "cores": cores, "kind": "oracle",
+            "sample": f"{n} of the {len(imgs)} batch images, whole path per image (fp64 oracle), "
+                      f"{cores} threads, {dt:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--batch", type=int, default=256)
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(images would shard across GPUs with no exchange); run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    import synth
+    import paper_1705_09776_amd as cd
+
+    B = args.batch
+    log(f"[bench] generating {B} images 640x480")
+    imgs = synth.fixed_batch(synth.SEED_BATCH, B)
+    sizes = [(640, 480)] * B
+    pipe = cd.Pipeline(sizes)
+    pipe.upload(list(imgs))
+    torch.cuda.synchronize()
+
+    log(f"[bench] warmup {args.warmup}")
+    for _ in range(args.warmup):
+        pipe.run()
+    torch.cuda.synchronize()
+    if pipe.sync_status() != cd.CDVS_OK:
+        raise RuntimeError("capacity overflow during warmup")
+
+    cd.cdvs_profile_enable(pipe.ctx, True)
+    log(f"[bench] timing {args.steps} steps")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        pipe.run()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    prof = cd.cdvs_profile_read(pipe.ctx)
+    cd.cdvs_profile_enable(pipe.ctx, False)
+    ms_per_step = (t1 - t0) * 1e3 / args.steps
+    value = B / (ms_per_step * 1e-3)
+
+    n_kp = int(pipe.d_count.sum().item())
+    n_ori = int(pipe.d_count_ori.sum().item())
+    alg = algorithmic(sizes, n_kp, n_ori)
+    kernels = {}
+    for name, (ms, launches) in prof.items():
+        if launches == 0:
+            continue
+        per_step = launches / args.steps
+        kernels[name] = {"ms_per_step": round(ms / args.steps, 4), "launches_per_step": per_step,
+                         "avg_launch_us": round(ms * 1e3 / launches, 2)}
+    dom = max(kernels, key=lambda k: kernels[k]["ms_per_step"])
+    d = kernels[dom]
+    t_step_s = d["ms_per_step"] * 1e-3
+    a = alg[dom]
+    # roofline of the dominant kernel: its algorithmic bytes (or flops) over its
+    # own event-timed duration, per launch averaged over the timed region
+    if a["bytes"] is not None and a["flop"] is not None and a["flop"] / a["bytes"] > 9.8:
+        roof = {"bound": "alu", "achieved": round(a["flop"] / t_step_s / 1e12, 3), "peak": PEAK_FP32_TFLOPS,
+                "unit": "TFLOP/s"}
+    elif a["bytes"] is not None:
+        roof = {"bound": "hbm", "achieved": round(a["bytes"] / t_step_s / 1e9, 1), "peak": PEAK_HBM_GBS,
+                "unit": "GB/s"}
+    else:
+        roof = {"bound": "alu", "achieved": None, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s"}
+    roof["frac"] = round(roof["achieved"] / roof["peak"], 4) if roof["achieved"] is not None else None
+    roof["traffic"] = None
+    roof["kernel"] = dom
+    roof["launch_us"] = d["avg_launch_us"]
+    hbm_bytes = sum(v["bytes"] for v in alg.values() if v["bytes"] is not None)
+
+    out = {
+        "metric": "images/s at 640x480 (plain vs surrogate-gated @>=98% kp recall); HBM GB/s",
+        "value": round(value, 1),
+        "unit": "images/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic (seeded blobs on a ramp with noise, 640x480 u8)",
+        "config": {"workload": f"plain path, batch of {B} images 640x480, top-1000 keypoints described per image",
+                   "batch": B, "width": 640, "height": 480, "topk": 1000, "path": "plain"},
+        "model_hbm_gbs": round(hbm_bytes * args.steps / (t1 - t0) / 1e9, 1),
+        "keypoints_per_image": round(n_kp / B, 1),
+        "oriented_per_image": round(n_ori / B, 1),
+        "kernels": kernels,
+        "roofline": roof,
+    }
+    if not args.no_cpu_baseline:
+        log("[bench] cpu baseline (oracle)")
+        out["cpu_baseline"] = cpu_baseline(imgs, args.cpu_seconds)
+    out["host"] = {"cpu": platform.processor() or platform.machine(), "nproc": os.cpu_count()}
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,215 @@
+/*
+ * cdvs.h -- C ABI of the MI355X (gfx950) CDVS front half.
+ *
+ * The front half of a CDVS encoder ("Fast MPEG-CDVS Encoder with GPU-CPU
+ * Hybrid Computing", Duan et al.): Gaussian scale space, ALP keypoint
+ * detection, orientation assignment and the 128-D local descriptor, over a
+ * batch of 8-bit grayscale images.  Selection by relevance, compression and
+ * aggregation stay with the caller.
+ *
+ * Conventions for every call below
+ *   - Pointers prefixed d_ are device pointers (HIP device memory of the
+ *     current device); all others are host pointers.
+ *   - Device buffers passed in are owned by the caller; the library never
+ *     frees or retains them past the call.  The context owns only its own
+ *     small tables and scratch, allocated once by cdvs_ctx_create.
+ *   - `stream` is a hipStream_t (NULL = the null stream).  Compute calls only
+ *     enqueue work on it and return; they never synchronise, never allocate,
+ *     and may be captured into a HIP graph.  Errors detectable on the host
+ *     (null pointers, bad sizes, bad parameters) are returned at once and
+ *     nothing is enqueued.  Conditions only the device can see (a capacity
+ *     overflow) are latched in the context and returned by cdvs_sync_status.
+ *   - Two calls on the same context must not run concurrently (they share
+ *     the context's scratch); use one context per stream.
+ *   - Coordinates: pixel centres are at integers, x to the right, y down.
+ *     A keypoint of octave o has base-image coordinates (ix + dx) * 2^o.
+ */
+#ifndef CDVS_H
+#define CDVS_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    CDVS_OK = 0,
+    CDVS_ERR_ARG = -1,      /* null pointer, unsupported parameter value */
+    CDVS_ERR_SHAPE = -2,    /* image size, pitch or count out of range */
+    CDVS_ERR_CAPACITY = -3, /* results were truncated; what was written is valid */
+    CDVS_ERR_HIP = -4,      /* a HIP runtime call failed (message in cdvs_last_error) */
+    CDVS_ERR_STATE = -5,    /* call out of order (e.g. no context) */
+    CDVS_ERR_VERSION = -6   /* params.version does not match CDVS_PARAMS_VERSION */
+} cdvs_status;
+
+#define CDVS_PARAMS_VERSION 1
+#define CDVS_DESC_DIM 128
+#define CDVS_MIN_SIDE 16
+#define CDVS_MAX_SIDE 8192
+#define CDVS_MAX_IMAGES 65536
+#define CDVS_MAX_KP_CAPACITY 8192 /* per image */
+
+/* Method constants.  sigma0 and intervals are fixed by the compiled
+ * kernels (1.6 and 4: five scale images per octave, Gaussian radii 7, 5, 7,
+ * 9, 12); the others are read at run time.  Defaults: cdvs_default_params. */
+typedef struct {
+    int32_t version;     /* CDVS_PARAMS_VERSION */
+    float sigma0;        /* base scale of each octave (octave pixels): 1.6 */
+    int32_t intervals;   /* scale intervals per octave: 4 (images k = 0..4) */
+    int32_t min_side;    /* octaves continue until one has a short side < this: 32 */
+    float contrast;      /* minimum |p| of a candidate, 0..255 intensity scale: 1.5 */
+    float edge_r;        /* reject when tr(H)^2/det(H) >= (r+1)^2/r: 10 */
+    int32_t border;      /* detection margin in octave pixels: 4 */
+    float max_offset;    /* reject a refinement offset beyond this per axis: 0.5 */
+    float dedup_dlog2;   /* cross-octave duplicates: |log2 sigma ratio| <= this: 0.25 */
+    float ori_radius;    /* orientation window radius / sigma: 3.96 */
+    float ori_wsigma;    /* orientation Gaussian weight sigma / sigma: 1.5 */
+    float ori_peak;      /* keep peaks above this fraction of the highest: 0.8 */
+    int32_t max_ori;     /* orientations per keypoint, 1..4: 4 */
+    float desc_cell;     /* descriptor cell side / sigma: 3 */
+    float desc_radius;   /* descriptor window radius / sigma: 6 */
+    float desc_wsigma;   /* descriptor Gaussian weight sigma / sigma: 6 */
+    float desc_clamp;    /* clamp after the first L2 normalisation: 0.2 */
+    int32_t topk;        /* keypoints kept per image (<= kp capacity): 1000 */
+} cdvs_params;
+
+/* One u8 image inside the caller's packed image buffer: byte offset of its
+ * first row, width and height in pixels, row pitch in bytes (>= width). */
+typedef struct {
+    int64_t offset;
+    int32_t width, height, pitch;
+    int32_t reserved; /* 0 */
+} cdvs_image_desc;
+
+/* 48-byte keypoint record (relevance features of Sec. III-B, Eq. (5):
+ * sigma, p, rho, p_ss; distance to the image centre follows from x, y). */
+typedef struct {
+    float x, y;      /* base-image pixels */
+    float sigma;     /* scale in base-image pixels */
+    float p;         /* ALP response at (x, y, sigma), refined */
+    float theta;     /* orientation in [0, 2 pi) (0 before cdvs_orient) */
+    float rho;       /* tr(H)^2 / det(H) of the response surface */
+    float p_ss;      /* d^2 p / d sigma^2 at the extremum (octave units) */
+    float peak;      /* orientation histogram peak height (0 before cdvs_orient) */
+    int32_t image;   /* index of the image in the batch */
+    int32_t octave;  /* octave o */
+    int32_t ix, iy;  /* integer position of the candidate in octave pixels */
+} cdvs_keypoint;
+
+typedef struct cdvs_ctx cdvs_ctx;
+
+/* Defaults listed in cdvs_params. */
+cdvs_params cdvs_default_params(void);
+
+/* Host-only check of a batch description and parameters; touches no device.
+ * Returns CDVS_OK or the error cdvs_ctx_create would return.  `msg` (may be
+ * NULL) receives a NUL-terminated reason, at most msg_len bytes. */
+cdvs_status cdvs_validate(const cdvs_params* params, const cdvs_image_desc* images, int32_t n_images,
+                          int32_t kp_capacity, char* msg, int32_t msg_len);
+
+/* Create a context for one batch layout: n_images images described by the
+ * host array `images` (copied).  kp_capacity is the per-image record count
+ * of every keypoint buffer passed to the calls below (topk <= kp_capacity).
+ * Allocates the context's device tables and scratch on the current device
+ * (scratch is about 0.4 MB per image).  On failure *out is NULL. */
+cdvs_status cdvs_ctx_create(const cdvs_params* params, const cdvs_image_desc* images, int32_t n_images,
+                            int32_t kp_capacity, cdvs_ctx** out);
+void cdvs_ctx_destroy(cdvs_ctx* ctx);
+
+/* Reason for the last error of a context (or of the last failed
+ * cdvs_ctx_create when ctx is NULL).  Valid until the next call. */
+const char* cdvs_last_error(const cdvs_ctx* ctx);
+
+/* Size in bytes of the pyramid buffer (all images, octaves and scales). */
+int64_t cdvs_pyramid_bytes(const cdvs_ctx* ctx);
+int32_t cdvs_num_octaves(const cdvs_ctx* ctx, int32_t image);
+
+/* Where plane G_{o,k} of image `image` lives in the pyramid buffer: offset
+ * in floats from its start, width, height and row pitch in floats. */
+cdvs_status cdvs_plane_layout(const cdvs_ctx* ctx, int32_t image, int32_t octave, int32_t k,
+                              int64_t* offset, int32_t* width, int32_t* height, int32_t* pitch);
+
+/* Scale space (Sec. III-A, Eq. (1); Sec. IV-A, Algorithm 1 stage A and its
+ * downsampling step).  Reads the packed u8 images at d_images (layout given
+ * at context creation) and writes every G_{o,k}, k = 0..4, as FP32 planes
+ * on the 0..255 scale into d_pyr (cdvs_pyramid_bytes bytes, 256-byte
+ * aligned).  G_{0,0} is the input blurred by sigma0 (the input is taken as
+ * sharp); G_{o,k} is G_{o,0} blurred by sigma0 sqrt(2^(k/2) - 1); G_{o+1,0}
+ * takes the even samples of G_{o,4}.  Separable, vertical pass first,
+ * clamp-to-edge borders. */
+cdvs_status cdvs_pyramid(cdvs_ctx* ctx, const uint8_t* d_images, float* d_pyr, void* stream);
+
+/* ALP detection (Sec. III-A, Eqs. (2)-(3); Algorithm 1 stages A-C) on a
+ * pyramid written by cdvs_pyramid.  Per pixel: scale-normalised 5-point
+ * Laplacians L_k, the least-squares cubic p(sigma) through them, its extremal
+ * scale in [sigma_0, sigma_4) where |p| peaks, |p| >= contrast, a strict
+ * extremum against the 8 neighbours' cubics at the same scale, then one
+ * quadratic refinement step (unstable candidates dropped).  Candidates of
+ * adjacent octaves that are close in (x, y, sigma) with the same sign keep
+ * only the higher |p|.  Writes per image the topk strongest keypoints in
+ * canonical order (|p| desc, octave, iy, ix asc) to d_kp[image][0..] and
+ * their number to d_count[image].  d_kp: n_images x kp_capacity records,
+ * d_count: n_images int32.  d_mask must be NULL (reserved). */
+cdvs_status cdvs_alp_detect(cdvs_ctx* ctx, const float* d_pyr, const uint8_t* d_mask, cdvs_keypoint* d_kp,
+                            int32_t* d_count, void* stream);
+
+/* Orientation assignment (Sec. III-B and IV-B, Algorithm 2 stage A): for
+ * each input keypoint a 36-bin histogram of gradient angles of G_{o,k*}
+ * (k* the nearest scale image) over pixels strictly within ori_radius*sigma,
+ * weighted by magnitude and a Gaussian of ori_wsigma*sigma, split linearly
+ * between neighbouring bins; every strict local maximum above ori_peak x the
+ * highest gives one output record (at most max_ori, highest first), its angle
+ * refined by a parabola.  Output per image: records in input order, cut at
+ * topk.  d_kp_in/d_count_in as written by cdvs_alp_detect; d_kp_out and
+ * d_count_out have the same shapes and must not alias the inputs. */
+cdvs_status cdvs_orient(cdvs_ctx* ctx, const float* d_pyr, const cdvs_keypoint* d_kp_in,
+                        const int32_t* d_count_in, cdvs_keypoint* d_kp_out, int32_t* d_count_out,
+                        void* stream);
+
+/* Local descriptor (Sec. III-B and IV-B, Algorithm 2 stage B): for each
+ * oriented keypoint, the 4x4-cell x 8-bin histogram of gradient angles
+ * relative to theta over pixels strictly within desc_radius*sigma, offsets
+ * rotated by -theta and measured in cells of desc_cell*sigma, weighted by
+ * magnitude and a Gaussian of desc_wsigma*sigma, split trilinearly; then
+ * L2-normalised, clamped at desc_clamp and L2-normalised again.  Element
+ * (row*4 + col)*8 + bin.  d_desc: n_images x kp_capacity x 128 floats; rows
+ * at or beyond d_count[image] are left untouched. */
+cdvs_status cdvs_describe(cdvs_ctx* ctx, const float* d_pyr, const cdvs_keypoint* d_kp, const int32_t* d_count,
+                          float* d_desc, void* stream);
+
+/* Synchronise `stream`, then return CDVS_ERR_CAPACITY if any call since the
+ * last cdvs_sync_status dropped results (more candidates than the context's
+ * scratch holds), else CDVS_OK; clears the latch.  The only blocking call. */
+cdvs_status cdvs_sync_status(cdvs_ctx* ctx, void* stream);
+
+/* Candidate scratch size per image (pre-deduplication candidates). */
+int32_t cdvs_candidate_capacity(const cdvs_ctx* ctx);
+
+/* Per-kernel timing with HIP events (tracing).  While enabled, every kernel
+ * the compute calls launch is bracketed by a pair of events recorded on the
+ * call's stream (so a context being captured into a graph must not have it
+ * enabled).  cdvs_profile_read synchronises on the last event, adds each
+ * bracket's elapsed time to total_ms[id] and launches[id] (arrays of
+ * CDVS_KERNEL_COUNT entries, overwritten) and forgets the brackets.  Up to
+ * 16384 brackets are kept between reads; later launches go unrecorded. */
+typedef enum {
+    CDVS_KERNEL_PREBLUR = 0,  /* u8 input -> G_{0,0} */
+    CDVS_KERNEL_SCALES,       /* G_{o,0} -> G_{o,1..4} and G_{o+1,0}, one launch per octave */
+    CDVS_KERNEL_CLEAR,        /* candidate counters */
+    CDVS_KERNEL_DETECT,       /* LoG + ALP + NMS + refinement, one launch per octave */
+    CDVS_KERNEL_FINALIZE,     /* cross-octave duplicates, sort, top-k */
+    CDVS_KERNEL_ORIENT,       /* orientation histograms and peaks */
+    CDVS_KERNEL_ORIENT_COMPACT,
+    CDVS_KERNEL_DESCRIBE,     /* 4x4x8 descriptors */
+    CDVS_KERNEL_COUNT
+} cdvs_kernel_id;
+
+cdvs_status cdvs_profile_enable(cdvs_ctx* ctx, int32_t enable);
+cdvs_status cdvs_profile_read(cdvs_ctx* ctx, double* total_ms, int32_t* launches);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CDVS_H */

@@ -1,0 +1,308 @@
+"""Python binding of the gfx950 CDVS front-half library (libcdvs.so).
+
+Argument marshalling only: every step of the path runs in the library's HIP
+kernels.  PyTorch provides device memory and streams.  The functions keep the
+names of the C ABI (include/cdvs.h); ``Pipeline`` owns the buffers of one
+batch layout and runs the four stages.
+
+Importing this package never compiles anything; ``build()`` does.  If the
+library has not been built, ``lib()`` raises -- there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libcdvs.so")
+_lib = None
+
+CDVS_OK = 0
+CDVS_ERR_ARG = -1
+CDVS_ERR_SHAPE = -2
+CDVS_ERR_CAPACITY = -3
+CDVS_ERR_HIP = -4
+CDVS_ERR_STATE = -5
+CDVS_ERR_VERSION = -6
+CDVS_PARAMS_VERSION = 1
+DESC_DIM = 128
+
+_STATUS = {0: "CDVS_OK", -1: "CDVS_ERR_ARG", -2: "CDVS_ERR_SHAPE", -3: "CDVS_ERR_CAPACITY",
+           -4: "CDVS_ERR_HIP", -5: "CDVS_ERR_STATE", -6: "CDVS_ERR_VERSION"}
+
+
+class CdvsError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{_STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class Params(ctypes.Structure):
+    _fields_ = [("version", ctypes.c_int32), ("sigma0", ctypes.c_float), ("intervals", ctypes.c_int32),
+                ("min_side", ctypes.c_int32), ("contrast", ctypes.c_float), ("edge_r", ctypes.c_float),
+                ("border", ctypes.c_int32), ("max_offset", ctypes.c_float), ("dedup_dlog2", ctypes.c_float),
+                ("ori_radius", ctypes.c_float), ("ori_wsigma", ctypes.c_float), ("ori_peak", ctypes.c_float),
+                ("max_ori", ctypes.c_int32), ("desc_cell", ctypes.c_float), ("desc_radius", ctypes.c_float),
+                ("desc_wsigma", ctypes.c_float), ("desc_clamp", ctypes.c_float), ("topk", ctypes.c_int32)]
+
+
+class ImageDesc(ctypes.Structure):
+    _fields_ = [("offset", ctypes.c_int64), ("width", ctypes.c_int32), ("height", ctypes.c_int32),
+                ("pitch", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+# 48-byte cdvs_keypoint
+KP_DTYPE = np.dtype([("x", "f4"), ("y", "f4"), ("sigma", "f4"), ("p", "f4"), ("theta", "f4"),
+                     ("rho", "f4"), ("p_ss", "f4"), ("peak", "f4"), ("image", "i4"), ("octave", "i4"),
+                     ("ix", "i4"), ("iy", "i4")])
+assert KP_DTYPE.itemsize == 48
+
+# Every symbol include/cdvs.h declares.
+EXPORTS = ["cdvs_default_params", "cdvs_validate", "cdvs_ctx_create", "cdvs_ctx_destroy", "cdvs_last_error",
+           "cdvs_pyramid_bytes", "cdvs_num_octaves", "cdvs_plane_layout", "cdvs_pyramid", "cdvs_alp_detect",
+           "cdvs_orient", "cdvs_describe", "cdvs_sync_status", "cdvs_candidate_capacity",
+           "cdvs_profile_enable", "cdvs_profile_read"]
+
+KERNEL_NAMES = ["preblur", "scales", "clear", "detect", "finalize", "orient", "orient_compact", "describe"]
+
+
+def build() -> str:
+    from . import hipbuild
+    return hipbuild.build()
+
+
+def lib():
+    """The loaded libcdvs.so; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_1705_09776_amd.hipbuild`")
+    L = ctypes.CDLL(LIB_PATH)
+    vp, i32, i64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64
+    P = ctypes.POINTER(Params)
+    sig = {
+        "cdvs_default_params": (Params, []),
+        "cdvs_validate": (i32, [P, ctypes.POINTER(ImageDesc), i32, i32, ctypes.c_char_p, i32]),
+        "cdvs_ctx_create": (i32, [P, ctypes.POINTER(ImageDesc), i32, i32, ctypes.POINTER(vp)]),
+        "cdvs_ctx_destroy": (None, [vp]),
+        "cdvs_last_error": (ctypes.c_char_p, [vp]),
+        "cdvs_pyramid_bytes": (i64, [vp]),
+        "cdvs_num_octaves": (i32, [vp, i32]),
+        "cdvs_plane_layout": (i32, [vp, i32, i32, i32, ctypes.POINTER(i64), ctypes.POINTER(i32),
+                                    ctypes.POINTER(i32), ctypes.POINTER(i32)]),
+        "cdvs_pyramid": (i32, [vp, vp, vp, vp]),
+        "cdvs_alp_detect": (i32, [vp, vp, vp, vp, vp, vp]),
+        "cdvs_orient": (i32, [vp, vp, vp, vp, vp, vp, vp]),
+        "cdvs_describe": (i32, [vp, vp, vp, vp, vp, vp]),
+        "cdvs_sync_status": (i32, [vp, vp]),
+        "cdvs_candidate_capacity": (i32, [vp]),
+        "cdvs_profile_enable": (i32, [vp, i32]),
+        "cdvs_profile_read": (i32, [vp, vp, vp]),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(L, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = L
+    return L
+
+
+def default_params() -> Params:
+    return lib().cdvs_default_params()
+
+
+def _ptr(t) -> int | None:
+    return None if t is None else int(t.data_ptr())
+
+
+def _stream(stream) -> int | None:
+    if stream is None:
+        import torch
+        return int(torch.cuda.current_stream().cuda_stream)
+    return int(getattr(stream, "cuda_stream", stream))
+
+
+def _check(ctx, st: int):
+    if st != CDVS_OK:
+        raise CdvsError(st, lib().cdvs_last_error(ctx).decode(errors="replace"))
+
+
+def cdvs_validate(params: Params, descs, kp_capacity: int):
+    arr = (ImageDesc * len(descs))(*descs)
+    buf = ctypes.create_string_buffer(256)
+    st = lib().cdvs_validate(ctypes.byref(params), arr, len(descs), kp_capacity, buf, 256)
+    return st, buf.value.decode()
+
+
+def cdvs_ctx_create(params: Params, descs, kp_capacity: int):
+    arr = (ImageDesc * len(descs))(*descs)
+    out = ctypes.c_void_p()
+    st = lib().cdvs_ctx_create(ctypes.byref(params), arr, len(descs), kp_capacity, ctypes.byref(out))
+    _check(None, st)
+    return out
+
+
+def cdvs_ctx_destroy(ctx):
+    lib().cdvs_ctx_destroy(ctx)
+
+
+def cdvs_pyramid(ctx, d_images, d_pyr, stream=None):
+    _check(ctx, lib().cdvs_pyramid(ctx, _ptr(d_images), _ptr(d_pyr), _stream(stream)))
+
+
+def cdvs_alp_detect(ctx, d_pyr, d_mask, d_kp, d_count, stream=None):
+    _check(ctx, lib().cdvs_alp_detect(ctx, _ptr(d_pyr), _ptr(d_mask), _ptr(d_kp), _ptr(d_count), _stream(stream)))
+
+
+def cdvs_orient(ctx, d_pyr, d_kp_in, d_count_in, d_kp_out, d_count_out, stream=None):
+    _check(ctx, lib().cdvs_orient(ctx, _ptr(d_pyr), _ptr(d_kp_in), _ptr(d_count_in), _ptr(d_kp_out),
+                                  _ptr(d_count_out), _stream(stream)))
+
+
+def cdvs_describe(ctx, d_pyr, d_kp, d_count, d_desc, stream=None):
+    _check(ctx, lib().cdvs_describe(ctx, _ptr(d_pyr), _ptr(d_kp), _ptr(d_count), _ptr(d_desc), _stream(stream)))
+
+
+def cdvs_sync_status(ctx, stream=None) -> int:
+    st = lib().cdvs_sync_status(ctx, _stream(stream))
+    if st not in (CDVS_OK, CDVS_ERR_CAPACITY):
+        _check(ctx, st)
+    return st
+
+
+def cdvs_profile_enable(ctx, enable: bool):
+    _check(ctx, lib().cdvs_profile_enable(ctx, 1 if enable else 0))
+
+
+def cdvs_profile_read(ctx):
+    """{kernel name: (total ms, launches)} since the last read."""
+    ms = np.zeros(len(KERNEL_NAMES), dtype=np.float64)
+    n = np.zeros(len(KERNEL_NAMES), dtype=np.int32)
+    _check(ctx, lib().cdvs_profile_read(ctx, ms.ctypes.data, n.ctypes.data))
+    return {k: (float(ms[i]), int(n[i])) for i, k in enumerate(KERNEL_NAMES)}
+
+
+def cdvs_plane_layout(ctx, image: int, octave: int, k: int):
+    off, w, h, p = ctypes.c_int64(), ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+    _check(ctx, lib().cdvs_plane_layout(ctx, image, octave, k, ctypes.byref(off), ctypes.byref(w),
+                                        ctypes.byref(h), ctypes.byref(p)))
+    return off.value, w.value, h.value, p.value
+
+
+def pack_images(images):
+    """Pack a list of 2-D uint8 arrays (or an (n, H, W) array) into one byte
+    buffer with 64-byte-aligned rows; returns (buffer, descriptors)."""
+    descs, off, chunks = [], 0, []
+    for im in images:
+        im = np.ascontiguousarray(im, dtype=np.uint8)
+        h, w = im.shape
+        pitch = (w + 63) // 64 * 64
+        buf = np.zeros((h, pitch), dtype=np.uint8)
+        buf[:, :w] = im
+        descs.append(ImageDesc(off, w, h, pitch, 0))
+        chunks.append(buf.reshape(-1))
+        off += buf.size
+    return np.concatenate(chunks), descs
+
+
+class Pipeline:
+    """Device buffers and context for one batch layout.
+
+    ``run()`` enqueues cdvs_pyramid -> cdvs_alp_detect -> cdvs_orient ->
+    cdvs_describe on the current torch stream."""
+
+    def __init__(self, sizes, params: Params | None = None, kp_capacity: int | None = None, device="cuda"):
+        import torch
+        self.torch = torch
+        self.params = params if params is not None else default_params()
+        self.kp_capacity = kp_capacity or max(1, self.params.topk)
+        self.sizes = [tuple(s) for s in sizes]          # (width, height)
+        self.descs, off = [], 0
+        for (w, h) in self.sizes:
+            pitch = (w + 63) // 64 * 64
+            self.descs.append(ImageDesc(off, w, h, pitch, 0))
+            off += pitch * h
+        self.image_bytes = off
+        self.n = len(self.sizes)
+        self.ctx = cdvs_ctx_create(self.params, self.descs, self.kp_capacity)
+        L = lib()
+        self.pyr_bytes = int(L.cdvs_pyramid_bytes(self.ctx))
+        dev = torch.device(device)
+        self.d_images = torch.zeros(self.image_bytes, dtype=torch.uint8, device=dev)
+        self.d_pyr = torch.empty(self.pyr_bytes // 4, dtype=torch.float32, device=dev)
+        self.d_kp = torch.zeros((self.n, self.kp_capacity, 12), dtype=torch.int32, device=dev)
+        self.d_count = torch.zeros(self.n, dtype=torch.int32, device=dev)
+        self.d_kp_ori = torch.zeros((self.n, self.kp_capacity, 12), dtype=torch.int32, device=dev)
+        self.d_count_ori = torch.zeros(self.n, dtype=torch.int32, device=dev)
+        self.d_desc = torch.zeros((self.n, self.kp_capacity, DESC_DIM), dtype=torch.float32, device=dev)
+
+    def close(self):
+        if getattr(self, "ctx", None):
+            cdvs_ctx_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def upload(self, images):
+        assert len(images) == self.n
+        host = np.zeros(self.image_bytes, dtype=np.uint8)
+        for im, d in zip(images, self.descs):
+            im = np.asarray(im, dtype=np.uint8)
+            assert im.shape == (d.height, d.width)
+            host[d.offset:d.offset + d.pitch * d.height].reshape(d.height, d.pitch)[:, :d.width] = im
+        self.d_images.copy_(self.torch.from_numpy(host))
+
+    def pyramid(self, stream=None):
+        cdvs_pyramid(self.ctx, self.d_images, self.d_pyr, stream)
+
+    def detect(self, stream=None):
+        cdvs_alp_detect(self.ctx, self.d_pyr, None, self.d_kp, self.d_count, stream)
+
+    def orient(self, stream=None):
+        cdvs_orient(self.ctx, self.d_pyr, self.d_kp, self.d_count, self.d_kp_ori, self.d_count_ori, stream)
+
+    def describe(self, stream=None):
+        cdvs_describe(self.ctx, self.d_pyr, self.d_kp_ori, self.d_count_ori, self.d_desc, stream)
+
+    def run(self, stream=None):
+        self.pyramid(stream)
+        self.detect(stream)
+        self.orient(stream)
+        self.describe(stream)
+
+    def sync_status(self, stream=None) -> int:
+        return cdvs_sync_status(self.ctx, stream)
+
+    # -- host read-back helpers (tests) ---------------------------------
+    def plane(self, image, octave, k):
+        off, w, h, pitch = cdvs_plane_layout(self.ctx, image, octave, k)
+        flat = self.d_pyr[off:off + pitch * h].view(h, pitch)[:, :w]
+        return flat.cpu().numpy()
+
+    def num_octaves(self, image):
+        return int(lib().cdvs_num_octaves(self.ctx, image))
+
+    @staticmethod
+    def _records(t, counts):
+        arr = t.cpu().numpy().view(KP_DTYPE).reshape(t.shape[0], t.shape[1])
+        return [arr[i, :counts[i]].copy() for i in range(arr.shape[0])]
+
+    def keypoints(self):
+        counts = self.d_count.cpu().numpy()
+        return self._records(self.d_kp, counts)
+
+    def oriented(self):
+        counts = self.d_count_ori.cpu().numpy()
+        return self._records(self.d_kp_ori, counts)
+
+    def descriptors(self):
+        counts = self.d_count_ori.cpu().numpy()
+        d = self.d_desc.cpu().numpy()
+        return [d[i, :counts[i]].copy() for i in range(self.n)]

@@ -1,0 +1,512 @@
+// Host side of the gfx950 CDVS library: argument validation, the batch
+// layout (pyramid plane offsets, per-octave tile lists), the constant blocks
+// handed to the kernels, and the C ABI of include/cdvs.h.
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <string>
+#include <vector>
+
+#include "cdvs_internal.h"
+
+using namespace cdvs;
+
+struct cdvs_ctx {
+    cdvs_params params{};
+    int n = 0;
+    int kp_cap = 0;
+    std::vector<cdvs_image_desc> images;
+    std::vector<int> octaves;                  // per image
+    std::vector<OctGeom> geom;                 // [n][kMaxOctaves]
+    std::vector<OctJob> jobs;                  // grouped by octave
+    int max_oct = 0;
+    int job_start[kMaxOctaves + 1] = {};
+    int blur_tiles[kMaxOctaves] = {};
+    int det_tiles[kMaxOctaves] = {};
+    int64_t pyr_floats = 0;
+    Taps taps{};
+    DetParams det{};
+    OriParams ori{};
+    DescParams desc{};
+    float dedup_ratio = 0.f;
+    // device
+    OctJob* d_jobs = nullptr;
+    OctGeom* d_geom = nullptr;
+    cdvs_keypoint* d_cand = nullptr;
+    int32_t* d_cand_cnt = nullptr;
+    cdvs_keypoint* d_ori = nullptr;
+    int32_t* d_ori_cnt = nullptr;
+    int32_t* d_flags = nullptr;
+    std::string err;
+    // event brackets (cdvs_profile_*)
+    bool prof = false;
+    std::vector<hipEvent_t> ev;       // 2 per bracket
+    std::vector<int> ev_id;           // kernel id per bracket
+    int ev_used = 0;
+};
+
+namespace {
+
+thread_local std::string g_create_err;
+
+cdvs_status fail(cdvs_ctx* ctx, cdvs_status st, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    if (ctx) ctx->err = buf;
+    else g_create_err = buf;
+    return st;
+}
+
+int64_t round_up(int64_t v, int64_t a) { return (v + a - 1) / a * a; }
+
+int count_octaves(int w, int h, int min_side) {
+    int n = 1;
+    while (std::min(w, h) >= min_side) {
+        w = (w + 1) / 2;
+        h = (h + 1) / 2;
+        ++n;
+    }
+    return n;
+}
+
+// Gaussian taps exp(-p^2 / 2 s^2), |p| <= r, normalised to sum 1 (double),
+// stored as float.
+void make_taps(double s, int r, float* g) {
+    double e[2 * kMaxR + 1], sum = 0.0;
+    for (int p = -r; p <= r; ++p) {
+        e[p + r] = exp(-(double)(p * p) / (2.0 * s * s));
+        sum += e[p + r];
+    }
+    for (int i = 0; i < 2 * r + 1; ++i) g[i] = (float)(e[i] / sum);
+}
+
+// Least-squares cubic through (sigma_k, L_k), k = 0..4: coefficients
+// beta[k][i] of alpha_i = sum_k beta[k][i] L_k, i.e. (V^T V)^-1 V^T with
+// V_{k,i} = sigma_k^i, solved by Gauss-Jordan elimination in long double.
+void make_beta(const double* sig, float beta[kScales][4]) {
+    long double M[4][4 + kScales];
+    for (int i = 0; i < 4; ++i) {
+        for (int j = 0; j < 4; ++j) {
+            long double a = 0;
+            for (int k = 0; k < kScales; ++k) a += powl(sig[k], i) * powl(sig[k], j);
+            M[i][j] = a;
+        }
+        for (int k = 0; k < kScales; ++k) M[i][4 + k] = powl(sig[k], i);
+    }
+    for (int c = 0; c < 4; ++c) {
+        int piv = c;
+        for (int r = c + 1; r < 4; ++r)
+            if (fabsl(M[r][c]) > fabsl(M[piv][c])) piv = r;
+        if (piv != c)
+            for (int j = 0; j < 4 + kScales; ++j) {
+                long double t = M[c][j];
+                M[c][j] = M[piv][j];
+                M[piv][j] = t;
+            }
+        long double d = M[c][c];
+        for (int j = 0; j < 4 + kScales; ++j) M[c][j] /= d;
+        for (int r = 0; r < 4; ++r) {
+            if (r == c) continue;
+            long double f = M[r][c];
+            for (int j = 0; j < 4 + kScales; ++j) M[r][j] -= f * M[c][j];
+        }
+    }
+    for (int k = 0; k < kScales; ++k)
+        for (int i = 0; i < 4; ++i) beta[k][i] = (float)M[i][4 + k];
+}
+
+constexpr int kMaxBrackets = 16384;
+
+// Brackets one kernel launch with events when profiling is on.
+struct Bracket {
+    cdvs_ctx* c;
+    hipStream_t s;
+    int slot = -1;
+    Bracket(cdvs_ctx* ctx, int id, hipStream_t stream) : c(ctx), s(stream) {
+        if (c->prof && c->ev_used < kMaxBrackets) {
+            slot = c->ev_used++;
+            c->ev_id[slot] = id;
+            (void)hipEventRecord(c->ev[2 * slot], s);
+        }
+    }
+    ~Bracket() {
+        if (slot >= 0) (void)hipEventRecord(c->ev[2 * slot + 1], s);
+    }
+};
+
+#define HIP_OR_FAIL(ctx, expr)                                                                  \
+    do {                                                                                        \
+        hipError_t e_ = (expr);                                                                 \
+        if (e_ != hipSuccess) return fail(ctx, CDVS_ERR_HIP, "%s: %s", #expr, hipGetErrorString(e_)); \
+    } while (0)
+
+}  // namespace
+
+extern "C" {
+
+cdvs_params cdvs_default_params(void) {
+    cdvs_params p;
+    memset(&p, 0, sizeof(p));
+    p.version = CDVS_PARAMS_VERSION;
+    p.sigma0 = 1.6f;
+    p.intervals = 4;
+    p.min_side = 32;
+    p.contrast = 1.5f;
+    p.edge_r = 10.f;
+    p.border = 4;
+    p.max_offset = 0.5f;
+    p.dedup_dlog2 = 0.25f;
+    p.ori_radius = 3.96f;
+    p.ori_wsigma = 1.5f;
+    p.ori_peak = 0.8f;
+    p.max_ori = 4;
+    p.desc_cell = 3.f;
+    p.desc_radius = 6.f;
+    p.desc_wsigma = 6.f;
+    p.desc_clamp = 0.2f;
+    p.topk = 1000;
+    return p;
+}
+
+cdvs_status cdvs_validate(const cdvs_params* p, const cdvs_image_desc* im, int32_t n, int32_t kp_cap, char* msg,
+                          int32_t msg_len) {
+    char buf[256] = {0};
+    cdvs_status st = CDVS_OK;
+#define BAD(code, ...)                             \
+    do {                                           \
+        snprintf(buf, sizeof(buf), __VA_ARGS__);   \
+        st = code;                                 \
+        goto done;                                 \
+    } while (0)
+    if (!p) BAD(CDVS_ERR_ARG, "params is NULL");
+    if (p->version != CDVS_PARAMS_VERSION) BAD(CDVS_ERR_VERSION, "params.version %d != %d", p->version, CDVS_PARAMS_VERSION);
+    if (fabsf(p->sigma0 - 1.6f) > 1e-6f || p->intervals != 4)
+        BAD(CDVS_ERR_ARG, "kernels are compiled for sigma0 = 1.6 and intervals = 4");
+    if (p->min_side < 8) BAD(CDVS_ERR_ARG, "min_side %d < 8", p->min_side);
+    if (!(p->contrast >= 0.f)) BAD(CDVS_ERR_ARG, "contrast must be >= 0");
+    if (!(p->edge_r > 0.f)) BAD(CDVS_ERR_ARG, "edge_r must be > 0");
+    if (p->border < 1) BAD(CDVS_ERR_ARG, "border must be >= 1");
+    if (!(p->max_offset > 0.f)) BAD(CDVS_ERR_ARG, "max_offset must be > 0");
+    if (!(p->dedup_dlog2 >= 0.f)) BAD(CDVS_ERR_ARG, "dedup_dlog2 must be >= 0");
+    if (!(p->ori_radius > 0.f) || !(p->ori_radius <= 8.f)) BAD(CDVS_ERR_ARG, "ori_radius must be in (0, 8]");
+    if (!(p->ori_wsigma > 0.f)) BAD(CDVS_ERR_ARG, "ori_wsigma must be > 0");
+    if (!(p->ori_peak > 0.f) || !(p->ori_peak <= 1.f)) BAD(CDVS_ERR_ARG, "ori_peak must be in (0, 1]");
+    if (p->max_ori < 1 || p->max_ori > kMaxOri) BAD(CDVS_ERR_ARG, "max_ori must be in 1..%d", kMaxOri);
+    if (!(p->desc_cell > 0.f) || !(p->desc_radius > 0.f) || !(p->desc_radius <= 12.f) || !(p->desc_wsigma > 0.f))
+        BAD(CDVS_ERR_ARG, "descriptor geometry must be positive (radius <= 12)");
+    if (!(p->desc_clamp > 0.f)) BAD(CDVS_ERR_ARG, "desc_clamp must be > 0");
+    if (kp_cap < 1 || kp_cap > CDVS_MAX_KP_CAPACITY)
+        BAD(CDVS_ERR_SHAPE, "kp_capacity %d outside 1..%d", kp_cap, CDVS_MAX_KP_CAPACITY);
+    if (p->topk > kp_cap) BAD(CDVS_ERR_ARG, "topk %d > kp_capacity %d", p->topk, kp_cap);
+    if (n < 1 || n > CDVS_MAX_IMAGES) BAD(CDVS_ERR_SHAPE, "n_images %d outside 1..%d", n, CDVS_MAX_IMAGES);
+    if (!im) BAD(CDVS_ERR_ARG, "images is NULL");
+    for (int i = 0; i < n; ++i) {
+        const cdvs_image_desc& d = im[i];
+        if (d.width < CDVS_MIN_SIDE || d.height < CDVS_MIN_SIDE || d.width > CDVS_MAX_SIDE || d.height > CDVS_MAX_SIDE)
+            BAD(CDVS_ERR_SHAPE, "image %d: %dx%d outside %d..%d per side", i, d.width, d.height, CDVS_MIN_SIDE,
+                CDVS_MAX_SIDE);
+        if (d.pitch < d.width) BAD(CDVS_ERR_SHAPE, "image %d: pitch %d < width %d", i, d.pitch, d.width);
+        if (d.offset < 0) BAD(CDVS_ERR_SHAPE, "image %d: negative offset", i);
+        if (count_octaves(d.width, d.height, p->min_side) > kMaxOctaves)
+            BAD(CDVS_ERR_SHAPE, "image %d: more than %d octaves", i, kMaxOctaves);
+    }
+#undef BAD
+done:
+    if (msg && msg_len > 0) {
+        strncpy(msg, buf, (size_t)msg_len - 1);
+        msg[msg_len - 1] = 0;
+    }
+    return st;
+}
+
+const char* cdvs_last_error(const cdvs_ctx* ctx) { return ctx ? ctx->err.c_str() : g_create_err.c_str(); }
+
+void cdvs_ctx_destroy(cdvs_ctx* ctx) {
+    if (!ctx) return;
+    for (auto& e : ctx->ev) (void)hipEventDestroy(e);
+    (void)hipFree(ctx->d_jobs);
+    (void)hipFree(ctx->d_geom);
+    (void)hipFree(ctx->d_cand);
+    (void)hipFree(ctx->d_cand_cnt);
+    (void)hipFree(ctx->d_ori);
+    (void)hipFree(ctx->d_ori_cnt);
+    (void)hipFree(ctx->d_flags);
+    delete ctx;
+}
+
+static cdvs_status build_layout(cdvs_ctx* c) {
+    const cdvs_params& p = c->params;
+    c->octaves.resize(c->n);
+    c->geom.assign((size_t)c->n * kMaxOctaves, OctGeom{0, 0, 0, 0, 0});
+    std::vector<std::vector<OctJob>> per_oct(kMaxOctaves);
+    int64_t off = 0;
+    for (int i = 0; i < c->n; ++i) {
+        const cdvs_image_desc& d = c->images[i];
+        const int no = count_octaves(d.width, d.height, p.min_side);
+        c->octaves[i] = no;
+        c->max_oct = std::max(c->max_oct, no);
+        int w = d.width, h = d.height;
+        int64_t plane0[kMaxOctaves];
+        int pitch[kMaxOctaves], stride[kMaxOctaves], ws[kMaxOctaves], hs[kMaxOctaves];
+        for (int o = 0; o < no; ++o) {
+            ws[o] = w;
+            hs[o] = h;
+            pitch[o] = (int)round_up(w, kPitchAlign);
+            stride[o] = (int)round_up((int64_t)pitch[o] * h, 64);
+            plane0[o] = off;
+            off += (int64_t)stride[o] * kScales;
+            c->geom[(size_t)i * kMaxOctaves + o] = OctGeom{plane0[o], w, h, pitch[o], stride[o]};
+            w = (w + 1) / 2;
+            h = (h + 1) / 2;
+        }
+        for (int o = 0; o < no; ++o) {
+            OctJob j;
+            memset(&j, 0, sizeof(j));
+            j.plane0 = plane0[o];
+            j.next0 = (o + 1 < no) ? plane0[o + 1] : -1;
+            j.src = d.offset;
+            j.w = ws[o];
+            j.h = hs[o];
+            j.pitch = pitch[o];
+            j.plane_stride = stride[o];
+            j.next_w = (o + 1 < no) ? ws[o + 1] : 0;
+            j.next_h = (o + 1 < no) ? hs[o + 1] : 0;
+            j.next_pitch = (o + 1 < no) ? pitch[o + 1] : 0;
+            j.src_pitch = d.pitch;
+            j.image = i;
+            j.octave = o;
+            j.tiles_x_blur = (ws[o] + kBlurTW - 1) / kBlurTW;
+            j.tiles_x_det = (ws[o] + kDetTW - 1) / kDetTW;
+            per_oct[o].push_back(j);
+        }
+    }
+    c->pyr_floats = off;
+    c->jobs.clear();
+    for (int o = 0; o < kMaxOctaves; ++o) {
+        c->job_start[o] = (int)c->jobs.size();
+        int tb = 0, td = 0;
+        for (OctJob& j : per_oct[o]) {
+            j.tile0_blur = tb;
+            j.tile0_det = td;
+            tb += j.tiles_x_blur * ((j.h + kBlurTH - 1) / kBlurTH);
+            td += j.tiles_x_det * ((j.h + kDetTH - 1) / kDetTH);
+            c->jobs.push_back(j);
+        }
+        c->blur_tiles[o] = tb;
+        c->det_tiles[o] = td;
+    }
+    c->job_start[kMaxOctaves] = (int)c->jobs.size();
+    return CDVS_OK;
+}
+
+static void build_constants(cdvs_ctx* c) {
+    const cdvs_params& p = c->params;
+    const double s0 = 1.6;
+    const int radii[kScales] = {kR0, kR1, kR2, kR3, kR4};
+    memset(&c->taps, 0, sizeof(c->taps));
+    for (int k = 0; k < kScales; ++k) {
+        const double s = (k == 0) ? s0 : s0 * sqrt(pow(2.0, k / 2.0) - 1.0);
+        make_taps(s, radii[k], c->taps.g[k]);
+    }
+    double sig[kScales];
+    for (int k = 0; k < kScales; ++k) sig[k] = s0 * pow(2.0, k / 4.0);
+    make_beta(sig, c->det.beta);
+    for (int k = 0; k < kScales; ++k) c->det.sig2[k] = (float)(sig[k] * sig[k]);
+    c->det.lo = (float)sig[0];
+    c->det.hi = (float)sig[kScales - 1];
+    c->det.contrast = p.contrast;
+    c->det.edge_lim = (p.edge_r + 1.f) * (p.edge_r + 1.f) / p.edge_r;
+    c->det.max_off = p.max_offset;
+    c->det.border = p.border;
+    c->det.cand_cap = kCandCap;
+    c->dedup_ratio = (float)pow(2.0, (double)p.dedup_dlog2);
+    c->ori = OriParams{p.ori_radius, p.ori_wsigma, p.ori_peak, p.sigma0, p.max_ori, c->kp_cap};
+    c->desc = DescParams{p.desc_cell, p.desc_radius, p.desc_wsigma, p.desc_clamp, p.sigma0, c->kp_cap};
+}
+
+cdvs_status cdvs_ctx_create(const cdvs_params* params, const cdvs_image_desc* images, int32_t n_images,
+                            int32_t kp_capacity, cdvs_ctx** out) {
+    if (!out) return fail(nullptr, CDVS_ERR_ARG, "out is NULL");
+    *out = nullptr;
+    char msg[256];
+    cdvs_status st = cdvs_validate(params, images, n_images, kp_capacity, msg, sizeof(msg));
+    if (st != CDVS_OK) return fail(nullptr, st, "%s", msg);
+    cdvs_ctx* c = new cdvs_ctx();
+    c->params = *params;
+    c->n = n_images;
+    c->kp_cap = kp_capacity;
+    c->images.assign(images, images + n_images);
+    build_layout(c);
+    build_constants(c);
+    hipError_t e = hipSuccess;
+    const size_t n = (size_t)n_images;
+#define ALLOC(ptr, bytes)                                                        \
+    do {                                                                         \
+        e = hipMalloc((void**)&(ptr), (bytes));                                  \
+        if (e != hipSuccess) {                                                   \
+            fail(nullptr, CDVS_ERR_HIP, "hipMalloc(%zu): %s", (size_t)(bytes), hipGetErrorString(e)); \
+            cdvs_ctx_destroy(c);                                                 \
+            return CDVS_ERR_HIP;                                                 \
+        }                                                                        \
+    } while (0)
+    ALLOC(c->d_jobs, sizeof(OctJob) * std::max<size_t>(1, c->jobs.size()));
+    ALLOC(c->d_geom, sizeof(OctGeom) * c->geom.size());
+    ALLOC(c->d_cand, sizeof(cdvs_keypoint) * n * kCandCap);
+    ALLOC(c->d_cand_cnt, sizeof(int32_t) * n);
+    ALLOC(c->d_ori, sizeof(cdvs_keypoint) * n * kp_capacity * kMaxOri);
+    ALLOC(c->d_ori_cnt, sizeof(int32_t) * n * kp_capacity);
+    ALLOC(c->d_flags, sizeof(int32_t));
+#undef ALLOC
+    if ((e = hipMemcpy(c->d_jobs, c->jobs.data(), sizeof(OctJob) * c->jobs.size(), hipMemcpyHostToDevice)) != hipSuccess ||
+        (e = hipMemcpy(c->d_geom, c->geom.data(), sizeof(OctGeom) * c->geom.size(), hipMemcpyHostToDevice)) != hipSuccess ||
+        (e = hipMemset(c->d_flags, 0, sizeof(int32_t))) != hipSuccess ||
+        (e = hipMemset(c->d_cand_cnt, 0, sizeof(int32_t) * n)) != hipSuccess) {
+        fail(nullptr, CDVS_ERR_HIP, "context upload: %s", hipGetErrorString(e));
+        cdvs_ctx_destroy(c);
+        return CDVS_ERR_HIP;
+    }
+    *out = c;
+    return CDVS_OK;
+}
+
+int64_t cdvs_pyramid_bytes(const cdvs_ctx* ctx) { return ctx ? ctx->pyr_floats * (int64_t)sizeof(float) : -1; }
+
+int32_t cdvs_num_octaves(const cdvs_ctx* ctx, int32_t image) {
+    if (!ctx || image < 0 || image >= ctx->n) return -1;
+    return ctx->octaves[image];
+}
+
+int32_t cdvs_candidate_capacity(const cdvs_ctx* ctx) { return ctx ? kCandCap : -1; }
+
+cdvs_status cdvs_plane_layout(const cdvs_ctx* ctx, int32_t image, int32_t octave, int32_t k, int64_t* offset,
+                              int32_t* width, int32_t* height, int32_t* pitch) {
+    if (!ctx) return CDVS_ERR_STATE;
+    if (image < 0 || image >= ctx->n || octave < 0 || octave >= ctx->octaves[image] || k < 0 || k >= kScales)
+        return CDVS_ERR_ARG;
+    const OctGeom& g = ctx->geom[(size_t)image * kMaxOctaves + octave];
+    if (offset) *offset = g.plane0 + (int64_t)k * g.plane_stride;
+    if (width) *width = g.w;
+    if (height) *height = g.h;
+    if (pitch) *pitch = g.pitch;
+    return CDVS_OK;
+}
+
+cdvs_status cdvs_pyramid(cdvs_ctx* ctx, const uint8_t* d_images, float* d_pyr, void* stream) {
+    if (!ctx) return CDVS_ERR_STATE;
+    if (!d_images || !d_pyr) return fail(ctx, CDVS_ERR_ARG, "cdvs_pyramid: null device pointer");
+    if (((uintptr_t)d_pyr & 255) != 0) return fail(ctx, CDVS_ERR_ARG, "cdvs_pyramid: d_pyr not 256-byte aligned");
+    hipStream_t s = (hipStream_t)stream;
+    {
+        Bracket b(ctx, CDVS_KERNEL_PREBLUR, s);
+        HIP_OR_FAIL(ctx, launch_preblur(d_images, d_pyr, ctx->d_jobs + ctx->job_start[0],
+                                        ctx->job_start[1] - ctx->job_start[0], ctx->blur_tiles[0], ctx->taps, s));
+    }
+    for (int o = 0; o < ctx->max_oct; ++o) {
+        Bracket b(ctx, CDVS_KERNEL_SCALES, s);
+        HIP_OR_FAIL(ctx, launch_scales(d_pyr, ctx->d_jobs + ctx->job_start[o], ctx->job_start[o + 1] - ctx->job_start[o],
+                                       ctx->blur_tiles[o], ctx->taps, s));
+    }
+    return CDVS_OK;
+}
+
+cdvs_status cdvs_alp_detect(cdvs_ctx* ctx, const float* d_pyr, const uint8_t* d_mask, cdvs_keypoint* d_kp,
+                            int32_t* d_count, void* stream) {
+    if (!ctx) return CDVS_ERR_STATE;
+    if (!d_pyr || !d_kp || !d_count) return fail(ctx, CDVS_ERR_ARG, "cdvs_alp_detect: null device pointer");
+    if (d_mask) return fail(ctx, CDVS_ERR_ARG, "cdvs_alp_detect: d_mask is reserved and must be NULL");
+    hipStream_t s = (hipStream_t)stream;
+    {
+        Bracket b(ctx, CDVS_KERNEL_CLEAR, s);
+        HIP_OR_FAIL(ctx, launch_clear(ctx->d_cand_cnt, ctx->n, s));
+    }
+    for (int o = 0; o < ctx->max_oct; ++o) {
+        Bracket b(ctx, CDVS_KERNEL_DETECT, s);
+        HIP_OR_FAIL(ctx, launch_detect(d_pyr, ctx->d_jobs + ctx->job_start[o], ctx->job_start[o + 1] - ctx->job_start[o],
+                                       ctx->det_tiles[o], ctx->det, ctx->d_cand, ctx->d_cand_cnt, ctx->d_flags, s));
+    }
+    {
+        Bracket b(ctx, CDVS_KERNEL_FINALIZE, s);
+        HIP_OR_FAIL(ctx, launch_finalize(ctx->d_cand, ctx->d_cand_cnt, ctx->n, kCandCap, ctx->dedup_ratio,
+                                         ctx->params.topk, ctx->kp_cap, d_kp, d_count, s));
+    }
+    return CDVS_OK;
+}
+
+cdvs_status cdvs_orient(cdvs_ctx* ctx, const float* d_pyr, const cdvs_keypoint* d_kp_in, const int32_t* d_count_in,
+                        cdvs_keypoint* d_kp_out, int32_t* d_count_out, void* stream) {
+    if (!ctx) return CDVS_ERR_STATE;
+    if (!d_pyr || !d_kp_in || !d_count_in || !d_kp_out || !d_count_out)
+        return fail(ctx, CDVS_ERR_ARG, "cdvs_orient: null device pointer");
+    if ((const void*)d_kp_in == (const void*)d_kp_out || (const void*)d_count_in == (const void*)d_count_out)
+        return fail(ctx, CDVS_ERR_ARG, "cdvs_orient: outputs must not alias inputs");
+    hipStream_t s = (hipStream_t)stream;
+    {
+        Bracket b(ctx, CDVS_KERNEL_ORIENT, s);
+        HIP_OR_FAIL(ctx, launch_orient(d_pyr, ctx->d_geom, d_kp_in, d_count_in, ctx->n, ctx->ori, ctx->d_ori,
+                                       ctx->d_ori_cnt, s));
+    }
+    {
+        Bracket b(ctx, CDVS_KERNEL_ORIENT_COMPACT, s);
+        HIP_OR_FAIL(ctx, launch_orient_compact(ctx->d_ori, ctx->d_ori_cnt, d_count_in, ctx->n, ctx->kp_cap,
+                                               ctx->params.topk, d_kp_out, d_count_out, s));
+    }
+    return CDVS_OK;
+}
+
+cdvs_status cdvs_describe(cdvs_ctx* ctx, const float* d_pyr, const cdvs_keypoint* d_kp, const int32_t* d_count,
+                          float* d_desc, void* stream) {
+    if (!ctx) return CDVS_ERR_STATE;
+    if (!d_pyr || !d_kp || !d_count || !d_desc) return fail(ctx, CDVS_ERR_ARG, "cdvs_describe: null device pointer");
+    hipStream_t s = (hipStream_t)stream;
+    Bracket b(ctx, CDVS_KERNEL_DESCRIBE, s);
+    HIP_OR_FAIL(ctx, launch_describe(d_pyr, ctx->d_geom, d_kp, d_count, ctx->n, ctx->desc, d_desc, s));
+    return CDVS_OK;
+}
+
+cdvs_status cdvs_sync_status(cdvs_ctx* ctx, void* stream) {
+    if (!ctx) return CDVS_ERR_STATE;
+    HIP_OR_FAIL(ctx, hipStreamSynchronize((hipStream_t)stream));
+    int32_t flags = 0;
+    HIP_OR_FAIL(ctx, hipMemcpy(&flags, ctx->d_flags, sizeof(flags), hipMemcpyDeviceToHost));
+    if (flags) {
+        HIP_OR_FAIL(ctx, hipMemset(ctx->d_flags, 0, sizeof(int32_t)));
+        return fail(ctx, CDVS_ERR_CAPACITY, "candidate scratch overflowed (%d per image); results truncated", kCandCap);
+    }
+    return CDVS_OK;
+}
+
+cdvs_status cdvs_profile_enable(cdvs_ctx* ctx, int32_t enable) {
+    if (!ctx) return CDVS_ERR_STATE;
+    if (enable && ctx->ev.empty()) {
+        ctx->ev.resize(2 * kMaxBrackets);
+        ctx->ev_id.resize(kMaxBrackets);
+        for (auto& e : ctx->ev) HIP_OR_FAIL(ctx, hipEventCreate(&e));
+    }
+    ctx->prof = enable != 0;
+    return CDVS_OK;
+}
+
+cdvs_status cdvs_profile_read(cdvs_ctx* ctx, double* total_ms, int32_t* launches) {
+    if (!ctx) return CDVS_ERR_STATE;
+    if (!total_ms || !launches) return fail(ctx, CDVS_ERR_ARG, "cdvs_profile_read: null output");
+    for (int i = 0; i < CDVS_KERNEL_COUNT; ++i) {
+        total_ms[i] = 0.0;
+        launches[i] = 0;
+    }
+    if (ctx->ev_used > 0) HIP_OR_FAIL(ctx, hipEventSynchronize(ctx->ev[2 * ctx->ev_used - 1]));
+    for (int b = 0; b < ctx->ev_used; ++b) {
+        float ms = 0.f;
+        HIP_OR_FAIL(ctx, hipEventElapsedTime(&ms, ctx->ev[2 * b], ctx->ev[2 * b + 1]));
+        total_ms[ctx->ev_id[b]] += ms;
+        launches[ctx->ev_id[b]] += 1;
+    }
+    ctx->ev_used = 0;
+    return CDVS_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,107 @@
+// Internal declarations of the gfx950 CDVS library: device tables, kernel
+// parameter blocks and launchers.  Included by the library's own sources
+// only; the public interface is include/cdvs.h.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "cdvs.h"
+
+namespace cdvs {
+
+// Scale space of the compiled kernels: sigma0 = 1.6, S = 4, five images per
+// octave; direct blur sigmas s_0 = 1.6 (input pre-blur) and
+// s_k = 1.6 sqrt(2^(k/2) - 1), k = 1..4, truncated at ceil(4 s).
+constexpr int kScales = 5;
+constexpr int kR0 = 7, kR1 = 5, kR2 = 7, kR3 = 9, kR4 = 12;
+constexpr int kMaxR = 12;
+constexpr int kTapStride = 2 * kMaxR + 1;  // 25
+constexpr int kOriBins = 36;
+constexpr int kMaxOri = 4;
+constexpr int kDescDim = 128;
+constexpr int kMaxOctaves = 16;
+constexpr int kCandCap = 8192;  // pre-deduplication candidates per image
+
+// Row pitch of every pyramid plane, in floats.
+constexpr int kPitchAlign = 32;
+
+// Gaussian taps g_k[p], p = -r_k..r_k, stored at g[k][p + r_k].
+struct Taps {
+    float g[kScales][kTapStride];
+};
+
+// One (image, octave) unit of work.
+struct OctJob {
+    int64_t plane0;    // float offset of G_{o,0} in the pyramid buffer
+    int64_t next0;     // float offset of G_{o+1,0}, or -1 for the last octave
+    int64_t src;       // byte offset of the u8 image (used at octave 0)
+    int32_t w, h;      // octave size
+    int32_t pitch;     // floats
+    int32_t plane_stride;  // floats between G_{o,k} and G_{o,k+1}
+    int32_t next_w, next_h, next_pitch;
+    int32_t src_pitch;  // bytes
+    int32_t image;
+    int32_t octave;
+    int32_t tiles_x_blur, tile0_blur;  // tiling of the blur kernels
+    int32_t tiles_x_det, tile0_det;    // tiling of the detection kernel
+};
+
+// Per-image octave geometry for the keypoint kernels.
+struct OctGeom {
+    int64_t plane0;
+    int32_t w, h, pitch, plane_stride;
+};
+
+struct DetParams {
+    float beta[kScales][4];  // alpha_i = sum_k beta[k][i] L_k
+    float sig2[kScales];     // sigma_k^2 (octave units)
+    float lo, hi;            // extremal scale range [sigma_0, sigma_4)
+    float contrast;
+    float edge_lim;          // (r+1)^2 / r
+    float max_off;
+    int32_t border;
+    int32_t cand_cap;
+};
+
+struct OriParams {
+    float radius, wsigma, peak;
+    float sigma0;
+    int32_t max_ori;
+    int32_t kp_cap;
+};
+
+struct DescParams {
+    float cell, radius, wsigma, clamp;
+    float sigma0;
+    int32_t kp_cap;
+};
+
+// Bits of the device status word.
+constexpr int kFlagCandOverflow = 1;
+
+// Kernel tile shapes.
+constexpr int kBlurTW = 64, kBlurTH = 32, kBlurV = 8;
+constexpr int kDetTW = 64, kDetTH = 16;
+
+// Launchers (each enqueues on `stream`, returns the launch error).
+hipError_t launch_preblur(const uint8_t* images, float* pyr, const OctJob* jobs, int njobs, int ntiles,
+                          const Taps& taps, hipStream_t stream);
+hipError_t launch_scales(float* pyr, const OctJob* jobs, int njobs, int ntiles, const Taps& taps,
+                         hipStream_t stream);
+hipError_t launch_clear(int32_t* p, int n, hipStream_t stream);
+hipError_t launch_detect(const float* pyr, const OctJob* jobs, int njobs, int ntiles, const DetParams& dp,
+                         cdvs_keypoint* cand, int32_t* cand_cnt, int32_t* flags, hipStream_t stream);
+hipError_t launch_finalize(const cdvs_keypoint* cand, const int32_t* cand_cnt, int n_images, int cand_cap,
+                           float dedup_ratio, int topk, int kp_cap, cdvs_keypoint* kp, int32_t* count,
+                           hipStream_t stream);
+hipError_t launch_orient(const float* pyr, const OctGeom* geom, const cdvs_keypoint* kp, const int32_t* count,
+                         int n_images, const OriParams& op, cdvs_keypoint* ori, int32_t* ori_cnt,
+                         hipStream_t stream);
+hipError_t launch_orient_compact(const cdvs_keypoint* ori, const int32_t* ori_cnt, const int32_t* count_in,
+                                 int n_images, int kp_cap, int topk, cdvs_keypoint* out, int32_t* count_out,
+                                 hipStream_t stream);
+hipError_t launch_describe(const float* pyr, const OctGeom* geom, const cdvs_keypoint* kp, const int32_t* count,
+                           int n_images, const DescParams& dp, float* desc, hipStream_t stream);
+
+}  // namespace cdvs

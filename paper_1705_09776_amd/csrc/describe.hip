@@ -1,0 +1,293 @@
+// Orientation assignment and local descriptors on gfx950 (Sec. III-B and
+// Sec. IV-B, Algorithm 2 stages A and B).
+//
+// One 64-lane wave per keypoint, four keypoints per workgroup.  The lanes
+// sweep the bounding box of the keypoint's disk in row-major order (64
+// pixels per step, the paper's pixel-level parallelism over a patch of
+// variable size), and each in-disk pixel adds its weighted gradient to the
+// wave's histogram in LDS with float atomics.  Peak finding, ranking and
+// normalisation are wave-wide shuffles and ballots.
+#include "cdvs_internal.h"
+
+namespace cdvs {
+
+namespace {
+
+constexpr float kTwoPi = 6.283185307179586f;
+
+__device__ __forceinline__ float wave_sum(float v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+    return v;
+}
+
+__device__ __forceinline__ float wave_max(float v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v = fmaxf(v, __shfl_xor(v, off));
+    return v;
+}
+
+struct KpGeom {
+    const float* plane;  // G_{o,k*}
+    int w, h, pitch;
+    float cx, cy, s;     // octave pixels
+};
+
+__device__ __forceinline__ KpGeom keypoint_geometry(const float* pyr, const OctGeom* geom, int img,
+                                                    const cdvs_keypoint& k, float sigma0) {
+    KpGeom g;
+    const OctGeom og = geom[img * kMaxOctaves + k.octave];
+    const float sc = 1.0f / (float)(1 << k.octave);
+    g.cx = k.x * sc;
+    g.cy = k.y * sc;
+    g.s = k.sigma * sc;
+    // nearest scale image: round(4 log2(s / sigma0)), clamped to 0..4
+    const int ks = min(max((int)floorf(4.f * log2f(g.s / sigma0) + 0.5f), 0), kScales - 1);
+    g.plane = pyr + og.plane0 + (int64_t)ks * og.plane_stride;
+    g.w = og.w;
+    g.h = og.h;
+    g.pitch = og.pitch;
+    return g;
+}
+
+// Gradient at an interior pixel: central differences, angle in [0, 2 pi).
+__device__ __forceinline__ void gradient(const KpGeom& g, int u, int v, float& mag, float& ang) {
+    const float* row = g.plane + (int64_t)v * g.pitch;
+    const float gx = row[u + 1] - row[u - 1];
+    const float gy = row[u + g.pitch] - row[u - g.pitch];
+    mag = sqrtf(gx * gx + gy * gy);
+    float a = atan2f(gy, gx);
+    if (a < 0.f) a += kTwoPi;
+    if (a >= kTwoPi) a -= kTwoPi;
+    ang = a;
+}
+
+__global__ __launch_bounds__(256) void k_orient(const float* __restrict__ pyr, const OctGeom* __restrict__ geom,
+                                                const cdvs_keypoint* __restrict__ kp,
+                                                const int32_t* __restrict__ count, int n_images, OriParams op,
+                                                cdvs_keypoint* __restrict__ ori, int32_t* __restrict__ ori_cnt) {
+    __shared__ float hist[4][kOriBins];
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int64_t slot = (int64_t)blockIdx.x * 4 + wave;
+    const int img = (int)(slot / op.kp_cap), i = (int)(slot % op.kp_cap);
+    cdvs_keypoint k;
+    bool active = img < n_images && i < count[img];
+    if (active) {
+        k = kp[(int64_t)img * op.kp_cap + i];
+        active = k.octave >= 0 && k.octave < kMaxOctaves;
+    }
+    if (lane < kOriBins) hist[wave][lane] = 0.f;
+    __syncthreads();
+
+    if (active) {
+        const KpGeom g = keypoint_geometry(pyr, geom, img, k, op.sigma0);
+        const float R = op.radius * g.s;
+        const float R2 = R * R;
+        const float ws = op.wsigma * g.s;
+        const float den = 2.f * ws * ws;
+        const int u0 = max((int)ceilf(g.cx - R), 1), u1 = min((int)floorf(g.cx + R), g.w - 2);
+        const int v0 = max((int)ceilf(g.cy - R), 1), v1 = min((int)floorf(g.cy + R), g.h - 2);
+        const int bw = u1 - u0 + 1, bh = v1 - v0 + 1;
+        if (bw > 0 && bh > 0) {
+            for (int q = lane; q < bw * bh; q += 64) {
+                const int u = u0 + q % bw, v = v0 + q / bw;
+                const float dx = (float)u - g.cx, dy = (float)v - g.cy;
+                const float d2 = dx * dx + dy * dy;
+                if (!(d2 < R2)) continue;
+                float mag, ang;
+                gradient(g, u, v, mag, ang);
+                const float wt = mag * expf(-d2 / den);
+                const float fb = ang * (float)kOriBins / kTwoPi;
+                const float f0 = floorf(fb);
+                const float fr = fb - f0;
+                const int b0 = (((int)f0 % kOriBins) + kOriBins) % kOriBins;
+                const int b1 = (b0 + 1) % kOriBins;
+                atomicAdd(&hist[wave][b0], wt * (1.f - fr));
+                atomicAdd(&hist[wave][b1], wt * fr);
+            }
+        }
+    }
+    __syncthreads();
+    if (!active) return;
+
+    const float hb = lane < kOriBins ? hist[wave][lane] : 0.f;
+    const float hl = lane < kOriBins ? hist[wave][(lane + kOriBins - 1) % kOriBins] : 0.f;
+    const float hr = lane < kOriBins ? hist[wave][(lane + 1) % kOriBins] : 0.f;
+    const float mx = wave_max(hb);
+    const bool pk = lane < kOriBins && hb > hl && hb > hr && hb > op.peak * mx;
+    const uint64_t pm = __ballot(pk);
+    int rank = 0;
+    for (uint64_t m = pm; m; m &= m - 1) {
+        const int j = __ffsll((unsigned long long)m) - 1;
+        const float hj = __shfl(hb, j);
+        if (hj > hb || (hj == hb && j < lane)) ++rank;
+    }
+    const int64_t base = ((int64_t)img * op.kp_cap + i);
+    if (pk && rank < op.max_ori) {
+        const float off = 0.5f * (hl - hr) / (hl - 2.f * hb + hr);
+        float t = ((float)lane + off) * kTwoPi / (float)kOriBins;
+        if (t < 0.f) t += kTwoPi;
+        if (t >= kTwoPi) t -= kTwoPi;
+        cdvs_keypoint r = k;
+        r.theta = t;
+        r.peak = hb;
+        ori[base * kMaxOri + rank] = r;
+    }
+    if (lane == 0) ori_cnt[base] = min(__popcll(pm), op.max_ori);
+}
+
+// Expand the per-keypoint orientation records of one image in input order
+// and cut at `limit`.
+__global__ __launch_bounds__(256) void k_orient_compact(const cdvs_keypoint* __restrict__ ori,
+                                                        const int32_t* __restrict__ ori_cnt,
+                                                        const int32_t* __restrict__ count_in, int kp_cap, int limit,
+                                                        cdvs_keypoint* __restrict__ out,
+                                                        int32_t* __restrict__ count_out) {
+    __shared__ int part[256];
+    const int img = blockIdx.x, tid = threadIdx.x;
+    const int n = min(max(count_in[img], 0), kp_cap);
+    const int chunk = (n + 255) / 256;
+    const int beg = min(tid * chunk, n), end = min(beg + chunk, n);
+    const int32_t* cnt = ori_cnt + (int64_t)img * kp_cap;
+    int sum = 0;
+    for (int i = beg; i < end; ++i) sum += cnt[i];
+    part[tid] = sum;
+    __syncthreads();
+    for (int off = 1; off < 256; off <<= 1) {
+        const int v = tid >= off ? part[tid - off] : 0;
+        __syncthreads();
+        part[tid] += v;
+        __syncthreads();
+    }
+    int pos = part[tid] - sum;  // exclusive prefix
+    for (int i = beg; i < end && pos < limit; ++i) {
+        const int c = cnt[i];
+        for (int j = 0; j < c && pos + j < limit; ++j)
+            out[(int64_t)img * kp_cap + pos + j] = ori[((int64_t)img * kp_cap + i) * kMaxOri + j];
+        pos += c;
+    }
+    if (tid == 255) count_out[img] = min(part[255], limit);
+}
+
+__global__ __launch_bounds__(256) void k_describe(const float* __restrict__ pyr, const OctGeom* __restrict__ geom,
+                                                  const cdvs_keypoint* __restrict__ kp,
+                                                  const int32_t* __restrict__ count, int n_images, DescParams dp,
+                                                  float* __restrict__ desc) {
+    __shared__ float hist[4][kDescDim];
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int64_t slot = (int64_t)blockIdx.x * 4 + wave;
+    const int img = (int)(slot / dp.kp_cap), i = (int)(slot % dp.kp_cap);
+    cdvs_keypoint k;
+    bool active = img < n_images && i < count[img];
+    if (active) {
+        k = kp[(int64_t)img * dp.kp_cap + i];
+        active = k.octave >= 0 && k.octave < kMaxOctaves;
+    }
+    hist[wave][lane] = 0.f;
+    hist[wave][lane + 64] = 0.f;
+    __syncthreads();
+
+    if (active) {
+        const KpGeom g = keypoint_geometry(pyr, geom, img, k, dp.sigma0);
+        const float th = k.theta;
+        const float ct = cosf(th), st = sinf(th);
+        const float R = dp.radius * g.s;
+        const float R2 = R * R;
+        const float cw = dp.cell * g.s;
+        const float ws = dp.wsigma * g.s;
+        const float den = 2.f * ws * ws;
+        const int u0 = max((int)ceilf(g.cx - R), 1), u1 = min((int)floorf(g.cx + R), g.w - 2);
+        const int v0 = max((int)ceilf(g.cy - R), 1), v1 = min((int)floorf(g.cy + R), g.h - 2);
+        const int bw = u1 - u0 + 1, bh = v1 - v0 + 1;
+        if (bw > 0 && bh > 0) {
+            for (int q = lane; q < bw * bh; q += 64) {
+                const int u = u0 + q % bw, v = v0 + q / bw;
+                const float dx = (float)u - g.cx, dy = (float)v - g.cy;
+                const float d2 = dx * dx + dy * dy;
+                if (!(d2 < R2)) continue;
+                const float rx = (ct * dx + st * dy) / cw;
+                const float ry = (ct * dy - st * dx) / cw;
+                float mag, ang;
+                gradient(g, u, v, mag, ang);
+                float rel = ang - th;
+                if (rel < 0.f) rel += kTwoPi;
+                if (rel >= kTwoPi) rel -= kTwoPi;
+                const float wt = mag * expf(-d2 / den);
+                const float fx = rx + 1.5f, fy = ry + 1.5f, fo = rel * 8.f / kTwoPi;
+                const float x0f = floorf(fx), y0f = floorf(fy), o0f = floorf(fo);
+                const float ax = fx - x0f, ay = fy - y0f, ao = fo - o0f;
+                const int x0 = (int)x0f, y0 = (int)y0f, o0 = (int)o0f;
+#pragma unroll
+                for (int jy = 0; jy < 2; ++jy) {
+                    const int yy = y0 + jy;
+                    if (yy < 0 || yy > 3) continue;
+                    const float wy = jy ? ay : 1.f - ay;
+#pragma unroll
+                    for (int jx = 0; jx < 2; ++jx) {
+                        const int xx = x0 + jx;
+                        if (xx < 0 || xx > 3) continue;
+                        const float wx = jx ? ax : 1.f - ax;
+#pragma unroll
+                        for (int jo = 0; jo < 2; ++jo) {
+                            const int oo = ((o0 + jo) % 8 + 8) % 8;
+                            const float wo = jo ? ao : 1.f - ao;
+                            atomicAdd(&hist[wave][(yy * 4 + xx) * 8 + oo], wt * wy * wx * wo);
+                        }
+                    }
+                }
+            }
+        }
+    }
+    __syncthreads();
+    if (!active) return;
+
+    const float h0 = hist[wave][lane], h1 = hist[wave][lane + 64];
+    float* out = desc + (((int64_t)img * dp.kp_cap + i) * kDescDim);
+    const float n2 = wave_sum(h0 * h0 + h1 * h1);
+    if (!(n2 > 0.f)) {
+        out[lane] = 0.f;
+        out[lane + 64] = 0.f;
+        return;
+    }
+    const float inv = 1.f / sqrtf(n2);
+    const float t0 = fminf(h0 * inv, dp.clamp), t1 = fminf(h1 * inv, dp.clamp);
+    const float inv2 = 1.f / sqrtf(wave_sum(t0 * t0 + t1 * t1));
+    out[lane] = t0 * inv2;
+    out[lane + 64] = t1 * inv2;
+}
+
+int blocks_for(int n_images, int kp_cap) {
+    const int64_t waves = (int64_t)n_images * kp_cap;
+    return (int)((waves + 3) / 4);
+}
+
+}  // namespace
+
+hipError_t launch_orient(const float* pyr, const OctGeom* geom, const cdvs_keypoint* kp, const int32_t* count,
+                         int n_images, const OriParams& op, cdvs_keypoint* ori, int32_t* ori_cnt,
+                         hipStream_t stream) {
+    if (n_images <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_orient, dim3(blocks_for(n_images, op.kp_cap)), dim3(256), 0, stream, pyr, geom, kp, count,
+                       n_images, op, ori, ori_cnt);
+    return hipGetLastError();
+}
+
+hipError_t launch_orient_compact(const cdvs_keypoint* ori, const int32_t* ori_cnt, const int32_t* count_in,
+                                 int n_images, int kp_cap, int topk, cdvs_keypoint* out, int32_t* count_out,
+                                 hipStream_t stream) {
+    if (n_images <= 0) return hipSuccess;
+    const int limit = min(topk > 0 ? topk : kp_cap, kp_cap);
+    hipLaunchKernelGGL(k_orient_compact, dim3(n_images), dim3(256), 0, stream, ori, ori_cnt, count_in, kp_cap, limit,
+                       out, count_out);
+    return hipGetLastError();
+}
+
+hipError_t launch_describe(const float* pyr, const OctGeom* geom, const cdvs_keypoint* kp, const int32_t* count,
+                           int n_images, const DescParams& dp, float* desc, hipStream_t stream) {
+    if (n_images <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_describe, dim3(blocks_for(n_images, dp.kp_cap)), dim3(256), 0, stream, pyr, geom, kp, count,
+                       n_images, dp, desc);
+    return hipGetLastError();
+}
+
+}  // namespace cdvs

@@ -1,0 +1,184 @@
+// Gaussian scale space on gfx950 (Sec. III-A, Eq. (1); Sec. IV-A,
+// Algorithm 1 stage A and its final downsampling step).
+//
+// One 256-lane workgroup per 64x32 output tile of one (image, octave).  The
+// vertical pass reads input columns straight from global memory (adjacent
+// lanes = adjacent columns, so every load is a contiguous 256-byte row
+// segment; the halo rows are L1/L2 hits), keeps an 8-row window plus halo in
+// registers, and produces the column-filtered rows T_k of every scale at once
+// into LDS.  The horizontal pass reads T_k from LDS and writes each output
+// row with 16-byte stores.  The scale kernel also writes the even samples of
+// G_{o,4}, which is G_{o+1,0}, so no separate downsampling pass exists.
+#include "cdvs_internal.h"
+
+namespace cdvs {
+
+namespace {
+
+__device__ __forceinline__ int clampi(int v, int lo, int hi) { return min(max(v, lo), hi); }
+
+// Radius of tap set k: 0 = input pre-blur, 1..4 = scale images.
+__host__ __device__ constexpr int radius_of(int k) {
+    return k == 0 ? kR0 : k == 1 ? kR1 : k == 2 ? kR2 : k == 3 ? kR3 : kR4;
+}
+
+// Job owning global tile `tile` (jobs sorted by tile0_blur).
+__device__ __forceinline__ int find_blur_job(const OctJob* jobs, int njobs, int tile) {
+    int lo = 0, hi = njobs - 1;
+    while (lo < hi) {
+        int mid = (lo + hi + 1) >> 1;
+        if (jobs[mid].tile0_blur <= tile) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+// Column pass of tap set K over a register window of V + 2*HALO rows:
+// out[r] = sum_{p=-R..R} g_K[p] * win[r + HALO + p], taps in order p = -R..R.
+template <int K, int HALO, int V>
+__device__ __forceinline__ void column_pass(const float (&win)[V + 2 * HALO], const Taps& taps, float (&out)[V]) {
+    constexpr int R = radius_of(K);
+#pragma unroll
+    for (int r = 0; r < V; ++r) {
+        float acc = 0.f;
+#pragma unroll
+        for (int p = -R; p <= R; ++p) acc = fmaf(taps.g[K][p + R], win[r + HALO + p], acc);
+        out[r] = acc;
+    }
+}
+
+// Row pass of tap set K for 8 outputs of one LDS row (row points at column 0
+// of the T buffer, whose column c is image column x0 - HALO + c).
+template <int K, int HALO>
+__device__ __forceinline__ void row_pass(const float* row, int c0, const Taps& taps, float (&out)[8]) {
+    constexpr int R = radius_of(K);
+    float in[8 + 2 * R];
+#pragma unroll
+    for (int i = 0; i < 8 + 2 * R; ++i) in[i] = row[c0 + HALO - R + i];
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+        float acc = 0.f;
+#pragma unroll
+        for (int p = -R; p <= R; ++p) acc = fmaf(taps.g[K][p + R], in[c + R + p], acc);
+        out[c] = acc;
+    }
+}
+
+__device__ __forceinline__ void store8(float* dst, int x0, int w, const float (&v)[8]) {
+    if (x0 + 8 <= w) {
+        reinterpret_cast<float4*>(dst + x0)[0] = make_float4(v[0], v[1], v[2], v[3]);
+        reinterpret_cast<float4*>(dst + x0)[1] = make_float4(v[4], v[5], v[6], v[7]);
+    } else {
+#pragma unroll
+        for (int i = 0; i < 8; ++i)
+            if (x0 + i < w) dst[x0 + i] = v[i];
+    }
+}
+
+// Even samples of 8 outputs starting at even column x0 -> 4 values at x0/2.
+__device__ __forceinline__ void store_decimated(float* dst, int x0, int nw, const float (&v)[8]) {
+    const int d0 = x0 >> 1;
+    if (d0 + 4 <= nw) {
+        reinterpret_cast<float4*>(dst + d0)[0] = make_float4(v[0], v[2], v[4], v[6]);
+    } else {
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+            if (d0 + i < nw) dst[d0 + i] = v[2 * i];
+    }
+}
+
+// KFIRST..KFIRST+NK-1 are the tap sets applied; U8 selects the octave-0
+// pre-blur (input = u8 image, output = G_{0,0}); otherwise input = G_{o,0},
+// outputs G_{o,1..4} and the decimated G_{o+1,0}.
+template <int KFIRST, int NK, int HALO, bool U8>
+__global__ __launch_bounds__(256) void k_blur(const uint8_t* __restrict__ images, float* __restrict__ pyr,
+                                              const OctJob* __restrict__ jobs, int njobs, Taps taps) {
+    constexpr int TW = kBlurTW, TH = kBlurTH, V = kBlurV;
+    constexpr int C = TW + 2 * HALO;
+    constexpr int CP = C + 1;
+    constexpr int NG = TH / V;
+    __shared__ float T[NK][TH][CP];
+
+    const int tile = blockIdx.x;
+    const OctJob& job = jobs[find_blur_job(jobs, njobs, tile)];
+    const int lt = tile - job.tile0_blur;
+    const int tx0 = (lt % job.tiles_x_blur) * TW;
+    const int ty0 = (lt / job.tiles_x_blur) * TH;
+    const int w = job.w, h = job.h;
+
+    for (int t = threadIdx.x; t < C * NG; t += blockDim.x) {
+        const int col = t % C, grp = t / C;
+        const int gx = clampi(tx0 - HALO + col, 0, w - 1);
+        const int gy0 = ty0 + grp * V - HALO;
+        float win[V + 2 * HALO];
+        if constexpr (U8) {
+            const uint8_t* src = images + job.src + gx;
+#pragma unroll
+            for (int r = 0; r < V + 2 * HALO; ++r)
+                win[r] = (float)src[(int64_t)clampi(gy0 + r, 0, h - 1) * job.src_pitch];
+        } else {
+            const float* src = pyr + job.plane0 + gx;
+#pragma unroll
+            for (int r = 0; r < V + 2 * HALO; ++r) win[r] = src[(int64_t)clampi(gy0 + r, 0, h - 1) * job.pitch];
+        }
+        float out[V];
+        column_pass<KFIRST, HALO, V>(win, taps, out);
+#pragma unroll
+        for (int r = 0; r < V; ++r) T[0][grp * V + r][col] = out[r];
+        if constexpr (NK > 1) {
+            column_pass<KFIRST + 1, HALO, V>(win, taps, out);
+#pragma unroll
+            for (int r = 0; r < V; ++r) T[1 % NK][grp * V + r][col] = out[r];
+            column_pass<KFIRST + 2, HALO, V>(win, taps, out);
+#pragma unroll
+            for (int r = 0; r < V; ++r) T[2 % NK][grp * V + r][col] = out[r];
+            column_pass<KFIRST + 3, HALO, V>(win, taps, out);
+#pragma unroll
+            for (int r = 0; r < V; ++r) T[3 % NK][grp * V + r][col] = out[r];
+        }
+    }
+    __syncthreads();
+
+    for (int t = threadIdx.x; t < TH * (TW / 8); t += blockDim.x) {
+        const int row = t / (TW / 8), cg = t % (TW / 8);
+        const int gy = ty0 + row, gx0 = tx0 + cg * 8;
+        if (gy >= h || gx0 >= w) continue;
+        float out[8];
+        if constexpr (U8) {
+            row_pass<KFIRST, HALO>(&T[0][row][0], cg * 8, taps, out);
+            store8(pyr + job.plane0 + (int64_t)gy * job.pitch, gx0, w, out);
+        } else {
+            float* base = pyr + job.plane0 + (int64_t)gy * job.pitch;
+            row_pass<KFIRST, HALO>(&T[0][row][0], cg * 8, taps, out);
+            store8(base + (int64_t)1 * job.plane_stride, gx0, w, out);
+            row_pass<KFIRST + 1, HALO>(&T[1 % NK][row][0], cg * 8, taps, out);
+            store8(base + (int64_t)2 * job.plane_stride, gx0, w, out);
+            row_pass<KFIRST + 2, HALO>(&T[2 % NK][row][0], cg * 8, taps, out);
+            store8(base + (int64_t)3 * job.plane_stride, gx0, w, out);
+            row_pass<KFIRST + 3, HALO>(&T[3 % NK][row][0], cg * 8, taps, out);
+            store8(base + (int64_t)4 * job.plane_stride, gx0, w, out);
+            if (job.next0 >= 0 && (gy & 1) == 0)
+                store_decimated(pyr + job.next0 + (int64_t)(gy >> 1) * job.next_pitch, gx0, job.next_w, out);
+        }
+    }
+}
+
+}  // namespace
+
+hipError_t launch_preblur(const uint8_t* images, float* pyr, const OctJob* jobs, int njobs, int ntiles,
+                          const Taps& taps, hipStream_t stream) {
+    if (ntiles <= 0) return hipSuccess;
+    hipLaunchKernelGGL((k_blur<0, 1, kR0, true>), dim3(ntiles), dim3(256), 0, stream, images, pyr, jobs, njobs,
+                       taps);
+    return hipGetLastError();
+}
+
+hipError_t launch_scales(float* pyr, const OctJob* jobs, int njobs, int ntiles, const Taps& taps,
+                         hipStream_t stream) {
+    if (ntiles <= 0) return hipSuccess;
+    hipLaunchKernelGGL((k_blur<1, 4, kMaxR, false>), dim3(ntiles), dim3(256), 0, stream, nullptr, pyr, jobs,
+                       njobs, taps);
+    return hipGetLastError();
+}
+
+}  // namespace cdvs

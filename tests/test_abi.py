@@ -1,0 +1,108 @@
+"""C-ABI checks that need no GPU: the library loads, exports every symbol
+include/cdvs.h declares, and rejects bad arguments on the host."""
+import ctypes
+import os
+import re
+
+import pytest
+
+import paper_1705_09776_amd as cd
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared_functions():
+    src = open(os.path.join(ROOT, "include", "cdvs.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(cdvs_[a-z_]+)\s*\(", src)))
+
+
+def test_header_and_binding_agree():
+    assert _declared_functions() == sorted(cd.EXPORTS)
+
+
+def test_library_exports_every_declared_symbol():
+    L = cd.lib()
+    for name in _declared_functions():
+        assert hasattr(L, name), name
+    out = os.popen(f"nm -D --defined-only {cd.LIB_PATH}").read()
+    for name in _declared_functions():
+        assert re.search(rf"\bT {name}\b", out), name
+
+
+def test_struct_sizes():
+    assert ctypes.sizeof(cd.Params) == 72
+    assert ctypes.sizeof(cd.ImageDesc) == 24
+    assert cd.KP_DTYPE.itemsize == 48
+
+
+def test_default_params():
+    p = cd.default_params()
+    assert p.version == cd.CDVS_PARAMS_VERSION
+    assert abs(p.sigma0 - 1.6) < 1e-7 and p.intervals == 4 and p.min_side == 32
+    assert abs(p.contrast - 1.5) < 1e-7 and p.border == 4 and p.topk == 1000
+    assert abs(p.ori_radius - 3.96) < 1e-6 and abs(p.ori_peak - 0.8) < 1e-7 and p.max_ori == 4
+    assert p.desc_cell == 3 and p.desc_radius == 6 and abs(p.desc_clamp - 0.2) < 1e-7
+
+
+def test_defaults_agree_with_oracle_constants():
+    import oracle
+    o = oracle.Oracle.default_params()
+    p = cd.default_params()
+    for f in ["sigma0", "intervals", "min_side", "contrast", "edge_r", "border", "max_offset", "dedup_dlog2",
+              "ori_radius", "ori_wsigma", "ori_peak", "max_ori", "topk", "desc_cell", "desc_radius",
+              "desc_wsigma", "desc_clamp"]:
+        assert abs(getattr(o, f) - getattr(p, f)) < 1e-6, f
+
+
+def _desc(w=640, h=480, pitch=None, off=0):
+    return cd.ImageDesc(off, w, h, pitch or w, 0)
+
+
+@pytest.mark.parametrize("mutate,code", [
+    (lambda p, d: setattr(p, "version", 7), cd.CDVS_ERR_VERSION),
+    (lambda p, d: setattr(p, "sigma0", 1.5), cd.CDVS_ERR_ARG),
+    (lambda p, d: setattr(p, "intervals", 3), cd.CDVS_ERR_ARG),
+    (lambda p, d: setattr(p, "border", 0), cd.CDVS_ERR_ARG),
+    (lambda p, d: setattr(p, "max_ori", 5), cd.CDVS_ERR_ARG),
+    (lambda p, d: setattr(p, "topk", 5000), cd.CDVS_ERR_ARG),
+    (lambda p, d: setattr(p, "ori_peak", 0.0), cd.CDVS_ERR_ARG),
+    (lambda p, d: d.__setitem__(0, _desc(15, 480)), cd.CDVS_ERR_SHAPE),
+    (lambda p, d: d.__setitem__(0, _desc(640, 8193)), cd.CDVS_ERR_SHAPE),
+    (lambda p, d: d.__setitem__(0, _desc(640, 480, pitch=600)), cd.CDVS_ERR_SHAPE),
+    (lambda p, d: d.__setitem__(0, _desc(640, 480, off=-1)), cd.CDVS_ERR_SHAPE),
+])
+def test_validation_errors(mutate, code):
+    p = cd.default_params()
+    d = [_desc()]
+    mutate(p, d)
+    st, msg = cd.cdvs_validate(p, d, 1000)
+    assert st == code and msg
+    # cdvs_ctx_create validates before it touches any device
+    with pytest.raises(cd.CdvsError) as e:
+        cd.cdvs_ctx_create(p, d, 1000)
+    assert e.value.status == code
+
+
+def test_validation_counts():
+    p = cd.default_params()
+    assert cd.cdvs_validate(p, [_desc()], 1000)[0] == cd.CDVS_OK
+    assert cd.cdvs_validate(p, [_desc()], 0)[0] == cd.CDVS_ERR_SHAPE
+    assert cd.cdvs_validate(p, [_desc()], 9000)[0] == cd.CDVS_ERR_SHAPE
+    assert cd.cdvs_validate(p, [], 1000)[0] == cd.CDVS_ERR_SHAPE
+    L = cd.lib()
+    assert L.cdvs_validate(None, None, 1, 1000, None, 0) == cd.CDVS_ERR_ARG
+    assert L.cdvs_validate(ctypes.byref(p), None, 1, 1000, None, 0) == cd.CDVS_ERR_ARG
+    # null context
+    assert L.cdvs_pyramid(None, None, None, None) == cd.CDVS_ERR_STATE
+    assert L.cdvs_sync_status(None, None) == cd.CDVS_ERR_STATE
+    assert L.cdvs_pyramid_bytes(None) == -1
+
+
+def test_pack_images():
+    import numpy as np
+    a = np.arange(20 * 17, dtype=np.uint8).reshape(17, 20)
+    b = np.ones((30, 70), dtype=np.uint8)
+    buf, descs = cd.pack_images([a, b])
+    assert descs[0].pitch == 64 and descs[1].pitch == 128 and descs[1].offset == 64 * 17
+    np.testing.assert_array_equal(buf[:64 * 17].reshape(17, 64)[:, :20], a)
