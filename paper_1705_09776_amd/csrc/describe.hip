@@ -62,11 +62,39 @@ __device__ __forceinline__ void gradient(const KpGeom& g, int u, int v, float& m
     ang = a;
 }
 
+// Histogram copies per wave: lane l adds into copy l % kCopies, so lanes of
+// neighbouring pixels (which usually hit the same bin) do not serialise on
+// one LDS address; copies are staggered by one bank.
+constexpr int kCopies = 8;
+constexpr int kOriStride = kOriBins + 1;
+constexpr int kDescStride = kDescDim + 1;
+
+// Walks the bounding box [u0, u0+bw) x [v0, ...) in row-major order, 64
+// pixels per step, without integer division in the loop.
+struct BoxWalk {
+    int u, v, du, dv, u1;
+    __device__ __forceinline__ BoxWalk(int lane, int u0, int v0, int bw) {
+        u = u0 + lane % bw;
+        v = v0 + lane / bw;
+        du = 64 % bw;
+        dv = 64 / bw;
+        u1 = u0 + bw - 1;
+    }
+    __device__ __forceinline__ void next(int bw) {
+        u += du;
+        v += dv;
+        if (u > u1) {
+            u -= bw;
+            ++v;
+        }
+    }
+};
+
 __global__ __launch_bounds__(256) void k_orient(const float* __restrict__ pyr, const OctGeom* __restrict__ geom,
                                                 const cdvs_keypoint* __restrict__ kp,
                                                 const int32_t* __restrict__ count, int n_images, OriParams op,
                                                 cdvs_keypoint* __restrict__ ori, int32_t* __restrict__ ori_cnt) {
-    __shared__ float hist[4][kOriBins];
+    __shared__ float hist[4][kCopies * kOriStride];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int64_t slot = (int64_t)blockIdx.x * 4 + wave;
     const int img = (int)(slot / op.kp_cap), i = (int)(slot % op.kp_cap);
@@ -76,10 +104,11 @@ __global__ __launch_bounds__(256) void k_orient(const float* __restrict__ pyr, c
         k = kp[(int64_t)img * op.kp_cap + i];
         active = k.octave >= 0 && k.octave < kMaxOctaves;
     }
-    if (lane < kOriBins) hist[wave][lane] = 0.f;
+    for (int j = lane; j < kCopies * kOriStride; j += 64) hist[wave][j] = 0.f;
     __syncthreads();
 
     if (active) {
+        float* hc = &hist[wave][(lane & (kCopies - 1)) * kOriStride];
         const KpGeom g = keypoint_geometry(pyr, geom, img, k, op.sigma0);
         const float R = op.radius * g.s;
         const float R2 = R * R;
@@ -89,8 +118,9 @@ __global__ __launch_bounds__(256) void k_orient(const float* __restrict__ pyr, c
         const int v0 = max((int)ceilf(g.cy - R), 1), v1 = min((int)floorf(g.cy + R), g.h - 2);
         const int bw = u1 - u0 + 1, bh = v1 - v0 + 1;
         if (bw > 0 && bh > 0) {
-            for (int q = lane; q < bw * bh; q += 64) {
-                const int u = u0 + q % bw, v = v0 + q / bw;
+            BoxWalk bwk(lane, u0, v0, bw);
+            for (int q = lane; q < bw * bh; q += 64, bwk.next(bw)) {
+                const int u = bwk.u, v = bwk.v;
                 const float dx = (float)u - g.cx, dy = (float)v - g.cy;
                 const float d2 = dx * dx + dy * dy;
                 if (!(d2 < R2)) continue;
@@ -100,19 +130,28 @@ __global__ __launch_bounds__(256) void k_orient(const float* __restrict__ pyr, c
                 const float fb = ang * (float)kOriBins / kTwoPi;
                 const float f0 = floorf(fb);
                 const float fr = fb - f0;
-                const int b0 = (((int)f0 % kOriBins) + kOriBins) % kOriBins;
-                const int b1 = (b0 + 1) % kOriBins;
-                atomicAdd(&hist[wave][b0], wt * (1.f - fr));
-                atomicAdd(&hist[wave][b1], wt * fr);
+                int b0 = (int)f0;
+                b0 = b0 >= kOriBins ? b0 - kOriBins : b0;
+                const int b1 = b0 + 1 == kOriBins ? 0 : b0 + 1;
+                atomicAdd(hc + b0, wt * (1.f - fr));
+                atomicAdd(hc + b1, wt * fr);
             }
         }
     }
     __syncthreads();
     if (!active) return;
 
-    const float hb = lane < kOriBins ? hist[wave][lane] : 0.f;
-    const float hl = lane < kOriBins ? hist[wave][(lane + kOriBins - 1) % kOriBins] : 0.f;
-    const float hr = lane < kOriBins ? hist[wave][(lane + 1) % kOriBins] : 0.f;
+    auto bin = [&](int b) {
+        float t = 0.f;
+#pragma unroll
+        for (int c = 0; c < kCopies; ++c) t += hist[wave][c * kOriStride + b];
+        return t;
+    };
+    // every lane reads its bin and both neighbours from the summed copies
+    const float hsum = lane < kOriBins ? bin(lane) : 0.f;
+    const float hb = hsum;
+    const float hl = __shfl(hsum, lane == 0 ? kOriBins - 1 : lane - 1);
+    const float hr = __shfl(hsum, lane == kOriBins - 1 ? 0 : lane + 1);
     const float mx = wave_max(hb);
     const bool pk = lane < kOriBins && hb > hl && hb > hr && hb > op.peak * mx;
     const uint64_t pm = __ballot(pk);
@@ -173,7 +212,7 @@ __global__ __launch_bounds__(256) void k_describe(const float* __restrict__ pyr,
                                                   const cdvs_keypoint* __restrict__ kp,
                                                   const int32_t* __restrict__ count, int n_images, DescParams dp,
                                                   float* __restrict__ desc) {
-    __shared__ float hist[4][kDescDim];
+    __shared__ float hist[4][kCopies * kDescStride];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int64_t slot = (int64_t)blockIdx.x * 4 + wave;
     const int img = (int)(slot / dp.kp_cap), i = (int)(slot % dp.kp_cap);
@@ -183,11 +222,11 @@ __global__ __launch_bounds__(256) void k_describe(const float* __restrict__ pyr,
         k = kp[(int64_t)img * dp.kp_cap + i];
         active = k.octave >= 0 && k.octave < kMaxOctaves;
     }
-    hist[wave][lane] = 0.f;
-    hist[wave][lane + 64] = 0.f;
+    for (int j = lane; j < kCopies * kDescStride; j += 64) hist[wave][j] = 0.f;
     __syncthreads();
 
     if (active) {
+        float* hc = &hist[wave][(lane & (kCopies - 1)) * kDescStride];
         const KpGeom g = keypoint_geometry(pyr, geom, img, k, dp.sigma0);
         const float th = k.theta;
         const float ct = cosf(th), st = sinf(th);
@@ -200,8 +239,9 @@ __global__ __launch_bounds__(256) void k_describe(const float* __restrict__ pyr,
         const int v0 = max((int)ceilf(g.cy - R), 1), v1 = min((int)floorf(g.cy + R), g.h - 2);
         const int bw = u1 - u0 + 1, bh = v1 - v0 + 1;
         if (bw > 0 && bh > 0) {
-            for (int q = lane; q < bw * bh; q += 64) {
-                const int u = u0 + q % bw, v = v0 + q / bw;
+            BoxWalk bwk(lane, u0, v0, bw);
+            for (int q = lane; q < bw * bh; q += 64, bwk.next(bw)) {
+                const int u = bwk.u, v = bwk.v;
                 const float dx = (float)u - g.cx, dy = (float)v - g.cy;
                 const float d2 = dx * dx + dy * dy;
                 if (!(d2 < R2)) continue;
@@ -216,23 +256,21 @@ __global__ __launch_bounds__(256) void k_describe(const float* __restrict__ pyr,
                 const float fx = rx + 1.5f, fy = ry + 1.5f, fo = rel * 8.f / kTwoPi;
                 const float x0f = floorf(fx), y0f = floorf(fy), o0f = floorf(fo);
                 const float ax = fx - x0f, ay = fy - y0f, ao = fo - o0f;
-                const int x0 = (int)x0f, y0 = (int)y0f, o0 = (int)o0f;
+                const int x0 = (int)x0f, y0 = (int)y0f;
+                const int o0 = (int)o0f & 7, o1 = (o0 + 1) & 7;
 #pragma unroll
                 for (int jy = 0; jy < 2; ++jy) {
                     const int yy = y0 + jy;
-                    if (yy < 0 || yy > 3) continue;
-                    const float wy = jy ? ay : 1.f - ay;
+                    if ((unsigned)yy > 3u) continue;
+                    const float wy = wt * (jy ? ay : 1.f - ay);
 #pragma unroll
                     for (int jx = 0; jx < 2; ++jx) {
                         const int xx = x0 + jx;
-                        if (xx < 0 || xx > 3) continue;
-                        const float wx = jx ? ax : 1.f - ax;
-#pragma unroll
-                        for (int jo = 0; jo < 2; ++jo) {
-                            const int oo = ((o0 + jo) % 8 + 8) % 8;
-                            const float wo = jo ? ao : 1.f - ao;
-                            atomicAdd(&hist[wave][(yy * 4 + xx) * 8 + oo], wt * wy * wx * wo);
-                        }
+                        if ((unsigned)xx > 3u) continue;
+                        const float wyx = wy * (jx ? ax : 1.f - ax);
+                        float* cell = hc + (yy * 4 + xx) * 8;
+                        atomicAdd(cell + o0, wyx * (1.f - ao));
+                        atomicAdd(cell + o1, wyx * ao);
                     }
                 }
             }
@@ -241,7 +279,12 @@ __global__ __launch_bounds__(256) void k_describe(const float* __restrict__ pyr,
     __syncthreads();
     if (!active) return;
 
-    const float h0 = hist[wave][lane], h1 = hist[wave][lane + 64];
+    float h0 = 0.f, h1 = 0.f;
+#pragma unroll
+    for (int c = 0; c < kCopies; ++c) {
+        h0 += hist[wave][c * kDescStride + lane];
+        h1 += hist[wave][c * kDescStride + lane + 64];
+    }
     float* out = desc + (((int64_t)img * dp.kp_cap + i) * kDescDim);
     const float n2 = wave_sum(h0 * h0 + h1 * h1);
     if (!(n2 > 0.f)) {

@@ -91,11 +91,27 @@ __global__ __launch_bounds__(256) void k_detect(const float* __restrict__ pyr, c
     const int ty0 = (lt / job.tiles_x_det) * DTH;
     const int w = job.w, h = job.h;
 
-    for (int t = threadIdx.x; t < kScales * GH * GW; t += blockDim.x) {
-        const int k = t / (GH * GW), rem = t % (GH * GW);
-        const int ly = rem / GW, lx = rem % GW;
-        const int gx = clampi(tx0 - 2 + lx, 0, w - 1), gy = clampi(ty0 - 2 + ly, 0, h - 1);
-        G[k][ly][lx] = pyr[job.plane0 + (int64_t)k * job.plane_stride + (int64_t)gy * job.pitch + gx];
+    // stage the five planes (tile + 2-pixel halo, clamped): all loads of a
+    // lane are issued before the first LDS store, so their latencies overlap
+    {
+        constexpr int NTOT = kScales * GH * GW;
+        constexpr int NPER = (NTOT + 255) / 256;
+        float vals[NPER];
+#pragma unroll
+        for (int j = 0; j < NPER; ++j) {
+            const int t = threadIdx.x + j * 256;
+            if (t < NTOT) {
+                const int k = t / (GH * GW), rem = t % (GH * GW);
+                const int ly = rem / GW, lx = rem % GW;
+                const int gx = clampi(tx0 - 2 + lx, 0, w - 1), gy = clampi(ty0 - 2 + ly, 0, h - 1);
+                vals[j] = pyr[job.plane0 + (int64_t)k * job.plane_stride + (int64_t)gy * job.pitch + gx];
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < NPER; ++j) {
+            const int t = threadIdx.x + j * 256;
+            if (t < NTOT) (&G[0][0][0])[t] = vals[j];
+        }
     }
     __syncthreads();
 
@@ -208,17 +224,22 @@ __global__ void k_clear(int32_t* p, int n) {
 }
 
 constexpr int FIN_THREADS = 1024;
+constexpr int FIN_PER = kCandCap / FIN_THREADS;  // candidates per thread
 
-// Stage C + canonical sort + top-k for one image per workgroup.
+// Stage C + canonical sort + top-k for one image per workgroup.  The
+// candidates' (x, y, sigma, p) are staged in LDS for the pair loop; the same
+// LDS then holds the sort keys.
 __global__ __launch_bounds__(FIN_THREADS) void k_finalize(const cdvs_keypoint* __restrict__ cand,
                                                           const int32_t* __restrict__ cand_cnt, int cand_cap,
                                                           float ratio_lim, int topk, int kp_cap,
                                                           cdvs_keypoint* __restrict__ kp,
                                                           int32_t* __restrict__ count) {
-    __shared__ unsigned long long key[kCandCap];
-    __shared__ unsigned short idx[kCandCap];
+    // records: kCandCap float4 = 128 KB; keys + indices reuse the same bytes
+    __shared__ float4 rec[kCandCap];
     __shared__ int seg[kMaxOctaves + 2];
     __shared__ int n_alive;
+    unsigned long long* key = reinterpret_cast<unsigned long long*>(rec);
+    unsigned short* idx = reinterpret_cast<unsigned short*>(key + kCandCap);
 
     const int img = blockIdx.x;
     const cdvs_keypoint* c = cand + (int64_t)img * cand_cap;
@@ -228,38 +249,47 @@ __global__ __launch_bounds__(FIN_THREADS) void k_finalize(const cdvs_keypoint* _
     if (tid < kMaxOctaves + 2) seg[tid] = n;
     if (tid == 0) n_alive = 0;
     __syncthreads();
-    // seg[o] = first index whose octave >= o (the list is grouped by octave)
-    for (int i = tid; i < n; i += blockDim.x) {
-        const int b = c[i].octave;
-        const int a = (i == 0) ? -1 : c[i - 1].octave;
-        for (int o = a + 1; o <= b; ++o) seg[o] = i;
+    int oct[FIN_PER];
+#pragma unroll
+    for (int j = 0; j < FIN_PER; ++j) {
+        const int i = tid + j * FIN_THREADS;
+        oct[j] = -1;
+        if (i < n) {
+            const cdvs_keypoint a = c[i];
+            rec[i] = make_float4(a.x, a.y, a.sigma, a.p);
+            oct[j] = a.octave;
+            // seg[o] = first index whose octave >= o (the list is grouped by octave)
+            const int prev = (i == 0) ? -1 : c[i - 1].octave;
+            for (int o = prev + 1; o <= a.octave; ++o) seg[o] = i;
+        }
     }
     __syncthreads();
 
-    int npow = 1;
-    while (npow < n) npow <<= 1;
+    unsigned long long kk[FIN_PER];
     int local_alive = 0;
-    for (int i = tid; i < npow; i += blockDim.x) {
-        unsigned long long k = ~0ull;
+#pragma unroll
+    for (int j = 0; j < FIN_PER; ++j) {
+        const int i = tid + j * FIN_THREADS;
+        kk[j] = ~0ull;
         if (i < n) {
-            const cdvs_keypoint a = c[i];
-            const float aa = fabsf(a.p);
+            const float4 a = rec[i];
+            const int ao = oct[j];
+            const float aa = fabsf(a.w);
             bool alive = true;
             for (int d = -1; d <= 1 && alive; d += 2) {
-                const int o2 = a.octave + d;
+                const int o2 = ao + d;
                 if (o2 < 0 || o2 >= kMaxOctaves) continue;
-                const int om = max(a.octave, o2);
-                const float lim = (float)(1 << om);
+                const float lim = (float)(1 << max(ao, o2));
                 const float lim2 = lim * lim;
-                for (int j = seg[o2]; j < seg[o2 + 1]; ++j) {
-                    const cdvs_keypoint b = c[j];
-                    if ((a.p > 0.f) != (b.p > 0.f)) continue;
+                for (int jj = seg[o2]; jj < seg[o2 + 1]; ++jj) {
+                    const float4 b = rec[jj];
+                    if ((a.w > 0.f) != (b.w > 0.f)) continue;
                     const float dx = a.x - b.x, dy = a.y - b.y;
                     if (!(dx * dx + dy * dy <= lim2)) continue;
-                    const float shi = fmaxf(a.sigma, b.sigma), slo = fminf(a.sigma, b.sigma);
+                    const float shi = fmaxf(a.z, b.z), slo = fminf(a.z, b.z);
                     if (!(shi <= ratio_lim * slo)) continue;
-                    const float ab = fabsf(b.p);
-                    if (ab > aa || (ab == aa && o2 < a.octave)) {
+                    const float ab = fabsf(b.w);
+                    if (ab > aa || (ab == aa && o2 < ao)) {
                         alive = false;
                         break;
                     }
@@ -267,15 +297,25 @@ __global__ __launch_bounds__(FIN_THREADS) void k_finalize(const cdvs_keypoint* _
             }
             if (alive) {
                 ++local_alive;
-                k = ((unsigned long long)(~__float_as_uint(aa)) << 32) |
-                    ((unsigned long long)a.octave << 28) | ((unsigned long long)a.iy << 14) |
-                    (unsigned long long)a.ix;
+                const cdvs_keypoint& r = c[i];
+                kk[j] = ((unsigned long long)(~__float_as_uint(aa)) << 32) |
+                        ((unsigned long long)ao << 28) | ((unsigned long long)r.iy << 14) |
+                        (unsigned long long)r.ix;
             }
         }
-        key[i] = k;
-        idx[i] = (unsigned short)i;
     }
     if (local_alive) atomicAdd(&n_alive, local_alive);
+    int npow = 1;
+    while (npow < n) npow <<= 1;
+    __syncthreads();  // every lane is done reading rec[] before keys overwrite it
+#pragma unroll
+    for (int j = 0; j < FIN_PER; ++j) {
+        const int i = tid + j * FIN_THREADS;
+        if (i < npow) {
+            key[i] = kk[j];
+            idx[i] = (unsigned short)i;
+        }
+    }
     __syncthreads();
 
     // bitonic sort, ascending
