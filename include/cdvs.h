@@ -186,6 +186,17 @@ cdvs_status cdvs_sync_status(cdvs_ctx* ctx, void* stream);
 /* Candidate scratch size per image (pre-deduplication candidates). */
 int32_t cdvs_candidate_capacity(const cdvs_ctx* ctx);
 
+/* HIP graph of one whole pass.  cdvs_graph_capture records cdvs_pyramid,
+ * cdvs_alp_detect (plain), cdvs_orient and cdvs_describe on the given
+ * buffers into a graph owned by the context (capturing on a stream of its
+ * own; nothing runs), replacing any previous one.  cdvs_graph_launch enqueues
+ * one replay on `stream`; the buffers must stay valid while the graph exists.
+ * Capture is refused while event timing is enabled.  The graph holds only
+ * kernel nodes (counters are cleared by a kernel, never by a memset). */
+cdvs_status cdvs_graph_capture(cdvs_ctx* ctx, const uint8_t* d_images, float* d_pyr, cdvs_keypoint* d_kp,
+                               int32_t* d_count, cdvs_keypoint* d_kp_ori, int32_t* d_count_ori, float* d_desc);
+cdvs_status cdvs_graph_launch(cdvs_ctx* ctx, void* stream);
+
 /* Per-kernel timing with HIP events (tracing).  While enabled, every kernel
  * the compute calls launch is bracketed by a pair of events recorded on the
  * call's stream (so a context being captured into a graph must not have it

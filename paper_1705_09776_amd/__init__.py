@@ -63,7 +63,7 @@ assert KP_DTYPE.itemsize == 48
 EXPORTS = ["cdvs_default_params", "cdvs_validate", "cdvs_ctx_create", "cdvs_ctx_destroy", "cdvs_last_error",
            "cdvs_pyramid_bytes", "cdvs_num_octaves", "cdvs_plane_layout", "cdvs_pyramid", "cdvs_alp_detect",
            "cdvs_orient", "cdvs_describe", "cdvs_sync_status", "cdvs_candidate_capacity",
-           "cdvs_profile_enable", "cdvs_profile_read"]
+           "cdvs_graph_capture", "cdvs_graph_launch", "cdvs_profile_enable", "cdvs_profile_read"]
 
 KERNEL_NAMES = ["preblur", "scales", "clear", "detect", "finalize", "orient", "orient_compact", "describe"]
 
@@ -99,6 +99,8 @@ def lib():
         "cdvs_describe": (i32, [vp, vp, vp, vp, vp, vp]),
         "cdvs_sync_status": (i32, [vp, vp]),
         "cdvs_candidate_capacity": (i32, [vp]),
+        "cdvs_graph_capture": (i32, [vp, vp, vp, vp, vp, vp, vp, vp]),
+        "cdvs_graph_launch": (i32, [vp, vp]),
         "cdvs_profile_enable": (i32, [vp, i32]),
         "cdvs_profile_read": (i32, [vp, vp, vp]),
     }
@@ -171,6 +173,15 @@ def cdvs_sync_status(ctx, stream=None) -> int:
     if st not in (CDVS_OK, CDVS_ERR_CAPACITY):
         _check(ctx, st)
     return st
+
+
+def cdvs_graph_capture(ctx, d_images, d_pyr, d_kp, d_count, d_kp_ori, d_count_ori, d_desc):
+    _check(ctx, lib().cdvs_graph_capture(ctx, _ptr(d_images), _ptr(d_pyr), _ptr(d_kp), _ptr(d_count),
+                                         _ptr(d_kp_ori), _ptr(d_count_ori), _ptr(d_desc)))
+
+
+def cdvs_graph_launch(ctx, stream=None):
+    _check(ctx, lib().cdvs_graph_launch(ctx, _stream(stream)))
 
 
 def cdvs_profile_enable(ctx, enable: bool):
@@ -276,6 +287,14 @@ class Pipeline:
         self.detect(stream)
         self.orient(stream)
         self.describe(stream)
+
+    def capture(self):
+        """Capture the whole pass on this pipeline's buffers into a HIP graph."""
+        cdvs_graph_capture(self.ctx, self.d_images, self.d_pyr, self.d_kp, self.d_count, self.d_kp_ori,
+                           self.d_count_ori, self.d_desc)
+
+    def replay(self, stream=None):
+        cdvs_graph_launch(self.ctx, stream)
 
     def sync_status(self, stream=None) -> int:
         return cdvs_sync_status(self.ctx, stream)

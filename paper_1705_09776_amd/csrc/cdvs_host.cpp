@@ -31,6 +31,7 @@ struct cdvs_ctx {
     OriParams ori{};
     DescParams desc{};
     float dedup_ratio = 0.f;
+    int detect_grid = 0;  // persistent detection grid (workgroups)
     // device
     OctJob* d_jobs = nullptr;
     OctGeom* d_geom = nullptr;
@@ -45,6 +46,10 @@ struct cdvs_ctx {
     std::vector<hipEvent_t> ev;       // 2 per bracket
     std::vector<int> ev_id;           // kernel id per bracket
     int ev_used = 0;
+    // captured pass (cdvs_graph_*)
+    hipStream_t cap_stream = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t graph_exec = nullptr;
 };
 
 namespace {
@@ -228,6 +233,9 @@ const char* cdvs_last_error(const cdvs_ctx* ctx) { return ctx ? ctx->err.c_str()
 
 void cdvs_ctx_destroy(cdvs_ctx* ctx) {
     if (!ctx) return;
+    if (ctx->graph_exec) (void)hipGraphExecDestroy(ctx->graph_exec);
+    if (ctx->graph) (void)hipGraphDestroy(ctx->graph);
+    if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
     for (auto& e : ctx->ev) (void)hipEventDestroy(e);
     (void)hipFree(ctx->d_jobs);
     (void)hipFree(ctx->d_geom);
@@ -304,6 +312,16 @@ static cdvs_status build_layout(cdvs_ctx* c) {
     return CDVS_OK;
 }
 
+// Largest power of two s such that a histogram bin of a window of radius
+// `radius` (times the largest octave scale 2 sigma0) cannot exceed 2^32 - 1:
+// a box side holds at most 2R + 1 pixels and one pixel adds at most
+// |grad| <= 255 sqrt(2) < 361 to a bin (all weights are <= 1).
+static float fixed_scale(double radius, double sigma0) {
+    const double R = radius * 2.0 * sigma0;
+    const double bound = (2.0 * R + 1.0) * (2.0 * R + 1.0) * 361.0;
+    return (float)ldexp(1.0, (int)floor(log2(4294967295.0 / bound)));
+}
+
 static void build_constants(cdvs_ctx* c) {
     const cdvs_params& p = c->params;
     const double s0 = 1.6;
@@ -325,8 +343,10 @@ static void build_constants(cdvs_ctx* c) {
     c->det.border = p.border;
     c->det.cand_cap = kCandCap;
     c->dedup_ratio = (float)pow(2.0, (double)p.dedup_dlog2);
-    c->ori = OriParams{p.ori_radius, p.ori_wsigma, p.ori_peak, p.sigma0, p.max_ori, c->kp_cap};
-    c->desc = DescParams{p.desc_cell, p.desc_radius, p.desc_wsigma, p.desc_clamp, p.sigma0, c->kp_cap};
+    c->ori = OriParams{p.ori_radius, p.ori_wsigma, p.ori_peak, p.sigma0, fixed_scale(p.ori_radius, p.sigma0),
+                       p.max_ori, c->kp_cap};
+    c->desc = DescParams{p.desc_cell, p.desc_radius, p.desc_wsigma, p.desc_clamp, p.sigma0,
+                         fixed_scale(p.desc_radius, p.sigma0), c->kp_cap};
 }
 
 cdvs_status cdvs_ctx_create(const cdvs_params* params, const cdvs_image_desc* images, int32_t n_images,
@@ -370,6 +390,14 @@ cdvs_status cdvs_ctx_create(const cdvs_params* params, const cdvs_image_desc* im
         cdvs_ctx_destroy(c);
         return CDVS_ERR_HIP;
     }
+    // persistent detection: three 256-lane workgroups per compute unit (the
+    // kernel's LDS allows three)
+    int dev = 0, cus = 256;
+    if (hipGetDevice(&dev) == hipSuccess) {
+        int v = 0;
+        if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && v > 0) cus = v;
+    }
+    c->detect_grid = std::max(kXcds, (cus * 3) / kXcds * kXcds);
     *out = c;
     return CDVS_OK;
 }
@@ -427,7 +455,8 @@ cdvs_status cdvs_alp_detect(cdvs_ctx* ctx, const float* d_pyr, const uint8_t* d_
     for (int o = 0; o < ctx->max_oct; ++o) {
         Bracket b(ctx, CDVS_KERNEL_DETECT, s);
         HIP_OR_FAIL(ctx, launch_detect(d_pyr, ctx->d_jobs + ctx->job_start[o], ctx->job_start[o + 1] - ctx->job_start[o],
-                                       ctx->det_tiles[o], ctx->det, ctx->d_cand, ctx->d_cand_cnt, ctx->d_flags, s));
+                                       ctx->det_tiles[o], ctx->detect_grid, ctx->det, ctx->d_cand, ctx->d_cand_cnt,
+                                       ctx->d_flags, s));
     }
     {
         Bracket b(ctx, CDVS_KERNEL_FINALIZE, s);
@@ -477,6 +506,46 @@ cdvs_status cdvs_sync_status(cdvs_ctx* ctx, void* stream) {
         HIP_OR_FAIL(ctx, hipMemset(ctx->d_flags, 0, sizeof(int32_t)));
         return fail(ctx, CDVS_ERR_CAPACITY, "candidate scratch overflowed (%d per image); results truncated", kCandCap);
     }
+    return CDVS_OK;
+}
+
+cdvs_status cdvs_graph_capture(cdvs_ctx* ctx, const uint8_t* d_images, float* d_pyr, cdvs_keypoint* d_kp,
+                               int32_t* d_count, cdvs_keypoint* d_kp_ori, int32_t* d_count_ori, float* d_desc) {
+    if (!ctx) return CDVS_ERR_STATE;
+    if (ctx->prof) return fail(ctx, CDVS_ERR_STATE, "cdvs_graph_capture: disable event timing first");
+    if (!d_images || !d_pyr || !d_kp || !d_count || !d_kp_ori || !d_count_ori || !d_desc)
+        return fail(ctx, CDVS_ERR_ARG, "cdvs_graph_capture: null device pointer");
+    if (!ctx->cap_stream) HIP_OR_FAIL(ctx, hipStreamCreateWithFlags(&ctx->cap_stream, hipStreamNonBlocking));
+    if (ctx->graph_exec) {
+        (void)hipGraphExecDestroy(ctx->graph_exec);
+        ctx->graph_exec = nullptr;
+    }
+    if (ctx->graph) {
+        (void)hipGraphDestroy(ctx->graph);
+        ctx->graph = nullptr;
+    }
+    void* s = (void*)ctx->cap_stream;
+    HIP_OR_FAIL(ctx, hipStreamBeginCapture(ctx->cap_stream, hipStreamCaptureModeThreadLocal));
+    cdvs_status st = cdvs_pyramid(ctx, d_images, d_pyr, s);
+    if (st == CDVS_OK) st = cdvs_alp_detect(ctx, d_pyr, nullptr, d_kp, d_count, s);
+    if (st == CDVS_OK) st = cdvs_orient(ctx, d_pyr, d_kp, d_count, d_kp_ori, d_count_ori, s);
+    if (st == CDVS_OK) st = cdvs_describe(ctx, d_pyr, d_kp_ori, d_count_ori, d_desc, s);
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamEndCapture(ctx->cap_stream, &g);
+    if (st != CDVS_OK) {
+        if (g) (void)hipGraphDestroy(g);
+        return st;
+    }
+    if (e != hipSuccess) return fail(ctx, CDVS_ERR_HIP, "hipStreamEndCapture: %s", hipGetErrorString(e));
+    ctx->graph = g;
+    HIP_OR_FAIL(ctx, hipGraphInstantiate(&ctx->graph_exec, g, nullptr, nullptr, 0));
+    return CDVS_OK;
+}
+
+cdvs_status cdvs_graph_launch(cdvs_ctx* ctx, void* stream) {
+    if (!ctx) return CDVS_ERR_STATE;
+    if (!ctx->graph_exec) return fail(ctx, CDVS_ERR_STATE, "cdvs_graph_launch: no captured graph");
+    HIP_OR_FAIL(ctx, hipGraphLaunch(ctx->graph_exec, (hipStream_t)stream));
     return CDVS_OK;
 }
 

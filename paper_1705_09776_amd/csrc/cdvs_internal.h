@@ -67,6 +67,7 @@ struct DetParams {
 struct OriParams {
     float radius, wsigma, peak;
     float sigma0;
+    float fix;  // fixed-point scale of the LDS histogram
     int32_t max_ori;
     int32_t kp_cap;
 };
@@ -74,8 +75,21 @@ struct OriParams {
 struct DescParams {
     float cell, radius, wsigma, clamp;
     float sigma0;
+    float fix;  // fixed-point scale of the LDS histogram
     int32_t kp_cap;
 };
+
+// Workgroups are dealt to the 8 XCDs of an MI355X round-robin by block
+// index, and each XCD has its own L2.  xcd_remap turns block b of a grid of n
+// into a logical index such that every XCD walks one contiguous range of
+// tiles (neighbouring tiles share halo rows and columns through that XCD's
+// L2).  It is a bijection on [0, n).
+constexpr int kXcds = 8;
+__device__ __forceinline__ int xcd_remap(int b, int n) {
+    const int x = b % kXcds, i = b / kXcds;
+    const int per = n / kXcds, rem = n % kXcds;
+    return x * per + min(x, rem) + i;
+}
 
 // Bits of the device status word.
 constexpr int kFlagCandOverflow = 1;
@@ -90,7 +104,7 @@ hipError_t launch_preblur(const uint8_t* images, float* pyr, const OctJob* jobs,
 hipError_t launch_scales(float* pyr, const OctJob* jobs, int njobs, int ntiles, const Taps& taps,
                          hipStream_t stream);
 hipError_t launch_clear(int32_t* p, int n, hipStream_t stream);
-hipError_t launch_detect(const float* pyr, const OctJob* jobs, int njobs, int ntiles, const DetParams& dp,
+hipError_t launch_detect(const float* pyr, const OctJob* jobs, int njobs, int ntiles, int grid, const DetParams& dp,
                          cdvs_keypoint* cand, int32_t* cand_cnt, int32_t* flags, hipStream_t stream);
 hipError_t launch_finalize(const cdvs_keypoint* cand, const int32_t* cand_cnt, int n_images, int cand_cap,
                            float dedup_ratio, int topk, int kp_cap, cdvs_keypoint* kp, int32_t* count,

@@ -62,9 +62,14 @@ __device__ __forceinline__ void gradient(const KpGeom& g, int u, int v, float& m
     ang = a;
 }
 
-// Histogram copies per wave: lane l adds into copy l % kCopies, so lanes of
-// neighbouring pixels (which usually hit the same bin) do not serialise on
-// one LDS address; copies are staggered by one bank.
+// Histograms accumulate in LDS as unsigned fixed point with integer atomics:
+// on gfx950 LDS float atomic adds run ~4.5x slower than integer ones, and
+// integer sums do not depend on the order of the adds.  The scale (OriParams
+// and DescParams .fix) is the largest power of two for which no bin can
+// overflow 32 bits; the host derives it from the window radius (2^14 for the
+// orientation window and 2^12 for the descriptor window at the defaults).
+// Histogram copies per wave: lane l adds into copy l % kCopies; copies are
+// staggered by one bank.
 constexpr int kCopies = 8;
 constexpr int kOriStride = kOriBins + 1;
 constexpr int kDescStride = kDescDim + 1;
@@ -94,9 +99,9 @@ __global__ __launch_bounds__(256) void k_orient(const float* __restrict__ pyr, c
                                                 const cdvs_keypoint* __restrict__ kp,
                                                 const int32_t* __restrict__ count, int n_images, OriParams op,
                                                 cdvs_keypoint* __restrict__ ori, int32_t* __restrict__ ori_cnt) {
-    __shared__ float hist[4][kCopies * kOriStride];
+    __shared__ uint32_t hist[4][kCopies * kOriStride];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int64_t slot = (int64_t)blockIdx.x * 4 + wave;
+    const int64_t slot = (int64_t)xcd_remap(blockIdx.x, gridDim.x) * 4 + wave;
     const int img = (int)(slot / op.kp_cap), i = (int)(slot % op.kp_cap);
     cdvs_keypoint k;
     bool active = img < n_images && i < count[img];
@@ -104,11 +109,11 @@ __global__ __launch_bounds__(256) void k_orient(const float* __restrict__ pyr, c
         k = kp[(int64_t)img * op.kp_cap + i];
         active = k.octave >= 0 && k.octave < kMaxOctaves;
     }
-    for (int j = lane; j < kCopies * kOriStride; j += 64) hist[wave][j] = 0.f;
+    for (int j = lane; j < kCopies * kOriStride; j += 64) hist[wave][j] = 0u;
     __syncthreads();
 
     if (active) {
-        float* hc = &hist[wave][(lane & (kCopies - 1)) * kOriStride];
+        uint32_t* hc = &hist[wave][(lane & (kCopies - 1)) * kOriStride];
         const KpGeom g = keypoint_geometry(pyr, geom, img, k, op.sigma0);
         const float R = op.radius * g.s;
         const float R2 = R * R;
@@ -133,8 +138,8 @@ __global__ __launch_bounds__(256) void k_orient(const float* __restrict__ pyr, c
                 int b0 = (int)f0;
                 b0 = b0 >= kOriBins ? b0 - kOriBins : b0;
                 const int b1 = b0 + 1 == kOriBins ? 0 : b0 + 1;
-                atomicAdd(hc + b0, wt * (1.f - fr));
-                atomicAdd(hc + b1, wt * fr);
+                atomicAdd(hc + b0, (uint32_t)(wt * (1.f - fr) * op.fix + 0.5f));
+                atomicAdd(hc + b1, (uint32_t)(wt * fr * op.fix + 0.5f));
             }
         }
     }
@@ -142,10 +147,10 @@ __global__ __launch_bounds__(256) void k_orient(const float* __restrict__ pyr, c
     if (!active) return;
 
     auto bin = [&](int b) {
-        float t = 0.f;
+        uint32_t t = 0u;
 #pragma unroll
         for (int c = 0; c < kCopies; ++c) t += hist[wave][c * kOriStride + b];
-        return t;
+        return (float)t / op.fix;
     };
     // every lane reads its bin and both neighbours from the summed copies
     const float hsum = lane < kOriBins ? bin(lane) : 0.f;
@@ -212,9 +217,9 @@ __global__ __launch_bounds__(256) void k_describe(const float* __restrict__ pyr,
                                                   const cdvs_keypoint* __restrict__ kp,
                                                   const int32_t* __restrict__ count, int n_images, DescParams dp,
                                                   float* __restrict__ desc) {
-    __shared__ float hist[4][kCopies * kDescStride];
+    __shared__ uint32_t hist[4][kCopies * kDescStride];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int64_t slot = (int64_t)blockIdx.x * 4 + wave;
+    const int64_t slot = (int64_t)xcd_remap(blockIdx.x, gridDim.x) * 4 + wave;
     const int img = (int)(slot / dp.kp_cap), i = (int)(slot % dp.kp_cap);
     cdvs_keypoint k;
     bool active = img < n_images && i < count[img];
@@ -222,11 +227,11 @@ __global__ __launch_bounds__(256) void k_describe(const float* __restrict__ pyr,
         k = kp[(int64_t)img * dp.kp_cap + i];
         active = k.octave >= 0 && k.octave < kMaxOctaves;
     }
-    for (int j = lane; j < kCopies * kDescStride; j += 64) hist[wave][j] = 0.f;
+    for (int j = lane; j < kCopies * kDescStride; j += 64) hist[wave][j] = 0u;
     __syncthreads();
 
     if (active) {
-        float* hc = &hist[wave][(lane & (kCopies - 1)) * kDescStride];
+        uint32_t* hc = &hist[wave][(lane & (kCopies - 1)) * kDescStride];
         const KpGeom g = keypoint_geometry(pyr, geom, img, k, dp.sigma0);
         const float th = k.theta;
         const float ct = cosf(th), st = sinf(th);
@@ -268,9 +273,9 @@ __global__ __launch_bounds__(256) void k_describe(const float* __restrict__ pyr,
                         const int xx = x0 + jx;
                         if ((unsigned)xx > 3u) continue;
                         const float wyx = wy * (jx ? ax : 1.f - ax);
-                        float* cell = hc + (yy * 4 + xx) * 8;
-                        atomicAdd(cell + o0, wyx * (1.f - ao));
-                        atomicAdd(cell + o1, wyx * ao);
+                        uint32_t* cell = hc + (yy * 4 + xx) * 8;
+                        atomicAdd(cell + o0, (uint32_t)(wyx * (1.f - ao) * dp.fix + 0.5f));
+                        atomicAdd(cell + o1, (uint32_t)(wyx * ao * dp.fix + 0.5f));
                     }
                 }
             }
@@ -279,12 +284,13 @@ __global__ __launch_bounds__(256) void k_describe(const float* __restrict__ pyr,
     __syncthreads();
     if (!active) return;
 
-    float h0 = 0.f, h1 = 0.f;
+    uint32_t i0 = 0u, i1 = 0u;
 #pragma unroll
     for (int c = 0; c < kCopies; ++c) {
-        h0 += hist[wave][c * kDescStride + lane];
-        h1 += hist[wave][c * kDescStride + lane + 64];
+        i0 += hist[wave][c * kDescStride + lane];
+        i1 += hist[wave][c * kDescStride + lane + 64];
     }
+    const float h0 = (float)i0 / dp.fix, h1 = (float)i1 / dp.fix;
     float* out = desc + (((int64_t)img * dp.kp_cap + i) * kDescDim);
     const float n2 = wave_sum(h0 * h0 + h1 * h1);
     if (!(n2 > 0.f)) {

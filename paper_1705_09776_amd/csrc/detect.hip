@@ -12,6 +12,8 @@
 // k_finalize: one workgroup per image.  Stage C (cross-octave duplicates)
 //   over adjacent-octave segments, then a bitonic sort in LDS on the 64-bit
 //   key (|p| desc, octave, iy, ix) and the top-k copy-out.
+#include <algorithm>
+
 #include "cdvs_internal.h"
 
 namespace cdvs {
@@ -78,140 +80,164 @@ constexpr int DTW = kDetTW, DTH = kDetTH;
 constexpr int GW = DTW + 4, GH = DTH + 4;
 constexpr int AW = DTW + 2, AH = DTH + 2;
 
+constexpr int DNTOT = kScales * GH * GW;
+constexpr int DNPER = (DNTOT + 255) / 256;
+
+// Issue every staging load of one tile (the five planes over the tile and a
+// 2-pixel clamped halo) into registers.
+__device__ __forceinline__ void load_tile(const float* __restrict__ pyr, const OctJob& job, int tx0, int ty0,
+                                          float (&vals)[DNPER]) {
+#pragma unroll
+    for (int j = 0; j < DNPER; ++j) {
+        const int t = threadIdx.x + j * 256;
+        if (t < DNTOT) {
+            const int k = t / (GH * GW), rem = t % (GH * GW);
+            const int ly = rem / GW, lx = rem % GW;
+            const int gx = clampi(tx0 - 2 + lx, 0, job.w - 1), gy = clampi(ty0 - 2 + ly, 0, job.h - 1);
+            vals[j] = pyr[job.plane0 + (int64_t)k * job.plane_stride + (int64_t)gy * job.pitch + gx];
+        }
+    }
+}
+
+// Persistent: the grid (a multiple of 8) is split evenly over the XCDs; each
+// workgroup walks its XCD's contiguous tile range with a stride, and the next
+// tile's loads are in flight while the current tile is computed.
 __global__ __launch_bounds__(256) void k_detect(const float* __restrict__ pyr, const OctJob* __restrict__ jobs,
-                                                int njobs, DetParams dp, cdvs_keypoint* __restrict__ cand,
+                                                int njobs, int ntiles, DetParams dp, cdvs_keypoint* __restrict__ cand,
                                                 int32_t* __restrict__ cand_cnt, int32_t* __restrict__ flags) {
     __shared__ float G[kScales][GH][GW];
     __shared__ float4 A[AH][AW];
 
-    const int tile = blockIdx.x;
-    const OctJob& job = jobs[find_det_job(jobs, njobs, tile)];
-    const int lt = tile - job.tile0_det;
-    const int tx0 = (lt % job.tiles_x_det) * DTW;
-    const int ty0 = (lt / job.tiles_x_det) * DTH;
-    const int w = job.w, h = job.h;
+    const int x = blockIdx.x % kXcds, slot = blockIdx.x / kXcds, nslot = gridDim.x / kXcds;
+    const int per = ntiles / kXcds, rem = ntiles % kXcds;
+    const int tbase = x * per + min(x, rem), cnt = per + (x < rem ? 1 : 0);
+    float vals[DNPER];
+    if (slot < cnt) {
+        const int tile = tbase + slot;
+        const OctJob& job = jobs[find_det_job(jobs, njobs, tile)];
+        const int lt = tile - job.tile0_det;
+        load_tile(pyr, job, (lt % job.tiles_x_det) * DTW, (lt / job.tiles_x_det) * DTH, vals);
+    }
+    for (int tj = slot; tj < cnt; tj += nslot) {
+        const int tile = tbase + tj;
+        const OctJob& job = jobs[find_det_job(jobs, njobs, tile)];
+        const int lt = tile - job.tile0_det;
+        const int tx0 = (lt % job.tiles_x_det) * DTW;
+        const int ty0 = (lt / job.tiles_x_det) * DTH;
+        const int w = job.w, h = job.h;
 
-    // stage the five planes (tile + 2-pixel halo, clamped): all loads of a
-    // lane are issued before the first LDS store, so their latencies overlap
-    {
-        constexpr int NTOT = kScales * GH * GW;
-        constexpr int NPER = (NTOT + 255) / 256;
-        float vals[NPER];
+        __syncthreads();  // the previous tile is done with G and A
 #pragma unroll
-        for (int j = 0; j < NPER; ++j) {
-            const int t = threadIdx.x + j * 256;
-            if (t < NTOT) {
-                const int k = t / (GH * GW), rem = t % (GH * GW);
-                const int ly = rem / GW, lx = rem % GW;
-                const int gx = clampi(tx0 - 2 + lx, 0, w - 1), gy = clampi(ty0 - 2 + ly, 0, h - 1);
-                vals[j] = pyr[job.plane0 + (int64_t)k * job.plane_stride + (int64_t)gy * job.pitch + gx];
+        for (int q = 0; q < DNPER; ++q) {
+            const int t = threadIdx.x + q * 256;
+            if (t < DNTOT) (&G[0][0][0])[t] = vals[q];
+        }
+        __syncthreads();
+        if (tj + nslot < cnt) {
+            const int tn = tbase + tj + nslot;
+            const OctJob& jn = jobs[find_det_job(jobs, njobs, tn)];
+            const int ltn = tn - jn.tile0_det;
+            load_tile(pyr, jn, (ltn % jn.tiles_x_det) * DTW, (ltn / jn.tiles_x_det) * DTH, vals);
+        }
+
+        for (int t = threadIdx.x; t < AH * AW; t += blockDim.x) {
+            const int ay = t / AW, ax = t % AW;
+            const int ly = ay + 1, lx = ax + 1;
+            float a0 = 0.f, a1 = 0.f, a2 = 0.f, a3 = 0.f;
+#pragma unroll
+            for (int k = 0; k < kScales; ++k) {
+                const float c = G[k][ly][lx];
+                float s = G[k][ly - 1][lx] + G[k][ly + 1][lx];
+                s = s + G[k][ly][lx - 1];
+                s = s + G[k][ly][lx + 1];
+                s = s - 4.f * c;
+                const float L = dp.sig2[k] * s;
+                a0 = fmaf(dp.beta[k][0], L, a0);
+                a1 = fmaf(dp.beta[k][1], L, a1);
+                a2 = fmaf(dp.beta[k][2], L, a2);
+                a3 = fmaf(dp.beta[k][3], L, a3);
             }
+            A[ay][ax] = make_float4(a0, a1, a2, a3);
         }
-#pragma unroll
-        for (int j = 0; j < NPER; ++j) {
-            const int t = threadIdx.x + j * 256;
-            if (t < NTOT) (&G[0][0][0])[t] = vals[j];
-        }
-    }
-    __syncthreads();
+        __syncthreads();
 
-    for (int t = threadIdx.x; t < AH * AW; t += blockDim.x) {
-        const int ay = t / AW, ax = t % AW;
-        const int ly = ay + 1, lx = ax + 1;
-        float a0 = 0.f, a1 = 0.f, a2 = 0.f, a3 = 0.f;
+        const int lane = threadIdx.x & 63;
+        const float scale = (float)(1 << job.octave);
+        for (int it = 0; it < DTW * DTH / 256; ++it) {
+            const int q = threadIdx.x + it * 256;
+            const int cy = q / DTW, cx = q % DTW;
+            const int gx = tx0 + cx, gy = ty0 + cy;
+            bool keep = false;
+            float s = 0.f, p = 0.f, pss = 0.f, ox = 0.f, oy = 0.f, pr = 0.f, rho = 0.f;
+            if (gx >= dp.border && gx <= w - 1 - dp.border && gy >= dp.border && gy <= h - 1 - dp.border) {
+                const float4 a = A[cy + 1][cx + 1];
+                if (alp_extremum(a, dp.lo, dp.hi, s, p, pss) && fabsf(p) >= dp.contrast) {
+                    float v[9];
+                    bool ext = true;
 #pragma unroll
-        for (int k = 0; k < kScales; ++k) {
-            const float c = G[k][ly][lx];
-            float s = G[k][ly - 1][lx] + G[k][ly + 1][lx];
-            s = s + G[k][ly][lx - 1];
-            s = s + G[k][ly][lx + 1];
-            s = s - 4.f * c;
-            const float L = dp.sig2[k] * s;
-            a0 = fmaf(dp.beta[k][0], L, a0);
-            a1 = fmaf(dp.beta[k][1], L, a1);
-            a2 = fmaf(dp.beta[k][2], L, a2);
-            a3 = fmaf(dp.beta[k][3], L, a3);
-        }
-        A[ay][ax] = make_float4(a0, a1, a2, a3);
-    }
-    __syncthreads();
-
-    const int lane = threadIdx.x & 63;
-    const float scale = (float)(1 << job.octave);
-    for (int it = 0; it < DTW * DTH / 256; ++it) {
-        const int q = threadIdx.x + it * 256;
-        const int cy = q / DTW, cx = q % DTW;
-        const int gx = tx0 + cx, gy = ty0 + cy;
-        bool keep = false;
-        float s = 0.f, p = 0.f, pss = 0.f, ox = 0.f, oy = 0.f, pr = 0.f, rho = 0.f;
-        if (gx >= dp.border && gx <= w - 1 - dp.border && gy >= dp.border && gy <= h - 1 - dp.border) {
-            const float4 a = A[cy + 1][cx + 1];
-            if (alp_extremum(a, dp.lo, dp.hi, s, p, pss) && fabsf(p) >= dp.contrast) {
-                float v[9];
-                bool ext = true;
+                    for (int j = -1; j <= 1; ++j)
 #pragma unroll
-                for (int j = -1; j <= 1; ++j)
-#pragma unroll
-                    for (int i = -1; i <= 1; ++i) {
-                        if (i == 0 && j == 0) {
-                            v[4] = p;
-                            continue;
+                        for (int i = -1; i <= 1; ++i) {
+                            if (i == 0 && j == 0) {
+                                v[4] = p;
+                                continue;
+                            }
+                            const float qv = horner(A[cy + 1 + j][cx + 1 + i], s);
+                            v[(j + 1) * 3 + (i + 1)] = qv;
+                            ext = ext && (p > 0.f ? (qv < p) : (qv > p));
                         }
-                        const float qv = horner(A[cy + 1 + j][cx + 1 + i], s);
-                        v[(j + 1) * 3 + (i + 1)] = qv;
-                        ext = ext && (p > 0.f ? (qv < p) : (qv > p));
-                    }
-                if (ext) {
-                    const float c = v[4];
-                    const float gxd = (v[5] - v[3]) * 0.5f;
-                    const float gyd = (v[7] - v[1]) * 0.5f;
-                    const float hxx = v[5] - 2.f * c + v[3];
-                    const float hyy = v[7] - 2.f * c + v[1];
-                    const float hxy = (v[8] - v[6] - v[2] + v[0]) * 0.25f;
-                    const float det = hxx * hyy - hxy * hxy;
-                    if (det > 0.f) {
-                        const float tr = hxx + hyy;
-                        const float ratio = tr * tr / det;
-                        if (ratio < dp.edge_lim) {
-                            const float dx = -(hyy * gxd - hxy * gyd) / det;
-                            const float dy = -(hxx * gyd - hxy * gxd) / det;
-                            if (!(fabsf(dx) > dp.max_off || fabsf(dy) > dp.max_off)) {
-                                ox = dx;
-                                oy = dy;
-                                pr = c + (gxd * dx + gyd * dy) * 0.5f;
-                                rho = ratio;
-                                keep = true;
+                    if (ext) {
+                        const float c = v[4];
+                        const float gxd = (v[5] - v[3]) * 0.5f;
+                        const float gyd = (v[7] - v[1]) * 0.5f;
+                        const float hxx = v[5] - 2.f * c + v[3];
+                        const float hyy = v[7] - 2.f * c + v[1];
+                        const float hxy = (v[8] - v[6] - v[2] + v[0]) * 0.25f;
+                        const float det = hxx * hyy - hxy * hxy;
+                        if (det > 0.f) {
+                            const float tr = hxx + hyy;
+                            const float ratio = tr * tr / det;
+                            if (ratio < dp.edge_lim) {
+                                const float dx = -(hyy * gxd - hxy * gyd) / det;
+                                const float dy = -(hxx * gyd - hxy * gxd) / det;
+                                if (!(fabsf(dx) > dp.max_off || fabsf(dy) > dp.max_off)) {
+                                    ox = dx;
+                                    oy = dy;
+                                    pr = c + (gxd * dx + gyd * dy) * 0.5f;
+                                    rho = ratio;
+                                    keep = true;
+                                }
                             }
                         }
                     }
                 }
             }
-        }
-        const uint64_t m = __ballot(keep);
-        if (m) {
-            const int leader = __ffsll((unsigned long long)m) - 1;
-            int base = 0;
-            if (lane == leader) base = atomicAdd(&cand_cnt[job.image], __popcll(m));
-            base = __shfl(base, leader);
-            if (keep) {
-                const int slot = base + __popcll(m & ((1ull << lane) - 1ull));
-                if (slot < dp.cand_cap) {
-                    cdvs_keypoint r;
-                    r.x = ((float)gx + ox) * scale;
-                    r.y = ((float)gy + oy) * scale;
-                    r.sigma = s * scale;
-                    r.p = pr;
-                    r.theta = 0.f;
-                    r.rho = rho;
-                    r.p_ss = pss;
-                    r.peak = 0.f;
-                    r.image = job.image;
-                    r.octave = job.octave;
-                    r.ix = gx;
-                    r.iy = gy;
-                    cand[(int64_t)job.image * dp.cand_cap + slot] = r;
-                } else {
-                    atomicOr(flags, kFlagCandOverflow);
+            const uint64_t m = __ballot(keep);
+            if (m) {
+                const int leader = __ffsll((unsigned long long)m) - 1;
+                int base = 0;
+                if (lane == leader) base = atomicAdd(&cand_cnt[job.image], __popcll(m));
+                base = __shfl(base, leader);
+                if (keep) {
+                    const int slot = base + __popcll(m & ((1ull << lane) - 1ull));
+                    if (slot < dp.cand_cap) {
+                        cdvs_keypoint r;
+                        r.x = ((float)gx + ox) * scale;
+                        r.y = ((float)gy + oy) * scale;
+                        r.sigma = s * scale;
+                        r.p = pr;
+                        r.theta = 0.f;
+                        r.rho = rho;
+                        r.p_ss = pss;
+                        r.peak = 0.f;
+                        r.image = job.image;
+                        r.octave = job.octave;
+                        r.ix = gx;
+                        r.iy = gy;
+                        cand[(int64_t)job.image * dp.cand_cap + slot] = r;
+                    } else {
+                        atomicOr(flags, kFlagCandOverflow);
+                    }
                 }
             }
         }
@@ -352,10 +378,13 @@ hipError_t launch_clear(int32_t* p, int n, hipStream_t stream) {
     return hipGetLastError();
 }
 
-hipError_t launch_detect(const float* pyr, const OctJob* jobs, int njobs, int ntiles, const DetParams& dp,
+hipError_t launch_detect(const float* pyr, const OctJob* jobs, int njobs, int ntiles, int grid, const DetParams& dp,
                          cdvs_keypoint* cand, int32_t* cand_cnt, int32_t* flags, hipStream_t stream) {
     if (ntiles <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_detect, dim3(ntiles), dim3(256), 0, stream, pyr, jobs, njobs, dp, cand, cand_cnt, flags);
+    // a multiple of the XCD count, no larger than needed
+    int g = std::min(grid, (ntiles + kXcds - 1) / kXcds * kXcds);
+    g = std::max(kXcds, g / kXcds * kXcds);
+    hipLaunchKernelGGL(k_detect, dim3(g), dim3(256), 0, stream, pyr, jobs, njobs, ntiles, dp, cand, cand_cnt, flags);
     return hipGetLastError();
 }
 

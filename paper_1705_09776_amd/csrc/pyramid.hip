@@ -99,7 +99,7 @@ __global__ __launch_bounds__(256) void k_blur(const uint8_t* __restrict__ images
     constexpr int NG = TH / V;
     __shared__ float T[NK][TH][CP];
 
-    const int tile = blockIdx.x;
+    const int tile = xcd_remap(blockIdx.x, gridDim.x);
     const OctJob& job = jobs[find_blur_job(jobs, njobs, tile)];
     const int lt = tile - job.tile0_blur;
     const int tx0 = (lt % job.tiles_x_blur) * TW;

@@ -249,3 +249,28 @@ def test_repeatable(single):
     np.testing.assert_array_equal(k1[["x", "y", "sigma", "p", "octave", "ix", "iy"]],
                                   k2[["x", "y", "sigma", "p", "octave", "ix", "iy"]])
     np.testing.assert_allclose(pipe.descriptors()[0], d1, atol=1e-6)
+
+
+def test_graph_replay_equals_eager():
+    """The captured pass (kernel nodes only) replayed several times, with
+    eager work on the same buffers in between, reproduces the eager run."""
+    imgs = list(synth.fixed_batch(synth.SEED_BATCH, 4))
+    pipe = _run(imgs)
+    k0 = [k.copy() for k in pipe.oriented()]
+    d0 = [d.copy() for d in pipe.descriptors()]
+    pipe.capture()
+    for r in range(3):
+        for t in (pipe.d_kp, pipe.d_count, pipe.d_kp_ori, pipe.d_count_ori, pipe.d_desc, pipe.d_pyr):
+            t.zero_()
+        torch.cuda.synchronize()
+        pipe.replay()
+        torch.cuda.synchronize()
+        assert pipe.sync_status() == cd.CDVS_OK
+        k1, d1 = pipe.oriented(), pipe.descriptors()
+        for i in range(len(imgs)):
+            np.testing.assert_array_equal(k1[i][["x", "y", "sigma", "p", "octave", "ix", "iy"]],
+                                          k0[i][["x", "y", "sigma", "p", "octave", "ix", "iy"]])
+            np.testing.assert_allclose(k1[i]["theta"], k0[i]["theta"], atol=1e-5)
+            np.testing.assert_allclose(d1[i], d0[i], atol=1e-5)
+        pipe.run()          # eager pass between replays
+        torch.cuda.synchronize()
