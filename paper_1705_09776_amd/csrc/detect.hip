@@ -42,15 +42,15 @@ __device__ __forceinline__ bool alp_extremum(const float4 a, float lo, float hi,
     float r[2];
     int nr = 0;
     if (A == 0.f) {
-        if (B != 0.f) r[nr++] = -C / B;
+        if (B != 0.f) r[nr++] = -__fdividef(C, B);
     } else {
         const float disc = B * B - 4.f * A * C;
         if (disc < 0.f) return false;
         const float sq = sqrtf(disc);
         const float q = (B >= 0.f) ? -(B + sq) * 0.5f : -(B - sq) * 0.5f;
         if (q != 0.f) {
-            r[nr++] = q / A;
-            r[nr++] = C / q;
+            r[nr++] = __fdividef(q, A);
+            r[nr++] = __fdividef(C, q);
         } else {
             r[nr++] = 0.f;
         }
@@ -77,25 +77,45 @@ __device__ __forceinline__ bool alp_extremum(const float4 a, float lo, float hi,
 }
 
 constexpr int DTW = kDetTW, DTH = kDetTH;
-constexpr int GW = DTW + 4, GH = DTH + 4;
+// staged columns: tx0-4 .. tx0+DTW+3 (16-byte aligned start); rows ty0-2 .. ty0+DTH+1
+constexpr int GW = DTW + 8, GH = DTH + 4;
+constexpr int GX = 2;  // staged column of image column tx0-2
 constexpr int AW = DTW + 2, AH = DTH + 2;
 
-constexpr int DNTOT = kScales * GH * GW;
-constexpr int DNPER = (DNTOT + 255) / 256;
+constexpr int DNV4 = kScales * GH * GW / 4;     // float4 chunks of the staged window
+constexpr int DNPER4 = (DNV4 + 255) / 256;      // chunks per lane
+static_assert(GW % 4 == 0, "staged rows are whole float4 chunks");
 
-// Issue every staging load of one tile (the five planes over the tile and a
-// 2-pixel clamped halo) into registers.
+// Stage the five planes over the tile plus a clamped halo: rows are clamped
+// per chunk; a chunk lying inside the image is one aligned 16-byte load, and
+// only chunks crossing the left or right image edge load four clamped
+// scalars.  Every load of a lane is issued before its values are needed.
 __device__ __forceinline__ void load_tile(const float* __restrict__ pyr, const OctJob& job, int tx0, int ty0,
-                                          float (&vals)[DNPER]) {
+                                          float4 (&vals)[DNPER4]) {
 #pragma unroll
-    for (int j = 0; j < DNPER; ++j) {
+    for (int j = 0; j < DNPER4; ++j) {
         const int t = threadIdx.x + j * 256;
-        if (t < DNTOT) {
-            const int k = t / (GH * GW), rem = t % (GH * GW);
-            const int ly = rem / GW, lx = rem % GW;
-            const int gx = clampi(tx0 - 2 + lx, 0, job.w - 1), gy = clampi(ty0 - 2 + ly, 0, job.h - 1);
-            vals[j] = pyr[job.plane0 + (int64_t)k * job.plane_stride + (int64_t)gy * job.pitch + gx];
+        if (t < DNV4) {
+            const int k = t / (GH * GW / 4), rem = t % (GH * GW / 4);
+            const int ly = rem / (GW / 4), c4 = rem % (GW / 4);
+            const int gy = clampi(ty0 - 2 + ly, 0, job.h - 1);
+            const int gx = tx0 - 4 + 4 * c4;
+            const float* row = pyr + job.plane0 + (int64_t)k * job.plane_stride + (int64_t)gy * job.pitch;
+            if (gx >= 0 && gx + 3 < job.w) {
+                vals[j] = *reinterpret_cast<const float4*>(row + gx);
+            } else {
+                vals[j] = make_float4(row[clampi(gx, 0, job.w - 1)], row[clampi(gx + 1, 0, job.w - 1)],
+                                      row[clampi(gx + 2, 0, job.w - 1)], row[clampi(gx + 3, 0, job.w - 1)]);
+            }
         }
+    }
+}
+
+__device__ __forceinline__ void store_tile(float* G, const float4 (&vals)[DNPER4]) {
+#pragma unroll
+    for (int j = 0; j < DNPER4; ++j) {
+        const int t = threadIdx.x + j * 256;
+        if (t < DNV4) reinterpret_cast<float4*>(G)[t] = vals[j];
     }
 }
 
@@ -105,13 +125,13 @@ __device__ __forceinline__ void load_tile(const float* __restrict__ pyr, const O
 __global__ __launch_bounds__(256) void k_detect(const float* __restrict__ pyr, const OctJob* __restrict__ jobs,
                                                 int njobs, int ntiles, DetParams dp, cdvs_keypoint* __restrict__ cand,
                                                 int32_t* __restrict__ cand_cnt, int32_t* __restrict__ flags) {
-    __shared__ float G[kScales][GH][GW];
+    __shared__ __align__(16) float G[kScales][GH][GW];
     __shared__ float4 A[AH][AW];
 
     const int x = blockIdx.x % kXcds, slot = blockIdx.x / kXcds, nslot = gridDim.x / kXcds;
     const int per = ntiles / kXcds, rem = ntiles % kXcds;
     const int tbase = x * per + min(x, rem), cnt = per + (x < rem ? 1 : 0);
-    float vals[DNPER];
+    float4 vals[DNPER4];
     if (slot < cnt) {
         const int tile = tbase + slot;
         const OctJob& job = jobs[find_det_job(jobs, njobs, tile)];
@@ -127,11 +147,7 @@ __global__ __launch_bounds__(256) void k_detect(const float* __restrict__ pyr, c
         const int w = job.w, h = job.h;
 
         __syncthreads();  // the previous tile is done with G and A
-#pragma unroll
-        for (int q = 0; q < DNPER; ++q) {
-            const int t = threadIdx.x + q * 256;
-            if (t < DNTOT) (&G[0][0][0])[t] = vals[q];
-        }
+        store_tile(&G[0][0][0], vals);
         __syncthreads();
         if (tj + nslot < cnt) {
             const int tn = tbase + tj + nslot;
@@ -142,7 +158,7 @@ __global__ __launch_bounds__(256) void k_detect(const float* __restrict__ pyr, c
 
         for (int t = threadIdx.x; t < AH * AW; t += blockDim.x) {
             const int ay = t / AW, ax = t % AW;
-            const int ly = ay + 1, lx = ax + 1;
+            const int ly = ay + 1, lx = ax + 1 + GX;
             float a0 = 0.f, a1 = 0.f, a2 = 0.f, a3 = 0.f;
 #pragma unroll
             for (int k = 0; k < kScales; ++k) {
@@ -196,10 +212,11 @@ __global__ __launch_bounds__(256) void k_detect(const float* __restrict__ pyr, c
                         const float det = hxx * hyy - hxy * hxy;
                         if (det > 0.f) {
                             const float tr = hxx + hyy;
-                            const float ratio = tr * tr / det;
+                            const float ratio = __fdividef(tr * tr, det);
                             if (ratio < dp.edge_lim) {
-                                const float dx = -(hyy * gxd - hxy * gyd) / det;
-                                const float dy = -(hxx * gyd - hxy * gxd) / det;
+                                const float rdet = 1.f / det;
+                                const float dx = -(hyy * gxd - hxy * gyd) * rdet;
+                                const float dy = -(hxx * gyd - hxy * gxd) * rdet;
                                 if (!(fabsf(dx) > dp.max_off || fabsf(dy) > dp.max_off)) {
                                     ox = dx;
                                     oy = dy;
