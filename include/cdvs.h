@@ -43,7 +43,7 @@ typedef enum {
     CDVS_ERR_VERSION = -6   /* params.version does not match CDVS_PARAMS_VERSION */
 } cdvs_status;
 
-#define CDVS_PARAMS_VERSION 1
+#define CDVS_PARAMS_VERSION 2
 #define CDVS_DESC_DIM 128
 #define CDVS_MIN_SIDE 16
 #define CDVS_MAX_SIDE 8192
@@ -72,6 +72,8 @@ typedef struct {
     float desc_wsigma;   /* descriptor Gaussian weight sigma / sigma: 6 */
     float desc_clamp;    /* clamp after the first L2 normalisation: 0.2 */
     int32_t topk;        /* keypoints kept per image (<= kp capacity): 1000 */
+    float mask_fmax;     /* gated detection: an (image, octave) whose mask has more
+                            than this fraction of active cells is examined densely: 0.6 */
 } cdvs_params;
 
 /* One u8 image inside the caller's packed image buffer: byte offset of its
@@ -150,7 +152,12 @@ cdvs_status cdvs_pyramid(cdvs_ctx* ctx, const uint8_t* d_images, float* d_pyr, v
  * only the higher |p|.  Writes per image the topk strongest keypoints in
  * canonical order (|p| desc, octave, iy, ix asc) to d_kp[image][0..] and
  * their number to d_count[image].  d_kp: n_images x kp_capacity records,
- * d_count: n_images int32.  d_mask must be NULL (reserved). */
+ * d_count: n_images int32.
+ * d_mask (NULL = every pixel): one byte per 4x4 cell of each base image (the
+ * cell layout of cdvs_cnn_cell_layout); an octave-o pixel (x, y) is examined
+ * only when bit o of the cell holding (x 2^o, y 2^o) / 4 is set -- neighbours
+ * are still read in full -- unless more than mask_fmax of that image's cells
+ * have bit o set, in which case octave o of that image is examined densely. */
 cdvs_status cdvs_alp_detect(cdvs_ctx* ctx, const float* d_pyr, const uint8_t* d_mask, cdvs_keypoint* d_kp,
                             int32_t* d_count, void* stream);
 
@@ -197,6 +204,57 @@ cdvs_status cdvs_graph_capture(cdvs_ctx* ctx, const uint8_t* d_images, float* d_
                                int32_t* d_count, cdvs_keypoint* d_kp_ori, int32_t* d_count_ori, float* d_desc);
 cdvs_status cdvs_graph_launch(cdvs_ctx* ctx, void* stream);
 
+/* ---------------------------------------------------------------------- */
+/* Surrogate candidate mask (a small learned CNN; not from the paper).       */
+/* ---------------------------------------------------------------------- */
+/* Each base image is seen as H4 x W4 cells of 4x4 pixels (H4 = ceil(H/4),
+ * W4 = ceil(W/4)); cells of all images are concatenated in batch order.
+ * Network: X0 = space-to-depth(4) of u8/255 (image edge-padded to a multiple
+ * of 4; channel 4*dy + dx); X_l = relu(conv3x3(X_{l-1})), l = 1..4, 16
+ * channels, zero padding; Z = X4 . Wh + bh, 6 logits per cell, logit o for
+ * octave o.  Activations are bf16 (16 per cell, HWC); convolutions run on
+ * bf16 MFMA with fp32 accumulation; the head is fp32.
+ * Parameters: CDVS_CNN_PARAMS fp32 values: for l = 1..4, W_l[9][16][16]
+ * ([tap][in][out], tap = 3(dy+1) + (dx+1)) then b_l[16]; then Wh[16][6]
+ * ([in][octave]) and bh[6]. */
+#define CDVS_CNN_PARAMS 9382
+#define CDVS_CNN_CHANNELS 16
+#define CDVS_CNN_HEADS 6
+#define CDVS_CNN_LAYERS 4
+
+/* Total cells of the batch, and where image `image`'s cells start. */
+int64_t cdvs_cnn_cells(const cdvs_ctx* ctx);
+cdvs_status cdvs_cnn_cell_layout(const cdvs_ctx* ctx, int32_t image, int64_t* cell0, int32_t* w4, int32_t* h4);
+
+/* Forward pass on the packed u8 images.  d_acts (caller scratch, required):
+ * CDVS_CNN_LAYERS x cells x 16 bf16 (uint16), receives every layer's output
+ * (kept for cdvs_cnn_backward).  d_logits (may be NULL): cells x 6 fp32.
+ * d_mask (may be NULL): cells bytes, bit o = sigmoid(Z_o) > tau, only for
+ * octaves the image has.  tau in (0, 1). */
+cdvs_status cdvs_cnn_forward(cdvs_ctx* ctx, const uint8_t* d_images, const float* d_params, uint16_t* d_acts,
+                             float* d_logits, uint8_t* d_mask, float tau, void* stream);
+
+/* Training labels from detector output (e.g. cdvs_alp_detect with a large
+ * topk): d_labels (cells uint32) gets bit o of the cell holding
+ * (ix 2^o, iy 2^o) / 4 of every keypoint of octave o; other bits 0. */
+cdvs_status cdvs_cnn_labels(cdvs_ctx* ctx, const cdvs_keypoint* d_kp, const int32_t* d_count, uint32_t* d_labels,
+                            void* stream);
+
+/* Loss and gradient for the forward pass whose d_acts / d_logits are given.
+ * Loss: mean over images of each image's mean, over its cells and its
+ * octaves o, of the positive-weighted cross-entropy
+ * w_o y softplus(-z) + (1 - y) softplus(z), y = label bit o, w = d_pos_weight
+ * (6 fp32).  d_grad (CDVS_CNN_PARAMS fp32) and d_loss (1 fp32) are
+ * overwritten.  d_work: caller scratch of 2 x cells x 16 uint16. */
+cdvs_status cdvs_cnn_backward(cdvs_ctx* ctx, const uint8_t* d_images, const float* d_params, const uint16_t* d_acts,
+                              const float* d_logits, const uint32_t* d_labels, const float* d_pos_weight,
+                              uint16_t* d_work, float* d_grad, float* d_loss, void* stream);
+
+/* One Adam step (Kingma and Ba 2015, bias-corrected, step >= 1) on the fp32
+ * parameters, with first and second moments d_m, d_v (CDVS_CNN_PARAMS each). */
+cdvs_status cdvs_cnn_adam(cdvs_ctx* ctx, float* d_params, const float* d_grad, float* d_m, float* d_v, int32_t step,
+                          float lr, float beta1, float beta2, float eps, void* stream);
+
 /* Per-kernel timing with HIP events (tracing).  While enabled, every kernel
  * the compute calls launch is bracketed by a pair of events recorded on the
  * call's stream (so a context being captured into a graph must not have it
@@ -213,6 +271,8 @@ typedef enum {
     CDVS_KERNEL_ORIENT,       /* orientation histograms and peaks */
     CDVS_KERNEL_ORIENT_COMPACT,
     CDVS_KERNEL_DESCRIBE,     /* 4x4x8 descriptors */
+    CDVS_KERNEL_CNN_FORWARD,  /* surrogate CNN: four convolutions and the head */
+    CDVS_KERNEL_MASK_COUNT,   /* active cells of a gating mask */
     CDVS_KERNEL_COUNT
 } cdvs_kernel_id;
 

@@ -26,7 +26,11 @@ CDVS_ERR_CAPACITY = -3
 CDVS_ERR_HIP = -4
 CDVS_ERR_STATE = -5
 CDVS_ERR_VERSION = -6
-CDVS_PARAMS_VERSION = 1
+CDVS_PARAMS_VERSION = 2
+CNN_PARAMS = 9382
+CNN_CHANNELS = 16
+CNN_HEADS = 6
+CNN_LAYERS = 4
 DESC_DIM = 128
 
 _STATUS = {0: "CDVS_OK", -1: "CDVS_ERR_ARG", -2: "CDVS_ERR_SHAPE", -3: "CDVS_ERR_CAPACITY",
@@ -45,7 +49,8 @@ class Params(ctypes.Structure):
                 ("border", ctypes.c_int32), ("max_offset", ctypes.c_float), ("dedup_dlog2", ctypes.c_float),
                 ("ori_radius", ctypes.c_float), ("ori_wsigma", ctypes.c_float), ("ori_peak", ctypes.c_float),
                 ("max_ori", ctypes.c_int32), ("desc_cell", ctypes.c_float), ("desc_radius", ctypes.c_float),
-                ("desc_wsigma", ctypes.c_float), ("desc_clamp", ctypes.c_float), ("topk", ctypes.c_int32)]
+                ("desc_wsigma", ctypes.c_float), ("desc_clamp", ctypes.c_float), ("topk", ctypes.c_int32),
+                ("mask_fmax", ctypes.c_float)]
 
 
 class ImageDesc(ctypes.Structure):
@@ -63,9 +68,12 @@ assert KP_DTYPE.itemsize == 48
 EXPORTS = ["cdvs_default_params", "cdvs_validate", "cdvs_ctx_create", "cdvs_ctx_destroy", "cdvs_last_error",
            "cdvs_pyramid_bytes", "cdvs_num_octaves", "cdvs_plane_layout", "cdvs_pyramid", "cdvs_alp_detect",
            "cdvs_orient", "cdvs_describe", "cdvs_sync_status", "cdvs_candidate_capacity",
-           "cdvs_graph_capture", "cdvs_graph_launch", "cdvs_profile_enable", "cdvs_profile_read"]
+           "cdvs_graph_capture", "cdvs_graph_launch", "cdvs_profile_enable", "cdvs_profile_read",
+           "cdvs_cnn_cells", "cdvs_cnn_cell_layout", "cdvs_cnn_forward", "cdvs_cnn_labels", "cdvs_cnn_backward",
+           "cdvs_cnn_adam"]
 
-KERNEL_NAMES = ["preblur", "scales", "clear", "detect", "finalize", "orient", "orient_compact", "describe"]
+KERNEL_NAMES = ["preblur", "scales", "clear", "detect", "finalize", "orient", "orient_compact", "describe",
+                "cnn_forward", "mask_count"]
 
 
 def build() -> str:
@@ -99,6 +107,13 @@ def lib():
         "cdvs_describe": (i32, [vp, vp, vp, vp, vp, vp]),
         "cdvs_sync_status": (i32, [vp, vp]),
         "cdvs_candidate_capacity": (i32, [vp]),
+        "cdvs_cnn_cells": (i64, [vp]),
+        "cdvs_cnn_cell_layout": (i32, [vp, i32, ctypes.POINTER(i64), ctypes.POINTER(i32), ctypes.POINTER(i32)]),
+        "cdvs_cnn_forward": (i32, [vp, vp, vp, vp, vp, vp, ctypes.c_float, vp]),
+        "cdvs_cnn_labels": (i32, [vp, vp, vp, vp, vp]),
+        "cdvs_cnn_backward": (i32, [vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]),
+        "cdvs_cnn_adam": (i32, [vp, vp, vp, vp, vp, i32, ctypes.c_float, ctypes.c_float, ctypes.c_float,
+                                ctypes.c_float, vp]),
         "cdvs_graph_capture": (i32, [vp, vp, vp, vp, vp, vp, vp, vp]),
         "cdvs_graph_launch": (i32, [vp, vp]),
         "cdvs_profile_enable": (i32, [vp, i32]),
@@ -173,6 +188,37 @@ def cdvs_sync_status(ctx, stream=None) -> int:
     if st not in (CDVS_OK, CDVS_ERR_CAPACITY):
         _check(ctx, st)
     return st
+
+
+def cdvs_cnn_cells(ctx) -> int:
+    return int(lib().cdvs_cnn_cells(ctx))
+
+
+def cdvs_cnn_cell_layout(ctx, image: int):
+    c0, w4, h4 = ctypes.c_int64(), ctypes.c_int32(), ctypes.c_int32()
+    _check(ctx, lib().cdvs_cnn_cell_layout(ctx, image, ctypes.byref(c0), ctypes.byref(w4), ctypes.byref(h4)))
+    return c0.value, w4.value, h4.value
+
+
+def cdvs_cnn_forward(ctx, d_images, d_params, d_acts, d_logits=None, d_mask=None, tau=0.5, stream=None):
+    _check(ctx, lib().cdvs_cnn_forward(ctx, _ptr(d_images), _ptr(d_params), _ptr(d_acts), _ptr(d_logits),
+                                       _ptr(d_mask), float(tau), _stream(stream)))
+
+
+def cdvs_cnn_labels(ctx, d_kp, d_count, d_labels, stream=None):
+    _check(ctx, lib().cdvs_cnn_labels(ctx, _ptr(d_kp), _ptr(d_count), _ptr(d_labels), _stream(stream)))
+
+
+def cdvs_cnn_backward(ctx, d_images, d_params, d_acts, d_logits, d_labels, d_pos_weight, d_work, d_grad, d_loss,
+                      stream=None):
+    _check(ctx, lib().cdvs_cnn_backward(ctx, _ptr(d_images), _ptr(d_params), _ptr(d_acts), _ptr(d_logits),
+                                        _ptr(d_labels), _ptr(d_pos_weight), _ptr(d_work), _ptr(d_grad), _ptr(d_loss),
+                                        _stream(stream)))
+
+
+def cdvs_cnn_adam(ctx, d_params, d_grad, d_m, d_v, step, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8, stream=None):
+    _check(ctx, lib().cdvs_cnn_adam(ctx, _ptr(d_params), _ptr(d_grad), _ptr(d_m), _ptr(d_v), int(step), float(lr),
+                                    float(beta1), float(beta2), float(eps), _stream(stream)))
 
 
 def cdvs_graph_capture(ctx, d_images, d_pyr, d_kp, d_count, d_kp_ori, d_count_ori, d_desc):
@@ -273,8 +319,36 @@ class Pipeline:
     def pyramid(self, stream=None):
         cdvs_pyramid(self.ctx, self.d_images, self.d_pyr, stream)
 
-    def detect(self, stream=None):
-        cdvs_alp_detect(self.ctx, self.d_pyr, None, self.d_kp, self.d_count, stream)
+    def detect(self, stream=None, mask=None):
+        cdvs_alp_detect(self.ctx, self.d_pyr, mask, self.d_kp, self.d_count, stream)
+
+    # -- surrogate CNN ----------------------------------------------------
+    def cnn_buffers(self):
+        """Allocate (once) the CNN activation, logit and mask buffers."""
+        if getattr(self, "d_acts", None) is None:
+            t = self.torch
+            self.ncells = cdvs_cnn_cells(self.ctx)
+            dev = self.d_pyr.device
+            self.d_acts = t.empty(CNN_LAYERS * self.ncells * CNN_CHANNELS, dtype=t.int16, device=dev)
+            self.d_logits = t.empty((self.ncells, CNN_HEADS), dtype=t.float32, device=dev)
+            self.d_mask = t.empty(self.ncells, dtype=t.uint8, device=dev)
+        return self.d_acts
+
+    def cnn_forward(self, params, tau=None, logits=True, stream=None):
+        self.cnn_buffers()
+        cdvs_cnn_forward(self.ctx, self.d_images, params, self.d_acts, self.d_logits if logits else None,
+                         self.d_mask if tau is not None else None, 0.5 if tau is None else tau, stream)
+
+    def run_gated(self, params, tau, stream=None):
+        """CNN mask -> pyramid -> gated detection -> orientation -> descriptors."""
+        self.cnn_forward(params, tau=tau, logits=False, stream=stream)
+        self.pyramid(stream)
+        self.detect(stream, mask=self.d_mask)
+        self.orient(stream)
+        self.describe(stream)
+
+    def cell_layout(self, image):
+        return cdvs_cnn_cell_layout(self.ctx, image)
 
     def orient(self, stream=None):
         cdvs_orient(self.ctx, self.d_pyr, self.d_kp, self.d_count, self.d_kp_ori, self.d_count_ori, stream)

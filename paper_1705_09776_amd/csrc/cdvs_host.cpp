@@ -32,6 +32,13 @@ struct cdvs_ctx {
     DescParams desc{};
     float dedup_ratio = 0.f;
     int detect_grid = 0;  // persistent detection grid (workgroups)
+    int wgrad_grid = 0;   // grid of the CNN weight-gradient kernels
+    // surrogate CNN cell grid
+    std::vector<CnnImage> cnn;
+    int64_t ncells = 0;
+    int cnn_tiles = 0, cnn_chunks = 0;
+    CnnImage* d_cnn = nullptr;
+    int32_t* d_active = nullptr;  // [n][kMaxOctaves] active mask cells
     // device
     OctJob* d_jobs = nullptr;
     OctGeom* d_geom = nullptr;
@@ -175,6 +182,7 @@ cdvs_params cdvs_default_params(void) {
     p.desc_wsigma = 6.f;
     p.desc_clamp = 0.2f;
     p.topk = 1000;
+    p.mask_fmax = 0.6f;
     return p;
 }
 
@@ -208,6 +216,7 @@ cdvs_status cdvs_validate(const cdvs_params* p, const cdvs_image_desc* im, int32
     if (kp_cap < 1 || kp_cap > CDVS_MAX_KP_CAPACITY)
         BAD(CDVS_ERR_SHAPE, "kp_capacity %d outside 1..%d", kp_cap, CDVS_MAX_KP_CAPACITY);
     if (p->topk > kp_cap) BAD(CDVS_ERR_ARG, "topk %d > kp_capacity %d", p->topk, kp_cap);
+    if (!(p->mask_fmax >= 0.f) || !(p->mask_fmax <= 1.f)) BAD(CDVS_ERR_ARG, "mask_fmax must be in [0, 1]");
     if (n < 1 || n > CDVS_MAX_IMAGES) BAD(CDVS_ERR_SHAPE, "n_images %d outside 1..%d", n, CDVS_MAX_IMAGES);
     if (!im) BAD(CDVS_ERR_ARG, "images is NULL");
     for (int i = 0; i < n; ++i) {
@@ -244,6 +253,8 @@ void cdvs_ctx_destroy(cdvs_ctx* ctx) {
     (void)hipFree(ctx->d_ori);
     (void)hipFree(ctx->d_ori_cnt);
     (void)hipFree(ctx->d_flags);
+    (void)hipFree(ctx->d_cnn);
+    (void)hipFree(ctx->d_active);
     delete ctx;
 }
 
@@ -309,6 +320,31 @@ static cdvs_status build_layout(cdvs_ctx* c) {
         c->det_tiles[o] = td;
     }
     c->job_start[kMaxOctaves] = (int)c->jobs.size();
+    // surrogate CNN cells: 4x4-pixel cells of each base image
+    c->cnn.assign(c->n, CnnImage{});
+    int64_t cell = 0;
+    int tiles = 0, chunks = 0;
+    for (int i = 0; i < c->n; ++i) {
+        const cdvs_image_desc& d = c->images[i];
+        CnnImage& g = c->cnn[i];
+        g.cell0 = cell;
+        g.src = d.offset;
+        g.src_pitch = d.pitch;
+        g.H = d.height;
+        g.W = d.width;
+        g.H4 = (d.height + 3) / 4;
+        g.W4 = (d.width + 3) / 4;
+        g.n_oct = std::min(c->octaves[i], kCnnHeads);
+        g.tiles_x = (g.W4 + kCnnTileW - 1) / kCnnTileW;
+        g.tile0 = tiles;
+        g.chunk0 = chunks;
+        tiles += g.tiles_x * ((g.H4 + kCnnTileH - 1) / kCnnTileH);
+        chunks += g.tiles_x * g.H4;
+        cell += (int64_t)g.H4 * g.W4;
+    }
+    c->ncells = cell;
+    c->cnn_tiles = tiles;
+    c->cnn_chunks = chunks;
     return CDVS_OK;
 }
 
@@ -381,9 +417,12 @@ cdvs_status cdvs_ctx_create(const cdvs_params* params, const cdvs_image_desc* im
     ALLOC(c->d_ori, sizeof(cdvs_keypoint) * n * kp_capacity * kMaxOri);
     ALLOC(c->d_ori_cnt, sizeof(int32_t) * n * kp_capacity);
     ALLOC(c->d_flags, sizeof(int32_t));
+    ALLOC(c->d_cnn, sizeof(CnnImage) * n);
+    ALLOC(c->d_active, sizeof(int32_t) * n * kMaxOctaves);
 #undef ALLOC
     if ((e = hipMemcpy(c->d_jobs, c->jobs.data(), sizeof(OctJob) * c->jobs.size(), hipMemcpyHostToDevice)) != hipSuccess ||
         (e = hipMemcpy(c->d_geom, c->geom.data(), sizeof(OctGeom) * c->geom.size(), hipMemcpyHostToDevice)) != hipSuccess ||
+        (e = hipMemcpy(c->d_cnn, c->cnn.data(), sizeof(CnnImage) * n, hipMemcpyHostToDevice)) != hipSuccess ||
         (e = hipMemset(c->d_flags, 0, sizeof(int32_t))) != hipSuccess ||
         (e = hipMemset(c->d_cand_cnt, 0, sizeof(int32_t) * n)) != hipSuccess) {
         fail(nullptr, CDVS_ERR_HIP, "context upload: %s", hipGetErrorString(e));
@@ -398,6 +437,7 @@ cdvs_status cdvs_ctx_create(const cdvs_params* params, const cdvs_image_desc* im
         if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && v > 0) cus = v;
     }
     c->detect_grid = std::max(kXcds, (cus * 3) / kXcds * kXcds);
+    c->wgrad_grid = std::max(kXcds, cus * 2);
     *out = c;
     return CDVS_OK;
 }
@@ -446,8 +486,13 @@ cdvs_status cdvs_alp_detect(cdvs_ctx* ctx, const float* d_pyr, const uint8_t* d_
                             int32_t* d_count, void* stream) {
     if (!ctx) return CDVS_ERR_STATE;
     if (!d_pyr || !d_kp || !d_count) return fail(ctx, CDVS_ERR_ARG, "cdvs_alp_detect: null device pointer");
-    if (d_mask) return fail(ctx, CDVS_ERR_ARG, "cdvs_alp_detect: d_mask is reserved and must be NULL");
     hipStream_t s = (hipStream_t)stream;
+    GateParams gate{nullptr, nullptr, nullptr, 1.f};
+    if (d_mask) {
+        Bracket b(ctx, CDVS_KERNEL_MASK_COUNT, s);
+        HIP_OR_FAIL(ctx, launch_mask_count(d_mask, ctx->d_cnn, ctx->n, ctx->d_active, s));
+        gate = GateParams{d_mask, ctx->d_active, ctx->d_cnn, ctx->params.mask_fmax};
+    }
     {
         Bracket b(ctx, CDVS_KERNEL_CLEAR, s);
         HIP_OR_FAIL(ctx, launch_clear(ctx->d_cand_cnt, ctx->n, s));
@@ -455,8 +500,8 @@ cdvs_status cdvs_alp_detect(cdvs_ctx* ctx, const float* d_pyr, const uint8_t* d_
     for (int o = 0; o < ctx->max_oct; ++o) {
         Bracket b(ctx, CDVS_KERNEL_DETECT, s);
         HIP_OR_FAIL(ctx, launch_detect(d_pyr, ctx->d_jobs + ctx->job_start[o], ctx->job_start[o + 1] - ctx->job_start[o],
-                                       ctx->det_tiles[o], ctx->detect_grid, ctx->det, ctx->d_cand, ctx->d_cand_cnt,
-                                       ctx->d_flags, s));
+                                       ctx->det_tiles[o], ctx->detect_grid, ctx->det, gate, ctx->d_cand,
+                                       ctx->d_cand_cnt, ctx->d_flags, s));
     }
     {
         Bracket b(ctx, CDVS_KERNEL_FINALIZE, s);
@@ -506,6 +551,65 @@ cdvs_status cdvs_sync_status(cdvs_ctx* ctx, void* stream) {
         HIP_OR_FAIL(ctx, hipMemset(ctx->d_flags, 0, sizeof(int32_t)));
         return fail(ctx, CDVS_ERR_CAPACITY, "candidate scratch overflowed (%d per image); results truncated", kCandCap);
     }
+    return CDVS_OK;
+}
+
+int64_t cdvs_cnn_cells(const cdvs_ctx* ctx) { return ctx ? ctx->ncells : -1; }
+
+cdvs_status cdvs_cnn_cell_layout(const cdvs_ctx* ctx, int32_t image, int64_t* cell0, int32_t* w4, int32_t* h4) {
+    if (!ctx) return CDVS_ERR_STATE;
+    if (image < 0 || image >= ctx->n) return CDVS_ERR_ARG;
+    const CnnImage& g = ctx->cnn[image];
+    if (cell0) *cell0 = g.cell0;
+    if (w4) *w4 = g.W4;
+    if (h4) *h4 = g.H4;
+    return CDVS_OK;
+}
+
+cdvs_status cdvs_cnn_forward(cdvs_ctx* ctx, const uint8_t* d_images, const float* d_params, uint16_t* d_acts,
+                             float* d_logits, uint8_t* d_mask, float tau, void* stream) {
+    if (!ctx) return CDVS_ERR_STATE;
+    if (!d_images || !d_params || !d_acts) return fail(ctx, CDVS_ERR_ARG, "cdvs_cnn_forward: null device pointer");
+    if (d_mask && !(tau > 0.f && tau < 1.f)) return fail(ctx, CDVS_ERR_ARG, "cdvs_cnn_forward: tau must be in (0, 1)");
+    if (((uintptr_t)d_acts & 7) != 0) return fail(ctx, CDVS_ERR_ARG, "cdvs_cnn_forward: d_acts not 8-byte aligned");
+    const float zthr = d_mask ? logf(tau / (1.f - tau)) : 0.f;
+    hipStream_t s = (hipStream_t)stream;
+    Bracket b(ctx, CDVS_KERNEL_CNN_FORWARD, s);
+    HIP_OR_FAIL(ctx, launch_cnn_forward(d_images, d_params, (short*)d_acts, ctx->ncells, ctx->d_cnn, ctx->n,
+                                        ctx->cnn_tiles, d_logits, d_mask, zthr, s));
+    return CDVS_OK;
+}
+
+cdvs_status cdvs_cnn_labels(cdvs_ctx* ctx, const cdvs_keypoint* d_kp, const int32_t* d_count, uint32_t* d_labels,
+                            void* stream) {
+    if (!ctx) return CDVS_ERR_STATE;
+    if (!d_kp || !d_count || !d_labels) return fail(ctx, CDVS_ERR_ARG, "cdvs_cnn_labels: null device pointer");
+    HIP_OR_FAIL(ctx, launch_cnn_labels(d_kp, d_count, ctx->kp_cap, ctx->d_cnn, ctx->n, ctx->ncells, d_labels,
+                                       (hipStream_t)stream));
+    return CDVS_OK;
+}
+
+cdvs_status cdvs_cnn_backward(cdvs_ctx* ctx, const uint8_t* d_images, const float* d_params, const uint16_t* d_acts,
+                              const float* d_logits, const uint32_t* d_labels, const float* d_pos_weight,
+                              uint16_t* d_work, float* d_grad, float* d_loss, void* stream) {
+    if (!ctx) return CDVS_ERR_STATE;
+    if (!d_images || !d_params || !d_acts || !d_logits || !d_labels || !d_pos_weight || !d_work || !d_grad || !d_loss)
+        return fail(ctx, CDVS_ERR_ARG, "cdvs_cnn_backward: null device pointer");
+    if ((((uintptr_t)d_acts | (uintptr_t)d_work) & 7) != 0)
+        return fail(ctx, CDVS_ERR_ARG, "cdvs_cnn_backward: d_acts and d_work must be 8-byte aligned");
+    HIP_OR_FAIL(ctx, launch_cnn_backward(d_images, d_params, (const short*)d_acts, ctx->ncells, ctx->d_cnn, ctx->n,
+                                         ctx->cnn_tiles, ctx->cnn_chunks, d_logits, d_labels, d_pos_weight,
+                                         (short*)d_work, d_grad, d_loss, ctx->wgrad_grid, (hipStream_t)stream));
+    return CDVS_OK;
+}
+
+cdvs_status cdvs_cnn_adam(cdvs_ctx* ctx, float* d_params, const float* d_grad, float* d_m, float* d_v, int32_t step,
+                          float lr, float beta1, float beta2, float eps, void* stream) {
+    if (!ctx) return CDVS_ERR_STATE;
+    if (!d_params || !d_grad || !d_m || !d_v) return fail(ctx, CDVS_ERR_ARG, "cdvs_cnn_adam: null device pointer");
+    if (step < 1 || !(lr > 0.f) || !(beta1 >= 0.f && beta1 < 1.f) || !(beta2 >= 0.f && beta2 < 1.f) || !(eps > 0.f))
+        return fail(ctx, CDVS_ERR_ARG, "cdvs_cnn_adam: bad hyper-parameters");
+    HIP_OR_FAIL(ctx, launch_cnn_adam(d_params, d_grad, d_m, d_v, step, lr, beta1, beta2, eps, (hipStream_t)stream));
     return CDVS_OK;
 }
 

@@ -6,6 +6,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <algorithm>
+
 #include "cdvs.h"
 
 namespace cdvs {
@@ -94,6 +96,30 @@ __device__ __forceinline__ int xcd_remap(int b, int n) {
 // Bits of the device status word.
 constexpr int kFlagCandOverflow = 1;
 
+// Surrogate CNN geometry: one entry per image.
+constexpr int kCnnChannels = 16, kCnnHeads = 6, kCnnLayers = 4;
+constexpr int kCnnParams = kCnnLayers * (9 * 16 * 16 + 16) + 16 * 6 + 6;  // 9382
+constexpr int kCnnTileW = 16, kCnnTileH = 4;  // cells per conv workgroup
+struct CnnImage {
+    int64_t cell0;     // first cell of the image in the batch's cell arrays
+    int64_t src;       // byte offset of the u8 image
+    int32_t src_pitch, H, W;
+    int32_t H4, W4;    // grid of 4x4 cells
+    int32_t n_oct;     // octaves of the image (valid head channels)
+    int32_t tiles_x;   // 16-cell segments per row
+    int32_t tile0;     // first conv tile (16 x 4 cells) of the image
+    int32_t chunk0;    // first 16-cell row chunk of the image
+    int32_t pad;
+};
+
+// Gating of detection by a cell mask.
+struct GateParams {
+    const uint8_t* mask;     // per cell, bit o = octave o active; nullptr = plain
+    const int32_t* active;   // [image][kMaxOctaves] active cells of the mask
+    const CnnImage* cells;   // per image cell grid
+    float fmax;              // fraction of active cells above which detection is dense
+};
+
 // Kernel tile shapes.
 constexpr int kBlurTW = 64, kBlurTH = 32, kBlurV = 8;
 constexpr int kDetTW = 64, kDetTH = 16;
@@ -105,7 +131,8 @@ hipError_t launch_scales(float* pyr, const OctJob* jobs, int njobs, int ntiles, 
                          hipStream_t stream);
 hipError_t launch_clear(int32_t* p, int n, hipStream_t stream);
 hipError_t launch_detect(const float* pyr, const OctJob* jobs, int njobs, int ntiles, int grid, const DetParams& dp,
-                         cdvs_keypoint* cand, int32_t* cand_cnt, int32_t* flags, hipStream_t stream);
+                         const GateParams& gate, cdvs_keypoint* cand, int32_t* cand_cnt, int32_t* flags,
+                         hipStream_t stream);
 hipError_t launch_finalize(const cdvs_keypoint* cand, const int32_t* cand_cnt, int n_images, int cand_cap,
                            float dedup_ratio, int topk, int kp_cap, cdvs_keypoint* kp, int32_t* count,
                            hipStream_t stream);
@@ -117,5 +144,18 @@ hipError_t launch_orient_compact(const cdvs_keypoint* ori, const int32_t* ori_cn
                                  hipStream_t stream);
 hipError_t launch_describe(const float* pyr, const OctGeom* geom, const cdvs_keypoint* kp, const int32_t* count,
                            int n_images, const DescParams& dp, float* desc, hipStream_t stream);
+
+hipError_t launch_cnn_forward(const uint8_t* images, const float* params, short* acts, int64_t ncells,
+                              const CnnImage* imgs, int nimg, int ntiles, float* logits, uint8_t* mask, float zthr,
+                              hipStream_t s);
+hipError_t launch_cnn_backward(const uint8_t* images, const float* params, const short* acts, int64_t ncells,
+                               const CnnImage* imgs, int nimg, int ntiles, int nchunks, const float* logits,
+                               const uint32_t* labels, const float* pos_w, short* dbuf, float* grad, float* loss,
+                               int wgrid, hipStream_t s);
+hipError_t launch_cnn_adam(float* p, const float* g, float* m, float* v, int step, float lr, float b1, float b2,
+                           float eps, hipStream_t s);
+hipError_t launch_cnn_labels(const cdvs_keypoint* kp, const int32_t* count, int kp_cap, const CnnImage* imgs, int nimg,
+                             int64_t ncells, uint32_t* labels, hipStream_t s);
+hipError_t launch_mask_count(const uint8_t* mask, const CnnImage* imgs, int nimg, int32_t* active, hipStream_t s);
 
 }  // namespace cdvs

@@ -1,0 +1,470 @@
+// Surrogate candidate-mask CNN on gfx950 (not from the paper: a learned gate
+// in front of ALP detection).  Per image at 1/4 resolution:
+//   X0 = space-to-depth(4) of u8/255 (edge-padded to a multiple of 4),
+//   X_l = relu(conv3x3(X_{l-1})), l = 1..4, 16 -> 16 channels, zero padding,
+//   Z = X4 . Wh + bh (16 -> 6, one logit per octave), mask bit o = Z_o > logit(tau).
+// Activations are bf16 in HWC order (16 channels = 32 bytes per cell); the
+// 3x3 convolutions of the forward pass and of both backward passes are
+// v_mfma_f32_16x16x16_bf16 with fp32 accumulation; the head is fp32 VALU.
+//
+// MFMA 16x16x16 bf16 operand layout (wave64, checked on the device): lane l
+// holds A[l%16][4(l/16)+j] and B[4(l/16)+j][l%16] for j = 0..3, and
+// D[4(l/16)+r][l%16] for r = 0..3.
+//
+// Parameter vector (fp32, 9382): for l = 1..4: W_l[9][16][16] ([tap][ci][co],
+// tap = 3(dy+1)+(dx+1)) then b_l[16]; then Wh[16][6] ([c][o]) then bh[6].
+#include "cdvs_internal.h"
+
+namespace cdvs {
+
+namespace {
+
+typedef short s4 __attribute__((ext_vector_type(4)));
+typedef float f4 __attribute__((ext_vector_type(4)));
+
+constexpr int CC = kCnnChannels;   // 16
+constexpr int NHD = kCnnHeads;     // 6
+constexpr int CONV_W = 9 * CC * CC;
+constexpr int LAYER_P = CONV_W + CC;
+
+// float -> bf16 bits, round to nearest even (finite inputs)
+__device__ __forceinline__ short f2bf(float f) {
+    uint32_t u = __float_as_uint(f);
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    return (short)(u >> 16);
+}
+__device__ __forceinline__ float bf2f(short h) { return __uint_as_float(((uint32_t)(uint16_t)h) << 16); }
+
+__device__ __forceinline__ int find_cnn_image(const CnnImage* im, int n, int tile) {
+    int lo = 0, hi = n - 1;
+    while (lo < hi) {
+        int mid = (lo + hi + 1) >> 1;
+        if (im[mid].tile0 <= tile) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+__device__ __forceinline__ int find_cell_image(const CnnImage* im, int n, int64_t cell) {
+    int lo = 0, hi = n - 1;
+    while (lo < hi) {
+        int mid = (lo + hi + 1) >> 1;
+        if (im[mid].cell0 <= cell) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+// Four consecutive s2d channels ci = 4 kb + j (row kb of the 4x4 block,
+// columns j = 0..3) of cell (cy, cx), as bf16: u8/255 with edge clamping.
+__device__ __forceinline__ s4 s2d_frag(const uint8_t* __restrict__ images, const CnnImage& g, int cy, int cx,
+                                       int kb) {
+    const int y = min(4 * cy + kb, g.H - 1);
+    const uint8_t* row = images + g.src + (int64_t)y * g.src_pitch;
+    s4 b;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) b[j] = f2bf((float)row[min(4 * cx + j, g.W - 1)] / 255.f);
+    return b;
+}
+
+// One s2d channel ci of cell (cy, cx).
+__device__ __forceinline__ short s2d_chan(const uint8_t* __restrict__ images, const CnnImage& g, int cy, int cx,
+                                          int ci) {
+    const int y = min(4 * cy + (ci >> 2), g.H - 1), x = min(4 * cx + (ci & 3), g.W - 1);
+    return f2bf((float)images[g.src + (int64_t)y * g.src_pitch + x] / 255.f);
+}
+
+// Forward 3x3 conv + bias + relu for a 16-cell x 4-row tile (one wave per row).
+template <bool FIRST>
+__global__ __launch_bounds__(256) void k_conv_fwd(const uint8_t* __restrict__ images, const short* __restrict__ X,
+                                                  const float* __restrict__ Wl, const float* __restrict__ bl,
+                                                  short* __restrict__ Y, const CnnImage* __restrict__ imgs, int nimg) {
+    const int tile = xcd_remap(blockIdx.x, gridDim.x);
+    const CnnImage& g = imgs[find_cnn_image(imgs, nimg, tile)];
+    const int lt = tile - g.tile0;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int cy = (lt / g.tiles_x) * kCnnTileH + wave;
+    const int px = (lt % g.tiles_x) * kCnnTileW + (lane & 15);
+    const int kb = lane >> 4;
+    if (cy >= g.H4) return;
+    s4 a[9];
+#pragma unroll
+    for (int t = 0; t < 9; ++t)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) a[t][j] = f2bf(Wl[(t * CC + 4 * kb + j) * CC + (lane & 15)]);
+    f4 acc;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) acc[r] = bl[4 * kb + r];
+#pragma unroll
+    for (int t = 0; t < 9; ++t) {
+        const int yy = cy + t / 3 - 1, xx = px + t % 3 - 1;
+        s4 b = {0, 0, 0, 0};
+        if (yy >= 0 && yy < g.H4 && xx >= 0 && xx < g.W4) {
+            if constexpr (FIRST) b = s2d_frag(images, g, yy, xx, kb);
+            else b = *reinterpret_cast<const s4*>(X + (g.cell0 + (int64_t)yy * g.W4 + xx) * CC + 4 * kb);
+        }
+        acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[t], b, acc, 0, 0, 0);
+    }
+    if (px < g.W4) {
+        s4 o;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) o[r] = f2bf(fmaxf(acc[r], 0.f));
+        *reinterpret_cast<s4*>(Y + (g.cell0 + (int64_t)cy * g.W4 + px) * CC + 4 * kb) = o;
+    }
+}
+
+// 1x1 head: logits and/or mask bits, one thread per cell.
+__global__ __launch_bounds__(256) void k_head(const short* __restrict__ X4, const float* __restrict__ P,
+                                              const CnnImage* __restrict__ imgs, int nimg, int64_t ncells,
+                                              float* __restrict__ logits, uint8_t* __restrict__ mask, float zthr) {
+    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= ncells) return;
+    const float* Wh = P + kCnnLayers * LAYER_P;
+    const float* bh = Wh + CC * NHD;
+    float x[CC];
+    const uint4* src = reinterpret_cast<const uint4*>(X4 + c * CC);
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+        const uint4 v = src[q];
+        const uint32_t w4[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+        for (int h = 0; h < 4; ++h) {
+            x[8 * q + 2 * h] = __uint_as_float(w4[h] << 16);
+            x[8 * q + 2 * h + 1] = __uint_as_float(w4[h] & 0xFFFF0000u);
+        }
+    }
+    float z[NHD];
+#pragma unroll
+    for (int o = 0; o < NHD; ++o) {
+        float s = bh[o];
+#pragma unroll
+        for (int ch = 0; ch < CC; ++ch) s = fmaf(x[ch], Wh[ch * NHD + o], s);
+        z[o] = s;
+    }
+    if (logits) {
+#pragma unroll
+        for (int o = 0; o < NHD; ++o) logits[c * NHD + o] = z[o];
+    }
+    if (mask) {
+        const int n_oct = imgs[find_cell_image(imgs, nimg, c)].n_oct;
+        uint32_t bits = 0;
+#pragma unroll
+        for (int o = 0; o < NHD; ++o)
+            if (o < n_oct && z[o] > zthr) bits |= 1u << o;
+        mask[c] = (uint8_t)bits;
+    }
+}
+
+__device__ __forceinline__ float softplus(float z) { return fmaxf(z, 0.f) + log1pf(expf(-fabsf(z))); }
+
+// Head backward + loss: per cell dZ, the masked gradient dP4 = (dZ Wh^T) *
+// (X4 > 0) as bf16, and grid-stride partial sums of dWh, dbh and the loss
+// reduced per wave and added to the global gradient with atomics.  The loss
+// is the mean over images of each image's mean over cells and its octaves.
+__global__ __launch_bounds__(256) void k_head_bwd(const short* __restrict__ X4, const float* __restrict__ P,
+                                                  const float* __restrict__ logits, const uint32_t* __restrict__ labels,
+                                                  const float* __restrict__ pos_w, const CnnImage* __restrict__ imgs,
+                                                  int nimg, int64_t ncells, short* __restrict__ dP4,
+                                                  float* __restrict__ grad, float* __restrict__ loss) {
+    const float* Wh = P + kCnnLayers * LAYER_P;
+    float gW[CC * NHD], gb[NHD], lsum = 0.f;
+#pragma unroll
+    for (int i = 0; i < CC * NHD; ++i) gW[i] = 0.f;
+#pragma unroll
+    for (int o = 0; o < NHD; ++o) gb[o] = 0.f;
+    for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < ncells; c += (int64_t)gridDim.x * blockDim.x) {
+        const CnnImage& g = imgs[find_cell_image(imgs, nimg, c)];
+        const float scale = 1.f / ((float)g.H4 * (float)g.W4 * (float)g.n_oct * (float)nimg);
+        const uint32_t y = labels[c];
+        float x[CC];
+#pragma unroll
+        for (int ch = 0; ch < CC; ++ch) x[ch] = bf2f(X4[c * CC + ch]);
+        float dz[NHD];
+#pragma unroll
+        for (int o = 0; o < NHD; ++o) {
+            dz[o] = 0.f;
+            if (o < g.n_oct) {
+                const float z = logits[c * NHD + o];
+                const float yo = (float)((y >> o) & 1u), w = pos_w[o];
+                const float s = 1.f / (1.f + expf(-z));
+                dz[o] = (s * (w * yo + 1.f - yo) - w * yo) * scale;
+                lsum += (w * yo * softplus(-z) + (1.f - yo) * softplus(z)) * scale;
+            }
+            gb[o] += dz[o];
+        }
+        short out[CC];
+#pragma unroll
+        for (int ch = 0; ch < CC; ++ch) {
+            float d = 0.f;
+#pragma unroll
+            for (int o = 0; o < NHD; ++o) {
+                d = fmaf(Wh[ch * NHD + o], dz[o], d);
+                gW[ch * NHD + o] = fmaf(x[ch], dz[o], gW[ch * NHD + o]);
+            }
+            out[ch] = f2bf(x[ch] > 0.f ? d : 0.f);
+        }
+        s4* dst = reinterpret_cast<s4*>(dP4 + c * CC);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) dst[q] = s4{out[4 * q], out[4 * q + 1], out[4 * q + 2], out[4 * q + 3]};
+    }
+    const int lane = threadIdx.x & 63;
+    float* gWh = grad + kCnnLayers * LAYER_P;
+    float* gbh = gWh + CC * NHD;
+#pragma unroll
+    for (int i = 0; i < CC * NHD; ++i) {
+        float v = gW[i];
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+        if (lane == 0) atomicAdd(&gWh[i], v);
+    }
+#pragma unroll
+    for (int o = 0; o < NHD; ++o) {
+        float v = gb[o];
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+        if (lane == 0) atomicAdd(&gbh[o], v);
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) lsum += __shfl_xor(lsum, off);
+    if (lane == 0) atomicAdd(loss, lsum);
+}
+
+// Input gradient of layer l: dX_{l-1}[p][ci] = sum_t sum_co W[t][ci][co]
+// dP_l[p - d_t][co], then times (X_{l-1} > 0) to give dP_{l-1} (bf16).
+__global__ __launch_bounds__(256) void k_conv_bwd_data(const short* __restrict__ dP, const float* __restrict__ Wl,
+                                                       const short* __restrict__ Xprev, short* __restrict__ dPprev,
+                                                       const CnnImage* __restrict__ imgs, int nimg) {
+    const int tile = xcd_remap(blockIdx.x, gridDim.x);
+    const CnnImage& g = imgs[find_cnn_image(imgs, nimg, tile)];
+    const int lt = tile - g.tile0;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int cy = (lt / g.tiles_x) * kCnnTileH + wave;
+    const int px = (lt % g.tiles_x) * kCnnTileW + (lane & 15);
+    const int kb = lane >> 4;
+    if (cy >= g.H4) return;
+    s4 a[9];
+#pragma unroll
+    for (int t = 0; t < 9; ++t)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) a[t][j] = f2bf(Wl[(t * CC + (lane & 15)) * CC + 4 * kb + j]);
+    f4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int t = 0; t < 9; ++t) {
+        const int yy = cy - (t / 3 - 1), xx = px - (t % 3 - 1);
+        s4 b = {0, 0, 0, 0};
+        if (yy >= 0 && yy < g.H4 && xx >= 0 && xx < g.W4)
+            b = *reinterpret_cast<const s4*>(dP + (g.cell0 + (int64_t)yy * g.W4 + xx) * CC + 4 * kb);
+        acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[t], b, acc, 0, 0, 0);
+    }
+    if (px < g.W4) {
+        const int64_t off = (g.cell0 + (int64_t)cy * g.W4 + px) * CC + 4 * kb;
+        const s4 xp = *reinterpret_cast<const s4*>(Xprev + off);
+        s4 o;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) o[r] = f2bf(bf2f(xp[r]) > 0.f ? acc[r] : 0.f);
+        *reinterpret_cast<s4*>(dPprev + off) = o;
+    }
+}
+
+// Weight and bias gradients of layer l: dW[t][ci][co] = sum_p X_{l-1}[p + d_t][ci]
+// dP_l[p][co] as MFMAs with K = 16 pixels of one row; grid-stride over
+// 16-cell row chunks, per-lane partial sums added with global atomics.
+template <bool FIRST>
+__global__ __launch_bounds__(256) void k_conv_bwd_weight(const uint8_t* __restrict__ images,
+                                                         const short* __restrict__ Xprev, const short* __restrict__ dP,
+                                                         const CnnImage* __restrict__ imgs, int nimg, int nchunks,
+                                                         float* __restrict__ gW, float* __restrict__ gb) {
+    const int lane = threadIdx.x & 63, kb = lane >> 4, li = lane & 15;
+    const int wave_g = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int nwaves = (gridDim.x * blockDim.x) >> 6;
+    f4 acc[9];
+#pragma unroll
+    for (int t = 0; t < 9; ++t) acc[t] = f4{0.f, 0.f, 0.f, 0.f};
+    float bsum = 0.f;
+    for (int ch = wave_g; ch < nchunks; ch += nwaves) {
+        // chunk -> (image, row, 16-cell segment): chunks of an image are
+        // numbered row-major with tiles_x segments per row
+        int lo = 0, hi = nimg - 1;
+        while (lo < hi) {
+            int mid = (lo + hi + 1) >> 1;
+            if (imgs[mid].chunk0 <= ch) lo = mid;
+            else hi = mid - 1;
+        }
+        const CnnImage& g = imgs[lo];
+        const int lc = ch - g.chunk0;
+        const int cy = lc / g.tiles_x, cx0 = (lc % g.tiles_x) * kCnnTileW;
+        s4 b;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int xx = cx0 + 4 * kb + j;
+            b[j] = xx < g.W4 ? dP[(g.cell0 + (int64_t)cy * g.W4 + xx) * CC + li] : (short)0;
+            bsum += bf2f(b[j]);
+        }
+#pragma unroll
+        for (int t = 0; t < 9; ++t) {
+            const int yy = cy + t / 3 - 1;
+            s4 a;
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int xx = cx0 + 4 * kb + j + t % 3 - 1;
+                short v = 0;
+                if (yy >= 0 && yy < g.H4 && xx >= 0 && xx < g.W4) {
+                    if constexpr (FIRST) v = s2d_chan(images, g, yy, xx, li);
+                    else v = Xprev[(g.cell0 + (int64_t)yy * g.W4 + xx) * CC + li];
+                }
+                a[j] = v;
+            }
+            acc[t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc[t], 0, 0, 0);
+        }
+    }
+    // acc[t][r] = dW[t][ci = 4 kb + r][co = li]
+#pragma unroll
+    for (int t = 0; t < 9; ++t)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) atomicAdd(&gW[(t * CC + 4 * kb + r) * CC + li], acc[t][r]);
+    bsum += __shfl_xor(bsum, 16);
+    bsum += __shfl_xor(bsum, 32);
+    if (lane < 16) atomicAdd(&gb[li], bsum);
+}
+
+__global__ void k_fill(float* p, int n, float v) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+__global__ void k_fill_u32(uint32_t* p, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0u;
+}
+
+// Adam (Kingma and Ba 2015) with bias correction on fp32 master weights.
+__global__ void k_adam(float* __restrict__ p, const float* __restrict__ g, float* __restrict__ m, float* __restrict__ v,
+                       int n, float lr, float b1, float b2, float eps, float c1, float c2) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const float gi = g[i];
+    const float mi = b1 * m[i] + (1.f - b1) * gi;
+    const float vi = b2 * v[i] + (1.f - b2) * gi * gi;
+    m[i] = mi;
+    v[i] = vi;
+    p[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+}
+
+// Cell labels from detector keypoints: bit o of the cell holding
+// (ix 2^o, iy 2^o) / 4 for every keypoint of octave o.
+__global__ void k_labels(const cdvs_keypoint* __restrict__ kp, const int32_t* __restrict__ count, int kp_cap,
+                         const CnnImage* __restrict__ imgs, int nimg, uint32_t* __restrict__ labels) {
+    const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int img = (int)(s / kp_cap), i = (int)(s % kp_cap);
+    if (img >= nimg || i >= count[img]) return;
+    const cdvs_keypoint k = kp[s];
+    if (k.octave < 0 || k.octave >= kMaxOctaves) return;
+    const CnnImage& g = imgs[img];
+    const int cx = min((k.ix << k.octave) >> 2, g.W4 - 1), cy = min((k.iy << k.octave) >> 2, g.H4 - 1);
+    atomicOr(&labels[g.cell0 + (int64_t)cy * g.W4 + cx], 1u << k.octave);
+}
+
+// Active-cell count per (image, octave) of a mask, for the dense fallback.
+__global__ __launch_bounds__(256) void k_mask_count(const uint8_t* __restrict__ mask, const CnnImage* __restrict__ imgs,
+                                                    int32_t* __restrict__ active) {
+    __shared__ int cnt[NHD];
+    const CnnImage& g = imgs[blockIdx.x];
+    if (threadIdx.x < NHD) cnt[threadIdx.x] = 0;
+    __syncthreads();
+    int loc[NHD] = {0, 0, 0, 0, 0, 0};
+    const int64_t n = (int64_t)g.H4 * g.W4;
+    for (int64_t c = threadIdx.x; c < n; c += blockDim.x) {
+        const uint32_t b = mask[g.cell0 + c];
+#pragma unroll
+        for (int o = 0; o < NHD; ++o) loc[o] += (b >> o) & 1u;
+    }
+#pragma unroll
+    for (int o = 0; o < NHD; ++o)
+        if (loc[o]) atomicAdd(&cnt[o], loc[o]);
+    __syncthreads();
+    if (threadIdx.x < kMaxOctaves) active[blockIdx.x * kMaxOctaves + threadIdx.x] = threadIdx.x < NHD ? cnt[threadIdx.x] : 0;
+}
+
+}  // namespace
+
+hipError_t launch_cnn_forward(const uint8_t* images, const float* params, short* acts, int64_t ncells,
+                              const CnnImage* imgs, int nimg, int ntiles, float* logits, uint8_t* mask, float zthr,
+                              hipStream_t s) {
+    if (ntiles <= 0) return hipSuccess;
+    for (int l = 0; l < kCnnLayers; ++l) {
+        const float* W = params + l * LAYER_P;
+        const float* b = W + CONV_W;
+        short* Y = acts + (int64_t)l * ncells * CC;
+        if (l == 0)
+            hipLaunchKernelGGL(k_conv_fwd<true>, dim3(ntiles), dim3(256), 0, s, images, nullptr, W, b, Y, imgs, nimg);
+        else
+            hipLaunchKernelGGL(k_conv_fwd<false>, dim3(ntiles), dim3(256), 0, s, images,
+                               acts + (int64_t)(l - 1) * ncells * CC, W, b, Y, imgs, nimg);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    const int blocks = (int)((ncells + 255) / 256);
+    hipLaunchKernelGGL(k_head, dim3(blocks), dim3(256), 0, s, acts + (int64_t)(kCnnLayers - 1) * ncells * CC, params,
+                       imgs, nimg, ncells, logits, mask, zthr);
+    return hipGetLastError();
+}
+
+hipError_t launch_cnn_backward(const uint8_t* images, const float* params, const short* acts, int64_t ncells,
+                               const CnnImage* imgs, int nimg, int ntiles, int nchunks, const float* logits,
+                               const uint32_t* labels, const float* pos_w, short* dbuf, float* grad, float* loss,
+                               int wgrid, hipStream_t s) {
+    hipLaunchKernelGGL(k_fill, dim3((kCnnParams + 255) / 256), dim3(256), 0, s, grad, kCnnParams, 0.f);
+    hipLaunchKernelGGL(k_fill, dim3(1), dim3(64), 0, s, loss, 1, 0.f);
+    short* dA = dbuf;
+    short* dB = dbuf + ncells * CC;
+    const int hgrid = std::max(1, std::min((int)((ncells + 255) / 256), wgrid));
+    hipLaunchKernelGGL(k_head_bwd, dim3(hgrid), dim3(256), 0, s, acts + (int64_t)(kCnnLayers - 1) * ncells * CC,
+                       params, logits, labels, pos_w, imgs, nimg, ncells, dA, grad, loss);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    for (int l = kCnnLayers - 1; l >= 0; --l) {
+        const float* W = params + l * LAYER_P;
+        float* gW = grad + l * LAYER_P;
+        float* gb = gW + CONV_W;
+        const short* Xprev = l > 0 ? acts + (int64_t)(l - 1) * ncells * CC : nullptr;
+        if (l == 0)
+            hipLaunchKernelGGL(k_conv_bwd_weight<true>, dim3(wgrid), dim3(256), 0, s, images, nullptr, dA, imgs, nimg,
+                               nchunks, gW, gb);
+        else
+            hipLaunchKernelGGL(k_conv_bwd_weight<false>, dim3(wgrid), dim3(256), 0, s, images, Xprev, dA, imgs, nimg,
+                               nchunks, gW, gb);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+        if (l > 0) {
+            hipLaunchKernelGGL(k_conv_bwd_data, dim3(ntiles), dim3(256), 0, s, dA, W, Xprev, dB, imgs, nimg);
+            if ((e = hipGetLastError()) != hipSuccess) return e;
+            short* t = dA;
+            dA = dB;
+            dB = t;
+        }
+    }
+    return hipSuccess;
+}
+
+hipError_t launch_cnn_adam(float* p, const float* g, float* m, float* v, int step, float lr, float b1, float b2,
+                           float eps, hipStream_t s) {
+    const float c1 = 1.f - powf(b1, (float)step), c2 = 1.f - powf(b2, (float)step);
+    hipLaunchKernelGGL(k_adam, dim3((kCnnParams + 255) / 256), dim3(256), 0, s, p, g, m, v, kCnnParams, lr, b1, b2, eps,
+                       c1, c2);
+    return hipGetLastError();
+}
+
+hipError_t launch_cnn_labels(const cdvs_keypoint* kp, const int32_t* count, int kp_cap, const CnnImage* imgs, int nimg,
+                             int64_t ncells, uint32_t* labels, hipStream_t s) {
+    hipLaunchKernelGGL(k_fill_u32, dim3((unsigned)((ncells + 255) / 256)), dim3(256), 0, s, labels, ncells);
+    const int64_t slots = (int64_t)nimg * kp_cap;
+    hipLaunchKernelGGL(k_labels, dim3((unsigned)((slots + 255) / 256)), dim3(256), 0, s, kp, count, kp_cap, imgs, nimg,
+                       labels);
+    return hipGetLastError();
+}
+
+hipError_t launch_mask_count(const uint8_t* mask, const CnnImage* imgs, int nimg, int32_t* active, hipStream_t s) {
+    hipLaunchKernelGGL(k_mask_count, dim3(nimg), dim3(256), 0, s, mask, imgs, active);
+    return hipGetLastError();
+}
+
+}  // namespace cdvs

@@ -122,11 +122,19 @@ __device__ __forceinline__ void store_tile(float* G, const float4 (&vals)[DNPER4
 // Persistent: the grid (a multiple of 8) is split evenly over the XCDs; each
 // workgroup walks its XCD's contiguous tile range with a stride, and the next
 // tile's loads are in flight while the current tile is computed.
+// Mask gating (optional): an octave-o centre (x, y) is examined only when
+// bit o of the mask cell holding (x 2^o, y 2^o) / 4 is set, unless the
+// image's active-cell fraction for that octave exceeds gate.fmax (then the
+// octave is examined densely).  Tiles without an active centre are skipped
+// after staging, and alpha is computed only within one pixel of an active
+// centre (every pixel an active centre reads).
 __global__ __launch_bounds__(256) void k_detect(const float* __restrict__ pyr, const OctJob* __restrict__ jobs,
-                                                int njobs, int ntiles, DetParams dp, cdvs_keypoint* __restrict__ cand,
-                                                int32_t* __restrict__ cand_cnt, int32_t* __restrict__ flags) {
+                                                int njobs, int ntiles, DetParams dp, GateParams gate,
+                                                cdvs_keypoint* __restrict__ cand, int32_t* __restrict__ cand_cnt,
+                                                int32_t* __restrict__ flags) {
     __shared__ __align__(16) float G[kScales][GH][GW];
     __shared__ float4 A[AH][AW];
+    __shared__ uint8_t act[DTH][DTW];
 
     const int x = blockIdx.x % kXcds, slot = blockIdx.x / kXcds, nslot = gridDim.x / kXcds;
     const int per = ntiles / kXcds, rem = ntiles % kXcds;
@@ -148,7 +156,40 @@ __global__ __launch_bounds__(256) void k_detect(const float* __restrict__ pyr, c
 
         __syncthreads();  // the previous tile is done with G and A
         store_tile(&G[0][0][0], vals);
-        __syncthreads();
+        // gating of this tile (uniform across the workgroup)
+        bool gated = false;
+        if (gate.mask) {
+            const CnnImage& cg = gate.cells[job.image];
+            const int ncell = cg.H4 * cg.W4;
+            gated = (float)gate.active[job.image * kMaxOctaves + job.octave] <= gate.fmax * (float)ncell;
+            if (gated) {
+                for (int q = threadIdx.x; q < DTH * DTW; q += blockDim.x) {
+                    const int gx = tx0 + q % DTW, gy = ty0 + q / DTW;
+                    bool on = false;
+                    if (gx < w && gy < h) {
+                        const int cx = min((gx << job.octave) >> 2, cg.W4 - 1);
+                        const int cy = min((gy << job.octave) >> 2, cg.H4 - 1);
+                        on = (gate.mask[cg.cell0 + (int64_t)cy * cg.W4 + cx] >> job.octave) & 1;
+                    }
+                    act[q / DTW][q % DTW] = on;
+                }
+            }
+        }
+        // (the barrier inside __syncthreads_or publishes G and act)
+        if (__syncthreads_or(gated && threadIdx.x == 0)) {
+            // any active centre in the tile?
+            bool mine = false;
+            for (int q = threadIdx.x; q < DTH * DTW; q += blockDim.x) mine |= act[q / DTW][q % DTW] != 0;
+            if (!__syncthreads_or(mine)) {
+                if (tj + nslot < cnt) {
+                    const int tn = tbase + tj + nslot;
+                    const OctJob& jn = jobs[find_det_job(jobs, njobs, tn)];
+                    const int ltn = tn - jn.tile0_det;
+                    load_tile(pyr, jn, (ltn % jn.tiles_x_det) * DTW, (ltn / jn.tiles_x_det) * DTH, vals);
+                }
+                continue;
+            }
+        }
         if (tj + nslot < cnt) {
             const int tn = tbase + tj + nslot;
             const OctJob& jn = jobs[find_det_job(jobs, njobs, tn)];
@@ -159,6 +200,16 @@ __global__ __launch_bounds__(256) void k_detect(const float* __restrict__ pyr, c
         for (int t = threadIdx.x; t < AH * AW; t += blockDim.x) {
             const int ay = t / AW, ax = t % AW;
             const int ly = ay + 1, lx = ax + 1 + GX;
+            if (gated) {
+                // alpha at (ay, ax) is read only by centres (ay-1+dy, ax-1+dx)
+                bool need = false;
+                for (int dy = -2; dy <= 0; ++dy)
+                    for (int dx = -2; dx <= 0; ++dx) {
+                        const int cy = ay + dy, cx = ax + dx;
+                        if (cy >= 0 && cy < DTH && cx >= 0 && cx < DTW) need |= act[cy][cx] != 0;
+                    }
+                if (!need) continue;
+            }
             float a0 = 0.f, a1 = 0.f, a2 = 0.f, a3 = 0.f;
 #pragma unroll
             for (int k = 0; k < kScales; ++k) {
@@ -185,7 +236,8 @@ __global__ __launch_bounds__(256) void k_detect(const float* __restrict__ pyr, c
             const int gx = tx0 + cx, gy = ty0 + cy;
             bool keep = false;
             float s = 0.f, p = 0.f, pss = 0.f, ox = 0.f, oy = 0.f, pr = 0.f, rho = 0.f;
-            if (gx >= dp.border && gx <= w - 1 - dp.border && gy >= dp.border && gy <= h - 1 - dp.border) {
+            if (gx >= dp.border && gx <= w - 1 - dp.border && gy >= dp.border && gy <= h - 1 - dp.border &&
+                (!gated || act[cy][cx])) {
                 const float4 a = A[cy + 1][cx + 1];
                 if (alp_extremum(a, dp.lo, dp.hi, s, p, pss) && fabsf(p) >= dp.contrast) {
                     float v[9];
@@ -396,12 +448,14 @@ hipError_t launch_clear(int32_t* p, int n, hipStream_t stream) {
 }
 
 hipError_t launch_detect(const float* pyr, const OctJob* jobs, int njobs, int ntiles, int grid, const DetParams& dp,
-                         cdvs_keypoint* cand, int32_t* cand_cnt, int32_t* flags, hipStream_t stream) {
+                         const GateParams& gate, cdvs_keypoint* cand, int32_t* cand_cnt, int32_t* flags,
+                         hipStream_t stream) {
     if (ntiles <= 0) return hipSuccess;
     // a multiple of the XCD count, no larger than needed
     int g = std::min(grid, (ntiles + kXcds - 1) / kXcds * kXcds);
     g = std::max(kXcds, g / kXcds * kXcds);
-    hipLaunchKernelGGL(k_detect, dim3(g), dim3(256), 0, stream, pyr, jobs, njobs, ntiles, dp, cand, cand_cnt, flags);
+    hipLaunchKernelGGL(k_detect, dim3(g), dim3(256), 0, stream, pyr, jobs, njobs, ntiles, dp, gate, cand, cand_cnt,
+                       flags);
     return hipGetLastError();
 }
 

@@ -31,7 +31,7 @@ def test_library_exports_every_declared_symbol():
 
 
 def test_struct_sizes():
-    assert ctypes.sizeof(cd.Params) == 72
+    assert ctypes.sizeof(cd.Params) == 76
     assert ctypes.sizeof(cd.ImageDesc) == 24
     assert cd.KP_DTYPE.itemsize == 48
 
@@ -43,6 +43,7 @@ def test_default_params():
     assert abs(p.contrast - 1.5) < 1e-7 and p.border == 4 and p.topk == 1000
     assert abs(p.ori_radius - 3.96) < 1e-6 and abs(p.ori_peak - 0.8) < 1e-7 and p.max_ori == 4
     assert p.desc_cell == 3 and p.desc_radius == 6 and abs(p.desc_clamp - 0.2) < 1e-7
+    assert abs(p.mask_fmax - 0.6) < 1e-7
 
 
 def test_defaults_agree_with_oracle_constants():
@@ -67,6 +68,7 @@ def _desc(w=640, h=480, pitch=None, off=0):
     (lambda p, d: setattr(p, "max_ori", 5), cd.CDVS_ERR_ARG),
     (lambda p, d: setattr(p, "topk", 5000), cd.CDVS_ERR_ARG),
     (lambda p, d: setattr(p, "ori_peak", 0.0), cd.CDVS_ERR_ARG),
+    (lambda p, d: setattr(p, "mask_fmax", 1.5), cd.CDVS_ERR_ARG),
     (lambda p, d: d.__setitem__(0, _desc(15, 480)), cd.CDVS_ERR_SHAPE),
     (lambda p, d: d.__setitem__(0, _desc(640, 8193)), cd.CDVS_ERR_SHAPE),
     (lambda p, d: d.__setitem__(0, _desc(640, 480, pitch=600)), cd.CDVS_ERR_SHAPE),
