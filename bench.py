@@ -67,6 +67,48 @@ def algorithmic(sizes, n_kp, n_ori):
     }
 
 
+WEIGHTS = os.path.join(ROOT, "paper_1705_09776_amd", "weights", "surrogate_640x480.npz")
+
+
+def gated_leg(pipe, steps, B, plain_kp):
+    """The surrogate-gated pass on the same batch: CNN mask -> pyramid ->
+    gated detection -> orientation -> descriptors, K eager steps with
+    per-kernel events; recall of the plain top-1000 keypoints."""
+    import numpy as np
+    import torch
+    import paper_1705_09776_amd as cd
+    from paper_1705_09776_amd import surrogate
+    st = surrogate.load_checkpoint(WEIGHTS)
+    with open(os.path.splitext(WEIGHTS)[0] + ".json") as f:
+        tau = float(json.load(f)["tau"])
+    params = torch.from_numpy(st["params"]).cuda()
+    pipe.cnn_buffers()
+    for _ in range(2):
+        pipe.run_gated(params, tau)
+    torch.cuda.synchronize()
+    cd.cdvs_profile_enable(pipe.ctx, True)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        pipe.run_gated(params, tau)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    prof = cd.cdvs_profile_read(pipe.ctx)
+    cd.cdvs_profile_enable(pipe.ctx, False)
+    if pipe.sync_status() != cd.CDVS_OK:
+        raise RuntimeError("capacity overflow in the gated leg")
+    gk = pipe.keypoints()
+    key = lambda k: (int(k["octave"]), int(k["ix"]), int(k["iy"]))
+    hit = sum(len({key(k) for k in a} & {key(k) for k in b}) for a, b in zip(plain_kp, gk))
+    mask = pipe.d_mask.cpu().numpy()
+    act = sum(int(((mask >> o) & 1).sum()) for o in range(5))
+    ms = (t1 - t0) * 1e3 / steps
+    return {"value": round(B / (ms * 1e-3), 1), "unit": "images/s", "ms_per_step": round(ms, 4), "tau": tau,
+            "recall_top1000": round(hit / max(1, sum(len(a) for a in plain_kp)), 5),
+            "active_cell_fraction": round(act / (5 * mask.size), 4),
+            "timing": "K eager steps (CNN mask, pyramid, gated detection, orientation, descriptors)",
+            "kernels_ms_per_step": {k: round(v[0] / steps, 4) for k, v in prof.items() if v[1]}}
+
+
 def cpu_baseline(imgs, seconds: float):
     """The oracle (fp64 build) over a bounded sample of the same images, one
     image per thread on the host's cores."""
@@ -97,6 +139,7 @@ def main():
     ap.add_argument("--batch", type=int, default=256)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-gated", action="store_true")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -207,6 +250,11 @@ def main():
         "kernels": kernels,
         "roofline": roof,
     }
+    if os.path.exists(WEIGHTS) and not args.no_gated:
+        log("[bench] surrogate-gated leg")
+        plain_kp = [k.copy() for k in pipe.keypoints()]
+        out["plain_eager_images_per_s"] = round(B / (eager_ms * 1e-3), 1)
+        out["gated"] = gated_leg(pipe, args.steps, B, plain_kp)
     if not args.no_cpu_baseline:
         log("[bench] cpu baseline (oracle)")
         out["cpu_baseline"] = cpu_baseline(imgs, args.cpu_seconds)

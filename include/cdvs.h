@@ -204,6 +204,20 @@ cdvs_status cdvs_graph_capture(cdvs_ctx* ctx, const uint8_t* d_images, float* d_
                                int32_t* d_count, cdvs_keypoint* d_kp_ori, int32_t* d_count_ori, float* d_desc);
 cdvs_status cdvs_graph_launch(cdvs_ctx* ctx, void* stream);
 
+/* Tile-shape autotuning of the scale-plane kernel (CDVS_KERNEL_SCALES has
+ * CDVS_TUNE_VARIANTS tile shapes: 64x32, 128x16, 32x32, 64x16; every shape
+ * produces bit-identical planes).  cdvs_autotune times each shape on the
+ * context's batch (cdvs_pyramid on the given buffers, 1 warm-up + 3 timed
+ * runs, median; blocking) and keeps the fastest.  With cache_path (may be
+ * NULL) a JSON file keyed by (GPU arch, kernel, image size, batch-size
+ * bucket) is read first (a hit skips the timing) and updated after timing.
+ * cdvs_tune_get / cdvs_tune_set read and force the shape. */
+#define CDVS_TUNE_VARIANTS 4
+cdvs_status cdvs_autotune(cdvs_ctx* ctx, const uint8_t* d_images, float* d_pyr, const char* cache_path,
+                          void* stream);
+int32_t cdvs_tune_get(const cdvs_ctx* ctx, int32_t kernel);
+cdvs_status cdvs_tune_set(cdvs_ctx* ctx, int32_t kernel, int32_t variant);
+
 /* ---------------------------------------------------------------------- */
 /* Surrogate candidate mask (a small learned CNN; not from the paper).       */
 /* ---------------------------------------------------------------------- */

@@ -70,8 +70,10 @@ EXPORTS = ["cdvs_default_params", "cdvs_validate", "cdvs_ctx_create", "cdvs_ctx_
            "cdvs_orient", "cdvs_describe", "cdvs_sync_status", "cdvs_candidate_capacity",
            "cdvs_graph_capture", "cdvs_graph_launch", "cdvs_profile_enable", "cdvs_profile_read",
            "cdvs_cnn_cells", "cdvs_cnn_cell_layout", "cdvs_cnn_forward", "cdvs_cnn_labels", "cdvs_cnn_backward",
-           "cdvs_cnn_adam"]
+           "cdvs_cnn_adam", "cdvs_autotune", "cdvs_tune_get", "cdvs_tune_set"]
+TUNE_VARIANTS = 4
 
+KERNEL_SCALES = 1
 KERNEL_NAMES = ["preblur", "scales", "clear", "detect", "finalize", "orient", "orient_compact", "describe",
                 "cnn_forward", "mask_count"]
 
@@ -107,6 +109,9 @@ def lib():
         "cdvs_describe": (i32, [vp, vp, vp, vp, vp, vp]),
         "cdvs_sync_status": (i32, [vp, vp]),
         "cdvs_candidate_capacity": (i32, [vp]),
+        "cdvs_autotune": (i32, [vp, vp, vp, ctypes.c_char_p, vp]),
+        "cdvs_tune_get": (i32, [vp, i32]),
+        "cdvs_tune_set": (i32, [vp, i32, i32]),
         "cdvs_cnn_cells": (i64, [vp]),
         "cdvs_cnn_cell_layout": (i32, [vp, i32, ctypes.POINTER(i64), ctypes.POINTER(i32), ctypes.POINTER(i32)]),
         "cdvs_cnn_forward": (i32, [vp, vp, vp, vp, vp, vp, ctypes.c_float, vp]),
@@ -188,6 +193,19 @@ def cdvs_sync_status(ctx, stream=None) -> int:
     if st not in (CDVS_OK, CDVS_ERR_CAPACITY):
         _check(ctx, st)
     return st
+
+
+def cdvs_autotune(ctx, d_images, d_pyr, cache_path=None, stream=None):
+    _check(ctx, lib().cdvs_autotune(ctx, _ptr(d_images), _ptr(d_pyr),
+                                    cache_path.encode() if cache_path else None, _stream(stream)))
+
+
+def cdvs_tune_get(ctx, kernel: int) -> int:
+    return int(lib().cdvs_tune_get(ctx, kernel))
+
+
+def cdvs_tune_set(ctx, kernel: int, variant: int):
+    _check(ctx, lib().cdvs_tune_set(ctx, kernel, variant))
 
 
 def cdvs_cnn_cells(ctx) -> int:

@@ -6,6 +6,9 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <algorithm>
+#include <fstream>
+#include <sstream>
 #include <string>
 #include <vector>
 
@@ -23,7 +26,8 @@ struct cdvs_ctx {
     std::vector<OctJob> jobs;                  // grouped by octave
     int max_oct = 0;
     int job_start[kMaxOctaves + 1] = {};
-    int blur_tiles[kMaxOctaves] = {};
+    int blur_tiles[kBlurVariants][kMaxOctaves] = {};
+    int blur_variant = 0;  // scale-plane tile variant (cdvs_autotune)
     int det_tiles[kMaxOctaves] = {};
     int64_t pyr_floats = 0;
     Taps taps{};
@@ -299,7 +303,7 @@ static cdvs_status build_layout(cdvs_ctx* c) {
             j.src_pitch = d.pitch;
             j.image = i;
             j.octave = o;
-            j.tiles_x_blur = (ws[o] + kBlurTW - 1) / kBlurTW;
+            for (int v = 0; v < kBlurVariants; ++v) j.tiles_x_blur[v] = (ws[o] + blur_tw(v) - 1) / blur_tw(v);
             j.tiles_x_det = (ws[o] + kDetTW - 1) / kDetTW;
             per_oct[o].push_back(j);
         }
@@ -308,15 +312,17 @@ static cdvs_status build_layout(cdvs_ctx* c) {
     c->jobs.clear();
     for (int o = 0; o < kMaxOctaves; ++o) {
         c->job_start[o] = (int)c->jobs.size();
-        int tb = 0, td = 0;
+        int tb[kBlurVariants] = {}, td = 0;
         for (OctJob& j : per_oct[o]) {
-            j.tile0_blur = tb;
+            for (int v = 0; v < kBlurVariants; ++v) {
+                j.tile0_blur[v] = tb[v];
+                tb[v] += j.tiles_x_blur[v] * ((j.h + blur_th(v) - 1) / blur_th(v));
+            }
             j.tile0_det = td;
-            tb += j.tiles_x_blur * ((j.h + kBlurTH - 1) / kBlurTH);
             td += j.tiles_x_det * ((j.h + kDetTH - 1) / kDetTH);
             c->jobs.push_back(j);
         }
-        c->blur_tiles[o] = tb;
+        for (int v = 0; v < kBlurVariants; ++v) c->blur_tiles[v][o] = tb[v];
         c->det_tiles[o] = td;
     }
     c->job_start[kMaxOctaves] = (int)c->jobs.size();
@@ -472,12 +478,12 @@ cdvs_status cdvs_pyramid(cdvs_ctx* ctx, const uint8_t* d_images, float* d_pyr, v
     {
         Bracket b(ctx, CDVS_KERNEL_PREBLUR, s);
         HIP_OR_FAIL(ctx, launch_preblur(d_images, d_pyr, ctx->d_jobs + ctx->job_start[0],
-                                        ctx->job_start[1] - ctx->job_start[0], ctx->blur_tiles[0], ctx->taps, s));
+                                        ctx->job_start[1] - ctx->job_start[0], ctx->blur_tiles[0][0], ctx->taps, s));
     }
     for (int o = 0; o < ctx->max_oct; ++o) {
         Bracket b(ctx, CDVS_KERNEL_SCALES, s);
         HIP_OR_FAIL(ctx, launch_scales(d_pyr, ctx->d_jobs + ctx->job_start[o], ctx->job_start[o + 1] - ctx->job_start[o],
-                                       ctx->blur_tiles[o], ctx->taps, s));
+                                       ctx->blur_tiles[ctx->blur_variant][o], ctx->blur_variant, ctx->taps, s));
     }
     return CDVS_OK;
 }
@@ -650,6 +656,120 @@ cdvs_status cdvs_graph_launch(cdvs_ctx* ctx, void* stream) {
     if (!ctx) return CDVS_ERR_STATE;
     if (!ctx->graph_exec) return fail(ctx, CDVS_ERR_STATE, "cdvs_graph_launch: no captured graph");
     HIP_OR_FAIL(ctx, hipGraphLaunch(ctx->graph_exec, (hipStream_t)stream));
+    return CDVS_OK;
+}
+
+int32_t cdvs_tune_get(const cdvs_ctx* ctx, int32_t kernel) {
+    if (!ctx || kernel != CDVS_KERNEL_SCALES) return -1;
+    return ctx->blur_variant;
+}
+
+cdvs_status cdvs_tune_set(cdvs_ctx* ctx, int32_t kernel, int32_t variant) {
+    if (!ctx) return CDVS_ERR_STATE;
+    if (kernel != CDVS_KERNEL_SCALES) return fail(ctx, CDVS_ERR_ARG, "cdvs_tune_set: only CDVS_KERNEL_SCALES is tunable");
+    if (variant < 0 || variant >= kBlurVariants) return fail(ctx, CDVS_ERR_ARG, "cdvs_tune_set: variant out of range");
+    ctx->blur_variant = variant;
+    return CDVS_OK;
+}
+
+// Cache key: arch, kernel, size of the first image, batch size rounded up to a power of two.
+static std::string tune_key(const cdvs_ctx* ctx) {
+    std::string arch = "unknown";
+    int dev = 0;
+    hipDeviceProp_t prop;
+    if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess) {
+        arch = prop.gcnArchName;
+        arch = arch.substr(0, arch.find(':'));
+    }
+    int nb = 1;
+    while (nb < ctx->n) nb <<= 1;
+    char buf[160];
+    snprintf(buf, sizeof(buf), "%s:scales:%dx%d:n%d", arch.c_str(), ctx->images[0].width, ctx->images[0].height, nb);
+    return buf;
+}
+
+// The cache is a JSON object with one "key": {...} entry per line.
+static bool tune_cache_lookup(const char* path, const std::string& key, int* variant) {
+    std::ifstream f(path);
+    if (!f) return false;
+    std::string line, pat = "\"" + key + "\"";
+    while (std::getline(f, line)) {
+        if (line.find(pat) == std::string::npos) continue;
+        size_t p = line.find("\"variant\":");
+        if (p == std::string::npos) return false;
+        int v = atoi(line.c_str() + p + 10);
+        if (v < 0 || v >= kBlurVariants) return false;
+        *variant = v;
+        return true;
+    }
+    return false;
+}
+
+static void tune_cache_store(const char* path, const std::string& key, int variant, const float* us) {
+    std::vector<std::string> entries;
+    std::ifstream f(path);
+    std::string line, pat = "\"" + key + "\"";
+    while (f && std::getline(f, line)) {
+        size_t q = line.find('"');
+        if (q == std::string::npos || line.find(pat) != std::string::npos) continue;
+        size_t e = line.find_last_of('}');
+        if (e == std::string::npos) continue;
+        entries.push_back(line.substr(q, e - q + 1));
+    }
+    char buf[512];
+    snprintf(buf, sizeof(buf), "\"%s\": {\"variant\": %d, \"us\": [%.1f, %.1f, %.1f, %.1f]}", key.c_str(), variant, us[0],
+             us[1], us[2], us[3]);
+    entries.push_back(buf);
+    std::ofstream o(path, std::ios::trunc);
+    o << "{\n";
+    for (size_t i = 0; i < entries.size(); ++i) o << entries[i] << (i + 1 < entries.size() ? ",\n" : "\n");
+    o << "}\n";
+}
+
+cdvs_status cdvs_autotune(cdvs_ctx* ctx, const uint8_t* d_images, float* d_pyr, const char* cache_path, void* stream) {
+    if (!ctx) return CDVS_ERR_STATE;
+    if (!d_images || !d_pyr) return fail(ctx, CDVS_ERR_ARG, "cdvs_autotune: null device pointer");
+    const std::string key = tune_key(ctx);
+    int v = 0;
+    if (cache_path && tune_cache_lookup(cache_path, key, &v)) {
+        ctx->blur_variant = v;
+        return CDVS_OK;
+    }
+    hipStream_t s = (hipStream_t)stream;
+    hipEvent_t e0, e1;
+    HIP_OR_FAIL(ctx, hipEventCreate(&e0));
+    HIP_OR_FAIL(ctx, hipEventCreate(&e1));
+    const bool prof = ctx->prof;
+    ctx->prof = false;
+    float best = 1e30f, us[kBlurVariants];
+    int best_v = ctx->blur_variant;
+    cdvs_status st = CDVS_OK;
+    for (int var = 0; var < kBlurVariants && st == CDVS_OK; ++var) {
+        ctx->blur_variant = var;
+        float t[3];
+        st = cdvs_pyramid(ctx, d_images, d_pyr, stream);
+        for (int r = 0; r < 3 && st == CDVS_OK; ++r) {
+            (void)hipEventRecord(e0, s);
+            st = cdvs_pyramid(ctx, d_images, d_pyr, stream);
+            (void)hipEventRecord(e1, s);
+            (void)hipEventSynchronize(e1);
+            float ms = 0.f;
+            (void)hipEventElapsedTime(&ms, e0, e1);
+            t[r] = ms * 1e3f;
+        }
+        std::sort(t, t + 3);
+        us[var] = t[1];
+        if (us[var] < best) {
+            best = us[var];
+            best_v = var;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    ctx->prof = prof;
+    ctx->blur_variant = best_v;
+    if (st != CDVS_OK) return st;
+    if (cache_path) tune_cache_store(cache_path, key, best_v, us);
     return CDVS_OK;
 }
 

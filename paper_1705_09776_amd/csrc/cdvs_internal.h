@@ -45,7 +45,7 @@ struct OctJob {
     int32_t src_pitch;  // bytes
     int32_t image;
     int32_t octave;
-    int32_t tiles_x_blur, tile0_blur;  // tiling of the blur kernels
+    int32_t tiles_x_blur[4], tile0_blur[4];  // tiling of the blur kernels, per tile variant
     int32_t tiles_x_det, tile0_det;    // tiling of the detection kernel
 };
 
@@ -121,13 +121,18 @@ struct GateParams {
 };
 
 // Kernel tile shapes.
-constexpr int kBlurTW = 64, kBlurTH = 32, kBlurV = 8;
+// Scale-plane kernel tile variants (width x height, autotuned); the
+// pre-blur always uses variant 0.
+constexpr int kBlurVariants = 4;
+constexpr int kBlurV = 8;
+__host__ __device__ constexpr int blur_tw(int v) { return v == 1 ? 128 : v == 2 ? 32 : 64; }
+__host__ __device__ constexpr int blur_th(int v) { return v == 0 ? 32 : v == 1 ? 16 : v == 2 ? 32 : 16; }
 constexpr int kDetTW = 64, kDetTH = 16;
 
 // Launchers (each enqueues on `stream`, returns the launch error).
 hipError_t launch_preblur(const uint8_t* images, float* pyr, const OctJob* jobs, int njobs, int ntiles,
                           const Taps& taps, hipStream_t stream);
-hipError_t launch_scales(float* pyr, const OctJob* jobs, int njobs, int ntiles, const Taps& taps,
+hipError_t launch_scales(float* pyr, const OctJob* jobs, int njobs, int ntiles, int variant, const Taps& taps,
                          hipStream_t stream);
 hipError_t launch_clear(int32_t* p, int n, hipStream_t stream);
 hipError_t launch_detect(const float* pyr, const OctJob* jobs, int njobs, int ntiles, int grid, const DetParams& dp,

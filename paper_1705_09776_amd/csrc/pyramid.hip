@@ -22,12 +22,13 @@ __host__ __device__ constexpr int radius_of(int k) {
     return k == 0 ? kR0 : k == 1 ? kR1 : k == 2 ? kR2 : k == 3 ? kR3 : kR4;
 }
 
-// Job owning global tile `tile` (jobs sorted by tile0_blur).
+// Job owning global tile `tile` of tile variant VAR (jobs sorted by tile0).
+template <int VAR>
 __device__ __forceinline__ int find_blur_job(const OctJob* jobs, int njobs, int tile) {
     int lo = 0, hi = njobs - 1;
     while (lo < hi) {
         int mid = (lo + hi + 1) >> 1;
-        if (jobs[mid].tile0_blur <= tile) lo = mid;
+        if (jobs[mid].tile0_blur[VAR] <= tile) lo = mid;
         else hi = mid - 1;
     }
     return lo;
@@ -90,20 +91,21 @@ __device__ __forceinline__ void store_decimated(float* dst, int x0, int nw, cons
 // KFIRST..KFIRST+NK-1 are the tap sets applied; U8 selects the octave-0
 // pre-blur (input = u8 image, output = G_{0,0}); otherwise input = G_{o,0},
 // outputs G_{o,1..4} and the decimated G_{o+1,0}.
-template <int KFIRST, int NK, int HALO, bool U8>
+template <int KFIRST, int NK, int HALO, bool U8, int VAR>
 __global__ __launch_bounds__(256) void k_blur(const uint8_t* __restrict__ images, float* __restrict__ pyr,
                                               const OctJob* __restrict__ jobs, int njobs, Taps taps) {
-    constexpr int TW = kBlurTW, TH = kBlurTH, V = kBlurV;
+    constexpr int TW = blur_tw(VAR), TH = blur_th(VAR), V = kBlurV;
+    static_assert(TH % V == 0 && TW % 8 == 0, "tile shape");
     constexpr int C = TW + 2 * HALO;
     constexpr int CP = C + 1;
     constexpr int NG = TH / V;
     __shared__ float T[NK][TH][CP];
 
     const int tile = xcd_remap(blockIdx.x, gridDim.x);
-    const OctJob& job = jobs[find_blur_job(jobs, njobs, tile)];
-    const int lt = tile - job.tile0_blur;
-    const int tx0 = (lt % job.tiles_x_blur) * TW;
-    const int ty0 = (lt / job.tiles_x_blur) * TH;
+    const OctJob& job = jobs[find_blur_job<VAR>(jobs, njobs, tile)];
+    const int lt = tile - job.tile0_blur[VAR];
+    const int tx0 = (lt % job.tiles_x_blur[VAR]) * TW;
+    const int ty0 = (lt / job.tiles_x_blur[VAR]) * TH;
     const int w = job.w, h = job.h;
 
     for (int t = threadIdx.x; t < C * NG; t += blockDim.x) {
@@ -168,16 +170,28 @@ __global__ __launch_bounds__(256) void k_blur(const uint8_t* __restrict__ images
 hipError_t launch_preblur(const uint8_t* images, float* pyr, const OctJob* jobs, int njobs, int ntiles,
                           const Taps& taps, hipStream_t stream) {
     if (ntiles <= 0) return hipSuccess;
-    hipLaunchKernelGGL((k_blur<0, 1, kR0, true>), dim3(ntiles), dim3(256), 0, stream, images, pyr, jobs, njobs,
+    hipLaunchKernelGGL((k_blur<0, 1, kR0, true, 0>), dim3(ntiles), dim3(256), 0, stream, images, pyr, jobs, njobs,
                        taps);
     return hipGetLastError();
 }
 
-hipError_t launch_scales(float* pyr, const OctJob* jobs, int njobs, int ntiles, const Taps& taps,
+hipError_t launch_scales(float* pyr, const OctJob* jobs, int njobs, int ntiles, int variant, const Taps& taps,
                          hipStream_t stream) {
     if (ntiles <= 0) return hipSuccess;
-    hipLaunchKernelGGL((k_blur<1, 4, kMaxR, false>), dim3(ntiles), dim3(256), 0, stream, nullptr, pyr, jobs,
-                       njobs, taps);
+    switch (variant) {
+#define CASE(V)                                                                                                   \
+    case V:                                                                                                       \
+        hipLaunchKernelGGL((k_blur<1, 4, kMaxR, false, V>), dim3(ntiles), dim3(256), 0, stream, nullptr, pyr, jobs, \
+                           njobs, taps);                                                                          \
+        break;
+        CASE(0)
+        CASE(1)
+        CASE(2)
+        CASE(3)
+#undef CASE
+        default:
+            return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
 

@@ -43,10 +43,11 @@ def label_pipeline(batch: int, width=640, height=480) -> Pipeline:
 
 
 class Trainer:
-    def __init__(self, batch=32, width=640, height=480, lr=1e-3, seed=0, data_seed=4):
+    def __init__(self, batch=32, width=640, height=480, lr=1e-3, seed=0, data_seed=4, dataset=20000):
         import torch
         self.torch = torch
         self.batch, self.lr, self.data_seed = batch, lr, data_seed
+        self.dataset = dataset   # training images are indices 0..dataset-1, visited in order, epoch after epoch
         self.width, self.height = width, height
         self.pipe = label_pipeline(batch, width, height)
         self.pipe.cnn_buffers()
@@ -65,7 +66,11 @@ class Trainer:
     # -- data -----------------------------------------------------------
     def next_images(self):
         import synth
-        imgs = synth.fixed_batch(self.data_seed, self.batch, self.width, self.height, first=self.cursor)
+        first = self.cursor % self.dataset
+        n = min(self.batch, self.dataset - first)
+        imgs = list(synth.fixed_batch(self.data_seed, n, self.width, self.height, first=first))
+        if n < self.batch:
+            imgs += list(synth.fixed_batch(self.data_seed, self.batch - n, self.width, self.height, first=0))
         self.cursor += self.batch
         return list(imgs)
 

@@ -108,3 +108,10 @@ def test_pack_images():
     buf, descs = cd.pack_images([a, b])
     assert descs[0].pitch == 64 and descs[1].pitch == 128 and descs[1].offset == 64 * 17
     np.testing.assert_array_equal(buf[:64 * 17].reshape(17, 64)[:, :20], a)
+
+
+def test_tune_api_host_checks():
+    L = cd.lib()
+    assert L.cdvs_tune_get(None, cd.KERNEL_SCALES) == -1
+    assert L.cdvs_tune_set(None, cd.KERNEL_SCALES, 0) == cd.CDVS_ERR_STATE
+    assert L.cdvs_autotune(None, None, None, None, None) == cd.CDVS_ERR_STATE

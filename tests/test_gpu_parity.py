@@ -274,3 +274,35 @@ def test_graph_replay_equals_eager():
             np.testing.assert_allclose(d1[i], d0[i], atol=1e-5)
         pipe.run()          # eager pass between replays
         torch.cuda.synchronize()
+
+
+def test_scale_tile_variants_identical(tmp_path):
+    """Every tile shape of the scale-plane kernel writes the same planes bit
+    for bit (ragged sizes, so each shape has partial tiles), and the
+    autotuner picks one of them, caches it and reads the cache back."""
+    imgs = [synth.image(synth.SEED_RAGGED, i, w, h, nblobs=40)
+            for i, (w, h) in enumerate([(640, 480), (333, 217), (97, 61), (480, 640)])]
+    pipe = cd.Pipeline([(im.shape[1], im.shape[0]) for im in imgs])
+    pipe.upload(imgs)
+    ref = None
+    for v in range(cd.TUNE_VARIANTS):
+        cd.cdvs_tune_set(pipe.ctx, cd.KERNEL_SCALES, v)
+        pipe.d_pyr.fill_(float("nan"))
+        pipe.pyramid()
+        torch.cuda.synchronize()
+        got = pipe.d_pyr.cpu().numpy().view(np.uint32)
+        if ref is None:
+            ref = got.copy()
+        else:
+            np.testing.assert_array_equal(got, ref, err_msg=f"variant {v}")
+    cache = str(tmp_path / "tune.json")
+    cd.cdvs_autotune(pipe.ctx, pipe.d_images, pipe.d_pyr, cache)
+    v = cd.cdvs_tune_get(pipe.ctx, cd.KERNEL_SCALES)
+    assert 0 <= v < cd.TUNE_VARIANTS
+    import json
+    entries = json.load(open(cache))
+    assert len(entries) == 1 and list(entries.values())[0]["variant"] == v
+    other = (v + 1) % cd.TUNE_VARIANTS
+    cd.cdvs_tune_set(pipe.ctx, cd.KERNEL_SCALES, other)
+    cd.cdvs_autotune(pipe.ctx, pipe.d_images, pipe.d_pyr, cache)   # cache hit
+    assert cd.cdvs_tune_get(pipe.ctx, cd.KERNEL_SCALES) == v
