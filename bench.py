@@ -109,6 +109,109 @@ def gated_leg(pipe, steps, B, plain_kp):
             "kernels_ms_per_step": {k: round(v[0] / steps, 4) for k, v in prof.items() if v[1]}}
 
 
+def ragged_leg(steps, n=1024):
+    """Uneven sizes: n images, long side 640, aspect drawn from {4:3, 3:2,
+    16:9, 1:1, 3:4}, 100-400 blobs each, in one packed ragged context; the
+    scale-plane tile shape is picked by the autotuner, then K replays of the
+    captured pass are timed."""
+    import tempfile
+    import torch
+    import synth
+    import paper_1705_09776_amd as cd
+    imgs = synth.ragged_batch(synth.SEED_RAGGED, n)
+    sizes = [(im.shape[1], im.shape[0]) for im in imgs]
+    pipe = cd.Pipeline(sizes)
+    pipe.upload(imgs)
+    pipe.run()
+    torch.cuda.synchronize()
+    with tempfile.TemporaryDirectory() as td:
+        cache = os.path.join(td, "tune.json")
+        t0 = time.perf_counter()
+        cd.cdvs_autotune(pipe.ctx, pipe.d_images, pipe.d_pyr, cache)
+        t_tune = time.perf_counter() - t0
+        tune = list(json.load(open(cache)).values())[0]
+    pipe.capture()
+    pipe.replay()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        pipe.replay()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    if pipe.sync_status() != cd.CDVS_OK:
+        raise RuntimeError("capacity overflow in the ragged leg")
+    ms = (t1 - t0) * 1e3 / steps
+    npx = sum(octave_pixels(sizes))
+    return {"value": round(n / (ms * 1e-3), 1), "unit": "images/s", "ms_per_step": round(ms, 4), "images": n,
+            "octave_px_per_image": round(npx / n, 1),
+            "tile_variant": tune["variant"], "tile_variant_us": tune["us"], "autotune_s": round(t_tune, 3),
+            "timing": "K hipGraph replays of the whole plain pass over the packed ragged batch"}
+
+
+HIRES = (1280, 960)
+
+
+def stream_leg(n_images=4096, chunk=256, threads=16):
+    """High-resolution stream: n_images 1280x960 (400-1200 blobs, sigma up to
+    40 px) resident in HBM, surrogate-gated, in chunks of `chunk` images;
+    descriptors of the top 1000 keypoints per image go to pinned host
+    buffers and a host stand-in consumer (u8 coding of the descriptors, in
+    place of the CPU-side compression) overlapped with the next chunk."""
+    import numpy as np
+    import torch
+    import synth
+    import paper_1705_09776_amd as cd
+    from paper_1705_09776_amd import surrogate
+    W, H = HIRES
+    pipe = cd.Pipeline([(W, H)] * chunk)
+    n_chunks = n_images // chunk
+    d_all = synth.device_batch(synth.SEED_HIRES, n_chunks * chunk, W, H, 400, 1200, smax=40.0)
+    torch.cuda.synchronize()
+    st = surrogate.load_checkpoint(WEIGHTS)
+    with open(os.path.splitext(WEIGHTS)[0] + ".json") as f:
+        tau = float(json.load(f)["tau"])
+    params = torch.from_numpy(st["params"]).cuda()
+    sink = (np.zeros((n_chunks * chunk, pipe.kp_capacity, cd.DESC_DIM), dtype=np.uint8),
+            np.zeros(n_chunks * chunk, dtype=np.int32))
+    sink[0][:] = 1                                    # touch the pages before timing
+    # recall of the gated detector on the first chunk
+    ib = pipe.image_bytes
+    pipe.d_images = d_all[:ib]
+    pipe.run()
+    torch.cuda.synchronize()
+    plain = [k.copy() for k in pipe.keypoints()]
+    pipe.run_gated(params, tau)
+    torch.cuda.synchronize()
+    gk = pipe.keypoints()
+    key = lambda k: (int(k["octave"]), int(k["ix"]), int(k["iy"]))
+    hit = sum(len({key(k) for k in a} & {key(k) for k in b}) for a, b in zip(plain, gk))
+    recall = hit / max(1, sum(len(a) for a in plain))
+    mask = pipe.d_mask.cpu().numpy()
+    active = sum(int(((mask >> o) & 1).sum()) for o in range(6)) / (6 * mask.size)
+    # GPU only: the same chunks, gated, without the hand-off
+    pipe.stream(d_all, 1, params=params, tau=tau, threads=threads, sink=sink)      # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for c in range(n_chunks):
+        pipe.d_images = d_all[c * ib:(c + 1) * ib]
+        pipe.run_gated(params, tau)
+    torch.cuda.synchronize()
+    t_gpu = time.perf_counter() - t0
+    # end to end: compute, D2H into pinned slots, host consumer, overlapped
+    t0 = time.perf_counter()
+    pipe.stream(d_all, n_chunks, params=params, tau=tau, threads=threads, sink=sink)
+    t_e2e = time.perf_counter() - t0
+    n = n_chunks * chunk
+    d2h = n * pipe.kp_capacity * (cd.DESC_DIM * 4 + 48)
+    return {"value": round(n / t_e2e, 1), "unit": "images/s", "images": n, "chunk": chunk, "width": W, "height": H,
+            "gpu_only_images_per_s": round(n / t_gpu, 1), "overlap_efficiency": round(t_gpu / t_e2e, 4),
+            "d2h_gb": round(d2h / 1e9, 3), "tau": tau, "recall_first_chunk": round(recall, 5),
+            "active_cell_fraction_first_chunk": round(active, 4), "consumer_threads": threads,
+            "descriptors_kept": int(sink[1][:n].sum()),
+            "timing": "end to end over the stream (inputs resident in HBM; ends when the host consumer has "
+                      "finished the last chunk); gpu_only: the same chunks gated, eager, no hand-off"}
+
+
 def cpu_baseline(imgs, seconds: float):
     """The oracle (fp64 build) over a bounded sample of the same images, one
     image per thread on the host's cores."""
@@ -140,6 +243,9 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-gated", action="store_true")
+    ap.add_argument("--no-ragged", action="store_true")
+    ap.add_argument("--no-stream", action="store_true")
+    ap.add_argument("--stream-images", type=int, default=4096)
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -255,6 +361,14 @@ def main():
         plain_kp = [k.copy() for k in pipe.keypoints()]
         out["plain_eager_images_per_s"] = round(B / (eager_ms * 1e-3), 1)
         out["gated"] = gated_leg(pipe, args.steps, B, plain_kp)
+    if not args.no_ragged:
+        log("[bench] ragged leg (1024 images of uneven size)")
+        out["ragged"] = ragged_leg(args.steps)
+    if os.path.exists(WEIGHTS) and not args.no_stream:
+        log(f"[bench] high-resolution stream ({args.stream_images} images 1280x960)")
+        del pipe
+        torch.cuda.empty_cache()
+        out["stream"] = stream_leg(args.stream_images)
     if not args.no_cpu_baseline:
         log("[bench] cpu baseline (oracle)")
         out["cpu_baseline"] = cpu_baseline(imgs, args.cpu_seconds)

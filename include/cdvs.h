@@ -269,6 +269,66 @@ cdvs_status cdvs_cnn_backward(cdvs_ctx* ctx, const uint8_t* d_images, const floa
 cdvs_status cdvs_cnn_adam(cdvs_ctx* ctx, float* d_params, const float* d_grad, float* d_m, float* d_v, int32_t step,
                           float lr, float beta1, float beta2, float eps, void* stream);
 
+/* ---------------------------------------------------------------------- */
+/* Streaming many batches with the host hand-off overlapped.  In the hybrid
+ * encoder of Section 4 the CPU-side steps (selection, compression) run
+ * concurrently with the GPU modules; here a batch of the context's shape is
+ * the unit of that overlap.
+ *
+ * cdvs_stream processes n_chunks batches whose packed images lie at
+ * d_images + c * chunk_stride (each laid out as the context's image table
+ * says; chunk_stride >= the table's extent).  Per chunk, on `stream`:
+ * cdvs_pyramid, then (d_cnn_params != NULL) cdvs_cnn_forward into d_acts and
+ * d_mask with threshold tau and a gated cdvs_alp_detect, else the plain one,
+ * then cdvs_orient and cdvs_describe.  On an internal copy stream the counts,
+ * oriented keypoints and descriptors are copied into pinned host slot c % 2
+ * (caller-owned, from hipHostMalloc: n counts, n x kp_capacity keypoints,
+ * n x kp_capacity x 128 floats per slot), and a host thread then calls
+ * consumer(user, c, n, kp_capacity, counts, keypoints, descriptors) on it.
+ * Chunk c + 1's pyramid, mask and detection run while chunk c is copied; a
+ * slot is refilled only after the consumer returned from it.  Blocks until
+ * every chunk has been consumed.  A non-zero return of the consumer stops
+ * the stream (CDVS_ERR_STATE); a candidate overflow in any chunk is
+ * reported as CDVS_ERR_CAPACITY at the end (results still complete). */
+typedef struct {
+    float* d_pyr;                 /* cdvs_pyramid_bytes */
+    cdvs_keypoint* d_kp;          /* n x kp_capacity */
+    int32_t* d_count;             /* n */
+    cdvs_keypoint* d_kp_ori;      /* n x kp_capacity */
+    int32_t* d_count_ori;         /* n */
+    float* d_desc;                /* n x kp_capacity x 128 */
+    const float* d_cnn_params;    /* NULL: plain detection */
+    uint16_t* d_acts;             /* CDVS_CNN_LAYERS x cells x 16 (gated only) */
+    uint8_t* d_mask;              /* cells (gated only) */
+    float tau;                    /* mask threshold (gated only) */
+    int32_t* h_count[2];          /* pinned host double buffers */
+    cdvs_keypoint* h_kp[2];
+    float* h_desc[2];
+} cdvs_stream_buffers;
+
+typedef int32_t (*cdvs_chunk_consumer)(void* user, int32_t chunk, int32_t n_images, int32_t kp_capacity,
+                                       const int32_t* h_count, const cdvs_keypoint* h_kp, const float* h_desc);
+
+cdvs_status cdvs_stream(cdvs_ctx* ctx, const uint8_t* d_images, int64_t chunk_stride, int32_t n_chunks,
+                        const cdvs_stream_buffers* buf, cdvs_chunk_consumer consumer, void* user, void* stream);
+
+/* A host stand-in for the paper's CPU-side selection and compression (which
+ * is not built here): a cdvs_chunk_consumer that codes every descriptor
+ * element of each image's first min(count, keep) descriptors as
+ * u8 = min(255, floor(512 d + 1/2)) into out[image][k][128] (image =
+ * chunk * n_images + i, out laid out with kp_capacity rows per image) and
+ * stores the kept count in kept[image], using `threads` host threads.
+ * `user` points at a cdvs_standin_sink. */
+typedef struct {
+    uint8_t* out;
+    int32_t* kept;
+    int64_t total_images;   /* size of out / kept in images; chunks beyond it fail */
+    int32_t keep;
+    int32_t threads;
+} cdvs_standin_sink;
+int32_t cdvs_standin_consume(void* user, int32_t chunk, int32_t n_images, int32_t kp_capacity, const int32_t* h_count,
+                             const cdvs_keypoint* h_kp, const float* h_desc);
+
 /* Per-kernel timing with HIP events (tracing).  While enabled, every kernel
  * the compute calls launch is bracketed by a pair of events recorded on the
  * call's stream (so a context being captured into a graph must not have it

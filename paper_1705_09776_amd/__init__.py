@@ -70,7 +70,8 @@ EXPORTS = ["cdvs_default_params", "cdvs_validate", "cdvs_ctx_create", "cdvs_ctx_
            "cdvs_orient", "cdvs_describe", "cdvs_sync_status", "cdvs_candidate_capacity",
            "cdvs_graph_capture", "cdvs_graph_launch", "cdvs_profile_enable", "cdvs_profile_read",
            "cdvs_cnn_cells", "cdvs_cnn_cell_layout", "cdvs_cnn_forward", "cdvs_cnn_labels", "cdvs_cnn_backward",
-           "cdvs_cnn_adam", "cdvs_autotune", "cdvs_tune_get", "cdvs_tune_set"]
+           "cdvs_cnn_adam", "cdvs_autotune", "cdvs_tune_get", "cdvs_tune_set",
+           "cdvs_stream", "cdvs_standin_consume"]
 TUNE_VARIANTS = 4
 
 KERNEL_SCALES = 1
@@ -112,6 +113,8 @@ def lib():
         "cdvs_autotune": (i32, [vp, vp, vp, ctypes.c_char_p, vp]),
         "cdvs_tune_get": (i32, [vp, i32]),
         "cdvs_tune_set": (i32, [vp, i32, i32]),
+        "cdvs_stream": (i32, [vp, vp, i64, i32, ctypes.POINTER(StreamBuffers), vp, vp, vp]),
+        "cdvs_standin_consume": (i32, [vp, i32, i32, i32, vp, vp, vp]),
         "cdvs_cnn_cells": (i64, [vp]),
         "cdvs_cnn_cell_layout": (i32, [vp, i32, ctypes.POINTER(i64), ctypes.POINTER(i32), ctypes.POINTER(i32)]),
         "cdvs_cnn_forward": (i32, [vp, vp, vp, vp, vp, vp, ctypes.c_float, vp]),
@@ -283,6 +286,35 @@ def pack_images(images):
     return np.concatenate(chunks), descs
 
 
+class StreamBuffers(ctypes.Structure):
+    _fields_ = [("d_pyr", ctypes.c_void_p), ("d_kp", ctypes.c_void_p), ("d_count", ctypes.c_void_p),
+                ("d_kp_ori", ctypes.c_void_p), ("d_count_ori", ctypes.c_void_p), ("d_desc", ctypes.c_void_p),
+                ("d_cnn_params", ctypes.c_void_p), ("d_acts", ctypes.c_void_p), ("d_mask", ctypes.c_void_p),
+                ("tau", ctypes.c_float), ("h_count", ctypes.c_void_p * 2), ("h_kp", ctypes.c_void_p * 2),
+                ("h_desc", ctypes.c_void_p * 2)]
+
+
+class StandinSink(ctypes.Structure):
+    _fields_ = [("out", ctypes.c_void_p), ("kept", ctypes.c_void_p), ("total_images", ctypes.c_int64),
+                ("keep", ctypes.c_int32), ("threads", ctypes.c_int32)]
+
+
+# consumer(user, chunk, n_images, kp_capacity, h_count, h_kp, h_desc) -> int32 (0 = continue)
+CHUNK_CONSUMER = ctypes.CFUNCTYPE(ctypes.c_int32, ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                                  ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p)
+
+
+def cdvs_stream(ctx, d_images, chunk_stride: int, n_chunks: int, bufs: StreamBuffers, consumer, user, stream=None):
+    """consumer: a CHUNK_CONSUMER instance or a raw function address (int)."""
+    fn = consumer if isinstance(consumer, int) else ctypes.cast(consumer, ctypes.c_void_p).value
+    _check(ctx, lib().cdvs_stream(ctx, _ptr(d_images), chunk_stride, n_chunks, ctypes.byref(bufs), fn, user,
+                                  _stream(stream)))
+
+
+def standin_consumer_address() -> int:
+    return ctypes.cast(lib().cdvs_standin_consume, ctypes.c_void_p).value
+
+
 class Pipeline:
     """Device buffers and context for one batch layout.
 
@@ -325,14 +357,56 @@ class Pipeline:
         except Exception:
             pass
 
-    def upload(self, images):
+    def pack(self, images) -> np.ndarray:
+        """The batch laid out as the context's image table says (host bytes)."""
         assert len(images) == self.n
         host = np.zeros(self.image_bytes, dtype=np.uint8)
         for im, d in zip(images, self.descs):
             im = np.asarray(im, dtype=np.uint8)
             assert im.shape == (d.height, d.width)
             host[d.offset:d.offset + d.pitch * d.height].reshape(d.height, d.pitch)[:, :d.width] = im
-        self.d_images.copy_(self.torch.from_numpy(host))
+        return host
+
+    def upload(self, images):
+        self.d_images.copy_(self.torch.from_numpy(self.pack(images)))
+
+    # -- streaming ----------------------------------------------------------
+    def stream(self, d_all, n_chunks, params=None, tau=0.1, consumer=None, user=None, keep=None, threads=8,
+               stream=None, sink=None):
+        """cdvs_stream over n_chunks batches packed back to back in d_all
+        (chunk stride = image_bytes).  With consumer None the library's
+        stand-in consumer runs and (codes, kept) are returned: codes
+        (n_chunks * n, kp_capacity, 128) uint8, kept (n_chunks * n) int32
+        (pass them as `sink` to reuse arrays)."""
+        t = self.torch
+        assert d_all.numel() >= n_chunks * self.image_bytes
+        if getattr(self, "_slots", None) is None:
+            n, cap = self.n, self.kp_capacity
+            self._slots = [(t.empty(n, dtype=t.int32, pin_memory=True),
+                            t.empty(n * cap * 12, dtype=t.int32, pin_memory=True),
+                            t.empty(n * cap * DESC_DIM, dtype=t.float32, pin_memory=True)) for _ in range(2)]
+        b = StreamBuffers()
+        b.d_pyr, b.d_kp, b.d_count = _ptr(self.d_pyr), _ptr(self.d_kp), _ptr(self.d_count)
+        b.d_kp_ori, b.d_count_ori, b.d_desc = _ptr(self.d_kp_ori), _ptr(self.d_count_ori), _ptr(self.d_desc)
+        if params is not None:
+            self.cnn_buffers()
+            b.d_cnn_params, b.d_acts, b.d_mask, b.tau = _ptr(params), _ptr(self.d_acts), _ptr(self.d_mask), tau
+        for i in range(2):
+            b.h_count[i], b.h_kp[i], b.h_desc[i] = (_ptr(x) for x in self._slots[i])
+        result = None
+        if consumer is None:
+            if sink is None:
+                sink = (np.zeros((n_chunks * self.n, self.kp_capacity, DESC_DIM), dtype=np.uint8),
+                        np.zeros(n_chunks * self.n, dtype=np.int32))
+            codes, kept = sink
+            assert codes.shape[0] >= n_chunks * self.n and codes.dtype == np.uint8 and codes.flags.c_contiguous
+            assert codes.shape[1:] == (self.kp_capacity, DESC_DIM)
+            assert kept.dtype == np.int32 and kept.size >= n_chunks * self.n
+            c_sink = StandinSink(codes.ctypes.data, kept.ctypes.data, n_chunks * self.n,
+                                 self.kp_capacity if keep is None else keep, threads)
+            consumer, user, result = standin_consumer_address(), ctypes.addressof(c_sink), (codes, kept)
+        cdvs_stream(self.ctx, d_all, self.image_bytes, n_chunks, b, consumer, user, stream)
+        return result
 
     def pyramid(self, stream=None):
         cdvs_pyramid(self.ctx, self.d_images, self.d_pyr, stream)

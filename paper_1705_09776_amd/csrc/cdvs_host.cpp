@@ -7,7 +7,11 @@
 #include <string.h>
 
 #include <algorithm>
+#include <condition_variable>
+#include <deque>
 #include <fstream>
+#include <mutex>
+#include <thread>
 #include <sstream>
 #include <string>
 #include <vector>
@@ -800,6 +804,186 @@ cdvs_status cdvs_profile_read(cdvs_ctx* ctx, double* total_ms, int32_t* launches
     }
     ctx->ev_used = 0;
     return CDVS_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Streaming with the host hand-off overlapped.
+
+namespace {
+
+// Hands chunk indices to the host thread and counts what it has finished.
+struct ConsumerQueue {
+    std::mutex mu;
+    std::condition_variable cv;
+    std::deque<int> q;
+    int consumed = 0;     // chunks 0..consumed-1 are done
+    bool closed = false;  // no more chunks
+    bool failed = false;
+    int fail_chunk = -1, fail_rc = 0;
+    std::string fail_msg;
+};
+
+}  // namespace
+
+static int64_t images_extent(const cdvs_ctx* ctx) {
+    int64_t e = 0;
+    for (const auto& d : ctx->images) e = std::max(e, d.offset + (int64_t)d.pitch * d.height);
+    return e;
+}
+
+static void consumer_loop(ConsumerQueue* cq, const cdvs_stream_buffers* buf, hipEvent_t* copied,
+                          cdvs_chunk_consumer consumer, void* user, int n, int cap) {
+    for (;;) {
+        int c;
+        {
+            std::unique_lock<std::mutex> lk(cq->mu);
+            cq->cv.wait(lk, [&] { return !cq->q.empty() || cq->closed; });
+            if (cq->q.empty()) return;
+            c = cq->q.front();
+            cq->q.pop_front();
+        }
+        const int slot = c & 1;
+        hipError_t e = hipEventSynchronize(copied[slot]);
+        int32_t rc = 0;
+        bool skip;
+        {
+            std::lock_guard<std::mutex> lk(cq->mu);
+            skip = cq->failed;
+        }
+        if (e == hipSuccess && !skip) rc = consumer(user, c, n, cap, buf->h_count[slot], buf->h_kp[slot], buf->h_desc[slot]);
+        std::lock_guard<std::mutex> lk(cq->mu);
+        if (e != hipSuccess || rc != 0) {
+            if (!cq->failed) {
+                cq->failed = true;
+                cq->fail_chunk = c;
+                cq->fail_rc = rc;
+                cq->fail_msg = e != hipSuccess ? hipGetErrorString(e) : "";
+            }
+        }
+        cq->consumed = c + 1;
+        cq->cv.notify_all();
+    }
+}
+
+extern "C" {
+
+cdvs_status cdvs_stream(cdvs_ctx* ctx, const uint8_t* d_images, int64_t chunk_stride, int32_t n_chunks,
+                        const cdvs_stream_buffers* buf, cdvs_chunk_consumer consumer, void* user, void* stream) {
+    if (!ctx) return CDVS_ERR_STATE;
+    if (!buf || !consumer || !d_images) return fail(ctx, CDVS_ERR_ARG, "cdvs_stream: null argument");
+    if (!buf->d_pyr || !buf->d_kp || !buf->d_count || !buf->d_kp_ori || !buf->d_count_ori || !buf->d_desc)
+        return fail(ctx, CDVS_ERR_ARG, "cdvs_stream: null device buffer");
+    for (int sl = 0; sl < 2; ++sl)
+        if (!buf->h_count[sl] || !buf->h_kp[sl] || !buf->h_desc[sl])
+            return fail(ctx, CDVS_ERR_ARG, "cdvs_stream: null host slot %d", sl);
+    const bool gated = buf->d_cnn_params != nullptr;
+    if (gated && (!buf->d_acts || !buf->d_mask || !(buf->tau > 0.f && buf->tau < 1.f)))
+        return fail(ctx, CDVS_ERR_ARG, "cdvs_stream: gating needs d_acts, d_mask and tau in (0, 1)");
+    if (n_chunks < 0) return fail(ctx, CDVS_ERR_ARG, "cdvs_stream: n_chunks < 0");
+    if (n_chunks > 1 && chunk_stride < images_extent(ctx))
+        return fail(ctx, CDVS_ERR_ARG, "cdvs_stream: chunk_stride %lld below the batch extent %lld",
+                    (long long)chunk_stride, (long long)images_extent(ctx));
+    if (n_chunks == 0) return CDVS_OK;
+
+    const int n = ctx->n, cap = ctx->kp_cap;
+    hipStream_t s = (hipStream_t)stream, cs = nullptr;
+    hipEvent_t done[2] = {}, copied[2] = {};
+    HIP_OR_FAIL(ctx, hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+    cdvs_status st = CDVS_OK;
+    for (int i = 0; i < 2 && st == CDVS_OK; ++i) {
+        if (hipEventCreateWithFlags(&done[i], hipEventDisableTiming) != hipSuccess ||
+            hipEventCreateWithFlags(&copied[i], hipEventDisableTiming) != hipSuccess)
+            st = fail(ctx, CDVS_ERR_HIP, "cdvs_stream: hipEventCreate failed");
+    }
+    ConsumerQueue cq;
+    std::thread host;
+    if (st == CDVS_OK) host = std::thread(consumer_loop, &cq, buf, copied, consumer, user, n, cap);
+
+    auto enq = [&](hipError_t e, const char* what) {
+        if (e != hipSuccess && st == CDVS_OK) st = fail(ctx, CDVS_ERR_HIP, "cdvs_stream: %s: %s", what, hipGetErrorString(e));
+    };
+    for (int c = 0; c < n_chunks && st == CDVS_OK; ++c) {
+        const uint8_t* imgs = d_images + (int64_t)c * chunk_stride;
+        const int slot = c & 1;
+        st = cdvs_pyramid(ctx, imgs, buf->d_pyr, s);
+        if (st == CDVS_OK && gated)
+            st = cdvs_cnn_forward(ctx, imgs, buf->d_cnn_params, buf->d_acts, nullptr, buf->d_mask, buf->tau, s);
+        if (st == CDVS_OK) st = cdvs_alp_detect(ctx, buf->d_pyr, gated ? buf->d_mask : nullptr, buf->d_kp, buf->d_count, s);
+        // the oriented keypoints and descriptors of chunk c-1 must have left the device
+        if (st == CDVS_OK && c > 0) enq(hipStreamWaitEvent(s, copied[slot ^ 1], 0), "wait for copy");
+        if (st == CDVS_OK) st = cdvs_orient(ctx, buf->d_pyr, buf->d_kp, buf->d_count, buf->d_kp_ori, buf->d_count_ori, s);
+        if (st == CDVS_OK) st = cdvs_describe(ctx, buf->d_pyr, buf->d_kp_ori, buf->d_count_ori, buf->d_desc, s);
+        if (st == CDVS_OK) enq(hipEventRecord(done[slot], s), "record");
+        if (st != CDVS_OK) break;
+        {   // host slot `slot` last held chunk c-2: wait until it has been consumed
+            std::unique_lock<std::mutex> lk(cq.mu);
+            cq.cv.wait(lk, [&] { return cq.consumed >= c - 1 || cq.failed; });
+            if (cq.failed) break;
+        }
+        enq(hipStreamWaitEvent(cs, done[slot], 0), "copy wait");
+        enq(hipMemcpyAsync(buf->h_count[slot], buf->d_count_ori, sizeof(int32_t) * n, hipMemcpyDeviceToHost, cs), "D2H");
+        enq(hipMemcpyAsync(buf->h_kp[slot], buf->d_kp_ori, sizeof(cdvs_keypoint) * n * cap, hipMemcpyDeviceToHost, cs),
+            "D2H");
+        enq(hipMemcpyAsync(buf->h_desc[slot], buf->d_desc, sizeof(float) * 128 * (int64_t)n * cap, hipMemcpyDeviceToHost,
+                           cs), "D2H");
+        enq(hipEventRecord(copied[slot], cs), "record");
+        if (st != CDVS_OK) break;
+        std::lock_guard<std::mutex> lk(cq.mu);
+        cq.q.push_back(c);
+        cq.cv.notify_all();
+    }
+    if (host.joinable()) {
+        {
+            std::lock_guard<std::mutex> lk(cq.mu);
+            cq.closed = true;
+            cq.cv.notify_all();
+        }
+        host.join();
+    }
+    // nothing may still be in flight into the caller's buffers when we return
+    (void)hipStreamSynchronize(s);
+    (void)hipStreamSynchronize(cs);
+    for (int i = 0; i < 2; ++i) {
+        if (done[i]) (void)hipEventDestroy(done[i]);
+        if (copied[i]) (void)hipEventDestroy(copied[i]);
+    }
+    (void)hipStreamDestroy(cs);
+    if (st != CDVS_OK) return st;
+    if (cq.failed) {
+        if (!cq.fail_msg.empty())
+            return fail(ctx, CDVS_ERR_HIP, "cdvs_stream: chunk %d copy: %s", cq.fail_chunk, cq.fail_msg.c_str());
+        return fail(ctx, CDVS_ERR_STATE, "cdvs_stream: consumer returned %d for chunk %d", cq.fail_rc, cq.fail_chunk);
+    }
+    return cdvs_sync_status(ctx, stream);
+}
+
+int32_t cdvs_standin_consume(void* user, int32_t chunk, int32_t n_images, int32_t kp_capacity, const int32_t* h_count,
+                             const cdvs_keypoint* h_kp, const float* h_desc) {
+    (void)h_kp;
+    const cdvs_standin_sink* sk = (const cdvs_standin_sink*)user;
+    if (!sk || !sk->out || !sk->kept || !h_count || !h_desc || n_images < 0 || kp_capacity < 1) return 1;
+    const int64_t first = (int64_t)chunk * n_images;
+    if (chunk < 0 || first + n_images > sk->total_images) return 2;
+    const int nt = std::max(1, std::min(sk->threads, std::max(1, n_images)));
+    auto work = [&](int t) {
+        for (int i = t; i < n_images; i += nt) {
+            const int m = std::max(0, std::min({h_count[i], sk->keep, kp_capacity}));
+            const float* src = h_desc + (int64_t)i * kp_capacity * 128;
+            uint8_t* dst = sk->out + (first + i) * kp_capacity * 128;
+            for (int64_t j = 0; j < (int64_t)m * 128; ++j) {
+                const float q = floorf(src[j] * 512.f + 0.5f);
+                dst[j] = (uint8_t)(q >= 255.f ? 255 : (q <= 0.f ? 0 : (int)q));
+            }
+            sk->kept[first + i] = m;
+        }
+    };
+    std::vector<std::thread> pool;
+    for (int t = 1; t < nt; ++t) pool.emplace_back(work, t);
+    work(0);
+    for (auto& th : pool) th.join();
+    return 0;
 }
 
 }  // extern "C"

@@ -44,6 +44,57 @@ def build() -> str:
     return _LIB
 
 
+_DEV_SRC = os.path.join(_HERE, "synth_dev.hip")
+_DEV_LIB = os.path.join(_HERE, "libsynth_dev.so")
+_dev = None
+
+
+def build_device() -> str:
+    """Compile the device twin libsynth_dev.so for gfx950 (always recompiles)."""
+    tmp = _DEV_LIB + ".tmp"
+    subprocess.check_call(["hipcc", "-O3", "-std=c++17", "-fPIC", "-shared", "--offload-arch=gfx950",
+                           "-ffp-contract=off", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+                           "-o", tmp, _DEV_SRC])
+    os.replace(tmp, _DEV_LIB)
+    return _DEV_LIB
+
+
+def _load_device():
+    global _dev
+    if _dev is None:
+        if not os.path.exists(_DEV_LIB):
+            raise RuntimeError(f"{_DEV_LIB} is missing: run synth.build_device()")
+        lib = ctypes.CDLL(_DEV_LIB)
+        lib.synth_dev_batch.restype = ctypes.c_int
+        lib.synth_dev_batch.argtypes = [ctypes.c_uint64, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                        ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_double,
+                                        ctypes.c_double, ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p]
+        _dev = lib
+    return _dev
+
+
+def device_batch(seed: int, n: int, width: int, height: int, nmin: int, nmax: int | None = None,
+                 smin: float = 2.0, smax: float = 20.0, amax: float = 80.0, first: int = 0,
+                 out=None, pitch: int | None = None, image_stride: int | None = None):
+    """Images first..first+n-1 rendered on the current GPU into `out` (a
+    uint8 torch tensor, allocated when None) on torch's current stream;
+    image i at byte i * image_stride, rows of `pitch` bytes.  Byte for byte
+    the host generator's output (fixed_batch: nmin = nmax = nblobs;
+    hires_batch: nmin..nmax)."""
+    import torch
+    pitch = pitch or width
+    image_stride = image_stride or pitch * height
+    if out is None:
+        out = torch.empty(n * image_stride, dtype=torch.uint8, device="cuda")
+    assert out.dtype == torch.uint8 and out.is_cuda and out.numel() >= n * image_stride
+    rc = _load_device().synth_dev_batch(seed, first, n, width, height, pitch, nmin,
+                                        nmin if nmax is None else nmax, smin, smax, amax, out.data_ptr(),
+                                        image_stride, torch.cuda.current_stream().cuda_stream)
+    if rc != 0:
+        raise ValueError(f"synth_dev_batch failed ({rc})")
+    return out
+
+
 def _load():
     global _lib
     if _lib is not None:
@@ -108,6 +159,24 @@ def fixed_batch(seed: int, n: int, width: int = 640, height: int = 480, nblobs: 
     def one(i):
         rc = lib.synth_image(seed, first + i, width, height, width, nblobs, smin, smax, amax,
                              out[i].ctypes.data)
+        if rc != 0:
+            raise ValueError("synth_image: bad arguments")
+
+    with ThreadPoolExecutor(_pool_size(n)) as ex:
+        list(ex.map(one, range(n)))
+    return out
+
+
+def hires_batch(seed: int, n: int, width: int = 1280, height: int = 960, nmin: int = 400, nmax: int = 1200,
+                smin: float = 2.0, smax: float = 40.0, amax: float = 80.0, first: int = 0) -> np.ndarray:
+    """n images of one size with a per-image blob count drawn from U{nmin..nmax}
+    (the high-resolution stream recipe), shape (n, height, width), uint8."""
+    out = np.empty((n, height, width), dtype=np.uint8)
+    lib = _load()
+
+    def one(i):
+        nb = lib.synth_blob_count(seed, first + i, nmin, nmax)
+        rc = lib.synth_image(seed, first + i, width, height, width, nb, smin, smax, amax, out[i].ctypes.data)
         if rc != 0:
             raise ValueError("synth_image: bad arguments")
 

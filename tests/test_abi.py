@@ -115,3 +115,28 @@ def test_tune_api_host_checks():
     assert L.cdvs_tune_get(None, cd.KERNEL_SCALES) == -1
     assert L.cdvs_tune_set(None, cd.KERNEL_SCALES, 0) == cd.CDVS_ERR_STATE
     assert L.cdvs_autotune(None, None, None, None, None) == cd.CDVS_ERR_STATE
+
+
+def test_standin_consumer_on_host():
+    """The stand-in consumer is host code: check its coding and bounds."""
+    import numpy as np
+    L = cd.lib()
+    n, cap = 3, 5
+    rng = np.random.default_rng(2)
+    desc = rng.uniform(0, 0.6, size=(n, cap, 128)).astype(np.float32)
+    desc[0, 0, :4] = [0.0, 255.5 / 512, 254.5 / 512, 1.0]
+    counts = np.array([5, 2, 0], dtype=np.int32)
+    out = np.zeros((2 * n, cap, 128), dtype=np.uint8)
+    kept = np.full(2 * n, -1, dtype=np.int32)
+    sink = cd.StandinSink(out.ctypes.data, kept.ctypes.data, 2 * n, 4, 2)
+    rc = L.cdvs_standin_consume(ctypes.addressof(sink), 1, n, cap, counts.ctypes.data, None, desc.ctypes.data)
+    assert rc == 0
+    assert list(kept) == [-1, -1, -1, 4, 2, 0]
+    q = np.clip(np.floor(desc * np.float32(512) + np.float32(0.5)), 0, 255).astype(np.uint8)
+    np.testing.assert_array_equal(out[3, :4], q[0, :4])
+    np.testing.assert_array_equal(out[4, :2], q[1, :2])
+    assert out[3, 4].max() == 0 and out[5].max() == 0 and out[:3].max() == 0
+    assert list(out[3, 0, :4]) == [0, 255, 255, 255]
+    # a chunk past the sink's size is refused
+    assert L.cdvs_standin_consume(ctypes.addressof(sink), 2, n, cap, counts.ctypes.data, None, desc.ctypes.data) != 0
+    assert L.cdvs_stream(None, None, 0, 0, None, None, None, None) == cd.CDVS_ERR_STATE

@@ -1,0 +1,124 @@
+"""High-resolution streaming (1280x960, 6 octaves) on the GPU.
+
+* One 1280x960 image of the stream recipe against the fp32 oracle, to the
+  same bars as the 640x480 parity tests.
+* cdvs_stream over several chunks (so both pinned host slots are reused)
+  gives, chunk by chunk, what the eager calls give on the same chunk: the
+  stand-in consumer's u8 codes are recomputed from the eager descriptors
+  with the same fp32 rounding and must match exactly, plain and gated.
+* A consumer that fails stops the stream with CDVS_ERR_STATE (forced from
+  the host; every kernel still completes).
+"""
+import ctypes
+
+import numpy as np
+import pytest
+
+import synth
+from parity import rates
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+import paper_1705_09776_amd as cd  # noqa: E402
+from paper_1705_09776_amd import surrogate  # noqa: E402
+
+W, H = 1280, 960
+CHUNK = 4
+NCHUNK = 3
+
+
+@pytest.fixture(scope="module")
+def hires():
+    return synth.hires_batch(synth.SEED_HIRES, CHUNK * NCHUNK)
+
+
+def _codes(desc):
+    q = np.floor(desc.astype(np.float32) * np.float32(512) + np.float32(0.5))
+    return np.clip(q, 0, 255).astype(np.uint8)
+
+
+def test_hires_image_matches_oracle(hires, O32):
+    img = hires[0]
+    pipe = cd.Pipeline([(W, H)])
+    pipe.upload([img])
+    pipe.run()
+    torch.cuda.synchronize()
+    assert pipe.sync_status() == cd.CDVS_OK
+    assert pipe.num_octaves(0) == 6
+    kp, desc, _ = O32.run(img)
+    got, gdesc = pipe.oriented()[0], pipe.descriptors()[0]
+    r1, r2, pairs = rates(kp, got, oriented=True)
+    err = np.array([np.abs(desc[i] - gdesc[j]).max() for i, j in pairs])
+    print(f"1280x960: oriented match {r1:.4f}/{r2:.4f}, desc<=1e-3 {np.mean(err <= 1e-3):.4f}, max {err.max():.2e}")
+    assert len(got) == len(kp) == 1000
+    assert min(r1, r2) >= 0.99
+    assert err.max() <= 5e-2 and err.mean() <= 1e-3
+
+
+def _eager(pipe, chunks, params=None, tau=0.1):
+    out = []
+    for imgs in chunks:
+        pipe.upload(imgs)
+        if params is None:
+            pipe.run()
+        else:
+            pipe.run_gated(params, tau)
+        torch.cuda.synchronize()
+        out.append((pipe.d_count_ori.cpu().numpy().copy(), [d.copy() for d in pipe.descriptors()]))
+    return out
+
+
+@pytest.mark.parametrize("gated", [False, True])
+def test_stream_equals_eager(hires, gated):
+    pipe = cd.Pipeline([(W, H)] * CHUNK)
+    chunks = [hires[c * CHUNK:(c + 1) * CHUNK] for c in range(NCHUNK)]
+    params = torch.from_numpy(surrogate.init_params(3)).cuda() if gated else None
+    tau = 0.3
+    if gated:
+        # a threshold that leaves roughly 40% of the (cell, octave) entries active
+        pipe.upload(chunks[0])
+        pipe.cnn_forward(params, tau=None, logits=True)
+        z = pipe.d_logits.cpu().numpy()[:, :6].astype(np.float64)
+        tau = float(1.0 / (1.0 + np.exp(-np.quantile(z, 0.6))))
+    ref = _eager(pipe, chunks, params, tau=tau)
+    d_all = torch.empty(NCHUNK * pipe.image_bytes, dtype=torch.uint8, device="cuda")
+    for c, imgs in enumerate(chunks):
+        d_all[c * pipe.image_bytes:(c + 1) * pipe.image_bytes].copy_(torch.from_numpy(pipe.pack(imgs)))
+    for t in (pipe.d_kp_ori, pipe.d_desc):
+        t.zero_()
+    codes, kept = pipe.stream(d_all, NCHUNK, params=params, tau=tau, threads=3)
+    assert sum(int(r[0].sum()) for r in ref) > 0
+    for c in range(NCHUNK):
+        counts, descs = ref[c]
+        for i in range(CHUNK):
+            g = c * CHUNK + i
+            assert kept[g] == counts[i], (c, i)
+            np.testing.assert_array_equal(codes[g, :counts[i]], _codes(descs[i]), err_msg=f"chunk {c} image {i}")
+
+
+def test_stream_consumer_failure_stops(hires):
+    pipe = cd.Pipeline([(W, H)] * 2)
+    d_all = torch.empty(3 * pipe.image_bytes, dtype=torch.uint8, device="cuda")
+    for c in range(3):
+        d_all[c * pipe.image_bytes:(c + 1) * pipe.image_bytes].copy_(
+            torch.from_numpy(pipe.pack(hires[2 * c:2 * c + 2])))
+    seen = []
+
+    def consume(user, chunk, n, cap, h_count, h_kp, h_desc):
+        seen.append(chunk)
+        return 7 if chunk == 1 else 0
+
+    fn = cd.CHUNK_CONSUMER(consume)
+    with pytest.raises(cd.CdvsError) as e:
+        pipe.stream(d_all, 3, consumer=fn, user=None)
+    assert e.value.status == cd.CDVS_ERR_STATE
+    assert seen == [0, 1]
+    # the context is still usable
+    pipe.upload(list(hires[:2]))
+    pipe.run()
+    torch.cuda.synchronize()
+    assert pipe.sync_status() == cd.CDVS_OK
