@@ -240,9 +240,11 @@ cdvs_status cdvs_tune_set(cdvs_ctx* ctx, int32_t kernel, int32_t variant);
 int64_t cdvs_cnn_cells(const cdvs_ctx* ctx);
 cdvs_status cdvs_cnn_cell_layout(const cdvs_ctx* ctx, int32_t image, int64_t* cell0, int32_t* w4, int32_t* h4);
 
-/* Forward pass on the packed u8 images.  d_acts (caller scratch, required):
- * CDVS_CNN_LAYERS x cells x 16 bf16 (uint16), receives every layer's output
- * (kept for cdvs_cnn_backward).  d_logits (may be NULL): cells x 6 fp32.
+/* Forward pass on the packed u8 images.  d_acts (caller scratch, 8-byte
+ * aligned): CDVS_CNN_LAYERS x cells x 16 bf16 (uint16), receives every
+ * layer's output (kept for cdvs_cnn_backward); with d_acts NULL a fused
+ * inference kernel keeps all activations on chip and only the outputs below
+ * are written (same values).  d_logits (may be NULL): cells x 6 fp32.
  * d_mask (may be NULL): cells bytes, bit o = sigmoid(Z_o) > tau, only for
  * octaves the image has.  tau in (0, 1). */
 cdvs_status cdvs_cnn_forward(cdvs_ctx* ctx, const uint8_t* d_images, const float* d_params, uint16_t* d_acts,
@@ -278,8 +280,9 @@ cdvs_status cdvs_cnn_adam(cdvs_ctx* ctx, float* d_params, const float* d_grad, f
  * cdvs_stream processes n_chunks batches whose packed images lie at
  * d_images + c * chunk_stride (each laid out as the context's image table
  * says; chunk_stride >= the table's extent).  Per chunk, on `stream`:
- * cdvs_pyramid, then (d_cnn_params != NULL) cdvs_cnn_forward into d_acts and
- * d_mask with threshold tau and a gated cdvs_alp_detect, else the plain one,
+ * cdvs_pyramid, then (d_cnn_params != NULL) cdvs_cnn_forward (d_acts, which
+ * may be NULL) into d_mask with threshold tau and a gated cdvs_alp_detect,
+ * else the plain one,
  * then cdvs_orient and cdvs_describe.  On an internal copy stream the counts,
  * oriented keypoints and descriptors are copied into pinned host slot c % 2
  * (caller-owned, from hipHostMalloc: n counts, n x kp_capacity keypoints,
@@ -298,7 +301,7 @@ typedef struct {
     int32_t* d_count_ori;         /* n */
     float* d_desc;                /* n x kp_capacity x 128 */
     const float* d_cnn_params;    /* NULL: plain detection */
-    uint16_t* d_acts;             /* CDVS_CNN_LAYERS x cells x 16 (gated only) */
+    uint16_t* d_acts;             /* NULL (fused inference) or CDVS_CNN_LAYERS x cells x 16 */
     uint8_t* d_mask;              /* cells (gated only) */
     float tau;                    /* mask threshold (gated only) */
     int32_t* h_count[2];          /* pinned host double buffers */

@@ -390,7 +390,7 @@ class Pipeline:
         b.d_kp_ori, b.d_count_ori, b.d_desc = _ptr(self.d_kp_ori), _ptr(self.d_count_ori), _ptr(self.d_desc)
         if params is not None:
             self.cnn_buffers()
-            b.d_cnn_params, b.d_acts, b.d_mask, b.tau = _ptr(params), _ptr(self.d_acts), _ptr(self.d_mask), tau
+            b.d_cnn_params, b.d_acts, b.d_mask, b.tau = _ptr(params), None, _ptr(self.d_mask), tau
         for i in range(2):
             b.h_count[i], b.h_kp[i], b.h_desc[i] = (_ptr(x) for x in self._slots[i])
         result = None
@@ -426,14 +426,18 @@ class Pipeline:
             self.d_mask = t.empty(self.ncells, dtype=t.uint8, device=dev)
         return self.d_acts
 
-    def cnn_forward(self, params, tau=None, logits=True, stream=None):
+    def cnn_forward(self, params, tau=None, logits=True, stream=None, keep_acts=True):
+        """keep_acts: store every layer's activations (training); otherwise
+        the fused inference kernel runs."""
         self.cnn_buffers()
-        cdvs_cnn_forward(self.ctx, self.d_images, params, self.d_acts, self.d_logits if logits else None,
-                         self.d_mask if tau is not None else None, 0.5 if tau is None else tau, stream)
+        cdvs_cnn_forward(self.ctx, self.d_images, params, self.d_acts if keep_acts else None,
+                         self.d_logits if logits else None, self.d_mask if tau is not None else None,
+                         0.5 if tau is None else tau, stream)
 
     def run_gated(self, params, tau, stream=None):
-        """CNN mask -> pyramid -> gated detection -> orientation -> descriptors."""
-        self.cnn_forward(params, tau=tau, logits=False, stream=stream)
+        """CNN mask (fused inference) -> pyramid -> gated detection ->
+        orientation -> descriptors."""
+        self.cnn_forward(params, tau=tau, logits=False, stream=stream, keep_acts=False)
         self.pyramid(stream)
         self.detect(stream, mask=self.d_mask)
         self.orient(stream)

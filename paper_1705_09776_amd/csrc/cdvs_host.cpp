@@ -44,11 +44,17 @@ struct cdvs_ctx {
     // surrogate CNN cell grid
     std::vector<CnnImage> cnn;
     int64_t ncells = 0;
-    int cnn_tiles = 0, cnn_chunks = 0;
+    int cnn_tiles = 0, cnn_chunks = 0, cnn_ftiles = 0;
     CnnImage* d_cnn = nullptr;
     int32_t* d_active = nullptr;  // [n][kMaxOctaves] active mask cells
+    short* d_cnn_frag = nullptr;  // packed weight fragments of the fused inference kernel
+    uint64_t* d_gate_rows = nullptr;  // [detection tile][16] active-centre rows (gated detection)
+    int32_t* d_gate_state = nullptr;  // [detection tile] skip / sparse / dense
     // device
     OctJob* d_jobs = nullptr;
+    std::vector<DetTile> dtiles;               // detection tiles, grouped by octave
+    int dtile_start[kMaxOctaves + 1] = {};
+    DetTile* d_dtiles = nullptr;
     OctGeom* d_geom = nullptr;
     cdvs_keypoint* d_cand = nullptr;
     int32_t* d_cand_cnt = nullptr;
@@ -255,6 +261,7 @@ void cdvs_ctx_destroy(cdvs_ctx* ctx) {
     if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
     for (auto& e : ctx->ev) (void)hipEventDestroy(e);
     (void)hipFree(ctx->d_jobs);
+    (void)hipFree(ctx->d_dtiles);
     (void)hipFree(ctx->d_geom);
     (void)hipFree(ctx->d_cand);
     (void)hipFree(ctx->d_cand_cnt);
@@ -263,6 +270,9 @@ void cdvs_ctx_destroy(cdvs_ctx* ctx) {
     (void)hipFree(ctx->d_flags);
     (void)hipFree(ctx->d_cnn);
     (void)hipFree(ctx->d_active);
+    (void)hipFree(ctx->d_cnn_frag);
+    (void)hipFree(ctx->d_gate_rows);
+    (void)hipFree(ctx->d_gate_state);
     delete ctx;
 }
 
@@ -329,11 +339,33 @@ static cdvs_status build_layout(cdvs_ctx* c) {
         for (int v = 0; v < kBlurVariants; ++v) c->blur_tiles[v][o] = tb[v];
         c->det_tiles[o] = td;
     }
+    c->dtiles.clear();
+    for (int o = 0; o < kMaxOctaves; ++o) {
+        c->dtile_start[o] = (int)c->dtiles.size();
+        for (const OctJob& j : per_oct[o]) {
+            const int ty_n = (j.h + kDetTH - 1) / kDetTH;
+            for (int t = 0; t < j.tiles_x_det * ty_n; ++t) {
+                DetTile r;
+                memset(&r, 0, sizeof(r));
+                r.plane0 = j.plane0;
+                r.plane_stride = j.plane_stride;
+                r.pitch = j.pitch;
+                r.w = j.w;
+                r.h = j.h;
+                r.tx0 = (t % j.tiles_x_det) * kDetTW;
+                r.ty0 = (t / j.tiles_x_det) * kDetTH;
+                r.image = j.image;
+                r.octave = j.octave;
+                c->dtiles.push_back(r);
+            }
+        }
+    }
+    c->dtile_start[kMaxOctaves] = (int)c->dtiles.size();
     c->job_start[kMaxOctaves] = (int)c->jobs.size();
     // surrogate CNN cells: 4x4-pixel cells of each base image
     c->cnn.assign(c->n, CnnImage{});
     int64_t cell = 0;
-    int tiles = 0, chunks = 0;
+    int tiles = 0, chunks = 0, ftiles = 0;
     for (int i = 0; i < c->n; ++i) {
         const cdvs_image_desc& d = c->images[i];
         CnnImage& g = c->cnn[i];
@@ -348,6 +380,9 @@ static cdvs_status build_layout(cdvs_ctx* c) {
         g.tiles_x = (g.W4 + kCnnTileW - 1) / kCnnTileW;
         g.tile0 = tiles;
         g.chunk0 = chunks;
+        g.ftiles_x = (g.W4 + kCnnFusedW - 1) / kCnnFusedW;
+        g.ftile0 = ftiles;
+        ftiles += g.ftiles_x * ((g.H4 + kCnnFusedH - 1) / kCnnFusedH);
         tiles += g.tiles_x * ((g.H4 + kCnnTileH - 1) / kCnnTileH);
         chunks += g.tiles_x * g.H4;
         cell += (int64_t)g.H4 * g.W4;
@@ -355,6 +390,7 @@ static cdvs_status build_layout(cdvs_ctx* c) {
     c->ncells = cell;
     c->cnn_tiles = tiles;
     c->cnn_chunks = chunks;
+    c->cnn_ftiles = ftiles;
     return CDVS_OK;
 }
 
@@ -421,6 +457,7 @@ cdvs_status cdvs_ctx_create(const cdvs_params* params, const cdvs_image_desc* im
         }                                                                        \
     } while (0)
     ALLOC(c->d_jobs, sizeof(OctJob) * std::max<size_t>(1, c->jobs.size()));
+    ALLOC(c->d_dtiles, sizeof(DetTile) * std::max<size_t>(1, c->dtiles.size()));
     ALLOC(c->d_geom, sizeof(OctGeom) * c->geom.size());
     ALLOC(c->d_cand, sizeof(cdvs_keypoint) * n * kCandCap);
     ALLOC(c->d_cand_cnt, sizeof(int32_t) * n);
@@ -429,8 +466,13 @@ cdvs_status cdvs_ctx_create(const cdvs_params* params, const cdvs_image_desc* im
     ALLOC(c->d_flags, sizeof(int32_t));
     ALLOC(c->d_cnn, sizeof(CnnImage) * n);
     ALLOC(c->d_active, sizeof(int32_t) * n * kMaxOctaves);
+    ALLOC(c->d_cnn_frag, sizeof(short) * kCnnFragShorts);
+    ALLOC(c->d_gate_rows, sizeof(uint64_t) * kDetTH * std::max<size_t>(1, c->dtiles.size()));
+    ALLOC(c->d_gate_state, sizeof(int32_t) * std::max<size_t>(1, c->dtiles.size()));
 #undef ALLOC
     if ((e = hipMemcpy(c->d_jobs, c->jobs.data(), sizeof(OctJob) * c->jobs.size(), hipMemcpyHostToDevice)) != hipSuccess ||
+        (e = hipMemcpy(c->d_dtiles, c->dtiles.data(), sizeof(DetTile) * c->dtiles.size(), hipMemcpyHostToDevice)) !=
+            hipSuccess ||
         (e = hipMemcpy(c->d_geom, c->geom.data(), sizeof(OctGeom) * c->geom.size(), hipMemcpyHostToDevice)) != hipSuccess ||
         (e = hipMemcpy(c->d_cnn, c->cnn.data(), sizeof(CnnImage) * n, hipMemcpyHostToDevice)) != hipSuccess ||
         (e = hipMemset(c->d_flags, 0, sizeof(int32_t))) != hipSuccess ||
@@ -497,11 +539,13 @@ cdvs_status cdvs_alp_detect(cdvs_ctx* ctx, const float* d_pyr, const uint8_t* d_
     if (!ctx) return CDVS_ERR_STATE;
     if (!d_pyr || !d_kp || !d_count) return fail(ctx, CDVS_ERR_ARG, "cdvs_alp_detect: null device pointer");
     hipStream_t s = (hipStream_t)stream;
-    GateParams gate{nullptr, nullptr, nullptr, 1.f};
+    GateParams gate{nullptr, nullptr, nullptr, 1.f, nullptr, nullptr};
     if (d_mask) {
         Bracket b(ctx, CDVS_KERNEL_MASK_COUNT, s);
         HIP_OR_FAIL(ctx, launch_mask_count(d_mask, ctx->d_cnn, ctx->n, ctx->d_active, s));
-        gate = GateParams{d_mask, ctx->d_active, ctx->d_cnn, ctx->params.mask_fmax};
+        gate = GateParams{d_mask, ctx->d_active, ctx->d_cnn, ctx->params.mask_fmax, ctx->d_gate_rows, ctx->d_gate_state};
+        HIP_OR_FAIL(ctx, launch_gate_rows(ctx->d_dtiles, (int)ctx->dtiles.size(), ctx->det, gate, ctx->d_gate_rows,
+                                          ctx->d_gate_state, s));
     }
     {
         Bracket b(ctx, CDVS_KERNEL_CLEAR, s);
@@ -509,8 +553,13 @@ cdvs_status cdvs_alp_detect(cdvs_ctx* ctx, const float* d_pyr, const uint8_t* d_
     }
     for (int o = 0; o < ctx->max_oct; ++o) {
         Bracket b(ctx, CDVS_KERNEL_DETECT, s);
-        HIP_OR_FAIL(ctx, launch_detect(d_pyr, ctx->d_jobs + ctx->job_start[o], ctx->job_start[o + 1] - ctx->job_start[o],
-                                       ctx->det_tiles[o], ctx->detect_grid, ctx->det, gate, ctx->d_cand,
+        GateParams go = gate;
+        if (go.mask) {
+            go.rows += (int64_t)kDetTH * ctx->dtile_start[o];
+            go.state += ctx->dtile_start[o];
+        }
+        HIP_OR_FAIL(ctx, launch_detect(d_pyr, ctx->d_dtiles + ctx->dtile_start[o], ctx->det_tiles[o],
+                                       ctx->detect_grid, ctx->det, go, ctx->d_cand,
                                        ctx->d_cand_cnt, ctx->d_flags, s));
     }
     {
@@ -579,12 +628,18 @@ cdvs_status cdvs_cnn_cell_layout(const cdvs_ctx* ctx, int32_t image, int64_t* ce
 cdvs_status cdvs_cnn_forward(cdvs_ctx* ctx, const uint8_t* d_images, const float* d_params, uint16_t* d_acts,
                              float* d_logits, uint8_t* d_mask, float tau, void* stream) {
     if (!ctx) return CDVS_ERR_STATE;
-    if (!d_images || !d_params || !d_acts) return fail(ctx, CDVS_ERR_ARG, "cdvs_cnn_forward: null device pointer");
+    if (!d_images || !d_params) return fail(ctx, CDVS_ERR_ARG, "cdvs_cnn_forward: null device pointer");
     if (d_mask && !(tau > 0.f && tau < 1.f)) return fail(ctx, CDVS_ERR_ARG, "cdvs_cnn_forward: tau must be in (0, 1)");
     if (((uintptr_t)d_acts & 7) != 0) return fail(ctx, CDVS_ERR_ARG, "cdvs_cnn_forward: d_acts not 8-byte aligned");
     const float zthr = d_mask ? logf(tau / (1.f - tau)) : 0.f;
     hipStream_t s = (hipStream_t)stream;
     Bracket b(ctx, CDVS_KERNEL_CNN_FORWARD, s);
+    if (!d_acts) {
+        if (!d_logits && !d_mask) return CDVS_OK;
+        HIP_OR_FAIL(ctx, launch_cnn_infer(d_images, d_params, ctx->d_cnn_frag, ctx->d_cnn, ctx->n, ctx->cnn_ftiles,
+                                          d_logits, d_mask, zthr, s));
+        return CDVS_OK;
+    }
     HIP_OR_FAIL(ctx, launch_cnn_forward(d_images, d_params, (short*)d_acts, ctx->ncells, ctx->d_cnn, ctx->n,
                                         ctx->cnn_tiles, d_logits, d_mask, zthr, s));
     return CDVS_OK;
@@ -879,8 +934,8 @@ cdvs_status cdvs_stream(cdvs_ctx* ctx, const uint8_t* d_images, int64_t chunk_st
         if (!buf->h_count[sl] || !buf->h_kp[sl] || !buf->h_desc[sl])
             return fail(ctx, CDVS_ERR_ARG, "cdvs_stream: null host slot %d", sl);
     const bool gated = buf->d_cnn_params != nullptr;
-    if (gated && (!buf->d_acts || !buf->d_mask || !(buf->tau > 0.f && buf->tau < 1.f)))
-        return fail(ctx, CDVS_ERR_ARG, "cdvs_stream: gating needs d_acts, d_mask and tau in (0, 1)");
+    if (gated && (!buf->d_mask || !(buf->tau > 0.f && buf->tau < 1.f)))
+        return fail(ctx, CDVS_ERR_ARG, "cdvs_stream: gating needs d_mask and tau in (0, 1)");
     if (n_chunks < 0) return fail(ctx, CDVS_ERR_ARG, "cdvs_stream: n_chunks < 0");
     if (n_chunks > 1 && chunk_stride < images_extent(ctx))
         return fail(ctx, CDVS_ERR_ARG, "cdvs_stream: chunk_stride %lld below the batch extent %lld",

@@ -49,6 +49,19 @@ struct OctJob {
     int32_t tiles_x_det, tile0_det;    // tiling of the detection kernel
 };
 
+// One detection tile: everything the detection kernels need to stage and
+// label it, so that a tile costs one record load (no job search).
+struct DetTile {
+    int64_t plane0;        // float offset of G_{o,0}
+    int32_t plane_stride;  // floats between G_{o,k} and G_{o,k+1}
+    int32_t pitch;         // floats
+    int32_t w, h;          // octave size
+    int32_t tx0, ty0;      // tile origin (octave pixels)
+    int32_t image, octave;
+    int32_t pad[2];
+};
+static_assert(sizeof(DetTile) == 48, "DetTile is three 16-byte chunks");
+
 // Per-image octave geometry for the keypoint kernels.
 struct OctGeom {
     int64_t plane0;
@@ -100,6 +113,7 @@ constexpr int kFlagCandOverflow = 1;
 constexpr int kCnnChannels = 16, kCnnHeads = 6, kCnnLayers = 4;
 constexpr int kCnnParams = kCnnLayers * (9 * 16 * 16 + 16) + 16 * 6 + 6;  // 9382
 constexpr int kCnnTileW = 16, kCnnTileH = 4;  // cells per conv workgroup
+constexpr int kCnnFusedW = 32, kCnnFusedH = 16;  // output cells per fused-inference workgroup
 struct CnnImage {
     int64_t cell0;     // first cell of the image in the batch's cell arrays
     int64_t src;       // byte offset of the u8 image
@@ -109,7 +123,8 @@ struct CnnImage {
     int32_t tiles_x;   // 16-cell segments per row
     int32_t tile0;     // first conv tile (16 x 4 cells) of the image
     int32_t chunk0;    // first 16-cell row chunk of the image
-    int32_t pad;
+    int32_t ftiles_x;  // fused-inference tiles (kCnnFusedW x kCnnFusedH cells) per row
+    int32_t ftile0;    // first fused-inference tile of the image
 };
 
 // Gating of detection by a cell mask.
@@ -118,7 +133,10 @@ struct GateParams {
     const int32_t* active;   // [image][kMaxOctaves] active cells of the mask
     const CnnImage* cells;   // per image cell grid
     float fmax;              // fraction of active cells above which detection is dense
+    const uint64_t* rows;    // per detection tile: 16 active-centre row masks (k_gate_rows)
+    const int32_t* state;    // per detection tile: kTileSkip, kTileSparse or kTileDense
 };
+constexpr int kTileSkip = 0, kTileSparse = 1, kTileDense = 2;
 
 // Kernel tile shapes.
 // Scale-plane kernel tile variants (width x height, autotuned); the
@@ -135,7 +153,9 @@ hipError_t launch_preblur(const uint8_t* images, float* pyr, const OctJob* jobs,
 hipError_t launch_scales(float* pyr, const OctJob* jobs, int njobs, int ntiles, int variant, const Taps& taps,
                          hipStream_t stream);
 hipError_t launch_clear(int32_t* p, int n, hipStream_t stream);
-hipError_t launch_detect(const float* pyr, const OctJob* jobs, int njobs, int ntiles, int grid, const DetParams& dp,
+hipError_t launch_gate_rows(const DetTile* tiles, int ntiles, const DetParams& dp, const GateParams& gate,
+                            uint64_t* rows, int32_t* state, hipStream_t stream);
+hipError_t launch_detect(const float* pyr, const DetTile* tiles, int ntiles, int grid, const DetParams& dp,
                          const GateParams& gate, cdvs_keypoint* cand, int32_t* cand_cnt, int32_t* flags,
                          hipStream_t stream);
 hipError_t launch_finalize(const cdvs_keypoint* cand, const int32_t* cand_cnt, int n_images, int cand_cap,
@@ -150,6 +170,9 @@ hipError_t launch_orient_compact(const cdvs_keypoint* ori, const int32_t* ori_cn
 hipError_t launch_describe(const float* pyr, const OctGeom* geom, const cdvs_keypoint* kp, const int32_t* count,
                            int n_images, const DescParams& dp, float* desc, hipStream_t stream);
 
+constexpr int kCnnFragShorts = kCnnLayers * 9 * 64 * 4;   // packed MFMA weight fragments
+hipError_t launch_cnn_infer(const uint8_t* images, const float* params, short* frag, const CnnImage* imgs, int nimg,
+                            int ntiles, float* logits, uint8_t* mask, float zthr, hipStream_t s);
 hipError_t launch_cnn_forward(const uint8_t* images, const float* params, short* acts, int64_t ncells,
                               const CnnImage* imgs, int nimg, int ntiles, float* logits, uint8_t* mask, float zthr,
                               hipStream_t s);

@@ -155,6 +155,163 @@ __global__ __launch_bounds__(256) void k_head(const short* __restrict__ X4, cons
     }
 }
 
+// Fused inference: the four convolutions and the head for a 32 x 16 block of
+// output cells in one workgroup, with every activation kept in LDS (no
+// activation goes to HBM).  The workgroup stages the s2d input over the block
+// plus a 4-cell halo (one cell per layer) and each layer writes its output
+// over a region one cell smaller on every side, so the last layer covers
+// exactly the block.  Cells outside the image are written as zeros at every
+// layer, which is the zero padding of each convolution.  The arithmetic is
+// the unfused kernels' (same fragments, same MFMA order, same bf16
+// roundings), so logits and mask bits are identical to theirs.
+constexpr int FTW = kCnnFusedW, FTH = kCnnFusedH, FHALO = kCnnLayers;
+constexpr int FFW = FTW + 2 * FHALO, FFH = FTH + 2 * FHALO;   // 40 x 24 frame
+constexpr int FSTR = CC + 4;                                   // shorts per cell (40 B: spreads LDS banks)
+
+__device__ __forceinline__ int find_ftile_image(const CnnImage* im, int n, int tile) {
+    int lo = 0, hi = n - 1;
+    while (lo < hi) {
+        int mid = (lo + hi + 1) >> 1;
+        if (im[mid].ftile0 <= tile) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+// MFMA weight fragments of all layers, packed once per forward call:
+// frag[((l * 9 + t) * 64 + lane) * 4 + j] = bf16(W_l[t][4 (lane / 16) + j][lane % 16]),
+// exactly the A operand each lane of k_conv_fwd builds for itself.
+__global__ void k_cnn_pack(const float* __restrict__ P, short* __restrict__ frag) {
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < kCnnLayers * 9 * 64; i += gridDim.x * blockDim.x) {
+        const int lane = i % 64, t = (i / 64) % 9, l = i / (64 * 9);
+        const int kb = lane >> 4, n16 = lane & 15;
+        const float* Wl = P + l * LAYER_P;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) frag[i * 4 + j] = f2bf(Wl[(t * CC + 4 * kb + j) * CC + n16]);
+    }
+}
+
+constexpr int FSTAGE = FFH * FFW * 4 / 256;   // 4-pixel cell rows staged per lane
+static_assert(FFH * FFW * 4 % 256 == 0, "the frame's cell rows split evenly over the lanes");
+
+__global__ __launch_bounds__(256, 2) void k_cnn_infer(const uint8_t* __restrict__ images, const float* __restrict__ P,
+                                                      const short* __restrict__ frag,
+                                                      const CnnImage* __restrict__ imgs, int nimg,
+                                                      float* __restrict__ logits, uint8_t* __restrict__ mask,
+                                                      float zthr) {
+    __shared__ __align__(16) short buf[2][FFH * FFW * FSTR];
+    __shared__ short lut[256];
+    __shared__ float head[CC * NHD + NHD];
+    const int tile = xcd_remap(blockIdx.x, gridDim.x);
+    const CnnImage& g = imgs[find_ftile_image(imgs, nimg, tile)];
+    const int lt = tile - g.ftile0;
+    const int ty0 = (lt / g.ftiles_x) * FTH, tx0 = (lt % g.ftiles_x) * FTW;
+    const int oy = ty0 - FHALO, ox = tx0 - FHALO;   // image cell of frame (0, 0)
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, kb = lane >> 4;
+
+    // u8 -> bf16(u / 255) table (the same expression as s2d_frag)
+    lut[threadIdx.x] = f2bf((float)threadIdx.x / 255.f);
+    for (int i = threadIdx.x; i < CC * NHD + NHD; i += blockDim.x) head[i] = P[kCnnLayers * LAYER_P + i];
+    // layer 0 input: s2d of the frame, zero outside the image.  Lanes take
+    // consecutive cells of one pixel row (contiguous 4-byte groups); all
+    // loads are issued before the first conversion.
+    uint32_t px[FSTAGE];
+#pragma unroll
+    for (int k = 0; k < FSTAGE; ++k) {
+        const int it = threadIdx.x + k * 256;
+        const int fx = it % FFW, r4 = (it / FFW) & 3, fy = it / (FFW * 4);
+        const int cy = oy + fy, cx = ox + fx;
+        px[k] = 0;
+        if (cy >= 0 && cy < g.H4 && cx >= 0 && cx < g.W4) {
+            const int y = min(4 * cy + r4, g.H - 1);
+            const uint8_t* row = images + g.src + (int64_t)y * g.src_pitch;
+            const int x0 = 4 * cx;
+            if (x0 + 3 < g.W && ((uintptr_t)(row + x0) & 3) == 0) {
+                px[k] = *reinterpret_cast<const uint32_t*>(row + x0);
+            } else {
+#pragma unroll
+                for (int j = 0; j < 4; ++j) px[k] |= (uint32_t)row[min(x0 + j, g.W - 1)] << (8 * j);
+            }
+        }
+    }
+    __syncthreads();   // lut
+#pragma unroll
+    for (int k = 0; k < FSTAGE; ++k) {
+        const int it = threadIdx.x + k * 256;
+        const int fx = it % FFW, r4 = (it / FFW) & 3, fy = it / (FFW * 4);
+        const int cy = oy + fy, cx = ox + fx;
+        s4 v = {0, 0, 0, 0};
+        if (cy >= 0 && cy < g.H4 && cx >= 0 && cx < g.W4) {
+#pragma unroll
+            for (int j = 0; j < 4; ++j) v[j] = lut[(px[k] >> (8 * j)) & 255u];
+        }
+        *reinterpret_cast<s4*>(&buf[0][(fy * FFW + fx) * FSTR + 4 * r4]) = v;
+    }
+    s4 a[9];
+    const s4* fr = reinterpret_cast<const s4*>(frag);
+#pragma unroll
+    for (int t = 0; t < 9; ++t) a[t] = fr[t * 64 + lane];
+    __syncthreads();
+
+#pragma unroll 1
+    for (int l = 0; l < kCnnLayers; ++l) {
+        f4 bias;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) bias[r] = P[l * LAYER_P + CONV_W + 4 * kb + r];
+        // the next layer's fragments load while this layer computes
+        s4 an[9];
+        const int ln = l + 1 < kCnnLayers ? l + 1 : l;
+#pragma unroll
+        for (int t = 0; t < 9; ++t) an[t] = fr[(ln * 9 + t) * 64 + lane];
+        const short* X = buf[l & 1];
+        short* Y = buf[(l + 1) & 1];
+        const int lo = l + 1, C = FFW - 2 * lo, n = (FFH - 2 * lo) * C;
+        for (int q0 = wave * 16; q0 < n; q0 += 64) {
+            const int q = min(q0 + (lane & 15), n - 1);
+            const int fy = lo + q / C, fx = lo + q % C;
+            f4 acc = bias;
+#pragma unroll
+            for (int t = 0; t < 9; ++t) {
+                const s4 b = *reinterpret_cast<const s4*>(&X[((fy + t / 3 - 1) * FFW + fx + t % 3 - 1) * FSTR + 4 * kb]);
+                acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[t], b, acc, 0, 0, 0);
+            }
+            if (q0 + (lane & 15) < n) {
+                const int cy = oy + fy, cx = ox + fx;
+                const bool in = cy >= 0 && cy < g.H4 && cx >= 0 && cx < g.W4;
+                s4 o;
+#pragma unroll
+                for (int r = 0; r < 4; ++r) o[r] = in ? f2bf(fmaxf(acc[r], 0.f)) : (short)0;
+                *reinterpret_cast<s4*>(&Y[(fy * FFW + fx) * FSTR + 4 * kb]) = o;
+            }
+        }
+#pragma unroll
+        for (int t = 0; t < 9; ++t) a[t] = an[t];
+        __syncthreads();
+    }
+
+    // head on the last layer's output (kCnnLayers is even: it is in buf[0])
+    const short* X4 = buf[kCnnLayers & 1];
+    for (int q = threadIdx.x; q < FTH * FTW; q += blockDim.x) {
+        const int cy = ty0 + q / FTW, cx = tx0 + q % FTW;
+        if (cy >= g.H4 || cx >= g.W4) continue;
+        const short* xs = &X4[((FHALO + q / FTW) * FFW + FHALO + q % FTW) * FSTR];
+        float x[CC];
+#pragma unroll
+        for (int ch = 0; ch < CC; ++ch) x[ch] = bf2f(xs[ch]);
+        const int64_t c = g.cell0 + (int64_t)cy * g.W4 + cx;
+        uint32_t bits = 0;
+#pragma unroll
+        for (int o = 0; o < NHD; ++o) {
+            float s = head[CC * NHD + o];
+#pragma unroll
+            for (int ch = 0; ch < CC; ++ch) s = fmaf(x[ch], head[ch * NHD + o], s);
+            if (logits) logits[c * NHD + o] = s;
+            if (o < g.n_oct && s > zthr) bits |= 1u << o;
+        }
+        if (mask) mask[c] = (uint8_t)bits;
+    }
+}
+
 __device__ __forceinline__ float softplus(float z) { return fmaxf(z, 0.f) + log1pf(expf(-fabsf(z))); }
 
 // Head backward + loss: per cell dZ, the masked gradient dP4 = (dZ Wh^T) *
@@ -386,6 +543,15 @@ __global__ __launch_bounds__(256) void k_mask_count(const uint8_t* __restrict__ 
 }
 
 }  // namespace
+
+hipError_t launch_cnn_infer(const uint8_t* images, const float* params, short* frag, const CnnImage* imgs, int nimg,
+                            int ntiles, float* logits, uint8_t* mask, float zthr, hipStream_t s) {
+    if (ntiles <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_cnn_pack, dim3(9), dim3(256), 0, s, params, frag);
+    hipLaunchKernelGGL(k_cnn_infer, dim3(ntiles), dim3(256), 0, s, images, params, frag, imgs, nimg, logits, mask,
+                       zthr);
+    return hipGetLastError();
+}
 
 hipError_t launch_cnn_forward(const uint8_t* images, const float* params, short* acts, int64_t ncells,
                               const CnnImage* imgs, int nimg, int ntiles, float* logits, uint8_t* mask, float zthr,

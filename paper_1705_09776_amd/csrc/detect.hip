@@ -22,16 +22,6 @@ namespace {
 
 __device__ __forceinline__ int clampi(int v, int lo, int hi) { return min(max(v, lo), hi); }
 
-__device__ __forceinline__ int find_det_job(const OctJob* jobs, int njobs, int tile) {
-    int lo = 0, hi = njobs - 1;
-    while (lo < hi) {
-        int mid = (lo + hi + 1) >> 1;
-        if (jobs[mid].tile0_det <= tile) lo = mid;
-        else hi = mid - 1;
-    }
-    return lo;
-}
-
 __device__ __forceinline__ float horner(const float4 a, float s) { return fmaf(fmaf(fmaf(a.w, s, a.z), s, a.y), s, a.x); }
 
 // Extremal scale of p(s) = a.x + a.y s + a.z s^2 + a.w s^3 in [lo, hi) where
@@ -90,8 +80,8 @@ static_assert(GW % 4 == 0, "staged rows are whole float4 chunks");
 // per chunk; a chunk lying inside the image is one aligned 16-byte load, and
 // only chunks crossing the left or right image edge load four clamped
 // scalars.  Every load of a lane is issued before its values are needed.
-__device__ __forceinline__ void load_tile(const float* __restrict__ pyr, const OctJob& job, int tx0, int ty0,
-                                          float4 (&vals)[DNPER4]) {
+__device__ __forceinline__ void load_tile(const float* __restrict__ pyr, const DetTile& job, float4 (&vals)[DNPER4]) {
+    const int tx0 = job.tx0, ty0 = job.ty0;
 #pragma unroll
     for (int j = 0; j < DNPER4; ++j) {
         const int t = threadIdx.x + j * 256;
@@ -119,197 +109,373 @@ __device__ __forceinline__ void store_tile(float* G, const float4 (&vals)[DNPER4
     }
 }
 
+// Scale-normalised 5-point Laplacians of the five planes at staged pixel
+// (ly, lx), folded into the four ALP coefficients (Eqs. (2)-(3)).
+__device__ __forceinline__ float4 alpha_at(const float (&G)[kScales][GH][GW], int ly, int lx, const DetParams& dp) {
+    float a0 = 0.f, a1 = 0.f, a2 = 0.f, a3 = 0.f;
+#pragma unroll
+    for (int k = 0; k < kScales; ++k) {
+        const float c = G[k][ly][lx];
+        float s = G[k][ly - 1][lx] + G[k][ly + 1][lx];
+        s = s + G[k][ly][lx - 1];
+        s = s + G[k][ly][lx + 1];
+        s = s - 4.f * c;
+        const float L = dp.sig2[k] * s;
+        a0 = fmaf(dp.beta[k][0], L, a0);
+        a1 = fmaf(dp.beta[k][1], L, a1);
+        a2 = fmaf(dp.beta[k][2], L, a2);
+        a3 = fmaf(dp.beta[k][3], L, a3);
+    }
+    return make_float4(a0, a1, a2, a3);
+}
+
+struct Cand {
+    float s, p, pss, ox, oy, pr, rho;
+};
+
+// Tile centre (cy, cx): extremal scale, contrast, strict 8-neighbour test at
+// that scale, one quadratic refinement step (Algorithm 1 stages A-B).
+__device__ __forceinline__ bool eval_centre(const float4 (&A)[AH][AW], int cy, int cx, const DetParams& dp, Cand& o) {
+    const float4 a = A[cy + 1][cx + 1];
+    float s, p, pss;
+    if (!alp_extremum(a, dp.lo, dp.hi, s, p, pss) || !(fabsf(p) >= dp.contrast)) return false;
+    float v[9];
+    bool ext = true;
+#pragma unroll
+    for (int j = -1; j <= 1; ++j)
+#pragma unroll
+        for (int i = -1; i <= 1; ++i) {
+            if (i == 0 && j == 0) {
+                v[4] = p;
+                continue;
+            }
+            const float qv = horner(A[cy + 1 + j][cx + 1 + i], s);
+            v[(j + 1) * 3 + (i + 1)] = qv;
+            ext = ext && (p > 0.f ? (qv < p) : (qv > p));
+        }
+    if (!ext) return false;
+    const float c = v[4];
+    const float gxd = (v[5] - v[3]) * 0.5f;
+    const float gyd = (v[7] - v[1]) * 0.5f;
+    const float hxx = v[5] - 2.f * c + v[3];
+    const float hyy = v[7] - 2.f * c + v[1];
+    const float hxy = (v[8] - v[6] - v[2] + v[0]) * 0.25f;
+    const float det = hxx * hyy - hxy * hxy;
+    if (!(det > 0.f)) return false;
+    const float tr = hxx + hyy;
+    const float ratio = __fdividef(tr * tr, det);
+    if (!(ratio < dp.edge_lim)) return false;
+    const float rdet = 1.f / det;
+    const float dx = -(hyy * gxd - hxy * gyd) * rdet;
+    const float dy = -(hxx * gyd - hxy * gxd) * rdet;
+    if (fabsf(dx) > dp.max_off || fabsf(dy) > dp.max_off) return false;
+    o.s = s;
+    o.p = p;
+    o.pss = pss;
+    o.ox = dx;
+    o.oy = dy;
+    o.pr = c + (gxd * dx + gyd * dy) * 0.5f;
+    o.rho = ratio;
+    return true;
+}
+
+// Wave-level compaction of survivors into the image's candidate list: one
+// ballot and one atomic per wave.  Every lane of the wave must call it.
+__device__ __forceinline__ void emit(bool keep, const Cand& c, int gx, int gy, const DetTile& job, const DetParams& dp,
+                                     cdvs_keypoint* __restrict__ cand, int32_t* __restrict__ cand_cnt,
+                                     int32_t* __restrict__ flags) {
+    const int lane = threadIdx.x & 63;
+    const uint64_t m = __ballot(keep);
+    if (!m) return;
+    const int leader = __ffsll((unsigned long long)m) - 1;
+    int base = 0;
+    if (lane == leader) base = atomicAdd(&cand_cnt[job.image], __popcll(m));
+    base = __shfl(base, leader);
+    if (!keep) return;
+    const int slot = base + __popcll(m & ((1ull << lane) - 1ull));
+    if (slot >= dp.cand_cap) {
+        atomicOr(flags, kFlagCandOverflow);
+        return;
+    }
+    const float scale = (float)(1 << job.octave);
+    cdvs_keypoint r;
+    r.x = ((float)gx + c.ox) * scale;
+    r.y = ((float)gy + c.oy) * scale;
+    r.sigma = c.s * scale;
+    r.p = c.pr;
+    r.theta = 0.f;
+    r.rho = c.rho;
+    r.p_ss = c.pss;
+    r.peak = 0.f;
+    r.image = job.image;
+    r.octave = job.octave;
+    r.ix = gx;
+    r.iy = gy;
+    cand[(int64_t)job.image * dp.cand_cap + slot] = r;
+}
+
+// Tile records are fetched with vector loads (an address the compiler
+// cannot prove uniform), so that the wait for them is a vector-memory count:
+// a scalar load would be waited for at the next LDS access.  as_uniform()
+// moves the fields to scalar registers once the record has arrived.
+struct RawTile {
+    int4 a, b, c;
+};
+
+__device__ __forceinline__ RawTile fetch_tile(const DetTile* __restrict__ tiles, int idx) {
+    int z;
+    asm volatile("v_mov_b32 %0, 0" : "=v"(z));
+    const int4* q = reinterpret_cast<const int4*>(tiles + idx) + z;
+    return RawTile{q[0], q[1], q[2]};
+}
+
+__device__ __forceinline__ DetTile as_uniform(const RawTile& r) {
+    DetTile t;
+    t.plane0 = (int64_t)(uint32_t)__builtin_amdgcn_readfirstlane(r.a.x) |
+               ((int64_t)__builtin_amdgcn_readfirstlane(r.a.y) << 32);
+    t.plane_stride = __builtin_amdgcn_readfirstlane(r.a.z);
+    t.pitch = __builtin_amdgcn_readfirstlane(r.a.w);
+    t.w = __builtin_amdgcn_readfirstlane(r.b.x);
+    t.h = __builtin_amdgcn_readfirstlane(r.b.y);
+    t.tx0 = __builtin_amdgcn_readfirstlane(r.b.z);
+    t.ty0 = __builtin_amdgcn_readfirstlane(r.b.w);
+    t.image = __builtin_amdgcn_readfirstlane(r.c.x);
+    t.octave = __builtin_amdgcn_readfirstlane(r.c.y);
+    t.pad[0] = t.pad[1] = 0;
+    return t;
+}
+
 // Persistent: the grid (a multiple of 8) is split evenly over the XCDs; each
 // workgroup walks its XCD's contiguous tile range with a stride, and the next
 // tile's loads are in flight while the current tile is computed.
-// Mask gating (optional): an octave-o centre (x, y) is examined only when
-// bit o of the mask cell holding (x 2^o, y 2^o) / 4 is set, unless the
-// image's active-cell fraction for that octave exceeds gate.fmax (then the
-// octave is examined densely).  Tiles without an active centre are skipped
-// after staging, and alpha is computed only within one pixel of an active
-// centre (every pixel an active centre reads).
-__global__ __launch_bounds__(256) void k_detect(const float* __restrict__ pyr, const OctJob* __restrict__ jobs,
-                                                int njobs, int ntiles, DetParams dp, GateParams gate,
-                                                cdvs_keypoint* __restrict__ cand, int32_t* __restrict__ cand_cnt,
-                                                int32_t* __restrict__ flags) {
+__global__ __launch_bounds__(256) void k_detect(const float* __restrict__ pyr, const DetTile* __restrict__ tiles,
+                                                int ntiles, DetParams dp, cdvs_keypoint* __restrict__ cand,
+                                                int32_t* __restrict__ cand_cnt, int32_t* __restrict__ flags) {
     __shared__ __align__(16) float G[kScales][GH][GW];
     __shared__ float4 A[AH][AW];
-    __shared__ uint8_t act[DTH][DTW];
 
     const int x = blockIdx.x % kXcds, slot = blockIdx.x / kXcds, nslot = gridDim.x / kXcds;
     const int per = ntiles / kXcds, rem = ntiles % kXcds;
     const int tbase = x * per + min(x, rem), cnt = per + (x < rem ? 1 : 0);
+    if (slot >= cnt) return;   // uniform over the workgroup
     float4 vals[DNPER4];
-    if (slot < cnt) {
-        const int tile = tbase + slot;
-        const OctJob& job = jobs[find_det_job(jobs, njobs, tile)];
-        const int lt = tile - job.tile0_det;
-        load_tile(pyr, job, (lt % job.tiles_x_det) * DTW, (lt / job.tiles_x_det) * DTH, vals);
-    }
+    DetTile cur = as_uniform(fetch_tile(tiles, tbase + slot));
+    load_tile(pyr, cur, vals);
+    RawTile rn = fetch_tile(tiles, tbase + min(slot + nslot, cnt - 1));
     for (int tj = slot; tj < cnt; tj += nslot) {
-        const int tile = tbase + tj;
-        const OctJob& job = jobs[find_det_job(jobs, njobs, tile)];
-        const int lt = tile - job.tile0_det;
-        const int tx0 = (lt % job.tiles_x_det) * DTW;
-        const int ty0 = (lt / job.tiles_x_det) * DTH;
-        const int w = job.w, h = job.h;
-
+        // the record two tiles ahead is fetched a whole tile before it is needed
+        const RawTile rnn = fetch_tile(tiles, tbase + min(tj + 2 * nslot, cnt - 1));
         __syncthreads();  // the previous tile is done with G and A
         store_tile(&G[0][0][0], vals);
-        // gating of this tile (uniform across the workgroup)
-        bool gated = false;
-        if (gate.mask) {
-            const CnnImage& cg = gate.cells[job.image];
-            const int ncell = cg.H4 * cg.W4;
-            gated = (float)gate.active[job.image * kMaxOctaves + job.octave] <= gate.fmax * (float)ncell;
-            if (gated) {
-                for (int q = threadIdx.x; q < DTH * DTW; q += blockDim.x) {
-                    const int gx = tx0 + q % DTW, gy = ty0 + q / DTW;
-                    bool on = false;
-                    if (gx < w && gy < h) {
-                        const int cx = min((gx << job.octave) >> 2, cg.W4 - 1);
-                        const int cy = min((gy << job.octave) >> 2, cg.H4 - 1);
-                        on = (gate.mask[cg.cell0 + (int64_t)cy * cg.W4 + cx] >> job.octave) & 1;
-                    }
-                    act[q / DTW][q % DTW] = on;
-                }
-            }
-        }
-        // (the barrier inside __syncthreads_or publishes G and act)
-        if (__syncthreads_or(gated && threadIdx.x == 0)) {
-            // any active centre in the tile?
-            bool mine = false;
-            for (int q = threadIdx.x; q < DTH * DTW; q += blockDim.x) mine |= act[q / DTW][q % DTW] != 0;
-            if (!__syncthreads_or(mine)) {
-                if (tj + nslot < cnt) {
-                    const int tn = tbase + tj + nslot;
-                    const OctJob& jn = jobs[find_det_job(jobs, njobs, tn)];
-                    const int ltn = tn - jn.tile0_det;
-                    load_tile(pyr, jn, (ltn % jn.tiles_x_det) * DTW, (ltn / jn.tiles_x_det) * DTH, vals);
-                }
-                continue;
-            }
-        }
-        if (tj + nslot < cnt) {
-            const int tn = tbase + tj + nslot;
-            const OctJob& jn = jobs[find_det_job(jobs, njobs, tn)];
-            const int ltn = tn - jn.tile0_det;
-            load_tile(pyr, jn, (ltn % jn.tiles_x_det) * DTW, (ltn / jn.tiles_x_det) * DTH, vals);
-        }
-
+        __syncthreads();
+        const DetTile nxt = as_uniform(rn);
+        if (tj + nslot < cnt) load_tile(pyr, nxt, vals);
         for (int t = threadIdx.x; t < AH * AW; t += blockDim.x) {
             const int ay = t / AW, ax = t % AW;
-            const int ly = ay + 1, lx = ax + 1 + GX;
-            if (gated) {
-                // alpha at (ay, ax) is read only by centres (ay-1+dy, ax-1+dx)
-                bool need = false;
-                for (int dy = -2; dy <= 0; ++dy)
-                    for (int dx = -2; dx <= 0; ++dx) {
-                        const int cy = ay + dy, cx = ax + dx;
-                        if (cy >= 0 && cy < DTH && cx >= 0 && cx < DTW) need |= act[cy][cx] != 0;
-                    }
-                if (!need) continue;
-            }
-            float a0 = 0.f, a1 = 0.f, a2 = 0.f, a3 = 0.f;
-#pragma unroll
-            for (int k = 0; k < kScales; ++k) {
-                const float c = G[k][ly][lx];
-                float s = G[k][ly - 1][lx] + G[k][ly + 1][lx];
-                s = s + G[k][ly][lx - 1];
-                s = s + G[k][ly][lx + 1];
-                s = s - 4.f * c;
-                const float L = dp.sig2[k] * s;
-                a0 = fmaf(dp.beta[k][0], L, a0);
-                a1 = fmaf(dp.beta[k][1], L, a1);
-                a2 = fmaf(dp.beta[k][2], L, a2);
-                a3 = fmaf(dp.beta[k][3], L, a3);
-            }
-            A[ay][ax] = make_float4(a0, a1, a2, a3);
+            A[ay][ax] = alpha_at(G, ay + 1, ax + 1 + GX, dp);
         }
         __syncthreads();
-
-        const int lane = threadIdx.x & 63;
-        const float scale = (float)(1 << job.octave);
         for (int it = 0; it < DTW * DTH / 256; ++it) {
             const int q = threadIdx.x + it * 256;
             const int cy = q / DTW, cx = q % DTW;
-            const int gx = tx0 + cx, gy = ty0 + cy;
+            const int gx = cur.tx0 + cx, gy = cur.ty0 + cy;
+            Cand c{};
             bool keep = false;
-            float s = 0.f, p = 0.f, pss = 0.f, ox = 0.f, oy = 0.f, pr = 0.f, rho = 0.f;
-            if (gx >= dp.border && gx <= w - 1 - dp.border && gy >= dp.border && gy <= h - 1 - dp.border &&
-                (!gated || act[cy][cx])) {
-                const float4 a = A[cy + 1][cx + 1];
-                if (alp_extremum(a, dp.lo, dp.hi, s, p, pss) && fabsf(p) >= dp.contrast) {
-                    float v[9];
-                    bool ext = true;
+            if (gx >= dp.border && gx <= cur.w - 1 - dp.border && gy >= dp.border && gy <= cur.h - 1 - dp.border)
+                keep = eval_centre(A, cy, cx, dp, c);
+            emit(keep, c, gx, gy, cur, dp, cand, cand_cnt, flags);
+        }
+        cur = nxt;
+        rn = rnn;
+    }
+}
+
+// Gating pre-pass, one workgroup per detection tile (all octaves in one
+// launch): the tile's active-centre row masks (bit cx of row cy) and its
+// state.  An octave-o centre (x, y) is active when it lies inside the
+// detection border and bit o of the mask cell holding (x 2^o, y 2^o) / 4 is
+// set; when the image's active-cell fraction for that octave exceeds
+// gate.fmax the whole octave is dense (every border-valid centre active).
+__global__ __launch_bounds__(256) void k_gate_rows(const DetTile* __restrict__ tiles, DetParams dp, GateParams gate,
+                                                   uint64_t* __restrict__ rows_out, int32_t* __restrict__ state_out) {
+    __shared__ int any_s;
+    const DetTile job = tiles[blockIdx.x];
+    const CnnImage& cg = gate.cells[job.image];
+    const bool dense = (float)gate.active[job.image * kMaxOctaves + job.octave] > gate.fmax * (float)(cg.H4 * cg.W4);
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    if (threadIdx.x == 0) any_s = 0;
+    __syncthreads();
+    const int gx = job.tx0 + lane;
+    const int cx = min((gx << job.octave) >> 2, cg.W4 - 1);
+    bool any = false;
+    for (int cy = wave; cy < DTH; cy += 4) {
+        const int gy = job.ty0 + cy;
+        bool on = gx >= dp.border && gx <= job.w - 1 - dp.border && gy >= dp.border && gy <= job.h - 1 - dp.border;
+        if (on && !dense) {
+            const int cyc = min((gy << job.octave) >> 2, cg.H4 - 1);
+            on = (gate.mask[cg.cell0 + (int64_t)cyc * cg.W4 + cx] >> job.octave) & 1;
+        }
+        const uint64_t m = __ballot(on);
+        if (lane == 0) rows_out[(int64_t)blockIdx.x * DTH + cy] = m;
+        any |= m != 0;
+    }
+    if (any && lane == 0) atomicOr(&any_s, 1);
+    __syncthreads();
+    if (threadIdx.x == 0) state_out[blockIdx.x] = !any_s ? kTileSkip : (dense ? kTileDense : kTileSparse);
+}
+
+// Exclusive prefix of the values held by the lanes of a wave.
+__device__ __forceinline__ int wave_excl_scan(int v) {
+    const int lane = threadIdx.x & 63;
+    int x = v;
 #pragma unroll
-                    for (int j = -1; j <= 1; ++j)
-#pragma unroll
-                        for (int i = -1; i <= 1; ++i) {
-                            if (i == 0 && j == 0) {
-                                v[4] = p;
-                                continue;
-                            }
-                            const float qv = horner(A[cy + 1 + j][cx + 1 + i], s);
-                            v[(j + 1) * 3 + (i + 1)] = qv;
-                            ext = ext && (p > 0.f ? (qv < p) : (qv > p));
-                        }
-                    if (ext) {
-                        const float c = v[4];
-                        const float gxd = (v[5] - v[3]) * 0.5f;
-                        const float gyd = (v[7] - v[1]) * 0.5f;
-                        const float hxx = v[5] - 2.f * c + v[3];
-                        const float hyy = v[7] - 2.f * c + v[1];
-                        const float hxy = (v[8] - v[6] - v[2] + v[0]) * 0.25f;
-                        const float det = hxx * hyy - hxy * hxy;
-                        if (det > 0.f) {
-                            const float tr = hxx + hyy;
-                            const float ratio = __fdividef(tr * tr, det);
-                            if (ratio < dp.edge_lim) {
-                                const float rdet = 1.f / det;
-                                const float dx = -(hyy * gxd - hxy * gyd) * rdet;
-                                const float dy = -(hxx * gyd - hxy * gxd) * rdet;
-                                if (!(fabsf(dx) > dp.max_off || fabsf(dy) > dp.max_off)) {
-                                    ox = dx;
-                                    oy = dy;
-                                    pr = c + (gxd * dx + gyd * dy) * 0.5f;
-                                    rho = ratio;
-                                    keep = true;
-                                }
-                            }
-                        }
-                    }
+    for (int d = 1; d < 64; d <<= 1) {
+        const int y = __shfl_up(x, d);
+        if (lane >= d) x += y;
+    }
+    return x - v;
+}
+
+// A tile's gating state and row masks, fetched with vector loads like the
+// tile record (lanes 0..15 each hold one row).
+struct RawGate {
+    int state;
+    uint64_t row;
+};
+
+__device__ __forceinline__ RawGate fetch_gate(const GateParams& gate, int idx) {
+    int z;
+    asm volatile("v_mov_b32 %0, 0" : "=v"(z));
+    const int lane = threadIdx.x & 63;
+    RawGate r;
+    r.state = gate.state[idx + z];
+    r.row = gate.rows[(int64_t)idx * DTH + min(lane, DTH - 1) + z];
+    return r;
+}
+
+// Mask-gated detection: the same results as k_detect on every active centre
+// (see k_gate_rows).  Tiles without an active centre are neither loaded nor
+// computed; dense tiles run k_detect's body; on the other tiles the active
+// centres, and the pixels whose coefficients they read (one pixel around
+// each), are compacted into LDS work lists so that every lane of every wave
+// does useful work in both phases.
+__global__ __launch_bounds__(256, 3) void k_detect_gated(const float* __restrict__ pyr, const DetTile* __restrict__ tiles,
+                                                      int ntiles, DetParams dp, GateParams gate,
+                                                      cdvs_keypoint* __restrict__ cand,
+                                                      int32_t* __restrict__ cand_cnt, int32_t* __restrict__ flags) {
+    __shared__ __align__(16) float G[kScales][GH][GW];
+    __shared__ float4 A[AH][AW];
+    __shared__ uint16_t alist[AH * AW];
+    __shared__ uint16_t clist[DTH * DTW];
+
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int x = blockIdx.x % kXcds, slot = blockIdx.x / kXcds, nslot = gridDim.x / kXcds;
+    const int per = ntiles / kXcds, rem = ntiles % kXcds;
+    const int tbase = x * per + min(x, rem), cnt = per + (x < rem ? 1 : 0);
+    if (slot >= cnt) return;   // uniform over the workgroup
+    float4 vals[DNPER4];
+    DetTile cur = as_uniform(fetch_tile(tiles, tbase + slot));
+    RawGate gcur = fetch_gate(gate, tbase + slot);
+    int scur = __builtin_amdgcn_readfirstlane(gcur.state);
+    if (scur != kTileSkip) load_tile(pyr, cur, vals);
+    RawTile rn = fetch_tile(tiles, tbase + min(slot + nslot, cnt - 1));
+    RawGate gn = fetch_gate(gate, tbase + min(slot + nslot, cnt - 1));
+    for (int tj = slot; tj < cnt; tj += nslot) {
+        const int inn = tbase + min(tj + 2 * nslot, cnt - 1);
+        const RawTile rnn = fetch_tile(tiles, inn);
+        const RawGate gnn = fetch_gate(gate, inn);
+        const bool has_next = tj + nslot < cnt;
+        const DetTile nxt = as_uniform(rn);
+        const int snxt = has_next ? __builtin_amdgcn_readfirstlane(gn.state) : kTileSkip;
+        if (scur == kTileSkip) {
+            if (snxt != kTileSkip) load_tile(pyr, nxt, vals);
+        } else {
+            __syncthreads();  // the previous tile is done with G, A and the lists
+            store_tile(&G[0][0][0], vals);
+            __syncthreads();
+            if (snxt != kTileSkip) load_tile(pyr, nxt, vals);
+            if (scur == kTileDense) {
+                for (int t = threadIdx.x; t < AH * AW; t += blockDim.x) {
+                    const int ay = t / AW, ax = t % AW;
+                    A[ay][ax] = alpha_at(G, ay + 1, ax + 1 + GX, dp);
                 }
-            }
-            const uint64_t m = __ballot(keep);
-            if (m) {
-                const int leader = __ffsll((unsigned long long)m) - 1;
-                int base = 0;
-                if (lane == leader) base = atomicAdd(&cand_cnt[job.image], __popcll(m));
-                base = __shfl(base, leader);
-                if (keep) {
-                    const int slot = base + __popcll(m & ((1ull << lane) - 1ull));
-                    if (slot < dp.cand_cap) {
-                        cdvs_keypoint r;
-                        r.x = ((float)gx + ox) * scale;
-                        r.y = ((float)gy + oy) * scale;
-                        r.sigma = s * scale;
-                        r.p = pr;
-                        r.theta = 0.f;
-                        r.rho = rho;
-                        r.p_ss = pss;
-                        r.peak = 0.f;
-                        r.image = job.image;
-                        r.octave = job.octave;
-                        r.ix = gx;
-                        r.iy = gy;
-                        cand[(int64_t)job.image * dp.cand_cap + slot] = r;
-                    } else {
-                        atomicOr(flags, kFlagCandOverflow);
+                __syncthreads();
+                for (int it = 0; it < DTW * DTH / 256; ++it) {
+                    const int q = threadIdx.x + it * 256;
+                    const int cy = q / DTW, cx = q % DTW;
+                    const int gx = cur.tx0 + cx, gy = cur.ty0 + cy;
+                    Cand c{};
+                    bool keep = false;
+                    if (gx >= dp.border && gx <= cur.w - 1 - dp.border && gy >= dp.border &&
+                        gy <= cur.h - 1 - dp.border)
+                        keep = eval_centre(A, cy, cx, dp, c);
+                    emit(keep, c, gx, gy, cur, dp, cand, cand_cnt, flags);
+                }
+            } else {
+                // lanes 0..15 of every wave hold the row masks
+                const uint64_t myrow = lane < DTH ? gcur.row : 0ull;
+                // centre list: row bases from a wave scan of the row counts
+                const int rc = __popcll(myrow);
+                const int rb = wave_excl_scan(rc);
+                const int nc = __shfl(rb, DTH - 1) + __shfl(rc, DTH - 1);
+                for (int cy = wave; cy < DTH; cy += 4) {
+                    const uint64_t m = __shfl(myrow, cy);
+                    const int base = __shfl(rb, cy);
+                    if ((m >> lane) & 1)
+                        clist[base + __popcll(m & ((1ull << lane) - 1ull))] = (uint16_t)(cy * DTW + lane);
+                }
+                // coefficient list: alpha row ay is read by centre rows
+                // ay-2..ay, alpha column ax by centre columns ax-2..ax
+                const uint64_t r0 = __shfl(myrow, max(lane - 2, 0)), r1 = __shfl(myrow, max(lane - 1, 0));
+                const uint64_t r2 = __shfl(myrow, min(lane, 63));
+                uint64_t v = 0;
+                if (lane < AH) {
+                    if (lane - 2 >= 0 && lane - 2 < DTH) v |= r0;
+                    if (lane - 1 >= 0 && lane - 1 < DTH) v |= r1;
+                    if (lane < DTH) v |= r2;
+                }
+                const uint64_t vlo = v | (v << 1) | (v << 2);
+                const uint32_t vhi = (uint32_t)(((v >> 62) | (v >> 63)) & 1u) | (uint32_t)(((v >> 63) & 1u) << 1);
+                const int ac = __popcll(vlo) + __popc(vhi);
+                const int ab = wave_excl_scan(ac);
+                const int na = __shfl(ab, AH - 1) + __shfl(ac, AH - 1);
+                for (int ay = wave; ay < AH; ay += 4) {
+                    const uint64_t m = __shfl(vlo, ay);
+                    const uint32_t mh = __shfl(vhi, ay);
+                    const int base = __shfl(ab, ay);
+                    if ((m >> lane) & 1)
+                        alist[base + __popcll(m & ((1ull << lane) - 1ull))] = (uint16_t)(ay * AW + lane);
+                    if (lane < 2 && ((mh >> lane) & 1))
+                        alist[base + __popcll(m) + (lane == 1 ? (int)(mh & 1u) : 0)] = (uint16_t)(ay * AW + DTW + lane);
+                }
+                __syncthreads();
+                for (int i = threadIdx.x; i < na; i += blockDim.x) {
+                    const int idx = alist[i];
+                    const int ay = idx / AW, ax = idx % AW;
+                    A[ay][ax] = alpha_at(G, ay + 1, ax + 1 + GX, dp);
+                }
+                __syncthreads();
+                for (int i0 = 0; i0 < nc; i0 += blockDim.x) {
+                    const int i = i0 + threadIdx.x;
+                    Cand c{};
+                    bool keep = false;
+                    int gx = 0, gy = 0;
+                    if (i < nc) {
+                        const int idx = clist[i];
+                        const int cy = idx / DTW, cx = idx % DTW;
+                        gx = cur.tx0 + cx;
+                        gy = cur.ty0 + cy;
+                        keep = eval_centre(A, cy, cx, dp, c);
                     }
+                    emit(keep, c, gx, gy, cur, dp, cand, cand_cnt, flags);
                 }
             }
         }
+        cur = nxt;
+        gcur = gn;
+        scur = snxt;
+        rn = rnn;
+        gn = gnn;
     }
 }
 
@@ -447,15 +613,25 @@ hipError_t launch_clear(int32_t* p, int n, hipStream_t stream) {
     return hipGetLastError();
 }
 
-hipError_t launch_detect(const float* pyr, const OctJob* jobs, int njobs, int ntiles, int grid, const DetParams& dp,
+hipError_t launch_detect(const float* pyr, const DetTile* tiles, int ntiles, int grid, const DetParams& dp,
                          const GateParams& gate, cdvs_keypoint* cand, int32_t* cand_cnt, int32_t* flags,
                          hipStream_t stream) {
     if (ntiles <= 0) return hipSuccess;
     // a multiple of the XCD count, no larger than needed
     int g = std::min(grid, (ntiles + kXcds - 1) / kXcds * kXcds);
     g = std::max(kXcds, g / kXcds * kXcds);
-    hipLaunchKernelGGL(k_detect, dim3(g), dim3(256), 0, stream, pyr, jobs, njobs, ntiles, dp, gate, cand, cand_cnt,
-                       flags);
+    if (gate.mask)
+        hipLaunchKernelGGL(k_detect_gated, dim3(g), dim3(256), 0, stream, pyr, tiles, ntiles, dp, gate, cand, cand_cnt,
+                           flags);
+    else
+        hipLaunchKernelGGL(k_detect, dim3(g), dim3(256), 0, stream, pyr, tiles, ntiles, dp, cand, cand_cnt, flags);
+    return hipGetLastError();
+}
+
+hipError_t launch_gate_rows(const DetTile* tiles, int ntiles, const DetParams& dp, const GateParams& gate,
+                            uint64_t* rows, int32_t* state, hipStream_t stream) {
+    if (ntiles <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_gate_rows, dim3(ntiles), dim3(256), 0, stream, tiles, dp, gate, rows, state);
     return hipGetLastError();
 }
 

@@ -197,7 +197,7 @@ def evaluate(params, images, taus, topk=1000, fmax=None):
     dparams = params if hasattr(params, "data_ptr") else torch.from_numpy(np.asarray(params, np.float32)).cuda()
     key = lambda k: (int(k["octave"]), int(k["ix"]), int(k["iy"]))
     for tau in taus:
-        pipe_k.cnn_forward(dparams, tau=tau, logits=False)
+        pipe_k.cnn_forward(dparams, tau=tau, logits=False, keep_acts=False)
         cdvs_alp_detect(pipe_k.ctx, pipe_k.d_pyr, pipe_k.d_mask, pipe_k.d_kp, pipe_k.d_count)
         gk = pipe_k.keypoints()
         hit = sum(len({key(k) for k in a} & {key(k) for k in b}) for a, b in zip(plain_k, gk))

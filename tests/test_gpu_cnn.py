@@ -208,3 +208,18 @@ def test_gate_random_mask():
         got = {(int(k["octave"]), int(k["ix"]), int(k["iy"])) for k in gated[i]}
         assert len(want & got) >= 0.99 * len(want)
         assert 0.2 * len(plain[i]) < len(gated[i]) < 0.5 * len(plain[i])
+
+
+def test_fused_inference_equals_training_forward(fwd):
+    """The fused inference kernel (no activations stored) gives the training
+    forward's logits and mask bit for bit, on ragged sizes with partial
+    tiles."""
+    imgs, pipe, P, dP = fwd
+    logits = pipe.d_logits.cpu().numpy().copy()
+    mask = pipe.d_mask.cpu().numpy().copy()
+    pipe.d_logits.fill_(float("nan"))
+    pipe.d_mask.fill_(0xAA)
+    cd.cdvs_cnn_forward(pipe.ctx, pipe.d_images, dP, None, pipe.d_logits, pipe.d_mask, 0.3)
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(pipe.d_logits.cpu().numpy().view(np.uint32), logits.view(np.uint32))
+    np.testing.assert_array_equal(pipe.d_mask.cpu().numpy(), mask)
