@@ -68,6 +68,27 @@ def algorithmic(sizes, n_kp, n_ori):
 
 
 WEIGHTS = os.path.join(ROOT, "paper_1705_09776_amd", "weights", "surrogate_640x480.npz")
+WEIGHTS_HIRES = os.path.join(ROOT, "paper_1705_09776_amd", "weights", "surrogate_1280x960.npz")
+TRAFFIC = os.path.join(ROOT, "profiles", "traffic_plain_batch256_640x480.md")
+_PROFILE_NAME = {"detect": "k_detect", "describe": "k_describe", "scales": "k_blur<scales>", "orient": "k_orient",
+                 "finalize": "k_finalize", "preblur": "k_blur<preblur>"}
+
+
+def measured_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed counter summary
+    (256 images 640x480), or None when there is none or the kernel's source
+    has changed since the counters were taken."""
+    import hashlib
+    name = _PROFILE_NAME.get(kernel)
+    if name is None or not os.path.exists(TRAFFIC):
+        return None
+    csrc = os.path.join(ROOT, "paper_1705_09776_amd", "csrc")
+    for line in open(TRAFFIC):
+        f = line.split()
+        if len(f) == 5 and f[0] == "traffic" and f[1] == name:
+            data = open(os.path.join(csrc, f[3]), "rb").read() + open(os.path.join(csrc, "cdvs_internal.h"), "rb").read()
+            return int(f[2]) if hashlib.sha256(data).hexdigest() == f[4] else None
+    return None
 
 
 def gated_leg(pipe, steps, B, plain_kp):
@@ -167,8 +188,9 @@ def stream_leg(n_images=4096, chunk=256, threads=16):
     n_chunks = n_images // chunk
     d_all = synth.device_batch(synth.SEED_HIRES, n_chunks * chunk, W, H, 400, 1200, smax=40.0)
     torch.cuda.synchronize()
-    st = surrogate.load_checkpoint(WEIGHTS)
-    with open(os.path.splitext(WEIGHTS)[0] + ".json") as f:
+    wpath = WEIGHTS_HIRES if os.path.exists(WEIGHTS_HIRES) else WEIGHTS
+    st = surrogate.load_checkpoint(wpath)
+    with open(os.path.splitext(wpath)[0] + ".json") as f:
         tau = float(json.load(f)["tau"])
     params = torch.from_numpy(st["params"]).cuda()
     sink = (np.zeros((n_chunks * chunk, pipe.kp_capacity, cd.DESC_DIM), dtype=np.uint8),
@@ -205,7 +227,8 @@ def stream_leg(n_images=4096, chunk=256, threads=16):
     d2h = n * pipe.kp_capacity * (cd.DESC_DIM * 4 + 48)
     return {"value": round(n / t_e2e, 1), "unit": "images/s", "images": n, "chunk": chunk, "width": W, "height": H,
             "gpu_only_images_per_s": round(n / t_gpu, 1), "overlap_efficiency": round(t_gpu / t_e2e, 4),
-            "d2h_gb": round(d2h / 1e9, 3), "tau": tau, "recall_first_chunk": round(recall, 5),
+            "d2h_gb": round(d2h / 1e9, 3), "weights": os.path.basename(wpath), "tau": tau,
+            "recall_first_chunk": round(recall, 5),
             "active_cell_fraction_first_chunk": round(active, 4), "consumer_threads": threads,
             "descriptors_kept": int(sink[1][:n].sum()),
             "timing": "end to end over the stream (inputs resident in HBM; ends when the host consumer has "
@@ -327,7 +350,7 @@ def main():
     else:
         roof = {"bound": "alu", "achieved": None, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s"}
     roof["frac"] = round(roof["achieved"] / roof["peak"], 4) if roof["achieved"] is not None else None
-    roof["traffic"] = None
+    roof["traffic"] = measured_traffic(dom) if B == 256 else None   # HBM bytes per launch (rocprofv3 counters)
     roof["kernel"] = dom
     roof["launch_us"] = d["avg_launch_us"]
     hbm_bytes = sum(v["bytes"] for v in alg.values() if v["bytes"] is not None)

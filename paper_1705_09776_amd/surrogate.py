@@ -42,13 +42,29 @@ def label_pipeline(batch: int, width=640, height=480) -> Pipeline:
     return Pipeline([(width, height)] * batch, params=p, kp_capacity=LABEL_TOPK)
 
 
+# Training recipes: image size and generator arguments.
+RECIPES = {
+    "vga": dict(width=640, height=480, nmin=200, nmax=200, smax=20.0),
+    "hires": dict(width=1280, height=960, nmin=400, nmax=1200, smax=40.0),
+}
+
+
 class Trainer:
-    def __init__(self, batch=32, width=640, height=480, lr=1e-3, seed=0, data_seed=4, dataset=20000):
+    """recipe "vga": 640x480, 200 blobs, sigma U[2, 20] (host generator);
+    recipe "hires": 1280x960, 400-1200 blobs, sigma U[2, 40], rendered on the
+    device straight into the batch buffer."""
+
+    def __init__(self, batch=32, width=None, height=None, lr=1e-3, seed=0, data_seed=4, dataset=20000,
+                 recipe="vga"):
         import torch
         self.torch = torch
+        self.recipe = RECIPES[recipe]
+        width = width or self.recipe["width"]
+        height = height or self.recipe["height"]
         self.batch, self.lr, self.data_seed = batch, lr, data_seed
         self.dataset = dataset   # training images are indices 0..dataset-1, visited in order, epoch after epoch
         self.width, self.height = width, height
+        self.on_device = recipe == "hires"
         self.pipe = label_pipeline(batch, width, height)
         self.pipe.cnn_buffers()
         dev = self.pipe.d_pyr.device
@@ -64,6 +80,21 @@ class Trainer:
         self.cursor = 0          # index of the next training image
 
     # -- data -----------------------------------------------------------
+    def render_next(self):
+        """Render the next batch on the device into the pipeline's image buffer."""
+        import synth
+        r, first = self.recipe, self.cursor % self.dataset
+        n = min(self.batch, self.dataset - first)
+        stride = self.pipe.image_bytes // self.batch
+        assert stride == self.width * self.height
+        kw = dict(smax=r["smax"])
+        synth.device_batch(self.data_seed, n, self.width, self.height, r["nmin"], r["nmax"], first=first,
+                           out=self.pipe.d_images, **kw)
+        if n < self.batch:
+            synth.device_batch(self.data_seed, self.batch - n, self.width, self.height, r["nmin"], r["nmax"], first=0,
+                               out=self.pipe.d_images[n * stride:], **kw)
+        self.cursor += self.batch
+
     def next_images(self):
         import synth
         first = self.cursor % self.dataset
@@ -90,7 +121,10 @@ class Trainer:
 
     # -- one step ---------------------------------------------------------
     def train_step(self, images=None) -> float:
-        self.pipe.upload(images if images is not None else self.next_images())
+        if images is None and self.on_device:
+            self.render_next()
+        else:
+            self.pipe.upload(images if images is not None else self.next_images())
         self.make_labels()
         if self.pos_weight is None:
             self.estimate_pos_weight()
@@ -181,7 +215,7 @@ def evaluate(params, images, taus, topk=1000, fmax=None):
     if fmax is not None:
         p.mask_fmax = fmax
     pipe_k = Pipeline(sizes, params=p, kp_capacity=max(topk, 1))
-    pipe_all = label_pipeline(len(images)) if len(set(sizes)) == 1 else None
+    pipe_all = label_pipeline(len(images), *sizes[0]) if len(set(sizes)) == 1 else None
     pipe_k.upload(images)
     pipe_k.cnn_buffers()
     pipe_k.pyramid()
@@ -204,6 +238,16 @@ def evaluate(params, images, taus, topk=1000, fmax=None):
         rec = {"tau": tau, "recall_topk": hit / max(1, sum(len(a) for a in plain_k))}
         mask = pipe_k.d_mask.cpu().numpy()
         n_oct = [pipe_k.num_octaves(i) for i in range(len(images))]
+        rec["active_fraction_per_octave"] = []
+        for o in range(CNN_HEADS):
+            a = t = 0
+            for i in range(len(images)):
+                if o < n_oct[i]:
+                    c0, w4, h4 = pipe_k.cell_layout(i)
+                    a += int(((mask[c0:c0 + w4 * h4] >> o) & 1).sum())
+                    t += w4 * h4
+            if t:
+                rec["active_fraction_per_octave"].append(round(a / t, 4))
         act, tot = 0, 0
         for i in range(len(images)):
             c0, w4, h4 = pipe_k.cell_layout(i)

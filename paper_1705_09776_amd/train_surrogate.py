@@ -33,14 +33,22 @@ def main(argv=None):
     ap.add_argument("--resume", default=None)
     ap.add_argument("--eval", type=int, default=256, help="evaluation images (seed base 5)")
     ap.add_argument("--log-every", type=int, default=50)
+    ap.add_argument("--recipe", choices=["vga", "hires"], default="vga",
+                    help="vga: 640x480 (train seed base 4, eval 5); hires: 1280x960 (train 7, eval 6)")
+    ap.add_argument("--init", default=None, help="start from this checkpoint's parameters (fresh optimiser)")
     args = ap.parse_args(argv)
 
     import numpy as np
+    import torch
     import synth
     from paper_1705_09776_amd import surrogate
 
-    tr = surrogate.Trainer(batch=args.batch, lr=args.lr, seed=args.seed, data_seed=synth.SEED_TRAIN,
-                           dataset=args.images)
+    hires = args.recipe == "hires"
+    tr = surrogate.Trainer(batch=args.batch, lr=args.lr, seed=args.seed,
+                           data_seed=synth.SEED_HIRES_TRAIN if hires else synth.SEED_TRAIN,
+                           dataset=args.images, recipe=args.recipe)
+    if args.init:
+        tr.params.copy_(torch.from_numpy(surrogate.load_checkpoint(args.init)["params"]).to(tr.params.device))
     if args.resume:
         tr.load(args.resume)
     t0 = time.perf_counter()
@@ -50,13 +58,14 @@ def main(argv=None):
     if args.out:
         os.makedirs(os.path.dirname(os.path.abspath(args.out)), exist_ok=True)
         tr.save(args.out)
-    report = {"dataset": args.images, "images_seen": tr.cursor, "steps": tr.step, "batch": args.batch, "train_s": round(t_train, 1),
+    report = {"recipe": args.recipe, "init": args.init, "dataset": args.images, "images_seen": tr.cursor, "steps": tr.step, "batch": args.batch, "train_s": round(t_train, 1),
               "loss_first": float(np.mean(losses[:10])) if losses else None,
               "loss_last": float(np.mean(losses[-10:])) if losses else None,
               "pos_weight": tr.pos_weight.cpu().numpy().round(2).tolist() if tr.pos_weight is not None else None}
     if args.eval > 0:
         print(f"evaluating on {args.eval} images", file=sys.stderr, flush=True)
-        imgs = list(synth.fixed_batch(synth.SEED_EVAL, args.eval))
+        imgs = list(synth.hires_batch(synth.SEED_HIRES, args.eval) if hires
+                    else synth.fixed_batch(synth.SEED_EVAL, args.eval))
         report["sweep"] = surrogate.evaluate(tr.params, imgs, TAUS)
         ok = [r["tau"] for r in report["sweep"] if r["recall_topk"] >= 0.98]
         report["tau"] = max(ok) if ok else min(TAUS)

@@ -33,6 +33,7 @@ SEED_RAGGED = 3
 SEED_TRAIN = 4
 SEED_EVAL = 5
 SEED_HIRES = 6
+SEED_HIRES_TRAIN = 7
 
 
 def build() -> str:
