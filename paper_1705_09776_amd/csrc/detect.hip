@@ -75,6 +75,9 @@ constexpr int AW = DTW + 2, AH = DTH + 2;
 constexpr int DNV4 = kScales * GH * GW / 4;     // float4 chunks of the staged window
 constexpr int DNPER4 = (DNV4 + 255) / 256;      // chunks per lane
 static_assert(GW % 4 == 0, "staged rows are whole float4 chunks");
+// After the coefficients are computed the staging buffer holds the list of
+// contrast-passing centres (16 B each, at most one per centre).
+static_assert(kScales * GH * GW >= 4 * DTW * DTH, "the staging buffer holds the list of every centre");
 
 // Stage the five planes over the tile plus a clamped halo: rows are clamped
 // per chunk; a chunk lying inside the image is one aligned 16-byte load, and
@@ -133,12 +136,16 @@ struct Cand {
     float s, p, pss, ox, oy, pr, rho;
 };
 
-// Tile centre (cy, cx): extremal scale, contrast, strict 8-neighbour test at
-// that scale, one quadratic refinement step (Algorithm 1 stages A-B).
-__device__ __forceinline__ bool eval_centre(const float4 (&A)[AH][AW], int cy, int cx, const DetParams& dp, Cand& o) {
-    const float4 a = A[cy + 1][cx + 1];
-    float s, p, pss;
-    if (!alp_extremum(a, dp.lo, dp.hi, s, p, pss) || !(fabsf(p) >= dp.contrast)) return false;
+// Tile centre (cy, cx), first half: extremal scale and contrast.
+__device__ __forceinline__ bool centre_extremum(const float4 (&A)[AH][AW], int cy, int cx, const DetParams& dp,
+                                                float& s, float& p, float& pss) {
+    return alp_extremum(A[cy + 1][cx + 1], dp.lo, dp.hi, s, p, pss) && fabsf(p) >= dp.contrast;
+}
+
+// Second half: strict 8-neighbour test at the centre's scale and one
+// quadratic refinement step (Algorithm 1 stages A-B).
+__device__ __forceinline__ bool centre_refine(const float4 (&A)[AH][AW], int cy, int cx, float s, float p, float pss,
+                                              const DetParams& dp, Cand& o) {
     float v[9];
     bool ext = true;
 #pragma unroll
@@ -179,6 +186,19 @@ __device__ __forceinline__ bool eval_centre(const float4 (&A)[AH][AW], int cy, i
     return true;
 }
 
+// Appends (s, p, pss, centre index) of the lanes with `pass` to an LDS list
+// (one ballot and one LDS atomic per wave).  Every lane of the wave calls it.
+__device__ __forceinline__ void push_centre(bool pass, float s, float p, float pss, int q, float4* list, int* count) {
+    const int lane = threadIdx.x & 63;
+    const uint64_t m = __ballot(pass);
+    if (!m) return;
+    const int leader = __ffsll((unsigned long long)m) - 1;
+    int base = 0;
+    if (lane == leader) base = atomicAdd(count, __popcll(m));
+    base = __shfl(base, leader);
+    if (pass) list[base + __popcll(m & ((1ull << lane) - 1ull))] = make_float4(s, p, pss, __int_as_float(q));
+}
+
 // Wave-level compaction of survivors into the image's candidate list: one
 // ballot and one atomic per wave.  Every lane of the wave must call it.
 __device__ __forceinline__ void emit(bool keep, const Cand& c, int gx, int gy, const DetTile& job, const DetParams& dp,
@@ -214,35 +234,87 @@ __device__ __forceinline__ void emit(bool keep, const Cand& c, int gx, int gy, c
     cand[(int64_t)job.image * dp.cand_cap + slot] = r;
 }
 
-// Tile records are fetched with vector loads (an address the compiler
-// cannot prove uniform), so that the wait for them is a vector-memory count:
-// a scalar load would be waited for at the next LDS access.  as_uniform()
-// moves the fields to scalar registers once the record has arrived.
-struct RawTile {
-    int4 a, b, c;
-};
-
-__device__ __forceinline__ RawTile fetch_tile(const DetTile* __restrict__ tiles, int idx) {
-    int z;
-    asm volatile("v_mov_b32 %0, 0" : "=v"(z));
-    const int4* q = reinterpret_cast<const int4*>(tiles + idx) + z;
-    return RawTile{q[0], q[1], q[2]};
+// Second phase over the LDS list of contrast-passing centres: dense lanes
+// for the 3x3 test and refinement, survivors appended to the candidates.
+__device__ __forceinline__ void refine_list(const float4 (&A)[AH][AW], const float4* list, int n, const DetTile& job,
+                                           const DetParams& dp, cdvs_keypoint* __restrict__ cand,
+                                           int32_t* __restrict__ cand_cnt, int32_t* __restrict__ flags) {
+    for (int i0 = 0; i0 < n; i0 += blockDim.x) {
+        const int i = i0 + threadIdx.x;
+        Cand c{};
+        bool keep = false;
+        int gx = 0, gy = 0;
+        if (i < n) {
+            const float4 r = list[i];
+            const int q = __float_as_int(r.w);
+            const int cy = q / DTW, cx = q % DTW;
+            gx = job.tx0 + cx;
+            gy = job.ty0 + cy;
+            keep = centre_refine(A, cy, cx, r.x, r.y, r.z, dp, c);
+        }
+        emit(keep, c, gx, gy, job, dp, cand, cand_cnt, flags);
+    }
 }
 
-__device__ __forceinline__ DetTile as_uniform(const RawTile& r) {
+// Tile records are fetched with vector loads, lane i holding dword i (the
+// wait for a scalar load would come at the next LDS access, since both are
+// counted together); as_uniform() moves the fields to scalar registers once
+// the record has arrived.
+typedef int RawTile;
+
+__device__ __forceinline__ RawTile fetch_tile(const DetTile* __restrict__ tiles, int idx) {
+    const int lane = threadIdx.x & 63;
+    constexpr int kWords = (int)sizeof(DetTile) / 4;
+    return reinterpret_cast<const int*>(tiles + idx)[min(lane, kWords - 1)];
+}
+
+__device__ __forceinline__ DetTile as_uniform(RawTile r) {
     DetTile t;
-    t.plane0 = (int64_t)(uint32_t)__builtin_amdgcn_readfirstlane(r.a.x) |
-               ((int64_t)__builtin_amdgcn_readfirstlane(r.a.y) << 32);
-    t.plane_stride = __builtin_amdgcn_readfirstlane(r.a.z);
-    t.pitch = __builtin_amdgcn_readfirstlane(r.a.w);
-    t.w = __builtin_amdgcn_readfirstlane(r.b.x);
-    t.h = __builtin_amdgcn_readfirstlane(r.b.y);
-    t.tx0 = __builtin_amdgcn_readfirstlane(r.b.z);
-    t.ty0 = __builtin_amdgcn_readfirstlane(r.b.w);
-    t.image = __builtin_amdgcn_readfirstlane(r.c.x);
-    t.octave = __builtin_amdgcn_readfirstlane(r.c.y);
+    t.plane0 = (int64_t)(uint32_t)__builtin_amdgcn_readlane(r, 0) | ((int64_t)__builtin_amdgcn_readlane(r, 1) << 32);
+    t.plane_stride = __builtin_amdgcn_readlane(r, 2);
+    t.pitch = __builtin_amdgcn_readlane(r, 3);
+    t.w = __builtin_amdgcn_readlane(r, 4);
+    t.h = __builtin_amdgcn_readlane(r, 5);
+    t.tx0 = __builtin_amdgcn_readlane(r, 6);
+    t.ty0 = __builtin_amdgcn_readlane(r, 7);
+    t.image = __builtin_amdgcn_readlane(r, 8);
+    t.octave = __builtin_amdgcn_readlane(r, 9);
     t.pad[0] = t.pad[1] = 0;
     return t;
+}
+
+// One tile of the dense detector, its planes already in `vals`: stage,
+// start the loads of the next tile into the same registers, then
+// coefficients, extremal scales with contrast into an LDS list, and the 3x3
+// test and refinement on the list.
+__device__ __forceinline__ void dense_tile(const float* __restrict__ pyr, float (&G)[kScales][GH][GW],
+                                           float4 (&A)[AH][AW], int& nlist, float4 (&vals)[DNPER4],
+                                           const DetTile& cur, bool load_next, const DetTile& nxt, const DetParams& dp,
+                                           cdvs_keypoint* __restrict__ cand, int32_t* __restrict__ cand_cnt,
+                                           int32_t* __restrict__ flags) {
+    __syncthreads();  // the previous tile is done with G, A and the list
+    store_tile(&G[0][0][0], vals);
+    if (threadIdx.x == 0) nlist = 0;
+    __syncthreads();
+    if (load_next) load_tile(pyr, nxt, vals);
+    for (int t = threadIdx.x; t < AH * AW; t += blockDim.x) {
+        const int ay = t / AW, ax = t % AW;
+        A[ay][ax] = alpha_at(G, ay + 1, ax + 1 + GX, dp);
+    }
+    __syncthreads();
+    // contrast-passing centres go to a list in the (now free) staging buffer
+    float4* list = reinterpret_cast<float4*>(&G[0][0][0]);
+    for (int it = 0; it < DTW * DTH / 256; ++it) {
+        const int q = threadIdx.x + it * 256;
+        const int cy = q / DTW, cx = q % DTW;
+        const int gx = cur.tx0 + cx, gy = cur.ty0 + cy;
+        float cs = 0.f, cp = 0.f, cpss = 0.f;
+        const bool pass = gx >= dp.border && gx <= cur.w - 1 - dp.border && gy >= dp.border &&
+                          gy <= cur.h - 1 - dp.border && centre_extremum(A, cy, cx, dp, cs, cp, cpss);
+        push_centre(pass, cs, cp, cpss, q, list, &nlist);
+    }
+    __syncthreads();
+    refine_list(A, list, nlist, cur, dp, cand, cand_cnt, flags);
 }
 
 // Persistent: the grid (a multiple of 8) is split evenly over the XCDs; each
@@ -253,6 +325,7 @@ __global__ __launch_bounds__(256) void k_detect(const float* __restrict__ pyr, c
                                                 int32_t* __restrict__ cand_cnt, int32_t* __restrict__ flags) {
     __shared__ __align__(16) float G[kScales][GH][GW];
     __shared__ float4 A[AH][AW];
+    __shared__ int nlist;
 
     const int x = blockIdx.x % kXcds, slot = blockIdx.x / kXcds, nslot = gridDim.x / kXcds;
     const int per = ntiles / kXcds, rem = ntiles % kXcds;
@@ -265,26 +338,8 @@ __global__ __launch_bounds__(256) void k_detect(const float* __restrict__ pyr, c
     for (int tj = slot; tj < cnt; tj += nslot) {
         // the record two tiles ahead is fetched a whole tile before it is needed
         const RawTile rnn = fetch_tile(tiles, tbase + min(tj + 2 * nslot, cnt - 1));
-        __syncthreads();  // the previous tile is done with G and A
-        store_tile(&G[0][0][0], vals);
-        __syncthreads();
         const DetTile nxt = as_uniform(rn);
-        if (tj + nslot < cnt) load_tile(pyr, nxt, vals);
-        for (int t = threadIdx.x; t < AH * AW; t += blockDim.x) {
-            const int ay = t / AW, ax = t % AW;
-            A[ay][ax] = alpha_at(G, ay + 1, ax + 1 + GX, dp);
-        }
-        __syncthreads();
-        for (int it = 0; it < DTW * DTH / 256; ++it) {
-            const int q = threadIdx.x + it * 256;
-            const int cy = q / DTW, cx = q % DTW;
-            const int gx = cur.tx0 + cx, gy = cur.ty0 + cy;
-            Cand c{};
-            bool keep = false;
-            if (gx >= dp.border && gx <= cur.w - 1 - dp.border && gy >= dp.border && gy <= cur.h - 1 - dp.border)
-                keep = eval_centre(A, cy, cx, dp, c);
-            emit(keep, c, gx, gy, cur, dp, cand, cand_cnt, flags);
-        }
+        dense_tile(pyr, G, A, nlist, vals, cur, tj + nslot < cnt, nxt, dp, cand, cand_cnt, flags);
         cur = nxt;
         rn = rnn;
     }
@@ -367,6 +422,7 @@ __global__ __launch_bounds__(256, 3) void k_detect_gated(const float* __restrict
     __shared__ float4 A[AH][AW];
     __shared__ uint16_t alist[AH * AW];
     __shared__ uint16_t clist[DTH * DTW];
+    __shared__ int nlist;
 
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int x = blockIdx.x % kXcds, slot = blockIdx.x / kXcds, nslot = gridDim.x / kXcds;
@@ -392,6 +448,7 @@ __global__ __launch_bounds__(256, 3) void k_detect_gated(const float* __restrict
         } else {
             __syncthreads();  // the previous tile is done with G, A and the lists
             store_tile(&G[0][0][0], vals);
+            if (threadIdx.x == 0) nlist = 0;
             __syncthreads();
             if (snxt != kTileSkip) load_tile(pyr, nxt, vals);
             if (scur == kTileDense) {
@@ -400,17 +457,18 @@ __global__ __launch_bounds__(256, 3) void k_detect_gated(const float* __restrict
                     A[ay][ax] = alpha_at(G, ay + 1, ax + 1 + GX, dp);
                 }
                 __syncthreads();
+                float4* list = reinterpret_cast<float4*>(&G[0][0][0]);
                 for (int it = 0; it < DTW * DTH / 256; ++it) {
                     const int q = threadIdx.x + it * 256;
                     const int cy = q / DTW, cx = q % DTW;
                     const int gx = cur.tx0 + cx, gy = cur.ty0 + cy;
-                    Cand c{};
-                    bool keep = false;
-                    if (gx >= dp.border && gx <= cur.w - 1 - dp.border && gy >= dp.border &&
-                        gy <= cur.h - 1 - dp.border)
-                        keep = eval_centre(A, cy, cx, dp, c);
-                    emit(keep, c, gx, gy, cur, dp, cand, cand_cnt, flags);
+                    float cs = 0.f, cp = 0.f, cpss = 0.f;
+                    const bool pass = gx >= dp.border && gx <= cur.w - 1 - dp.border && gy >= dp.border &&
+                                      gy <= cur.h - 1 - dp.border && centre_extremum(A, cy, cx, dp, cs, cp, cpss);
+                    push_centre(pass, cs, cp, cpss, q, list, &nlist);
                 }
+                __syncthreads();
+                refine_list(A, list, nlist, cur, dp, cand, cand_cnt, flags);
             } else {
                 // lanes 0..15 of every wave hold the row masks
                 const uint64_t myrow = lane < DTH ? gcur.row : 0ull;
@@ -455,20 +513,20 @@ __global__ __launch_bounds__(256, 3) void k_detect_gated(const float* __restrict
                     A[ay][ax] = alpha_at(G, ay + 1, ax + 1 + GX, dp);
                 }
                 __syncthreads();
+                float4* list = reinterpret_cast<float4*>(&G[0][0][0]);
                 for (int i0 = 0; i0 < nc; i0 += blockDim.x) {
                     const int i = i0 + threadIdx.x;
-                    Cand c{};
-                    bool keep = false;
-                    int gx = 0, gy = 0;
+                    float cs = 0.f, cp = 0.f, cpss = 0.f;
+                    int q = 0;
+                    bool pass = false;
                     if (i < nc) {
-                        const int idx = clist[i];
-                        const int cy = idx / DTW, cx = idx % DTW;
-                        gx = cur.tx0 + cx;
-                        gy = cur.ty0 + cy;
-                        keep = eval_centre(A, cy, cx, dp, c);
+                        q = clist[i];
+                        pass = centre_extremum(A, q / DTW, q % DTW, dp, cs, cp, cpss);
                     }
-                    emit(keep, c, gx, gy, cur, dp, cand, cand_cnt, flags);
+                    push_centre(pass, cs, cp, cpss, q, list, &nlist);
                 }
+                __syncthreads();
+                refine_list(A, list, nlist, cur, dp, cand, cand_cnt, flags);
             }
         }
         cur = nxt;
