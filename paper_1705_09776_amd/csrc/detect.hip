@@ -545,102 +545,12 @@ __global__ void k_clear(int32_t* p, int n) {
 constexpr int FIN_THREADS = 1024;
 constexpr int FIN_PER = kCandCap / FIN_THREADS;  // candidates per thread
 
-// Stage C + canonical sort + top-k for one image per workgroup.  The
-// candidates' (x, y, sigma, p) are staged in LDS for the pair loop; the same
-// LDS then holds the sort keys.
-__global__ __launch_bounds__(FIN_THREADS) void k_finalize(const cdvs_keypoint* __restrict__ cand,
-                                                          const int32_t* __restrict__ cand_cnt, int cand_cap,
-                                                          float ratio_lim, int topk, int kp_cap,
-                                                          cdvs_keypoint* __restrict__ kp,
-                                                          int32_t* __restrict__ count) {
-    // records: kCandCap float4 = 128 KB; keys + indices reuse the same bytes
-    __shared__ float4 rec[kCandCap];
-    __shared__ int seg[kMaxOctaves + 2];
-    __shared__ int n_alive;
-    unsigned long long* key = reinterpret_cast<unsigned long long*>(rec);
-    unsigned short* idx = reinterpret_cast<unsigned short*>(key + kCandCap);
-
-    const int img = blockIdx.x;
-    const cdvs_keypoint* c = cand + (int64_t)img * cand_cap;
-    const int n = min(cand_cnt[img], cand_cap);
-    const int tid = threadIdx.x;
-
-    if (tid < kMaxOctaves + 2) seg[tid] = n;
-    if (tid == 0) n_alive = 0;
-    __syncthreads();
-    int oct[FIN_PER];
-#pragma unroll
-    for (int j = 0; j < FIN_PER; ++j) {
-        const int i = tid + j * FIN_THREADS;
-        oct[j] = -1;
-        if (i < n) {
-            const cdvs_keypoint a = c[i];
-            rec[i] = make_float4(a.x, a.y, a.sigma, a.p);
-            oct[j] = a.octave;
-            // seg[o] = first index whose octave >= o (the list is grouped by octave)
-            const int prev = (i == 0) ? -1 : c[i - 1].octave;
-            for (int o = prev + 1; o <= a.octave; ++o) seg[o] = i;
-        }
-    }
-    __syncthreads();
-
-    unsigned long long kk[FIN_PER];
-    int local_alive = 0;
-#pragma unroll
-    for (int j = 0; j < FIN_PER; ++j) {
-        const int i = tid + j * FIN_THREADS;
-        kk[j] = ~0ull;
-        if (i < n) {
-            const float4 a = rec[i];
-            const int ao = oct[j];
-            const float aa = fabsf(a.w);
-            bool alive = true;
-            for (int d = -1; d <= 1 && alive; d += 2) {
-                const int o2 = ao + d;
-                if (o2 < 0 || o2 >= kMaxOctaves) continue;
-                const float lim = (float)(1 << max(ao, o2));
-                const float lim2 = lim * lim;
-                for (int jj = seg[o2]; jj < seg[o2 + 1]; ++jj) {
-                    const float4 b = rec[jj];
-                    if ((a.w > 0.f) != (b.w > 0.f)) continue;
-                    const float dx = a.x - b.x, dy = a.y - b.y;
-                    if (!(dx * dx + dy * dy <= lim2)) continue;
-                    const float shi = fmaxf(a.z, b.z), slo = fminf(a.z, b.z);
-                    if (!(shi <= ratio_lim * slo)) continue;
-                    const float ab = fabsf(b.w);
-                    if (ab > aa || (ab == aa && o2 < ao)) {
-                        alive = false;
-                        break;
-                    }
-                }
-            }
-            if (alive) {
-                ++local_alive;
-                const cdvs_keypoint& r = c[i];
-                kk[j] = ((unsigned long long)(~__float_as_uint(aa)) << 32) |
-                        ((unsigned long long)ao << 28) | ((unsigned long long)r.iy << 14) |
-                        (unsigned long long)r.ix;
-            }
-        }
-    }
-    if (local_alive) atomicAdd(&n_alive, local_alive);
-    int npow = 1;
-    while (npow < n) npow <<= 1;
-    __syncthreads();  // every lane is done reading rec[] before keys overwrite it
-#pragma unroll
-    for (int j = 0; j < FIN_PER; ++j) {
-        const int i = tid + j * FIN_THREADS;
-        if (i < npow) {
-            key[i] = kk[j];
-            idx[i] = (unsigned short)i;
-        }
-    }
-    __syncthreads();
-
-    // bitonic sort, ascending
+// Ascending bitonic sort of npow (a power of two) 64-bit keys with 16-bit
+// payloads in LDS by the whole workgroup.
+__device__ __forceinline__ void bitonic_sort(unsigned long long* key, unsigned short* idx, int npow) {
     for (int size = 2; size <= npow; size <<= 1) {
         for (int stride = size >> 1; stride > 0; stride >>= 1) {
-            for (int t = tid; t < npow / 2; t += blockDim.x) {
+            for (int t = threadIdx.x; t < npow / 2; t += blockDim.x) {
                 const int lo = 2 * t - (t & (stride - 1));
                 const int hi = lo + stride;
                 const bool asc = (lo & size) == 0;
@@ -656,10 +566,123 @@ __global__ __launch_bounds__(FIN_THREADS) void k_finalize(const cdvs_keypoint* _
             __syncthreads();
         }
     }
+}
+
+// Stage C + canonical sort + top-k for one image per workgroup.  The
+// candidates are first sorted by (octave, y) so that each one meets only the
+// adjacent-octave candidates in a band of y around it (binary search, then a
+// short scan) instead of every candidate of those octaves; the decisions are
+// the same, as only pairs farther apart in y than the distance limit are
+// skipped.  Then the survivors are sorted by the canonical key.
+__global__ __launch_bounds__(FIN_THREADS) void k_finalize(const cdvs_keypoint* __restrict__ cand,
+                                                          const int32_t* __restrict__ cand_cnt, int cand_cap,
+                                                          float ratio_lim, int topk, int kp_cap,
+                                                          cdvs_keypoint* __restrict__ kp,
+                                                          int32_t* __restrict__ count) {
+    // 128 KB: sort keys + payloads, then the records (x, y, sigma, p) in
+    // (octave, y) order, then the final keys + payloads
+    __shared__ float4 rec[kCandCap];
+    __shared__ unsigned short perm[kCandCap];   // original index of each (octave, y)-sorted position
+    __shared__ int seg[kMaxOctaves + 2];        // first sorted position of each octave
+    __shared__ int n_alive;
+    unsigned long long* key = reinterpret_cast<unsigned long long*>(rec);
+    unsigned short* idx = reinterpret_cast<unsigned short*>(key + kCandCap);
+
+    const int img = blockIdx.x;
+    const cdvs_keypoint* c = cand + (int64_t)img * cand_cap;
+    const int n = min(cand_cnt[img], cand_cap);
+    const int tid = threadIdx.x;
+    int npow = 1;
+    while (npow < n) npow <<= 1;
+
+    if (tid < kMaxOctaves + 2) seg[tid] = n;
+    if (tid == 0) n_alive = 0;
+    for (int i = tid; i < npow; i += FIN_THREADS) {
+        // y >= 0, so its float bits order like the value
+        key[i] = i < n ? ((unsigned long long)c[i].octave << 32) | __float_as_uint(c[i].y) : ~0ull;
+        idx[i] = (unsigned short)i;
+    }
+    __syncthreads();
+    bitonic_sort(key, idx, npow);
+    for (int i = tid; i < n; i += FIN_THREADS) {
+        perm[i] = idx[i];
+        const int o = (int)(key[i] >> 32);
+        const int prev = i == 0 ? -1 : (int)(key[i - 1] >> 32);
+        for (int oo = prev + 1; oo <= o; ++oo) seg[oo] = i;
+    }
+    __syncthreads();   // keys are read; the records overwrite them
+    for (int i = tid; i < n; i += FIN_THREADS) {
+        const cdvs_keypoint a = c[perm[i]];
+        rec[i] = make_float4(a.x, a.y, a.sigma, a.p);
+    }
+    __syncthreads();
+
+    unsigned long long kk[FIN_PER];
+    int local_alive = 0;
+#pragma unroll
+    for (int j = 0; j < FIN_PER; ++j) {
+        const int i = tid + j * FIN_THREADS;
+        kk[j] = ~0ull;
+        if (i < n) {
+            const float4 a = rec[i];
+            int ao = 0;
+            while (ao + 1 < kMaxOctaves + 1 && seg[ao + 1] <= i) ++ao;
+            const float aa = fabsf(a.w);
+            bool alive = true;
+            for (int d = -1; d <= 1 && alive; d += 2) {
+                const int o2 = ao + d;
+                if (o2 < 0 || o2 >= kMaxOctaves) continue;
+                const float lim = (float)(1 << max(ao, o2));
+                const float lim2 = lim * lim;
+                // the band searched is one pixel wider than the limit, so
+                // rounding here cannot drop a pair the exact test keeps
+                const float ylo = a.y - (lim + 1.f), yhi = a.y + (lim + 1.f);
+                int lo = seg[o2], hi = seg[o2 + 1];
+                while (lo < hi) {
+                    const int mid = (lo + hi) >> 1;
+                    if (rec[mid].y < ylo) lo = mid + 1;
+                    else hi = mid;
+                }
+                for (int jj = lo; jj < seg[o2 + 1]; ++jj) {
+                    const float4 b = rec[jj];
+                    if (b.y > yhi) break;
+                    if ((a.w > 0.f) != (b.w > 0.f)) continue;
+                    const float dx = a.x - b.x, dy = a.y - b.y;
+                    if (!(dx * dx + dy * dy <= lim2)) continue;
+                    const float shi = fmaxf(a.z, b.z), slo = fminf(a.z, b.z);
+                    if (!(shi <= ratio_lim * slo)) continue;
+                    const float ab = fabsf(b.w);
+                    if (ab > aa || (ab == aa && o2 < ao)) {
+                        alive = false;
+                        break;
+                    }
+                }
+            }
+            if (alive) {
+                ++local_alive;
+                const cdvs_keypoint& r = c[perm[i]];
+                kk[j] = ((unsigned long long)(~__float_as_uint(aa)) << 32) |
+                        ((unsigned long long)ao << 28) | ((unsigned long long)r.iy << 14) |
+                        (unsigned long long)r.ix;
+            }
+        }
+    }
+    if (local_alive) atomicAdd(&n_alive, local_alive);
+    __syncthreads();  // every lane is done reading rec[] before keys overwrite it
+#pragma unroll
+    for (int j = 0; j < FIN_PER; ++j) {
+        const int i = tid + j * FIN_THREADS;
+        if (i < npow) {
+            key[i] = kk[j];
+            idx[i] = (unsigned short)i;
+        }
+    }
+    __syncthreads();
+    bitonic_sort(key, idx, npow);
 
     const int limit = min(topk > 0 ? topk : kp_cap, kp_cap);
     const int m = min(n_alive, limit);
-    for (int r = tid; r < m; r += blockDim.x) kp[(int64_t)img * kp_cap + r] = c[idx[r]];
+    for (int r = tid; r < m; r += blockDim.x) kp[(int64_t)img * kp_cap + r] = c[perm[idx[r]]];
     if (tid == 0) count[img] = m;
 }
 
