@@ -36,7 +36,7 @@ __device__ __forceinline__ bool alp_extremum(const float4 a, float lo, float hi,
     } else {
         const float disc = B * B - 4.f * A * C;
         if (disc < 0.f) return false;
-        const float sq = sqrtf(disc);
+        const float sq = __builtin_amdgcn_sqrtf(disc);   // hardware square root (1 ulp)
         const float q = (B >= 0.f) ? -(B + sq) * 0.5f : -(B - sq) * 0.5f;
         if (q != 0.f) {
             r[nr++] = __fdividef(q, A);

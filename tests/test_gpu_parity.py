@@ -306,3 +306,31 @@ def test_scale_tile_variants_identical(tmp_path):
     cd.cdvs_tune_set(pipe.ctx, cd.KERNEL_SCALES, other)
     cd.cdvs_autotune(pipe.ctx, pipe.d_images, pipe.d_pyr, cache)   # cache hit
     assert cd.cdvs_tune_get(pipe.ctx, cd.KERNEL_SCALES) == v
+
+
+def test_ragged_1024_sampled(O32):
+    """The uneven-size workload at its full size (1024 images, one packed
+    context, captured graph, autotuned tile shape): invariants on every
+    image, oracle parity on sampled ones."""
+    imgs = synth.ragged_batch(synth.SEED_RAGGED, 1024)
+    pipe = cd.Pipeline([(im.shape[1], im.shape[0]) for im in imgs])
+    pipe.upload(imgs)
+    cd.cdvs_autotune(pipe.ctx, pipe.d_images, pipe.d_pyr, None)
+    pipe.capture()
+    pipe.replay()
+    torch.cuda.synchronize()
+    assert pipe.sync_status() == cd.CDVS_OK
+    kps, oris, descs = pipe.keypoints(), pipe.oriented(), pipe.descriptors()
+    for i in range(len(imgs)):
+        assert 0 < len(kps[i]) <= 1000 and len(oris[i]) <= 1000
+        assert np.all(kps[i]["image"] == i)
+        assert np.all(np.diff(np.abs(kps[i]["p"])) <= 0)
+        np.testing.assert_allclose(np.linalg.norm(descs[i], axis=1), 1.0, atol=1e-5)
+    for i in (0, 517, 1023):
+        sel, ori, desc, _ = _oracle_stages(O32, imgs[i])
+        r1, r2, _ = rates(sel, kps[i])
+        q1, q2, err = _desc_agreement(ori, desc, oris[i], descs[i])
+        print(f"ragged image {i} {imgs[i].shape}: kp {r1:.4f}/{r2:.4f} ori {q1:.4f}/{q2:.4f} "
+              f"desc<=1e-3 {np.mean(err <= DESC_TOL):.4f}")
+        assert min(r1, r2, q1, q2) >= KP_RATE
+        assert err.max() <= 5e-2 and err.mean() <= 1e-3

@@ -122,3 +122,30 @@ def test_stream_consumer_failure_stops(hires):
     pipe.run()
     torch.cuda.synchronize()
     assert pipe.sync_status() == cd.CDVS_OK
+
+
+def test_stream_full_chunk_sampled(O32):
+    """Two chunks in the benchmark's launch configuration (256 images of
+    1280x960 per chunk, rendered on the device): sampled images' stand-in
+    codes equal the eager pass over their chunk, and agree with the oracle."""
+    n_chunks, chunk = 2, 256
+    pipe = cd.Pipeline([(W, H)] * chunk)
+    d_all = synth.device_batch(synth.SEED_HIRES, n_chunks * chunk, W, H, 400, 1200, smax=40.0)
+    codes, kept = pipe.stream(d_all, n_chunks, threads=8)
+    assert np.all(kept == 1000)
+    ib = pipe.image_bytes
+    for c, picks in ((0, (0, 255)), (1, (3,))):
+        pipe.d_images = d_all[c * ib:(c + 1) * ib]
+        pipe.run()
+        torch.cuda.synchronize()
+        descs = pipe.descriptors()
+        oris = pipe.oriented()
+        for i in picks:
+            g = c * chunk + i
+            np.testing.assert_array_equal(codes[g, :kept[g]], _codes(descs[i]))
+            img = d_all[g * W * H:(g + 1) * W * H].view(H, W).cpu().numpy()
+            kp, desc, _ = O32.run(img)
+            r1, r2, pairs = rates(kp, oris[i], oriented=True)
+            err = np.array([np.abs(desc[a] - descs[i][b]).max() for a, b in pairs])
+            print(f"stream image {g}: oriented {r1:.4f}/{r2:.4f} desc mean {err.mean():.2e}")
+            assert min(r1, r2) >= 0.99 and err.max() <= 5e-2 and err.mean() <= 1e-3
