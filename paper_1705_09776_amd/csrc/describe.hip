@@ -82,7 +82,7 @@ __device__ __forceinline__ void gradient(const KpGeom& g, int u, int v, float& m
     const float* row = g.plane + (int64_t)v * g.pitch;
     const float gx = row[u + 1] - row[u - 1];
     const float gy = row[u + g.pitch] - row[u - g.pitch];
-    mag = sqrtf(gx * gx + gy * gy);
+    mag = __builtin_amdgcn_sqrtf(gx * gx + gy * gy);   // hardware square root (1 ulp)
     ang = angle_2pi(gy, gx);
 }
 
@@ -155,15 +155,15 @@ __global__ __launch_bounds__(256) void k_orient(const float* __restrict__ pyr, c
                 if (!(d2 < R2)) continue;
                 float mag, ang;
                 gradient(g, u, v, mag, ang);
-                const float wt = mag * __expf(d2 * nid);
+                const float wt = mag * __expf(d2 * nid) * op.fix;   // in fixed-point units
                 const float fb = ang * ((float)kOriBins / kTwoPi);
                 const float f0 = floorf(fb);
                 const float fr = fb - f0;
                 int b0 = (int)f0;
                 b0 = b0 >= kOriBins ? b0 - kOriBins : b0;
                 const int b1 = b0 + 1 == kOriBins ? 0 : b0 + 1;
-                atomicAdd(hc + b0, (uint32_t)(wt * (1.f - fr) * op.fix + 0.5f));
-                atomicAdd(hc + b1, (uint32_t)(wt * fr * op.fix + 0.5f));
+                atomicAdd(hc + b0, (uint32_t)(wt - wt * fr + 0.5f));
+                atomicAdd(hc + b1, (uint32_t)(wt * fr + 0.5f));
             }
         }
     }
@@ -281,7 +281,7 @@ __global__ __launch_bounds__(256) void k_describe(const float* __restrict__ pyr,
                 float rel = ang - th;
                 if (rel < 0.f) rel += kTwoPi;
                 if (rel >= kTwoPi) rel -= kTwoPi;
-                const float wt = mag * __expf(d2 * nid);
+                const float wt = mag * __expf(d2 * nid) * dp.fix;   // in fixed-point units
                 const float fx = rx + 1.5f, fy = ry + 1.5f, fo = rel * (8.f / kTwoPi);
                 const float x0f = floorf(fx), y0f = floorf(fy), o0f = floorf(fo);
                 const float ax = fx - x0f, ay = fy - y0f, ao = fo - o0f;
@@ -297,9 +297,10 @@ __global__ __launch_bounds__(256) void k_describe(const float* __restrict__ pyr,
                         const int xx = x0 + jx;
                         if ((unsigned)xx > 3u) continue;
                         const float wyx = wy * (jx ? ax : 1.f - ax);
+                        const float w1 = wyx * ao;
                         uint32_t* cell = hc + (yy * 4 + xx) * 8;
-                        atomicAdd(cell + o0, (uint32_t)(wyx * (1.f - ao) * dp.fix + 0.5f));
-                        atomicAdd(cell + o1, (uint32_t)(wyx * ao * dp.fix + 0.5f));
+                        atomicAdd(cell + o0, (uint32_t)(wyx - w1 + 0.5f));
+                        atomicAdd(cell + o1, (uint32_t)(w1 + 0.5f));
                     }
                 }
             }
