@@ -170,7 +170,7 @@ hipError_t launch_orient_compact(const cdvs_keypoint* ori, const int32_t* ori_cn
 hipError_t launch_describe(const float* pyr, const OctGeom* geom, const cdvs_keypoint* kp, const int32_t* count,
                            int n_images, const DescParams& dp, float* desc, hipStream_t stream);
 
-constexpr int kCnnFragShorts = kCnnLayers * 9 * 64 * 4;   // packed MFMA weight fragments
+constexpr int kCnnFragShorts = kCnnLayers * 5 * 64 * 8;   // packed MFMA weight fragments (5 tap pairs)
 hipError_t launch_cnn_infer(const uint8_t* images, const float* params, short* frag, const CnnImage* imgs, int nimg,
                             int ntiles, float* logits, uint8_t* mask, float zthr, hipStream_t s);
 hipError_t launch_cnn_forward(const uint8_t* images, const float* params, short* acts, int64_t ncells,

@@ -20,7 +20,19 @@ namespace cdvs {
 namespace {
 
 typedef short s4 __attribute__((ext_vector_type(4)));
+typedef short s8 __attribute__((ext_vector_type(8)));
+typedef __bf16 b8 __attribute__((ext_vector_type(8)));
 typedef float f4 __attribute__((ext_vector_type(4)));
+
+// Forward 3x3 convolutions use v_mfma_f32_16x16x32_bf16, two taps per
+// instruction: lane l holds A[l%16][8(l/16)+j] and B[8(l/16)+j][l%16] for
+// j = 0..7 (checked on the device), so with k = 16 (tap - 2m) + ci the lanes
+// with l/16 = 2h + c carry tap 2m + h, input channels 8c..8c+7; the tenth tap
+// of the last pair is zero.
+constexpr int kTapPairs = 5;
+__device__ __forceinline__ f4 mfma32(const s8& a, const s8& b, const f4& c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(b8, a), __builtin_bit_cast(b8, b), c, 0, 0, 0);
+}
 
 constexpr int CC = kCnnChannels;   // 16
 constexpr int NHD = kCnnHeads;     // 6
@@ -85,25 +97,32 @@ __global__ __launch_bounds__(256) void k_conv_fwd(const uint8_t* __restrict__ im
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int cy = (lt / g.tiles_x) * kCnnTileH + wave;
     const int px = (lt % g.tiles_x) * kCnnTileW + (lane & 15);
-    const int kb = lane >> 4;
+    const int kb = lane >> 4, half = kb >> 1, c8 = (kb & 1) * 8;
     if (cy >= g.H4) return;
-    s4 a[9];
+    s8 a[kTapPairs];
 #pragma unroll
-    for (int t = 0; t < 9; ++t)
+    for (int m = 0; m < kTapPairs; ++m) {
+        const int t = 2 * m + half;
 #pragma unroll
-        for (int j = 0; j < 4; ++j) a[t][j] = f2bf(Wl[(t * CC + 4 * kb + j) * CC + (lane & 15)]);
+        for (int j = 0; j < 8; ++j) a[m][j] = t < 9 ? f2bf(Wl[(t * CC + c8 + j) * CC + (lane & 15)]) : (short)0;
+    }
     f4 acc;
 #pragma unroll
     for (int r = 0; r < 4; ++r) acc[r] = bl[4 * kb + r];
 #pragma unroll
-    for (int t = 0; t < 9; ++t) {
+    for (int m = 0; m < kTapPairs; ++m) {
+        const int t = 2 * m + half;
         const int yy = cy + t / 3 - 1, xx = px + t % 3 - 1;
-        s4 b = {0, 0, 0, 0};
-        if (yy >= 0 && yy < g.H4 && xx >= 0 && xx < g.W4) {
-            if constexpr (FIRST) b = s2d_frag(images, g, yy, xx, kb);
-            else b = *reinterpret_cast<const s4*>(X + (g.cell0 + (int64_t)yy * g.W4 + xx) * CC + 4 * kb);
+        s8 b = {0, 0, 0, 0, 0, 0, 0, 0};
+        if (t < 9 && yy >= 0 && yy < g.H4 && xx >= 0 && xx < g.W4) {
+            if constexpr (FIRST) {
+                const s4 lo = s2d_frag(images, g, yy, xx, 2 * (kb & 1)), hi = s2d_frag(images, g, yy, xx, 2 * (kb & 1) + 1);
+                b = s8{lo[0], lo[1], lo[2], lo[3], hi[0], hi[1], hi[2], hi[3]};
+            } else {
+                b = *reinterpret_cast<const s8*>(X + (g.cell0 + (int64_t)yy * g.W4 + xx) * CC + c8);
+            }
         }
-        acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[t], b, acc, 0, 0, 0);
+        acc = mfma32(a[m], b, acc);
     }
     if (px < g.W4) {
         s4 o;
@@ -166,7 +185,7 @@ __global__ __launch_bounds__(256) void k_head(const short* __restrict__ X4, cons
 // roundings), so logits and mask bits are identical to theirs.
 constexpr int FTW = kCnnFusedW, FTH = kCnnFusedH, FHALO = kCnnLayers;
 constexpr int FFW = FTW + 2 * FHALO, FFH = FTH + 2 * FHALO;   // 40 x 24 frame
-constexpr int FSTR = CC + 4;                                   // shorts per cell (40 B: spreads LDS banks)
+constexpr int FSTR = CC;                                       // shorts per cell (32 B, 16-byte aligned reads)
 
 __device__ __forceinline__ int find_ftile_image(const CnnImage* im, int n, int tile) {
     int lo = 0, hi = n - 1;
@@ -179,15 +198,15 @@ __device__ __forceinline__ int find_ftile_image(const CnnImage* im, int n, int t
 }
 
 // MFMA weight fragments of all layers, packed once per forward call:
-// frag[((l * 9 + t) * 64 + lane) * 4 + j] = bf16(W_l[t][4 (lane / 16) + j][lane % 16]),
-// exactly the A operand each lane of k_conv_fwd builds for itself.
+// frag[((l * kTapPairs + m) * 64 + lane) * 8 + j] is exactly the A operand
+// element j that lane `lane` of k_conv_fwd builds for tap pair m of layer l.
 __global__ void k_cnn_pack(const float* __restrict__ P, short* __restrict__ frag) {
-    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < kCnnLayers * 9 * 64; i += gridDim.x * blockDim.x) {
-        const int lane = i % 64, t = (i / 64) % 9, l = i / (64 * 9);
-        const int kb = lane >> 4, n16 = lane & 15;
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < kCnnLayers * kTapPairs * 64; i += gridDim.x * blockDim.x) {
+        const int lane = i % 64, m = (i / 64) % kTapPairs, l = i / (64 * kTapPairs);
+        const int kb = lane >> 4, t = 2 * m + (kb >> 1), c8 = (kb & 1) * 8;
         const float* Wl = P + l * LAYER_P;
 #pragma unroll
-        for (int j = 0; j < 4; ++j) frag[i * 4 + j] = f2bf(Wl[(t * CC + 4 * kb + j) * CC + n16]);
+        for (int j = 0; j < 8; ++j) frag[i * 8 + j] = t < 9 ? f2bf(Wl[(t * CC + c8 + j) * CC + (lane & 15)]) : (short)0;
     }
 }
 
@@ -247,10 +266,11 @@ __global__ __launch_bounds__(256, 2) void k_cnn_infer(const uint8_t* __restrict_
         }
         *reinterpret_cast<s4*>(&buf[0][(fy * FFW + fx) * FSTR + 4 * r4]) = v;
     }
-    s4 a[9];
-    const s4* fr = reinterpret_cast<const s4*>(frag);
+    const int half = kb >> 1, c8 = (kb & 1) * 8;
+    s8 a[kTapPairs];
+    const s8* fr = reinterpret_cast<const s8*>(frag);
 #pragma unroll
-    for (int t = 0; t < 9; ++t) a[t] = fr[t * 64 + lane];
+    for (int m = 0; m < kTapPairs; ++m) a[m] = fr[m * 64 + lane];
     __syncthreads();
 
 #pragma unroll 1
@@ -259,10 +279,10 @@ __global__ __launch_bounds__(256, 2) void k_cnn_infer(const uint8_t* __restrict_
 #pragma unroll
         for (int r = 0; r < 4; ++r) bias[r] = P[l * LAYER_P + CONV_W + 4 * kb + r];
         // the next layer's fragments load while this layer computes
-        s4 an[9];
+        s8 an[kTapPairs];
         const int ln = l + 1 < kCnnLayers ? l + 1 : l;
 #pragma unroll
-        for (int t = 0; t < 9; ++t) an[t] = fr[(ln * 9 + t) * 64 + lane];
+        for (int m = 0; m < kTapPairs; ++m) an[m] = fr[(ln * kTapPairs + m) * 64 + lane];
         const short* X = buf[l & 1];
         short* Y = buf[(l + 1) & 1];
         const int lo = l + 1, C = FFW - 2 * lo, n = (FFH - 2 * lo) * C;
@@ -271,9 +291,11 @@ __global__ __launch_bounds__(256, 2) void k_cnn_infer(const uint8_t* __restrict_
             const int fy = lo + q / C, fx = lo + q % C;
             f4 acc = bias;
 #pragma unroll
-            for (int t = 0; t < 9; ++t) {
-                const s4 b = *reinterpret_cast<const s4*>(&X[((fy + t / 3 - 1) * FFW + fx + t % 3 - 1) * FSTR + 4 * kb]);
-                acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[t], b, acc, 0, 0, 0);
+            for (int m = 0; m < kTapPairs; ++m) {
+                const int t = 2 * m + half;
+                s8 b = {0, 0, 0, 0, 0, 0, 0, 0};
+                if (t < 9) b = *reinterpret_cast<const s8*>(&X[((fy + t / 3 - 1) * FFW + fx + t % 3 - 1) * FSTR + c8]);
+                acc = mfma32(a[m], b, acc);
             }
             if (q0 + (lane & 15) < n) {
                 const int cy = oy + fy, cx = ox + fx;
@@ -285,7 +307,7 @@ __global__ __launch_bounds__(256, 2) void k_cnn_infer(const uint8_t* __restrict_
             }
         }
 #pragma unroll
-        for (int t = 0; t < 9; ++t) a[t] = an[t];
+        for (int m = 0; m < kTapPairs; ++m) a[m] = an[m];
         __syncthreads();
     }
 
