@@ -69,6 +69,7 @@ def algorithmic(sizes, n_kp, n_ori):
 
 WEIGHTS = os.path.join(ROOT, "paper_1705_09776_amd", "weights", "surrogate_640x480.npz")
 WEIGHTS_HIRES = os.path.join(ROOT, "paper_1705_09776_amd", "weights", "surrogate_1280x960.npz")
+WEIGHTS_T4 = os.path.join(ROOT, "paper_1705_09776_amd", "weights", "surrogate_640x480_t4.npz")
 TRAFFIC = os.path.join(ROOT, "profiles", "traffic_plain_batch256_640x480.md")
 _PROFILE_NAME = {"detect": "k_detect", "describe": "k_describe", "scales": "k_blur<scales>", "orient": "k_orient",
                  "finalize": "k_finalize", "preblur": "k_blur<preblur>"}
@@ -128,6 +129,62 @@ def gated_leg(pipe, steps, B, plain_kp):
             "active_cell_fraction": round(act / (5 * mask.size), 4),
             "timing": "K eager steps (CNN mask, pyramid, gated detection, orientation, descriptors)",
             "kernels_ms_per_step": {k: round(v[0] / steps, 4) for k, v in prof.items() if v[1]}}
+
+
+def sparse_leg(imgs, steps, contrast=4.0):
+    """Sensitivity point with sparse keypoints: the same batch with contrast
+    threshold T = 4 (instead of 1.5), plain pass (graph replays) against the
+    pass gated by a network trained on T = 4 labels (eager steps)."""
+    import torch
+    import paper_1705_09776_amd as cd
+    from paper_1705_09776_amd import surrogate
+    B = len(imgs)
+    p = cd.default_params()
+    p.contrast = contrast
+    pipe = cd.Pipeline([(640, 480)] * B, params=p)
+    pipe.upload(list(imgs))
+    pipe.run()
+    pipe.capture()
+    pipe.replay()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        pipe.replay()
+    torch.cuda.synchronize()
+    t_plain = (time.perf_counter() - t0) / steps
+    pipe.run()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        pipe.run()
+    torch.cuda.synchronize()
+    t_plain_eager = (time.perf_counter() - t0) / steps
+    plain_kp = [k.copy() for k in pipe.keypoints()]
+    st = surrogate.load_checkpoint(WEIGHTS_T4)
+    with open(os.path.splitext(WEIGHTS_T4)[0] + ".json") as f:
+        tau = float(json.load(f)["tau"])
+    params = torch.from_numpy(st["params"]).cuda()
+    for _ in range(2):
+        pipe.run_gated(params, tau)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        pipe.run_gated(params, tau)
+    torch.cuda.synchronize()
+    t_gated = (time.perf_counter() - t0) / steps
+    if pipe.sync_status() != cd.CDVS_OK:
+        raise RuntimeError("capacity overflow in the sparse leg")
+    gk = pipe.keypoints()
+    key = lambda k: (int(k["octave"]), int(k["ix"]), int(k["iy"]))
+    hit = sum(len({key(k) for k in a} & {key(k) for k in b}) for a, b in zip(plain_kp, gk))
+    mask = pipe.d_mask.cpu().numpy()
+    act = sum(int(((mask >> o) & 1).sum()) for o in range(5))
+    return {"contrast": contrast, "tau": tau, "keypoints_per_image": round(sum(len(k) for k in plain_kp) / B, 1),
+            "plain_images_per_s": round(B / t_plain, 1), "plain_eager_images_per_s": round(B / t_plain_eager, 1),
+            "gated_images_per_s": round(B / t_gated, 1),
+            "recall_top1000": round(hit / max(1, sum(len(a) for a in plain_kp)), 5),
+            "active_cell_fraction": round(act / (5 * mask.size), 4),
+            "timing": "plain: K graph replays (and K eager steps); gated: K eager steps"}
 
 
 def ragged_leg(steps, n=1024):
@@ -384,6 +441,9 @@ def main():
         plain_kp = [k.copy() for k in pipe.keypoints()]
         out["plain_eager_images_per_s"] = round(B / (eager_ms * 1e-3), 1)
         out["gated"] = gated_leg(pipe, args.steps, B, plain_kp)
+    if os.path.exists(WEIGHTS_T4) and not args.no_gated:
+        log("[bench] sparse-keypoint sensitivity leg (contrast 4)")
+        out["sparse_t4"] = sparse_leg(imgs, args.steps)
     if not args.no_ragged:
         log("[bench] ragged leg (1024 images of uneven size)")
         out["ragged"] = ragged_leg(args.steps)

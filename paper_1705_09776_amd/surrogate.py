@@ -36,9 +36,11 @@ def init_params(seed: int = 0) -> np.ndarray:
     return p
 
 
-def label_pipeline(batch: int, width=640, height=480) -> Pipeline:
+def label_pipeline(batch: int, width=640, height=480, contrast=None) -> Pipeline:
     p = default_params()
     p.topk = LABEL_TOPK
+    if contrast is not None:
+        p.contrast = contrast
     return Pipeline([(width, height)] * batch, params=p, kp_capacity=LABEL_TOPK)
 
 
@@ -55,7 +57,7 @@ class Trainer:
     device straight into the batch buffer."""
 
     def __init__(self, batch=32, width=None, height=None, lr=1e-3, seed=0, data_seed=4, dataset=20000,
-                 recipe="vga"):
+                 recipe="vga", contrast=None):
         import torch
         self.torch = torch
         self.recipe = RECIPES[recipe]
@@ -65,7 +67,8 @@ class Trainer:
         self.dataset = dataset   # training images are indices 0..dataset-1, visited in order, epoch after epoch
         self.width, self.height = width, height
         self.on_device = recipe == "hires"
-        self.pipe = label_pipeline(batch, width, height)
+        self.contrast = contrast    # detector contrast threshold of the labels (None: the default)
+        self.pipe = label_pipeline(batch, width, height, contrast)
         self.pipe.cnn_buffers()
         dev = self.pipe.d_pyr.device
         self.params = torch.from_numpy(init_params(seed)).to(dev)
@@ -200,7 +203,7 @@ def load_checkpoint(path: str) -> dict:
     return state
 
 
-def evaluate(params, images, taus, topk=1000, fmax=None):
+def evaluate(params, images, taus, topk=1000, fmax=None, contrast=None):
     """Recall of the gated detector against the plain one on `images`.
 
     Returns one dict per tau: recall over all final keypoints (top-k set to
@@ -214,8 +217,10 @@ def evaluate(params, images, taus, topk=1000, fmax=None):
     p.topk = topk
     if fmax is not None:
         p.mask_fmax = fmax
+    if contrast is not None:
+        p.contrast = contrast
     pipe_k = Pipeline(sizes, params=p, kp_capacity=max(topk, 1))
-    pipe_all = label_pipeline(len(images), *sizes[0]) if len(set(sizes)) == 1 else None
+    pipe_all = label_pipeline(len(images), *sizes[0], contrast=contrast) if len(set(sizes)) == 1 else None
     pipe_k.upload(images)
     pipe_k.cnn_buffers()
     pipe_k.pyramid()

@@ -19,7 +19,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
-TAUS = [0.02, 0.05, 0.1, 0.2, 0.3, 0.5]
+TAUS = [0.005, 0.01, 0.02, 0.05, 0.1, 0.2, 0.3, 0.5]
 
 
 def main(argv=None):
@@ -36,6 +36,8 @@ def main(argv=None):
     ap.add_argument("--recipe", choices=["vga", "hires"], default="vga",
                     help="vga: 640x480 (train seed base 4, eval 5); hires: 1280x960 (train 7, eval 6)")
     ap.add_argument("--init", default=None, help="start from this checkpoint's parameters (fresh optimiser)")
+    ap.add_argument("--contrast", type=float, default=None,
+                    help="detector contrast threshold for labels and evaluation (default: the library's, 1.5)")
     args = ap.parse_args(argv)
 
     import numpy as np
@@ -46,7 +48,7 @@ def main(argv=None):
     hires = args.recipe == "hires"
     tr = surrogate.Trainer(batch=args.batch, lr=args.lr, seed=args.seed,
                            data_seed=synth.SEED_HIRES_TRAIN if hires else synth.SEED_TRAIN,
-                           dataset=args.images, recipe=args.recipe)
+                           dataset=args.images, recipe=args.recipe, contrast=args.contrast)
     if args.init:
         tr.params.copy_(torch.from_numpy(surrogate.load_checkpoint(args.init)["params"]).to(tr.params.device))
     if args.resume:
@@ -58,7 +60,7 @@ def main(argv=None):
     if args.out:
         os.makedirs(os.path.dirname(os.path.abspath(args.out)), exist_ok=True)
         tr.save(args.out)
-    report = {"recipe": args.recipe, "init": args.init, "dataset": args.images, "images_seen": tr.cursor, "steps": tr.step, "batch": args.batch, "train_s": round(t_train, 1),
+    report = {"recipe": args.recipe, "init": args.init, "contrast": args.contrast, "dataset": args.images, "images_seen": tr.cursor, "steps": tr.step, "batch": args.batch, "train_s": round(t_train, 1),
               "loss_first": float(np.mean(losses[:10])) if losses else None,
               "loss_last": float(np.mean(losses[-10:])) if losses else None,
               "pos_weight": tr.pos_weight.cpu().numpy().round(2).tolist() if tr.pos_weight is not None else None}
@@ -66,10 +68,10 @@ def main(argv=None):
         print(f"evaluating on {args.eval} images", file=sys.stderr, flush=True)
         imgs = list(synth.hires_batch(synth.SEED_HIRES, args.eval) if hires
                     else synth.fixed_batch(synth.SEED_EVAL, args.eval))
-        report["sweep"] = surrogate.evaluate(tr.params, imgs, TAUS)
+        report["sweep"] = surrogate.evaluate(tr.params, imgs, TAUS, contrast=args.contrast)
         ok = [r["tau"] for r in report["sweep"] if r["recall_topk"] >= 0.98]
         report["tau"] = max(ok) if ok else min(TAUS)
-        untrained = surrogate.evaluate(surrogate.init_params(args.seed), imgs, [report["tau"]])
+        untrained = surrogate.evaluate(surrogate.init_params(args.seed), imgs, [report["tau"]], contrast=args.contrast)
         report["untrained_at_tau"] = untrained[0]
     if args.out:
         with open(os.path.splitext(args.out)[0] + ".json", "w") as f:

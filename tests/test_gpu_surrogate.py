@@ -37,3 +37,16 @@ def test_trained_mask_beats_untrained():
     assert trained["active_fraction"] <= 0.45
     assert untrained["recall_topk"] < trained["recall_topk"] - 0.02 or \
         untrained["active_fraction"] > 1.5 * trained["active_fraction"]
+
+
+def test_sparse_keypoint_model():
+    """At contrast threshold 4 (sparse keypoints) the committed T = 4 model,
+    at its stored threshold, keeps >= 98% of the plain detector's keypoints
+    on held-out images with a quarter of the (cell, octave) entries active."""
+    w = os.path.join(ROOT, "paper_1705_09776_amd", "weights", "surrogate_640x480_t4.npz")
+    st = surrogate.load_checkpoint(w)
+    tau = json.load(open(os.path.splitext(w)[0] + ".json"))["tau"]
+    imgs = list(synth.fixed_batch(synth.SEED_EVAL, 64, first=3000))
+    r = surrogate.evaluate(st["params"], imgs, [tau], contrast=4.0)[0]
+    print("T=4", r)
+    assert r["recall_topk"] >= 0.975 and r["active_fraction"] <= 0.35
