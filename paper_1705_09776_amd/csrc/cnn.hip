@@ -286,24 +286,39 @@ __global__ __launch_bounds__(256, 2) void k_cnn_infer(const uint8_t* __restrict_
         const short* X = buf[l & 1];
         short* Y = buf[(l + 1) & 1];
         const int lo = l + 1, C = FFW - 2 * lo, n = (FFH - 2 * lo) * C;
-        for (int q0 = wave * 16; q0 < n; q0 += 64) {
-            const int q = min(q0 + (lane & 15), n - 1);
-            const int fy = lo + q / C, fx = lo + q % C;
-            f4 acc = bias;
+        // two independent 16-cell blocks per wave step, so that consecutive
+        // MFMAs do not wait on each other's accumulator
+        for (int q0 = wave * 32; q0 < n; q0 += 128) {
+            int fy[2], fx[2];
+            f4 acc[2] = {bias, bias};
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const int q = min(q0 + 16 * h + (lane & 15), n - 1);
+                fy[h] = lo + q / C;
+                fx[h] = lo + q % C;
+            }
 #pragma unroll
             for (int m = 0; m < kTapPairs; ++m) {
                 const int t = 2 * m + half;
-                s8 b = {0, 0, 0, 0, 0, 0, 0, 0};
-                if (t < 9) b = *reinterpret_cast<const s8*>(&X[((fy + t / 3 - 1) * FFW + fx + t % 3 - 1) * FSTR + c8]);
-                acc = mfma32(a[m], b, acc);
-            }
-            if (q0 + (lane & 15) < n) {
-                const int cy = oy + fy, cx = ox + fx;
-                const bool in = cy >= 0 && cy < g.H4 && cx >= 0 && cx < g.W4;
-                s4 o;
 #pragma unroll
-                for (int r = 0; r < 4; ++r) o[r] = in ? f2bf(fmaxf(acc[r], 0.f)) : (short)0;
-                *reinterpret_cast<s4*>(&Y[(fy * FFW + fx) * FSTR + 4 * kb]) = o;
+                for (int h = 0; h < 2; ++h) {
+                    s8 b = {0, 0, 0, 0, 0, 0, 0, 0};
+                    if (t < 9)
+                        b = *reinterpret_cast<const s8*>(
+                            &X[((fy[h] + t / 3 - 1) * FFW + fx[h] + t % 3 - 1) * FSTR + c8]);
+                    acc[h] = mfma32(a[m], b, acc[h]);
+                }
+            }
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                if (q0 + 16 * h + (lane & 15) < n) {
+                    const int cy = oy + fy[h], cx = ox + fx[h];
+                    const bool in = cy >= 0 && cy < g.H4 && cx >= 0 && cx < g.W4;
+                    s4 o;
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) o[r] = in ? f2bf(fmaxf(acc[h][r], 0.f)) : (short)0;
+                    *reinterpret_cast<s4*>(&Y[(fy[h] * FFW + fx[h]) * FSTR + 4 * kb]) = o;
+                }
             }
         }
 #pragma unroll

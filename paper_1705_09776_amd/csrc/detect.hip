@@ -345,38 +345,37 @@ __global__ __launch_bounds__(256) void k_detect(const float* __restrict__ pyr, c
     }
 }
 
-// Gating pre-pass, one workgroup per detection tile (all octaves in one
+// Gating pre-pass, one wave per detection tile (all octaves in one
 // launch): the tile's active-centre row masks (bit cx of row cy) and its
 // state.  An octave-o centre (x, y) is active when it lies inside the
 // detection border and bit o of the mask cell holding (x 2^o, y 2^o) / 4 is
 // set; when the image's active-cell fraction for that octave exceeds
 // gate.fmax the whole octave is dense (every border-valid centre active).
-__global__ __launch_bounds__(256) void k_gate_rows(const DetTile* __restrict__ tiles, DetParams dp, GateParams gate,
-                                                   uint64_t* __restrict__ rows_out, int32_t* __restrict__ state_out) {
-    __shared__ int any_s;
-    const DetTile job = tiles[blockIdx.x];
+__global__ __launch_bounds__(256) void k_gate_rows(const DetTile* __restrict__ tiles, int ntiles, DetParams dp,
+                                                   GateParams gate, uint64_t* __restrict__ rows_out,
+                                                   int32_t* __restrict__ state_out) {
+    // one wave per tile, lane = tile column
+    const int tile = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+    if (tile >= ntiles) return;   // uniform over the wave
+    const DetTile job = tiles[tile];
     const CnnImage& cg = gate.cells[job.image];
     const bool dense = (float)gate.active[job.image * kMaxOctaves + job.octave] > gate.fmax * (float)(cg.H4 * cg.W4);
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    if (threadIdx.x == 0) any_s = 0;
-    __syncthreads();
     const int gx = job.tx0 + lane;
     const int cx = min((gx << job.octave) >> 2, cg.W4 - 1);
+    const bool colok = gx >= dp.border && gx <= job.w - 1 - dp.border;
     bool any = false;
-    for (int cy = wave; cy < DTH; cy += 4) {
+    for (int cy = 0; cy < DTH; ++cy) {
         const int gy = job.ty0 + cy;
-        bool on = gx >= dp.border && gx <= job.w - 1 - dp.border && gy >= dp.border && gy <= job.h - 1 - dp.border;
+        bool on = colok && gy >= dp.border && gy <= job.h - 1 - dp.border;
         if (on && !dense) {
             const int cyc = min((gy << job.octave) >> 2, cg.H4 - 1);
             on = (gate.mask[cg.cell0 + (int64_t)cyc * cg.W4 + cx] >> job.octave) & 1;
         }
         const uint64_t m = __ballot(on);
-        if (lane == 0) rows_out[(int64_t)blockIdx.x * DTH + cy] = m;
+        if (lane == cy) rows_out[(int64_t)tile * DTH + cy] = m;
         any |= m != 0;
     }
-    if (any && lane == 0) atomicOr(&any_s, 1);
-    __syncthreads();
-    if (threadIdx.x == 0) state_out[blockIdx.x] = !any_s ? kTileSkip : (dense ? kTileDense : kTileSparse);
+    if (lane == 0) state_out[tile] = !any ? kTileSkip : (dense ? kTileDense : kTileSparse);
 }
 
 // Exclusive prefix of the values held by the lanes of a wave.
@@ -712,7 +711,7 @@ hipError_t launch_detect(const float* pyr, const DetTile* tiles, int ntiles, int
 hipError_t launch_gate_rows(const DetTile* tiles, int ntiles, const DetParams& dp, const GateParams& gate,
                             uint64_t* rows, int32_t* state, hipStream_t stream) {
     if (ntiles <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_gate_rows, dim3(ntiles), dim3(256), 0, stream, tiles, dp, gate, rows, state);
+    hipLaunchKernelGGL(k_gate_rows, dim3((ntiles + 3) / 4), dim3(256), 0, stream, tiles, ntiles, dp, gate, rows, state);
     return hipGetLastError();
 }
 
