@@ -157,7 +157,9 @@ cdvs_status cdvs_pyramid(cdvs_ctx* ctx, const uint8_t* d_images, float* d_pyr, v
  * cell layout of cdvs_cnn_cell_layout); an octave-o pixel (x, y) is examined
  * only when bit o of the cell holding (x 2^o, y 2^o) / 4 is set -- neighbours
  * are still read in full -- unless more than mask_fmax of that image's cells
- * have bit o set, in which case octave o of that image is examined densely. */
+ * have bit o set, in which case octave o of that image is examined densely.
+ * d_pyr must be 256-byte aligned (as cdvs_pyramid requires), else
+ * CDVS_ERR_ARG. */
 cdvs_status cdvs_alp_detect(cdvs_ctx* ctx, const float* d_pyr, const uint8_t* d_mask, cdvs_keypoint* d_kp,
                             int32_t* d_count, void* stream);
 
@@ -211,7 +213,10 @@ cdvs_status cdvs_graph_launch(cdvs_ctx* ctx, void* stream);
  * runs, median; blocking) and keeps the fastest.  With cache_path (may be
  * NULL) a JSON file keyed by (GPU arch, kernel, image size, batch-size
  * bucket) is read first (a hit skips the timing) and updated after timing.
- * cdvs_tune_get / cdvs_tune_set read and force the shape. */
+ * cdvs_tune_get / cdvs_tune_set read and force the shape.  A captured graph
+ * keeps the shape that was selected when it was captured.  The cache file is
+ * a JSON object with one "key": {...} entry per line; an unreadable file is
+ * treated as empty and rewritten. */
 #define CDVS_TUNE_VARIANTS 4
 cdvs_status cdvs_autotune(cdvs_ctx* ctx, const uint8_t* d_images, float* d_pyr, const char* cache_path,
                           void* stream);

@@ -538,6 +538,7 @@ cdvs_status cdvs_alp_detect(cdvs_ctx* ctx, const float* d_pyr, const uint8_t* d_
                             int32_t* d_count, void* stream) {
     if (!ctx) return CDVS_ERR_STATE;
     if (!d_pyr || !d_kp || !d_count) return fail(ctx, CDVS_ERR_ARG, "cdvs_alp_detect: null device pointer");
+    if (((uintptr_t)d_pyr & 255) != 0) return fail(ctx, CDVS_ERR_ARG, "cdvs_alp_detect: d_pyr not 256-byte aligned");
     hipStream_t s = (hipStream_t)stream;
     GateParams gate{nullptr, nullptr, nullptr, 1.f, nullptr, nullptr};
     if (d_mask) {
@@ -575,6 +576,7 @@ cdvs_status cdvs_orient(cdvs_ctx* ctx, const float* d_pyr, const cdvs_keypoint* 
     if (!ctx) return CDVS_ERR_STATE;
     if (!d_pyr || !d_kp_in || !d_count_in || !d_kp_out || !d_count_out)
         return fail(ctx, CDVS_ERR_ARG, "cdvs_orient: null device pointer");
+    if (((uintptr_t)d_pyr & 255) != 0) return fail(ctx, CDVS_ERR_ARG, "cdvs_orient: d_pyr not 256-byte aligned");
     if ((const void*)d_kp_in == (const void*)d_kp_out || (const void*)d_count_in == (const void*)d_count_out)
         return fail(ctx, CDVS_ERR_ARG, "cdvs_orient: outputs must not alias inputs");
     hipStream_t s = (hipStream_t)stream;
@@ -595,6 +597,7 @@ cdvs_status cdvs_describe(cdvs_ctx* ctx, const float* d_pyr, const cdvs_keypoint
                           float* d_desc, void* stream) {
     if (!ctx) return CDVS_ERR_STATE;
     if (!d_pyr || !d_kp || !d_count || !d_desc) return fail(ctx, CDVS_ERR_ARG, "cdvs_describe: null device pointer");
+    if (((uintptr_t)d_pyr & 255) != 0) return fail(ctx, CDVS_ERR_ARG, "cdvs_describe: d_pyr not 256-byte aligned");
     hipStream_t s = (hipStream_t)stream;
     Bracket b(ctx, CDVS_KERNEL_DESCRIBE, s);
     HIP_OR_FAIL(ctx, launch_describe(d_pyr, ctx->d_geom, d_kp, d_count, ctx->n, ctx->desc, d_desc, s));
@@ -771,6 +774,8 @@ static void tune_cache_store(const char* path, const std::string& key, int varia
     while (f && std::getline(f, line)) {
         size_t q = line.find('"');
         if (q == std::string::npos || line.find(pat) != std::string::npos) continue;
+        // keep only well-formed entries of other keys; anything else is dropped
+        if (line.find("\"variant\": ") == std::string::npos || line.find("\"us\": [") == std::string::npos) continue;
         size_t e = line.find_last_of('}');
         if (e == std::string::npos) continue;
         entries.push_back(line.substr(q, e - q + 1));

@@ -306,6 +306,11 @@ def test_scale_tile_variants_identical(tmp_path):
     cd.cdvs_tune_set(pipe.ctx, cd.KERNEL_SCALES, other)
     cd.cdvs_autotune(pipe.ctx, pipe.d_images, pipe.d_pyr, cache)   # cache hit
     assert cd.cdvs_tune_get(pipe.ctx, cd.KERNEL_SCALES) == v
+    # a corrupt cache is replaced by a valid one
+    bad = str(tmp_path / "bad.json")
+    open(bad, "w").write("not json {\n\"x\": }\n")
+    cd.cdvs_autotune(pipe.ctx, pipe.d_images, pipe.d_pyr, bad)
+    assert len(json.load(open(bad))) == 1
 
 
 def test_ragged_1024_sampled(O32):
@@ -334,3 +339,17 @@ def test_ragged_1024_sampled(O32):
               f"desc<=1e-3 {np.mean(err <= DESC_TOL):.4f}")
         assert min(r1, r2, q1, q2) >= KP_RATE
         assert err.max() <= 5e-2 and err.mean() <= 1e-3
+
+
+def test_misaligned_pyramid_rejected():
+    """Host-side argument checks: a pyramid pointer off the 256-byte
+    alignment is refused by every call that reads it, before any launch."""
+    pipe = cd.Pipeline([(64, 48)])
+    bad = pipe.d_pyr[1:]
+    for call in (lambda: cd.cdvs_pyramid(pipe.ctx, pipe.d_images, bad),
+                 lambda: cd.cdvs_alp_detect(pipe.ctx, bad, None, pipe.d_kp, pipe.d_count),
+                 lambda: cd.cdvs_orient(pipe.ctx, bad, pipe.d_kp, pipe.d_count, pipe.d_kp_ori, pipe.d_count_ori),
+                 lambda: cd.cdvs_describe(pipe.ctx, bad, pipe.d_kp_ori, pipe.d_count_ori, pipe.d_desc)):
+        with pytest.raises(cd.CdvsError) as e:
+            call()
+        assert e.value.status == cd.CDVS_ERR_ARG
