@@ -52,6 +52,11 @@ struct cdvs_ctx {
     int32_t* d_gate_state = nullptr;  // [detection tile] skip / sparse / dense
     // device
     OctJob* d_jobs = nullptr;
+    std::vector<int32_t> blur_owner;           // [variant][octave][tile] -> job (relative to job_start[octave])
+    int blur_owner_start[kBlurVariants][kMaxOctaves] = {};
+    int32_t* d_blur_owner = nullptr;
+    std::vector<int32_t> cnn_owner;            // fused CNN tile -> image
+    int32_t* d_cnn_owner = nullptr;
     std::vector<DetTile> dtiles;               // detection tiles, grouped by octave
     int dtile_start[kMaxOctaves + 1] = {};
     DetTile* d_dtiles = nullptr;
@@ -262,6 +267,8 @@ void cdvs_ctx_destroy(cdvs_ctx* ctx) {
     for (auto& e : ctx->ev) (void)hipEventDestroy(e);
     (void)hipFree(ctx->d_jobs);
     (void)hipFree(ctx->d_dtiles);
+    (void)hipFree(ctx->d_blur_owner);
+    (void)hipFree(ctx->d_cnn_owner);
     (void)hipFree(ctx->d_geom);
     (void)hipFree(ctx->d_cand);
     (void)hipFree(ctx->d_cand_cnt);
@@ -339,6 +346,16 @@ static cdvs_status build_layout(cdvs_ctx* c) {
         for (int v = 0; v < kBlurVariants; ++v) c->blur_tiles[v][o] = tb[v];
         c->det_tiles[o] = td;
     }
+    c->blur_owner.clear();
+    for (int v = 0; v < kBlurVariants; ++v)
+        for (int o = 0; o < kMaxOctaves; ++o) {
+            c->blur_owner_start[v][o] = (int)c->blur_owner.size();
+            for (size_t j = 0; j < per_oct[o].size(); ++j) {
+                const OctJob& jb = per_oct[o][j];
+                const int nt = jb.tiles_x_blur[v] * ((jb.h + blur_th(v) - 1) / blur_th(v));
+                for (int t = 0; t < nt; ++t) c->blur_owner.push_back((int32_t)j);
+            }
+        }
     c->dtiles.clear();
     for (int o = 0; o < kMaxOctaves; ++o) {
         c->dtile_start[o] = (int)c->dtiles.size();
@@ -383,6 +400,7 @@ static cdvs_status build_layout(cdvs_ctx* c) {
         g.ftiles_x = (g.W4 + kCnnFusedW - 1) / kCnnFusedW;
         g.ftile0 = ftiles;
         ftiles += g.ftiles_x * ((g.H4 + kCnnFusedH - 1) / kCnnFusedH);
+        c->cnn_owner.resize(ftiles, i);
         tiles += g.tiles_x * ((g.H4 + kCnnTileH - 1) / kCnnTileH);
         chunks += g.tiles_x * g.H4;
         cell += (int64_t)g.H4 * g.W4;
@@ -458,6 +476,8 @@ cdvs_status cdvs_ctx_create(const cdvs_params* params, const cdvs_image_desc* im
     } while (0)
     ALLOC(c->d_jobs, sizeof(OctJob) * std::max<size_t>(1, c->jobs.size()));
     ALLOC(c->d_dtiles, sizeof(DetTile) * std::max<size_t>(1, c->dtiles.size()));
+    ALLOC(c->d_blur_owner, sizeof(int32_t) * std::max<size_t>(1, c->blur_owner.size()));
+    ALLOC(c->d_cnn_owner, sizeof(int32_t) * std::max<size_t>(1, c->cnn_owner.size()));
     ALLOC(c->d_geom, sizeof(OctGeom) * c->geom.size());
     ALLOC(c->d_cand, sizeof(cdvs_keypoint) * n * kCandCap);
     ALLOC(c->d_cand_cnt, sizeof(int32_t) * n);
@@ -473,6 +493,10 @@ cdvs_status cdvs_ctx_create(const cdvs_params* params, const cdvs_image_desc* im
     if ((e = hipMemcpy(c->d_jobs, c->jobs.data(), sizeof(OctJob) * c->jobs.size(), hipMemcpyHostToDevice)) != hipSuccess ||
         (e = hipMemcpy(c->d_dtiles, c->dtiles.data(), sizeof(DetTile) * c->dtiles.size(), hipMemcpyHostToDevice)) !=
             hipSuccess ||
+        (e = hipMemcpy(c->d_blur_owner, c->blur_owner.data(), sizeof(int32_t) * c->blur_owner.size(),
+                       hipMemcpyHostToDevice)) != hipSuccess ||
+        (e = hipMemcpy(c->d_cnn_owner, c->cnn_owner.data(), sizeof(int32_t) * c->cnn_owner.size(),
+                       hipMemcpyHostToDevice)) != hipSuccess ||
         (e = hipMemcpy(c->d_geom, c->geom.data(), sizeof(OctGeom) * c->geom.size(), hipMemcpyHostToDevice)) != hipSuccess ||
         (e = hipMemcpy(c->d_cnn, c->cnn.data(), sizeof(CnnImage) * n, hipMemcpyHostToDevice)) != hipSuccess ||
         (e = hipMemset(c->d_flags, 0, sizeof(int32_t))) != hipSuccess ||
@@ -524,12 +548,15 @@ cdvs_status cdvs_pyramid(cdvs_ctx* ctx, const uint8_t* d_images, float* d_pyr, v
     {
         Bracket b(ctx, CDVS_KERNEL_PREBLUR, s);
         HIP_OR_FAIL(ctx, launch_preblur(d_images, d_pyr, ctx->d_jobs + ctx->job_start[0],
-                                        ctx->job_start[1] - ctx->job_start[0], ctx->blur_tiles[0][0], ctx->taps, s));
+                                        ctx->d_blur_owner + ctx->blur_owner_start[0][0], ctx->blur_tiles[0][0],
+                                        ctx->taps, s));
     }
     for (int o = 0; o < ctx->max_oct; ++o) {
         Bracket b(ctx, CDVS_KERNEL_SCALES, s);
-        HIP_OR_FAIL(ctx, launch_scales(d_pyr, ctx->d_jobs + ctx->job_start[o], ctx->job_start[o + 1] - ctx->job_start[o],
-                                       ctx->blur_tiles[ctx->blur_variant][o], ctx->blur_variant, ctx->taps, s));
+        const int v = ctx->blur_variant;
+        HIP_OR_FAIL(ctx, launch_scales(d_pyr, ctx->d_jobs + ctx->job_start[o],
+                                       ctx->d_blur_owner + ctx->blur_owner_start[v][o], ctx->blur_tiles[v][o], v,
+                                       ctx->taps, s));
     }
     return CDVS_OK;
 }
@@ -639,8 +666,8 @@ cdvs_status cdvs_cnn_forward(cdvs_ctx* ctx, const uint8_t* d_images, const float
     Bracket b(ctx, CDVS_KERNEL_CNN_FORWARD, s);
     if (!d_acts) {
         if (!d_logits && !d_mask) return CDVS_OK;
-        HIP_OR_FAIL(ctx, launch_cnn_infer(d_images, d_params, ctx->d_cnn_frag, ctx->d_cnn, ctx->n, ctx->cnn_ftiles,
-                                          d_logits, d_mask, zthr, s));
+        HIP_OR_FAIL(ctx, launch_cnn_infer(d_images, d_params, ctx->d_cnn_frag, ctx->d_cnn, ctx->d_cnn_owner,
+                                          ctx->cnn_ftiles, d_logits, d_mask, zthr, s));
         return CDVS_OK;
     }
     HIP_OR_FAIL(ctx, launch_cnn_forward(d_images, d_params, (short*)d_acts, ctx->ncells, ctx->d_cnn, ctx->n,

@@ -148,10 +148,10 @@ __host__ __device__ constexpr int blur_th(int v) { return v == 0 ? 32 : v == 1 ?
 constexpr int kDetTW = 64, kDetTH = 16;
 
 // Launchers (each enqueues on `stream`, returns the launch error).
-hipError_t launch_preblur(const uint8_t* images, float* pyr, const OctJob* jobs, int njobs, int ntiles,
+hipError_t launch_preblur(const uint8_t* images, float* pyr, const OctJob* jobs, const int32_t* owner, int ntiles,
                           const Taps& taps, hipStream_t stream);
-hipError_t launch_scales(float* pyr, const OctJob* jobs, int njobs, int ntiles, int variant, const Taps& taps,
-                         hipStream_t stream);
+hipError_t launch_scales(float* pyr, const OctJob* jobs, const int32_t* owner, int ntiles, int variant,
+                         const Taps& taps, hipStream_t stream);
 hipError_t launch_clear(int32_t* p, int n, hipStream_t stream);
 hipError_t launch_gate_rows(const DetTile* tiles, int ntiles, const DetParams& dp, const GateParams& gate,
                             uint64_t* rows, int32_t* state, hipStream_t stream);
@@ -171,8 +171,8 @@ hipError_t launch_describe(const float* pyr, const OctGeom* geom, const cdvs_key
                            int n_images, const DescParams& dp, float* desc, hipStream_t stream);
 
 constexpr int kCnnFragShorts = kCnnLayers * 5 * 64 * 8;   // packed MFMA weight fragments (5 tap pairs)
-hipError_t launch_cnn_infer(const uint8_t* images, const float* params, short* frag, const CnnImage* imgs, int nimg,
-                            int ntiles, float* logits, uint8_t* mask, float zthr, hipStream_t s);
+hipError_t launch_cnn_infer(const uint8_t* images, const float* params, short* frag, const CnnImage* imgs,
+                            const int32_t* owner, int ntiles, float* logits, uint8_t* mask, float zthr, hipStream_t s);
 hipError_t launch_cnn_forward(const uint8_t* images, const float* params, short* acts, int64_t ncells,
                               const CnnImage* imgs, int nimg, int ntiles, float* logits, uint8_t* mask, float zthr,
                               hipStream_t s);

@@ -187,15 +187,6 @@ constexpr int FTW = kCnnFusedW, FTH = kCnnFusedH, FHALO = kCnnLayers;
 constexpr int FFW = FTW + 2 * FHALO, FFH = FTH + 2 * FHALO;   // 40 x 24 frame
 constexpr int FSTR = CC;                                       // shorts per cell (32 B, 16-byte aligned reads)
 
-__device__ __forceinline__ int find_ftile_image(const CnnImage* im, int n, int tile) {
-    int lo = 0, hi = n - 1;
-    while (lo < hi) {
-        int mid = (lo + hi + 1) >> 1;
-        if (im[mid].ftile0 <= tile) lo = mid;
-        else hi = mid - 1;
-    }
-    return lo;
-}
 
 // MFMA weight fragments of all layers, packed once per forward call:
 // frag[((l * kTapPairs + m) * 64 + lane) * 8 + j] is exactly the A operand
@@ -215,14 +206,15 @@ static_assert(FFH * FFW * 4 % 256 == 0, "the frame's cell rows split evenly over
 
 __global__ __launch_bounds__(256, 2) void k_cnn_infer(const uint8_t* __restrict__ images, const float* __restrict__ P,
                                                       const short* __restrict__ frag,
-                                                      const CnnImage* __restrict__ imgs, int nimg,
+                                                      const CnnImage* __restrict__ imgs,
+                                                      const int32_t* __restrict__ owner,
                                                       float* __restrict__ logits, uint8_t* __restrict__ mask,
                                                       float zthr) {
     __shared__ __align__(16) short buf[2][FFH * FFW * FSTR];
     __shared__ short lut[256];
     __shared__ float head[CC * NHD + NHD];
     const int tile = xcd_remap(blockIdx.x, gridDim.x);
-    const CnnImage& g = imgs[find_ftile_image(imgs, nimg, tile)];
+    const CnnImage& g = imgs[owner[tile]];   // per-tile owner table: one load, no search
     const int lt = tile - g.ftile0;
     const int ty0 = (lt / g.ftiles_x) * FTH, tx0 = (lt % g.ftiles_x) * FTW;
     const int oy = ty0 - FHALO, ox = tx0 - FHALO;   // image cell of frame (0, 0)
@@ -581,11 +573,11 @@ __global__ __launch_bounds__(256) void k_mask_count(const uint8_t* __restrict__ 
 
 }  // namespace
 
-hipError_t launch_cnn_infer(const uint8_t* images, const float* params, short* frag, const CnnImage* imgs, int nimg,
-                            int ntiles, float* logits, uint8_t* mask, float zthr, hipStream_t s) {
+hipError_t launch_cnn_infer(const uint8_t* images, const float* params, short* frag, const CnnImage* imgs,
+                            const int32_t* owner, int ntiles, float* logits, uint8_t* mask, float zthr, hipStream_t s) {
     if (ntiles <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_cnn_pack, dim3(9), dim3(256), 0, s, params, frag);
-    hipLaunchKernelGGL(k_cnn_infer, dim3(ntiles), dim3(256), 0, s, images, params, frag, imgs, nimg, logits, mask,
+    hipLaunchKernelGGL(k_cnn_infer, dim3(ntiles), dim3(256), 0, s, images, params, frag, imgs, owner, logits, mask,
                        zthr);
     return hipGetLastError();
 }

@@ -22,18 +22,6 @@ __host__ __device__ constexpr int radius_of(int k) {
     return k == 0 ? kR0 : k == 1 ? kR1 : k == 2 ? kR2 : k == 3 ? kR3 : kR4;
 }
 
-// Job owning global tile `tile` of tile variant VAR (jobs sorted by tile0).
-template <int VAR>
-__device__ __forceinline__ int find_blur_job(const OctJob* jobs, int njobs, int tile) {
-    int lo = 0, hi = njobs - 1;
-    while (lo < hi) {
-        int mid = (lo + hi + 1) >> 1;
-        if (jobs[mid].tile0_blur[VAR] <= tile) lo = mid;
-        else hi = mid - 1;
-    }
-    return lo;
-}
-
 // Column pass of tap set K over a register window of V + 2*HALO rows:
 // out[r] = sum_{p=-R..R} g_K[p] * win[r + HALO + p], taps in order p = -R..R.
 template <int K, int HALO, int V>
@@ -93,7 +81,8 @@ __device__ __forceinline__ void store_decimated(float* dst, int x0, int nw, cons
 // outputs G_{o,1..4} and the decimated G_{o+1,0}.
 template <int KFIRST, int NK, int HALO, bool U8, int VAR>
 __global__ __launch_bounds__(256) void k_blur(const uint8_t* __restrict__ images, float* __restrict__ pyr,
-                                              const OctJob* __restrict__ jobs, int njobs, Taps taps) {
+                                              const OctJob* __restrict__ jobs, const int32_t* __restrict__ owner,
+                                              Taps taps) {
     constexpr int TW = blur_tw(VAR), TH = blur_th(VAR), V = kBlurV;
     static_assert(TH % V == 0 && TW % 8 == 0, "tile shape");
     constexpr int C = TW + 2 * HALO;
@@ -102,7 +91,7 @@ __global__ __launch_bounds__(256) void k_blur(const uint8_t* __restrict__ images
     __shared__ float T[NK][TH][CP];
 
     const int tile = xcd_remap(blockIdx.x, gridDim.x);
-    const OctJob& job = jobs[find_blur_job<VAR>(jobs, njobs, tile)];
+    const OctJob& job = jobs[owner[tile]];   // per-tile owner table: one load, no search
     const int lt = tile - job.tile0_blur[VAR];
     const int tx0 = (lt % job.tiles_x_blur[VAR]) * TW;
     const int ty0 = (lt / job.tiles_x_blur[VAR]) * TH;
@@ -167,22 +156,22 @@ __global__ __launch_bounds__(256) void k_blur(const uint8_t* __restrict__ images
 
 }  // namespace
 
-hipError_t launch_preblur(const uint8_t* images, float* pyr, const OctJob* jobs, int njobs, int ntiles,
+hipError_t launch_preblur(const uint8_t* images, float* pyr, const OctJob* jobs, const int32_t* owner, int ntiles,
                           const Taps& taps, hipStream_t stream) {
     if (ntiles <= 0) return hipSuccess;
-    hipLaunchKernelGGL((k_blur<0, 1, kR0, true, 0>), dim3(ntiles), dim3(256), 0, stream, images, pyr, jobs, njobs,
+    hipLaunchKernelGGL((k_blur<0, 1, kR0, true, 0>), dim3(ntiles), dim3(256), 0, stream, images, pyr, jobs, owner,
                        taps);
     return hipGetLastError();
 }
 
-hipError_t launch_scales(float* pyr, const OctJob* jobs, int njobs, int ntiles, int variant, const Taps& taps,
-                         hipStream_t stream) {
+hipError_t launch_scales(float* pyr, const OctJob* jobs, const int32_t* owner, int ntiles, int variant,
+                         const Taps& taps, hipStream_t stream) {
     if (ntiles <= 0) return hipSuccess;
     switch (variant) {
 #define CASE(V)                                                                                                   \
     case V:                                                                                                       \
         hipLaunchKernelGGL((k_blur<1, 4, kMaxR, false, V>), dim3(ntiles), dim3(256), 0, stream, nullptr, pyr, jobs, \
-                           njobs, taps);                                                                          \
+                           owner, taps);                                                                          \
         break;
         CASE(0)
         CASE(1)
