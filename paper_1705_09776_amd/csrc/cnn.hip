@@ -201,10 +201,10 @@ __global__ void k_cnn_pack(const float* __restrict__ P, short* __restrict__ frag
     }
 }
 
-constexpr int FSTAGE = FFH * FFW * 4 / 256;   // 4-pixel cell rows staged per lane
-static_assert(FFH * FFW * 4 % 256 == 0, "the frame's cell rows split evenly over the lanes");
+constexpr int FTHREADS = 512;                       // 8 waves: twice the latency hiding of 4 at the same LDS
+constexpr int FSTAGE = (FFH * FFW * 4 + FTHREADS - 1) / FTHREADS;   // 4-pixel cell rows staged per lane
 
-__global__ __launch_bounds__(256, 2) void k_cnn_infer(const uint8_t* __restrict__ images, const float* __restrict__ P,
+__global__ __launch_bounds__(FTHREADS, 2) void k_cnn_infer(const uint8_t* __restrict__ images, const float* __restrict__ P,
                                                       const short* __restrict__ frag,
                                                       const CnnImage* __restrict__ imgs,
                                                       const int32_t* __restrict__ owner,
@@ -221,7 +221,7 @@ __global__ __launch_bounds__(256, 2) void k_cnn_infer(const uint8_t* __restrict_
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, kb = lane >> 4;
 
     // u8 -> bf16(u / 255) table (the same expression as s2d_frag)
-    lut[threadIdx.x] = f2bf((float)threadIdx.x / 255.f);
+    if (threadIdx.x < 256) lut[threadIdx.x] = f2bf((float)threadIdx.x / 255.f);
     for (int i = threadIdx.x; i < CC * NHD + NHD; i += blockDim.x) head[i] = P[kCnnLayers * LAYER_P + i];
     // layer 0 input: s2d of the frame, zero outside the image.  Lanes take
     // consecutive cells of one pixel row (contiguous 4-byte groups); all
@@ -229,11 +229,11 @@ __global__ __launch_bounds__(256, 2) void k_cnn_infer(const uint8_t* __restrict_
     uint32_t px[FSTAGE];
 #pragma unroll
     for (int k = 0; k < FSTAGE; ++k) {
-        const int it = threadIdx.x + k * 256;
+        const int it = threadIdx.x + k * FTHREADS;
         const int fx = it % FFW, r4 = (it / FFW) & 3, fy = it / (FFW * 4);
         const int cy = oy + fy, cx = ox + fx;
         px[k] = 0;
-        if (cy >= 0 && cy < g.H4 && cx >= 0 && cx < g.W4) {
+        if (it < FFH * FFW * 4 && cy >= 0 && cy < g.H4 && cx >= 0 && cx < g.W4) {
             const int y = min(4 * cy + r4, g.H - 1);
             const uint8_t* row = images + g.src + (int64_t)y * g.src_pitch;
             const int x0 = 4 * cx;
@@ -248,7 +248,8 @@ __global__ __launch_bounds__(256, 2) void k_cnn_infer(const uint8_t* __restrict_
     __syncthreads();   // lut
 #pragma unroll
     for (int k = 0; k < FSTAGE; ++k) {
-        const int it = threadIdx.x + k * 256;
+        const int it = threadIdx.x + k * FTHREADS;
+        if (it >= FFH * FFW * 4) break;
         const int fx = it % FFW, r4 = (it / FFW) & 3, fy = it / (FFW * 4);
         const int cy = oy + fy, cx = ox + fx;
         s4 v = {0, 0, 0, 0};
@@ -280,7 +281,7 @@ __global__ __launch_bounds__(256, 2) void k_cnn_infer(const uint8_t* __restrict_
         const int lo = l + 1, C = FFW - 2 * lo, n = (FFH - 2 * lo) * C;
         // two independent 16-cell blocks per wave step, so that consecutive
         // MFMAs do not wait on each other's accumulator
-        for (int q0 = wave * 32; q0 < n; q0 += 128) {
+        for (int q0 = wave * 32; q0 < n; q0 += 32 * (FTHREADS / 64)) {
             int fy[2], fx[2];
             f4 acc[2] = {bias, bias};
 #pragma unroll
@@ -577,8 +578,8 @@ hipError_t launch_cnn_infer(const uint8_t* images, const float* params, short* f
                             const int32_t* owner, int ntiles, float* logits, uint8_t* mask, float zthr, hipStream_t s) {
     if (ntiles <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_cnn_pack, dim3(9), dim3(256), 0, s, params, frag);
-    hipLaunchKernelGGL(k_cnn_infer, dim3(ntiles), dim3(256), 0, s, images, params, frag, imgs, owner, logits, mask,
-                       zthr);
+    hipLaunchKernelGGL(k_cnn_infer, dim3(ntiles), dim3(FTHREADS), 0, s, images, params, frag, imgs, owner, logits,
+                       mask, zthr);
     return hipGetLastError();
 }
 
