@@ -75,6 +75,64 @@ _PROFILE_NAME = {"detect": "k_detect", "describe": "k_describe", "scales": "k_bl
                  "finalize": "k_finalize", "preblur": "k_blur<preblur>"}
 
 
+def measured_path_bytes():
+    """HBM bytes per step of the whole plain path from the committed counter
+    summary (every kernel's source unchanged), else None."""
+    total = 0
+    for k, n in (("detect", 5), ("scales", 5), ("describe", 1), ("orient", 1), ("finalize", 1), ("preblur", 1)):
+        b = measured_traffic(k)
+        if b is None:
+            return None
+        total += b * n
+    return total
+
+
+def achievable_hbm_gbs(nbytes=2 << 30, reps=5):
+    """Device-to-device copy rate (read + write bytes per second): what a
+    plain streaming kernel reaches on this GPU."""
+    import torch
+    a = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda").fill_(1.0)
+    b = torch.empty_like(a)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    dt = e0.elapsed_time(e1) * 1e-3 / reps
+    del a, b
+    torch.cuda.empty_cache()
+    return 2 * nbytes / dt / 1e9
+
+
+def single_leg(reps=200):
+    """One 640x480 image (the single-image workload): latency of one captured
+    pass, launch-bound rather than bandwidth-bound."""
+    import torch
+    import synth
+    import paper_1705_09776_amd as cd
+    img = synth.image(synth.SEED_SINGLE, 0, 640, 480)
+    pipe = cd.Pipeline([(640, 480)])
+    pipe.upload([img])
+    pipe.run()
+    pipe.capture()
+    for _ in range(10):
+        pipe.replay()
+    torch.cuda.synchronize()
+    lat = []
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        pipe.replay()
+        torch.cuda.synchronize()
+        lat.append(time.perf_counter() - t0)
+    lat.sort()
+    return {"latency_ms_median": round(lat[len(lat) // 2] * 1e3, 4), "latency_ms_p90": round(lat[int(0.9 * len(lat))] * 1e3, 4),
+            "keypoints": int(pipe.d_count_ori.item()),
+            "timing": f"{reps} replays of the captured pass, each followed by a device synchronisation"}
+
+
 def measured_traffic(kernel):
     """HBM bytes per launch of `kernel` from the committed counter summary
     (256 images 640x480), or None when there is none or the kernel's source
@@ -325,6 +383,8 @@ def main():
     ap.add_argument("--no-gated", action="store_true")
     ap.add_argument("--no-ragged", action="store_true")
     ap.add_argument("--no-stream", action="store_true")
+    ap.add_argument("--no-single", action="store_true")
+    ap.add_argument("--no-sparse", action="store_true")
     ap.add_argument("--stream-images", type=int, default=4096)
     args = ap.parse_args()
 
@@ -412,6 +472,15 @@ def main():
     roof["launch_us"] = d["avg_launch_us"]
     hbm_bytes = sum(v["bytes"] for v in alg.values() if v["bytes"] is not None)
 
+    ach = achievable_hbm_gbs()
+    path_bytes = measured_path_bytes() if B == 256 else None
+    hbm = {"model_gbs": round(hbm_bytes * args.steps / (t1 - t0) / 1e9, 1), "achievable_copy_gbs": round(ach, 1),
+           "model_frac_of_peak": round(hbm_bytes * args.steps / (t1 - t0) / 1e9 / PEAK_HBM_GBS, 4),
+           "model_frac_of_achievable": round(hbm_bytes * args.steps / (t1 - t0) / 1e9 / ach, 4)}
+    if path_bytes is not None:
+        g = path_bytes / (ms_per_step * 1e-3) / 1e9
+        hbm.update({"counter_gbs": round(g, 1), "counter_frac_of_peak": round(g / PEAK_HBM_GBS, 4),
+                    "counter_frac_of_achievable": round(g / ach, 4)})
     out = {
         "metric": "images/s at 640x480 (plain vs surrogate-gated @>=98% kp recall); HBM GB/s",
         "value": round(value, 1),
@@ -428,6 +497,7 @@ def main():
         "config": {"workload": f"plain path, batch of {B} images 640x480, top-1000 keypoints described per image",
                    "batch": B, "width": 640, "height": 480, "topk": 1000, "path": "plain"},
         "model_hbm_gbs": round(hbm_bytes * args.steps / (t1 - t0) / 1e9, 1),
+        "hbm": hbm,
         "timing": "value: K back-to-back hipGraph replays of the whole pass; kernels: K eager steps with "
                   "per-kernel HIP events",
         "eager_ms_per_step": round(eager_ms, 4),
@@ -441,7 +511,10 @@ def main():
         plain_kp = [k.copy() for k in pipe.keypoints()]
         out["plain_eager_images_per_s"] = round(B / (eager_ms * 1e-3), 1)
         out["gated"] = gated_leg(pipe, args.steps, B, plain_kp)
-    if os.path.exists(WEIGHTS_T4) and not args.no_gated:
+    if not args.no_single:
+        log("[bench] single image latency")
+        out["single"] = single_leg()
+    if os.path.exists(WEIGHTS_T4) and not args.no_gated and not args.no_sparse:
         log("[bench] sparse-keypoint sensitivity leg (contrast 4)")
         out["sparse_t4"] = sparse_leg(imgs, args.steps)
     if not args.no_ragged:
