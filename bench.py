@@ -358,9 +358,12 @@ def cpu_baseline(imgs, seconds: float):
     O = oracle.Oracle("f64")
     cores = os.cpu_count() or 1
     cores = min(cores, 16)
-    t0 = time.perf_counter()
-    O.run(imgs[0], image=0)                # probe one image
-    per = time.perf_counter() - t0
+    single = []
+    for _ in range(5):                     # one image, one thread: median of 5
+        t0 = time.perf_counter()
+        O.run(imgs[0], image=0)
+        single.append(time.perf_counter() - t0)
+    per = sorted(single)[2]
     # about `seconds` of wall time on all threads; images cycle through the batch
     n = max(cores, int(seconds * cores / max(per, 1e-3)))
     t0 = time.perf_counter()
@@ -368,6 +371,7 @@ def cpu_baseline(imgs, seconds: float):
         list(ex.map(lambda i: O.run(imgs[i % len(imgs)], image=i), range(n)))
     dt = time.perf_counter() - t0
     return {"value": round(n / dt, 3), "unit": "images/s", "cores": cores, "kind": "oracle",
+            "single_thread_ms_per_image": round(per * 1e3, 1),
             "sample": f"{n} images drawn in order from the {len(imgs)}-image batch (cycling), whole path "
                       f"per image (fp64 oracle, one image per thread), {cores} threads, {dt:.1f} s"}
 
