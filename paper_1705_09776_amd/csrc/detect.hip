@@ -283,43 +283,15 @@ __device__ __forceinline__ DetTile as_uniform(RawTile r) {
     return t;
 }
 
-// One tile of the dense detector, its planes already in `vals`: stage,
-// start the loads of the next tile into the same registers, then
-// coefficients, extremal scales with contrast into an LDS list, and the 3x3
-// test and refinement on the list.
-__device__ __forceinline__ void dense_tile(const float* __restrict__ pyr, float (&G)[kScales][GH][GW],
-                                           float4 (&A)[AH][AW], int& nlist, float4 (&vals)[DNPER4],
-                                           const DetTile& cur, bool load_next, const DetTile& nxt, const DetParams& dp,
-                                           cdvs_keypoint* __restrict__ cand, int32_t* __restrict__ cand_cnt,
-                                           int32_t* __restrict__ flags) {
-    __syncthreads();  // the previous tile is done with G, A and the list
-    store_tile(&G[0][0][0], vals);
-    if (threadIdx.x == 0) nlist = 0;
-    __syncthreads();
-    if (load_next) load_tile(pyr, nxt, vals);
-    for (int t = threadIdx.x; t < AH * AW; t += blockDim.x) {
-        const int ay = t / AW, ax = t % AW;
-        A[ay][ax] = alpha_at(G, ay + 1, ax + 1 + GX, dp);
-    }
-    __syncthreads();
-    // contrast-passing centres go to a list in the (now free) staging buffer
-    float4* list = reinterpret_cast<float4*>(&G[0][0][0]);
-    for (int it = 0; it < DTW * DTH / 256; ++it) {
-        const int q = threadIdx.x + it * 256;
-        const int cy = q / DTW, cx = q % DTW;
-        const int gx = cur.tx0 + cx, gy = cur.ty0 + cy;
-        float cs = 0.f, cp = 0.f, cpss = 0.f;
-        const bool pass = gx >= dp.border && gx <= cur.w - 1 - dp.border && gy >= dp.border &&
-                          gy <= cur.h - 1 - dp.border && centre_extremum(A, cy, cx, dp, cs, cp, cpss);
-        push_centre(pass, cs, cp, cpss, q, list, &nlist);
-    }
-    __syncthreads();
-    refine_list(A, list, nlist, cur, dp, cand, cand_cnt, flags);
-}
-
 // Persistent: the grid (a multiple of 8) is split evenly over the XCDs; each
 // workgroup walks its XCD's contiguous tile range with a stride, and the next
 // tile's loads are in flight while the current tile is computed.
+// The refinement of a tile's contrast-passing centres (which ends in global
+// atomics whose results are awaited) runs at the start of the next
+// iteration, before that iteration issues its prefetch: a wait on a global
+// atomic also waits for every vector load issued before it, so this way the
+// prefetched planes are in flight during the coefficients and extremal
+// scales, and the atomics only ever wait for loads about to be consumed.
 __global__ __launch_bounds__(256) void k_detect(const float* __restrict__ pyr, const DetTile* __restrict__ tiles,
                                                 int ntiles, DetParams dp, cdvs_keypoint* __restrict__ cand,
                                                 int32_t* __restrict__ cand_cnt, int32_t* __restrict__ flags) {
@@ -331,18 +303,43 @@ __global__ __launch_bounds__(256) void k_detect(const float* __restrict__ pyr, c
     const int per = ntiles / kXcds, rem = ntiles % kXcds;
     const int tbase = x * per + min(x, rem), cnt = per + (x < rem ? 1 : 0);
     if (slot >= cnt) return;   // uniform over the workgroup
+    float4* list = reinterpret_cast<float4*>(&G[0][0][0]);   // contrast-passing centres, after the coefficients
     float4 vals[DNPER4];
     DetTile cur = as_uniform(fetch_tile(tiles, tbase + slot));
+    DetTile prev = cur;
     load_tile(pyr, cur, vals);
     RawTile rn = fetch_tile(tiles, tbase + min(slot + nslot, cnt - 1));
     for (int tj = slot; tj < cnt; tj += nslot) {
         // the record two tiles ahead is fetched a whole tile before it is needed
         const RawTile rnn = fetch_tile(tiles, tbase + min(tj + 2 * nslot, cnt - 1));
         const DetTile nxt = as_uniform(rn);
-        dense_tile(pyr, G, A, nlist, vals, cur, tj + nslot < cnt, nxt, dp, cand, cand_cnt, flags);
+        __syncthreads();  // the previous tile's list and coefficients are complete
+        if (tj != slot) refine_list(A, list, nlist, prev, dp, cand, cand_cnt, flags);
+        __syncthreads();  // the previous tile is done with G, A and the list
+        store_tile(&G[0][0][0], vals);
+        if (threadIdx.x == 0) nlist = 0;
+        __syncthreads();
+        if (tj + nslot < cnt) load_tile(pyr, nxt, vals);
+        for (int t = threadIdx.x; t < AH * AW; t += blockDim.x) {
+            const int ay = t / AW, ax = t % AW;
+            A[ay][ax] = alpha_at(G, ay + 1, ax + 1 + GX, dp);
+        }
+        __syncthreads();
+        for (int it = 0; it < DTW * DTH / 256; ++it) {
+            const int q = threadIdx.x + it * 256;
+            const int cy = q / DTW, cx = q % DTW;
+            const int gx = cur.tx0 + cx, gy = cur.ty0 + cy;
+            float cs = 0.f, cp = 0.f, cpss = 0.f;
+            const bool pass = gx >= dp.border && gx <= cur.w - 1 - dp.border && gy >= dp.border &&
+                              gy <= cur.h - 1 - dp.border && centre_extremum(A, cy, cx, dp, cs, cp, cpss);
+            push_centre(pass, cs, cp, cpss, q, list, &nlist);
+        }
+        prev = cur;
         cur = nxt;
         rn = rnn;
     }
+    __syncthreads();
+    refine_list(A, list, nlist, prev, dp, cand, cand_cnt, flags);
 }
 
 // Gating pre-pass, one wave per detection tile (all octaves in one
