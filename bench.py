@@ -79,11 +79,11 @@ def measured_path_bytes():
     """HBM bytes per step of the whole plain path from the committed counter
     summary (every kernel's source unchanged), else None."""
     total = 0
-    for k, n in (("detect", 5), ("scales", 5), ("describe", 1), ("orient", 1), ("finalize", 1), ("preblur", 1)):
+    for k in ("detect", "scales", "describe", "orient", "finalize", "preblur"):
         b = measured_traffic(k)
         if b is None:
             return None
-        total += b * n
+        total += b
     return total
 
 
@@ -134,7 +134,7 @@ def single_leg(reps=200):
 
 
 def measured_traffic(kernel):
-    """HBM bytes per launch of `kernel` from the committed counter summary
+    """HBM bytes per step of `kernel` from the committed counter summary
     (256 images 640x480), or None when there is none or the kernel's source
     has changed since the counters were taken."""
     import hashlib
@@ -471,7 +471,8 @@ def main():
     else:
         roof = {"bound": "alu", "achieved": None, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s"}
     roof["frac"] = round(roof["achieved"] / roof["peak"], 4) if roof["achieved"] is not None else None
-    roof["traffic"] = measured_traffic(dom) if B == 256 else None   # HBM bytes per launch (rocprofv3 counters)
+    step_bytes = measured_traffic(dom) if B == 256 else None       # HBM bytes per step (rocprofv3 counters)
+    roof["traffic"] = round(step_bytes / d["launches_per_step"]) if step_bytes is not None else None  # per launch
     roof["kernel"] = dom
     roof["launch_us"] = d["avg_launch_us"]
     hbm_bytes = sum(v["bytes"] for v in alg.values() if v["bytes"] is not None)

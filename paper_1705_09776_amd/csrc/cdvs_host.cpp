@@ -579,6 +579,8 @@ cdvs_status cdvs_alp_detect(cdvs_ctx* ctx, const float* d_pyr, const uint8_t* d_
         Bracket b(ctx, CDVS_KERNEL_CLEAR, s);
         HIP_OR_FAIL(ctx, launch_clear(ctx->d_cand_cnt, ctx->n, s));
     }
+    // one persistent launch per octave (measured faster than a single launch
+    // over all octaves); the finalisation does not rely on the order
     for (int o = 0; o < ctx->max_oct; ++o) {
         Bracket b(ctx, CDVS_KERNEL_DETECT, s);
         GateParams go = gate;
@@ -587,8 +589,7 @@ cdvs_status cdvs_alp_detect(cdvs_ctx* ctx, const float* d_pyr, const uint8_t* d_
             go.state += ctx->dtile_start[o];
         }
         HIP_OR_FAIL(ctx, launch_detect(d_pyr, ctx->d_dtiles + ctx->dtile_start[o], ctx->det_tiles[o],
-                                       ctx->detect_grid, ctx->det, go, ctx->d_cand,
-                                       ctx->d_cand_cnt, ctx->d_flags, s));
+                                       ctx->detect_grid, ctx->det, go, ctx->d_cand, ctx->d_cand_cnt, ctx->d_flags, s));
     }
     {
         Bracket b(ctx, CDVS_KERNEL_FINALIZE, s);

@@ -8,7 +8,7 @@
 //   centre pixel: extremal scale, contrast test, strict 8-neighbour test at
 //   that scale, one quadratic refinement step.  Survivors are compacted with
 //   one wave ballot and one atomic per wave into the image's candidate list.
-//   Octaves are launched in order, so each image's list is grouped by octave.
+//   One persistent launch per octave covers that octave of every image.
 // k_finalize: one workgroup per image.  Stage C (cross-octave duplicates)
 //   over adjacent-octave segments, then a bitonic sort in LDS on the 64-bit
 //   key (|p| desc, octave, iy, ix) and the top-k copy-out.
