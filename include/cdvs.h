@@ -158,6 +158,13 @@ cdvs_status cdvs_pyramid(cdvs_ctx* ctx, const uint8_t* d_images, float* d_pyr, v
  * only when bit o of the cell holding (x 2^o, y 2^o) / 4 is set -- neighbours
  * are still read in full -- unless more than mask_fmax of that image's cells
  * have bit o set, in which case octave o of that image is examined densely.
+ * Each image holds up to max(8192, W*H/64 rounded up to 256) candidates
+ * before stage C; one that finds more than its capacity keeps those stored
+ * and latches an overflow.  Stage C and the top-k work on at most 8192
+ * candidates per image: an image with more is first cut to its 8192 largest
+ * |p|, which leaves the result unchanged whenever its last kept keypoint is
+ * stronger than the weakest of those (a candidate is only ever removed by a
+ * stronger one); when it is not, the image is latched as inexact.
  * d_pyr must be 256-byte aligned (as cdvs_pyramid requires), else
  * CDVS_ERR_ARG. */
 cdvs_status cdvs_alp_detect(cdvs_ctx* ctx, const float* d_pyr, const uint8_t* d_mask, cdvs_keypoint* d_kp,
@@ -188,11 +195,13 @@ cdvs_status cdvs_describe(cdvs_ctx* ctx, const float* d_pyr, const cdvs_keypoint
                           float* d_desc, void* stream);
 
 /* Synchronise `stream`, then return CDVS_ERR_CAPACITY if any call since the
- * last cdvs_sync_status dropped results (more candidates than the context's
- * scratch holds), else CDVS_OK; clears the latch.  The only blocking call. */
+ * last cdvs_sync_status latched a candidate overflow or an inexact top-k
+ * (see cdvs_alp_detect), else CDVS_OK; clears the latch.  The only blocking
+ * call. */
 cdvs_status cdvs_sync_status(cdvs_ctx* ctx, void* stream);
 
-/* Candidate scratch size per image (pre-deduplication candidates). */
+/* Smallest candidate capacity over the context's images (pre-deduplication
+ * candidates: max(8192, W*H/64 rounded up to 256) per image). */
 int32_t cdvs_candidate_capacity(const cdvs_ctx* ctx);
 
 /* HIP graph of one whole pass.  cdvs_graph_capture records cdvs_pyramid,

@@ -211,6 +211,10 @@ def cdvs_tune_set(ctx, kernel: int, variant: int):
     _check(ctx, lib().cdvs_tune_set(ctx, kernel, variant))
 
 
+def cdvs_candidate_capacity(ctx) -> int:
+    return int(lib().cdvs_candidate_capacity(ctx))
+
+
 def cdvs_cnn_cells(ctx) -> int:
     return int(lib().cdvs_cnn_cells(ctx))
 
@@ -477,6 +481,9 @@ class Pipeline:
 
     def num_octaves(self, image):
         return int(lib().cdvs_num_octaves(self.ctx, image))
+
+    def candidate_capacity(self):
+        return cdvs_candidate_capacity(self.ctx)
 
     @staticmethod
     def _records(t, counts):

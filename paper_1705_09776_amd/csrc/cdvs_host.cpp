@@ -61,7 +61,12 @@ struct cdvs_ctx {
     int dtile_start[kMaxOctaves + 1] = {};
     DetTile* d_dtiles = nullptr;
     OctGeom* d_geom = nullptr;
-    cdvs_keypoint* d_cand = nullptr;
+    cdvs_keypoint* d_cand = nullptr;           // per image: cand_cap[i] records from cand_off[i]
+    std::vector<int64_t> cand_off;
+    std::vector<int32_t> cand_cap;
+    int64_t* d_cand_off = nullptr;
+    int32_t* d_cand_capv = nullptr;
+    cdvs_keypoint* d_sel = nullptr;            // [image][kCandCap] strongest candidates (only when needed)
     int32_t* d_cand_cnt = nullptr;
     cdvs_keypoint* d_ori = nullptr;
     int32_t* d_ori_cnt = nullptr;
@@ -271,6 +276,9 @@ void cdvs_ctx_destroy(cdvs_ctx* ctx) {
     (void)hipFree(ctx->d_cnn_owner);
     (void)hipFree(ctx->d_geom);
     (void)hipFree(ctx->d_cand);
+    (void)hipFree(ctx->d_cand_off);
+    (void)hipFree(ctx->d_cand_capv);
+    (void)hipFree(ctx->d_sel);
     (void)hipFree(ctx->d_cand_cnt);
     (void)hipFree(ctx->d_ori);
     (void)hipFree(ctx->d_ori_cnt);
@@ -356,6 +364,18 @@ static cdvs_status build_layout(cdvs_ctx* c) {
                 for (int t = 0; t < nt; ++t) c->blur_owner.push_back((int32_t)j);
             }
         }
+    // candidate capacity per image: kCandCap, or one slot per 64 base pixels
+    // for larger images (noise extrema of the first octave alone come to
+    // about one per 200 pixels at the default contrast)
+    c->cand_off.assign(c->n, 0);
+    c->cand_cap.assign(c->n, 0);
+    int64_t cand_total = 0;
+    for (int i = 0; i < c->n; ++i) {
+        const int64_t want = round_up((int64_t)c->images[i].width * c->images[i].height / 64, kCandBlock);
+        c->cand_cap[i] = (int32_t)std::min<int64_t>(std::max<int64_t>(kCandCap, want), 1 << 24);
+        c->cand_off[i] = cand_total;
+        cand_total += c->cand_cap[i];
+    }
     c->dtiles.clear();
     for (int o = 0; o < kMaxOctaves; ++o) {
         c->dtile_start[o] = (int)c->dtiles.size();
@@ -373,6 +393,8 @@ static cdvs_status build_layout(cdvs_ctx* c) {
                 r.ty0 = (t / j.tiles_x_det) * kDetTH;
                 r.image = j.image;
                 r.octave = j.octave;
+                r.cand_cap = c->cand_cap[j.image];
+                r.cand_blk = (int32_t)(c->cand_off[j.image] / kCandBlock);
                 c->dtiles.push_back(r);
             }
         }
@@ -441,7 +463,6 @@ static void build_constants(cdvs_ctx* c) {
     c->det.edge_lim = (p.edge_r + 1.f) * (p.edge_r + 1.f) / p.edge_r;
     c->det.max_off = p.max_offset;
     c->det.border = p.border;
-    c->det.cand_cap = kCandCap;
     c->dedup_ratio = (float)pow(2.0, (double)p.dedup_dlog2);
     c->ori = OriParams{p.ori_radius, p.ori_wsigma, p.ori_peak, p.sigma0, fixed_scale(p.ori_radius, p.sigma0),
                        p.max_ori, c->kp_cap};
@@ -479,7 +500,18 @@ cdvs_status cdvs_ctx_create(const cdvs_params* params, const cdvs_image_desc* im
     ALLOC(c->d_blur_owner, sizeof(int32_t) * std::max<size_t>(1, c->blur_owner.size()));
     ALLOC(c->d_cnn_owner, sizeof(int32_t) * std::max<size_t>(1, c->cnn_owner.size()));
     ALLOC(c->d_geom, sizeof(OctGeom) * c->geom.size());
-    ALLOC(c->d_cand, sizeof(cdvs_keypoint) * n * kCandCap);
+    {
+        int64_t total = 0;
+        int32_t cmax = 0;
+        for (int i = 0; i < n; ++i) {
+            total += c->cand_cap[i];
+            cmax = std::max(cmax, c->cand_cap[i]);
+        }
+        ALLOC(c->d_cand, sizeof(cdvs_keypoint) * total);
+        ALLOC(c->d_cand_off, sizeof(int64_t) * n);
+        ALLOC(c->d_cand_capv, sizeof(int32_t) * n);
+        if (cmax > kCandCap) ALLOC(c->d_sel, sizeof(cdvs_keypoint) * n * kCandCap);
+    }
     ALLOC(c->d_cand_cnt, sizeof(int32_t) * n);
     ALLOC(c->d_ori, sizeof(cdvs_keypoint) * n * kp_capacity * kMaxOri);
     ALLOC(c->d_ori_cnt, sizeof(int32_t) * n * kp_capacity);
@@ -499,6 +531,9 @@ cdvs_status cdvs_ctx_create(const cdvs_params* params, const cdvs_image_desc* im
                        hipMemcpyHostToDevice)) != hipSuccess ||
         (e = hipMemcpy(c->d_geom, c->geom.data(), sizeof(OctGeom) * c->geom.size(), hipMemcpyHostToDevice)) != hipSuccess ||
         (e = hipMemcpy(c->d_cnn, c->cnn.data(), sizeof(CnnImage) * n, hipMemcpyHostToDevice)) != hipSuccess ||
+        (e = hipMemcpy(c->d_cand_off, c->cand_off.data(), sizeof(int64_t) * n, hipMemcpyHostToDevice)) != hipSuccess ||
+        (e = hipMemcpy(c->d_cand_capv, c->cand_cap.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice)) !=
+            hipSuccess ||
         (e = hipMemset(c->d_flags, 0, sizeof(int32_t))) != hipSuccess ||
         (e = hipMemset(c->d_cand_cnt, 0, sizeof(int32_t) * n)) != hipSuccess) {
         fail(nullptr, CDVS_ERR_HIP, "context upload: %s", hipGetErrorString(e));
@@ -525,7 +560,12 @@ int32_t cdvs_num_octaves(const cdvs_ctx* ctx, int32_t image) {
     return ctx->octaves[image];
 }
 
-int32_t cdvs_candidate_capacity(const cdvs_ctx* ctx) { return ctx ? kCandCap : -1; }
+int32_t cdvs_candidate_capacity(const cdvs_ctx* ctx) {
+    if (!ctx) return -1;
+    int32_t m = ctx->cand_cap.empty() ? kCandCap : ctx->cand_cap[0];
+    for (int32_t v : ctx->cand_cap) m = std::min(m, v);
+    return m;
+}
 
 cdvs_status cdvs_plane_layout(const cdvs_ctx* ctx, int32_t image, int32_t octave, int32_t k, int64_t* offset,
                               int32_t* width, int32_t* height, int32_t* pitch) {
@@ -593,8 +633,11 @@ cdvs_status cdvs_alp_detect(cdvs_ctx* ctx, const float* d_pyr, const uint8_t* d_
     }
     {
         Bracket b(ctx, CDVS_KERNEL_FINALIZE, s);
-        HIP_OR_FAIL(ctx, launch_finalize(ctx->d_cand, ctx->d_cand_cnt, ctx->n, kCandCap, ctx->dedup_ratio,
-                                         ctx->params.topk, ctx->kp_cap, d_kp, d_count, s));
+        HIP_OR_FAIL(ctx, launch_select(ctx->d_cand, ctx->d_cand_cnt, ctx->d_cand_off, ctx->d_cand_capv, ctx->n,
+                                       ctx->d_sel, s));
+        HIP_OR_FAIL(ctx, launch_finalize(ctx->d_cand, ctx->d_cand_cnt, ctx->d_cand_off, ctx->d_cand_capv, ctx->d_sel,
+                                         ctx->n, ctx->dedup_ratio, ctx->params.topk, ctx->kp_cap, d_kp, d_count,
+                                         ctx->d_flags, s));
     }
     return CDVS_OK;
 }
@@ -639,7 +682,13 @@ cdvs_status cdvs_sync_status(cdvs_ctx* ctx, void* stream) {
     HIP_OR_FAIL(ctx, hipMemcpy(&flags, ctx->d_flags, sizeof(flags), hipMemcpyDeviceToHost));
     if (flags) {
         HIP_OR_FAIL(ctx, hipMemset(ctx->d_flags, 0, sizeof(int32_t)));
-        return fail(ctx, CDVS_ERR_CAPACITY, "candidate scratch overflowed (%d per image); results truncated", kCandCap);
+        if (flags & kFlagCandOverflow)
+            return fail(ctx, CDVS_ERR_CAPACITY,
+                        "candidate scratch overflowed (an image found more candidates than its capacity, "
+                        "max(%d, W*H/64)); results truncated", kCandCap);
+        return fail(ctx, CDVS_ERR_CAPACITY,
+                    "an image with more than %d candidates kept keypoints as weak as the weakest of its %d "
+                    "strongest; its top-k may differ from the exact one", kCandCap, kCandCap);
     }
     return CDVS_OK;
 }

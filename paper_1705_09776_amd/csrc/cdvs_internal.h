@@ -58,9 +58,11 @@ struct DetTile {
     int32_t w, h;          // octave size
     int32_t tx0, ty0;      // tile origin (octave pixels)
     int32_t image, octave;
-    int32_t pad[2];
+    int32_t cand_cap;      // the image's candidate capacity
+    int32_t cand_blk;      // the image's first candidate slot / kCandBlock
 };
 static_assert(sizeof(DetTile) == 48, "DetTile is three 16-byte chunks");
+constexpr int kCandBlock = 256;   // candidate regions start on multiples of this many records
 
 // Per-image octave geometry for the keypoint kernels.
 struct OctGeom {
@@ -76,7 +78,6 @@ struct DetParams {
     float edge_lim;          // (r+1)^2 / r
     float max_off;
     int32_t border;
-    int32_t cand_cap;
 };
 
 struct OriParams {
@@ -108,6 +109,7 @@ __device__ __forceinline__ int xcd_remap(int b, int n) {
 
 // Bits of the device status word.
 constexpr int kFlagCandOverflow = 1;
+constexpr int kFlagSelectInexact = 2;   // a reduced image's top-k reached its selection threshold
 
 // Surrogate CNN geometry: one entry per image.
 constexpr int kCnnChannels = 16, kCnnHeads = 6, kCnnLayers = 4;
@@ -158,8 +160,11 @@ hipError_t launch_gate_rows(const DetTile* tiles, int ntiles, const DetParams& d
 hipError_t launch_detect(const float* pyr, const DetTile* tiles, int ntiles, int grid, const DetParams& dp,
                          const GateParams& gate, cdvs_keypoint* cand, int32_t* cand_cnt, int32_t* flags,
                          hipStream_t stream);
-hipError_t launch_finalize(const cdvs_keypoint* cand, const int32_t* cand_cnt, int n_images, int cand_cap,
-                           float dedup_ratio, int topk, int kp_cap, cdvs_keypoint* kp, int32_t* count,
+hipError_t launch_select(const cdvs_keypoint* cand, const int32_t* cand_cnt, const int64_t* cand_off,
+                         const int32_t* cand_capv, int n_images, cdvs_keypoint* sel, hipStream_t stream);
+hipError_t launch_finalize(const cdvs_keypoint* cand, const int32_t* cand_cnt, const int64_t* cand_off,
+                           const int32_t* cand_capv, const cdvs_keypoint* sel, int n_images, float dedup_ratio,
+                           int topk, int kp_cap, cdvs_keypoint* kp, int32_t* count, int32_t* flags,
                            hipStream_t stream);
 hipError_t launch_orient(const float* pyr, const OctGeom* geom, const cdvs_keypoint* kp, const int32_t* count,
                          int n_images, const OriParams& op, cdvs_keypoint* ori, int32_t* ori_cnt,

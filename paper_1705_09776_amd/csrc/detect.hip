@@ -213,7 +213,7 @@ __device__ __forceinline__ void emit(bool keep, const Cand& c, int gx, int gy, c
     base = __shfl(base, leader);
     if (!keep) return;
     const int slot = base + __popcll(m & ((1ull << lane) - 1ull));
-    if (slot >= dp.cand_cap) {
+    if (slot >= job.cand_cap) {
         atomicOr(flags, kFlagCandOverflow);
         return;
     }
@@ -231,7 +231,7 @@ __device__ __forceinline__ void emit(bool keep, const Cand& c, int gx, int gy, c
     r.octave = job.octave;
     r.ix = gx;
     r.iy = gy;
-    cand[(int64_t)job.image * dp.cand_cap + slot] = r;
+    cand[(int64_t)job.cand_blk * kCandBlock + slot] = r;
 }
 
 // Second phase over the LDS list of contrast-passing centres: dense lanes
@@ -279,7 +279,8 @@ __device__ __forceinline__ DetTile as_uniform(RawTile r) {
     t.ty0 = __builtin_amdgcn_readlane(r, 7);
     t.image = __builtin_amdgcn_readlane(r, 8);
     t.octave = __builtin_amdgcn_readlane(r, 9);
-    t.pad[0] = t.pad[1] = 0;
+    t.cand_cap = __builtin_amdgcn_readlane(r, 10);
+    t.cand_blk = __builtin_amdgcn_readlane(r, 11);
     return t;
 }
 
@@ -541,6 +542,63 @@ __global__ void k_clear(int32_t* p, int n) {
 constexpr int FIN_THREADS = 1024;
 constexpr int FIN_PER = kCandCap / FIN_THREADS;  // candidates per thread
 
+// Top-kCandCap selection by |p| for images with more candidates than the
+// finalisation holds (one workgroup per image; the others return at once).
+// The kCandCap-th largest |p| is found by a three-round radix select on the
+// float bits of |p| (11, 11 and 10 bits; non-negative floats order like
+// their bits), then every candidate above it and enough of those equal to it
+// are copied out (in no particular order: the finalisation sorts).
+__global__ __launch_bounds__(FIN_THREADS) void k_select(const cdvs_keypoint* __restrict__ cand,
+                                                        const int32_t* __restrict__ cand_cnt,
+                                                        const int64_t* __restrict__ cand_off,
+                                                        const int32_t* __restrict__ cand_capv,
+                                                        cdvs_keypoint* __restrict__ sel) {
+    __shared__ int hist[2048];
+    __shared__ uint32_t prefix_s, need_s;
+    __shared__ int n_out, n_tie;
+    const int img = blockIdx.x;
+    const int n = min(cand_cnt[img], cand_capv[img]);
+    if (n <= kCandCap) return;   // uniform over the workgroup
+    const cdvs_keypoint* c = cand + cand_off[img];
+    cdvs_keypoint* out = sel + (int64_t)img * kCandCap;
+    if (threadIdx.x == 0) {
+        prefix_s = 0u;
+        need_s = kCandCap;
+        n_out = 0;
+        n_tie = 0;
+    }
+    uint32_t mask = 0u;   // bits of the threshold fixed so far
+    const int shifts[3] = {21, 10, 0}, widths[3] = {11, 11, 10};
+    for (int round = 0; round < 3; ++round) {
+        const int sh = shifts[round], nb = 1 << widths[round];
+        for (int b = threadIdx.x; b < nb; b += blockDim.x) hist[b] = 0;
+        __syncthreads();
+        const uint32_t prefix = prefix_s;
+        for (int i = threadIdx.x; i < n; i += blockDim.x) {
+            const uint32_t key = __float_as_uint(fabsf(c[i].p));
+            if ((key & mask) == prefix) atomicAdd(&hist[(key >> sh) & (nb - 1)], 1);
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            // walk the bins from the top until `need` keys are covered
+            uint32_t need = need_s;
+            int b = nb - 1;
+            for (; b > 0 && (uint32_t)hist[b] < need; --b) need -= (uint32_t)hist[b];
+            prefix_s = prefix | ((uint32_t)b << sh);
+            need_s = need;   // keys still needed from bin b (the threshold's bin)
+        }
+        mask |= (uint32_t)(nb - 1) << sh;
+        __syncthreads();
+    }
+    const uint32_t thr = prefix_s, ties = need_s;   // keep every key > thr and `ties` keys == thr
+    for (int i = threadIdx.x; i < n; i += blockDim.x) {
+        const uint32_t key = __float_as_uint(fabsf(c[i].p));
+        bool take = key > thr;
+        if (key == thr) take = atomicAdd(&n_tie, 1) < (int)ties;
+        if (take) out[atomicAdd(&n_out, 1)] = c[i];
+    }
+}
+
 // Ascending bitonic sort of npow (a power of two) 64-bit keys with 16-bit
 // payloads in LDS by the whole workgroup.
 __device__ __forceinline__ void bitonic_sort(unsigned long long* key, unsigned short* idx, int npow) {
@@ -571,33 +629,49 @@ __device__ __forceinline__ void bitonic_sort(unsigned long long* key, unsigned s
 // the same, as only pairs farther apart in y than the distance limit are
 // skipped.  Then the survivors are sorted by the canonical key.
 __global__ __launch_bounds__(FIN_THREADS) void k_finalize(const cdvs_keypoint* __restrict__ cand,
-                                                          const int32_t* __restrict__ cand_cnt, int cand_cap,
+                                                          const int32_t* __restrict__ cand_cnt,
+                                                          const int64_t* __restrict__ cand_off,
+                                                          const int32_t* __restrict__ cand_capv,
+                                                          const cdvs_keypoint* __restrict__ sel,
                                                           float ratio_lim, int topk, int kp_cap,
                                                           cdvs_keypoint* __restrict__ kp,
-                                                          int32_t* __restrict__ count) {
+                                                          int32_t* __restrict__ count,
+                                                          int32_t* __restrict__ flags) {
     // 128 KB: sort keys + payloads, then the records (x, y, sigma, p) in
     // (octave, y) order, then the final keys + payloads
     __shared__ float4 rec[kCandCap];
     __shared__ unsigned short perm[kCandCap];   // original index of each (octave, y)-sorted position
     __shared__ int seg[kMaxOctaves + 2];        // first sorted position of each octave
     __shared__ int n_alive;
+    __shared__ uint32_t min_bits;               // smallest |p| (as bits) of a reduced image's set
     unsigned long long* key = reinterpret_cast<unsigned long long*>(rec);
     unsigned short* idx = reinterpret_cast<unsigned short*>(key + kCandCap);
 
     const int img = blockIdx.x;
-    const cdvs_keypoint* c = cand + (int64_t)img * cand_cap;
-    const int n = min(cand_cnt[img], cand_cap);
+    // an image with more candidates than the LDS holds was reduced to its
+    // kCandCap strongest by k_select (exactly the ones stage C and the top-k
+    // can keep: a candidate only ever loses to a stronger one)
+    const int n_all = min(cand_cnt[img], cand_capv[img]);
+    const cdvs_keypoint* c = n_all > kCandCap ? sel + (int64_t)img * kCandCap : cand + cand_off[img];
+    const int n = min(n_all, kCandCap);
     const int tid = threadIdx.x;
     int npow = 1;
     while (npow < n) npow <<= 1;
 
     if (tid < kMaxOctaves + 2) seg[tid] = n;
-    if (tid == 0) n_alive = 0;
+    if (tid == 0) {
+        n_alive = 0;
+        min_bits = 0xffffffffu;
+    }
+    __syncthreads();
+    uint32_t my_min = 0xffffffffu;
     for (int i = tid; i < npow; i += FIN_THREADS) {
         // y >= 0, so its float bits order like the value
         key[i] = i < n ? ((unsigned long long)c[i].octave << 32) | __float_as_uint(c[i].y) : ~0ull;
         idx[i] = (unsigned short)i;
+        if (i < n) my_min = min(my_min, __float_as_uint(fabsf(c[i].p)));
     }
+    if (n_all > kCandCap) atomicMin(&min_bits, my_min);
     __syncthreads();
     bitonic_sort(key, idx, npow);
     for (int i = tid; i < n; i += FIN_THREADS) {
@@ -679,7 +753,17 @@ __global__ __launch_bounds__(FIN_THREADS) void k_finalize(const cdvs_keypoint* _
     const int limit = min(topk > 0 ? topk : kp_cap, kp_cap);
     const int m = min(n_alive, limit);
     for (int r = tid; r < m; r += blockDim.x) kp[(int64_t)img * kp_cap + r] = c[perm[idx[r]]];
-    if (tid == 0) count[img] = m;
+    if (tid == 0) {
+        count[img] = m;
+        // A reduced image's output is exact when its last kept keypoint is
+        // stronger than every candidate k_select dropped: each kept one was
+        // judged against all candidates at least as strong, and no dropped
+        // candidate could rank among them.  Otherwise the image is flagged.
+        if (n_all > kCandCap && limit > 0) {
+            const bool exact = n_alive >= limit && ~(uint32_t)(key[limit - 1] >> 32) > min_bits;
+            if (!exact) atomicOr(flags, kFlagSelectInexact);
+        }
+    }
 }
 
 }  // namespace
@@ -712,12 +796,20 @@ hipError_t launch_gate_rows(const DetTile* tiles, int ntiles, const DetParams& d
     return hipGetLastError();
 }
 
-hipError_t launch_finalize(const cdvs_keypoint* cand, const int32_t* cand_cnt, int n_images, int cand_cap,
-                           float dedup_ratio, int topk, int kp_cap, cdvs_keypoint* kp, int32_t* count,
+hipError_t launch_select(const cdvs_keypoint* cand, const int32_t* cand_cnt, const int64_t* cand_off,
+                         const int32_t* cand_capv, int n_images, cdvs_keypoint* sel, hipStream_t stream) {
+    if (n_images <= 0 || !sel) return hipSuccess;
+    hipLaunchKernelGGL(k_select, dim3(n_images), dim3(FIN_THREADS), 0, stream, cand, cand_cnt, cand_off, cand_capv, sel);
+    return hipGetLastError();
+}
+
+hipError_t launch_finalize(const cdvs_keypoint* cand, const int32_t* cand_cnt, const int64_t* cand_off,
+                           const int32_t* cand_capv, const cdvs_keypoint* sel, int n_images, float dedup_ratio,
+                           int topk, int kp_cap, cdvs_keypoint* kp, int32_t* count, int32_t* flags,
                            hipStream_t stream) {
     if (n_images <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_finalize, dim3(n_images), dim3(FIN_THREADS), 0, stream, cand, cand_cnt, cand_cap,
-                       dedup_ratio, topk, kp_cap, kp, count);
+    hipLaunchKernelGGL(k_finalize, dim3(n_images), dim3(FIN_THREADS), 0, stream, cand, cand_cnt, cand_off, cand_capv,
+                       sel, dedup_ratio, topk, kp_cap, kp, count, flags);
     return hipGetLastError();
 }
 

@@ -353,3 +353,92 @@ def test_misaligned_pyramid_rejected():
         with pytest.raises(cd.CdvsError) as e:
             call()
         assert e.value.status == cd.CDVS_ERR_ARG
+
+
+def _lattice(W, H, period):
+    """128 + 100 sin(2 pi x / period) sin(2 pi y / period): four blob-like
+    extrema per period squared, far denser than natural images."""
+    y, x = np.mgrid[0:H, 0:W]
+    v = 128 + 100 * np.sin(2 * np.pi * x / period) * np.sin(2 * np.pi * y / period)
+    return np.clip(np.rint(v), 0, 255).astype(np.uint8)
+
+
+@pytest.fixture(scope="module")
+def large(O32):
+    """A 4096x4096 image: ~58k candidates, more than the 8192 that stage C
+    and the top-k hold per image, so the GPU first keeps the 8192 strongest."""
+    img = synth.image(synth.SEED_SINGLE, 1, 4096, 4096, nblobs=2000)
+    _, flat = O32.pyramid(img)
+    cand = O32.detect(flat, 4096, 4096, cap=1 << 18)
+    assert 8192 < len(cand) < (1 << 18)
+    alive = O32.dedup(cand)
+    return img, cand, alive
+
+
+def test_large_image_strongest_selection_exact(large, O32):
+    img, cand, alive = large
+    sel = O32.select(cand, alive)
+    pipe = _run([img])   # asserts CDVS_OK: the top-1000 was provably exact
+    assert pipe.candidate_capacity() >= len(cand)
+    got = pipe.keypoints()[0]
+    assert len(got) == len(sel) == 1000
+    r_ref, r_got, _ = rates(sel, got)
+    print(f"4096x4096: {len(cand)} candidates, match {r_ref:.4f} / {r_got:.4f}")
+    assert r_ref >= KP_RATE and r_got >= KP_RATE
+    assert np.all(np.diff(np.abs(got["p"])) <= 0)
+
+
+def test_large_image_inexact_topk_latched(large, O32):
+    """topk = 8192 on that image reaches the weakest of the 8192 strongest
+    candidates: the result is flagged, and what is written is still the
+    exact ranking down to the selection threshold."""
+    img, cand, alive = large
+    p = cd.default_params()
+    p.topk = 8192
+    pipe = cd.Pipeline([(4096, 4096)], params=p, kp_capacity=8192)
+    pipe.upload([img])
+    pipe.run()
+    assert pipe.sync_status() == cd.CDVS_ERR_CAPACITY
+    assert pipe.sync_status() == cd.CDVS_OK   # the latch was cleared
+    got = pipe.keypoints()[0]
+    thr = np.sort(np.abs(cand["p"]))[::-1][8191]
+    ref = O32.select(cand, alive, 8192)
+    ref = ref[np.abs(ref["p"]) > thr * (1 + 1e-3)]
+    got = got[np.abs(got["p"]) > thr * (1 + 1e-3)]
+    r_ref, r_got, _ = rates(ref, got)
+    print(f"above threshold: {len(ref)} oracle, {len(got)} gpu, match {r_ref:.4f} / {r_got:.4f}")
+    assert len(ref) > 4000
+    assert r_ref >= KP_RATE and r_got >= KP_RATE
+
+
+def test_candidate_overflow_latched(O32):
+    """A period-11 sine lattice gives ~9800 candidates in 640x480, more than
+    its 8192-candidate capacity: the overflow is reported, and every keypoint
+    written is one of the oracle's candidates."""
+    img = _lattice(640, 480, 11)
+    _, flat = O32.pyramid(img)
+    cand = O32.detect(flat, 640, 480, cap=1 << 18)
+    assert len(cand) > 8192
+    pipe = cd.Pipeline([(640, 480)])
+    assert pipe.candidate_capacity() == 8192
+    pipe.upload([img])
+    pipe.run()
+    assert pipe.sync_status() == cd.CDVS_ERR_CAPACITY
+    got = pipe.keypoints()[0]
+    assert len(got) == 1000
+    _, r_got, _ = rates(cand, got)
+    assert r_got >= KP_RATE
+
+
+def test_max_side_images(O32):
+    """The longest sides the library accepts (8192) in a ragged pair."""
+    a = synth.image(synth.SEED_SINGLE, 2, 8192, 64, nblobs=100)
+    b = synth.image(synth.SEED_SINGLE, 3, 64, 8192, nblobs=100)
+    pipe = _run([a, b])
+    kps = pipe.keypoints()
+    for i, im in enumerate([a, b]):
+        sel, _, _, _ = _oracle_stages(O32, im)
+        assert len(sel) > 100
+        r1, r2, _ = rates(sel, kps[i])
+        assert min(r1, r2) >= KP_RATE
+        assert pipe.num_octaves(i) == O32.num_octaves(im.shape[1], im.shape[0])
