@@ -60,6 +60,8 @@ struct cdvs_ctx {
     std::vector<DetTile> dtiles;               // detection tiles, grouped by octave
     int dtile_start[kMaxOctaves + 1] = {};
     DetTile* d_dtiles = nullptr;
+    std::vector<DetTile> strips;   // ungated detection: image-major, then octave, then row-major strips
+    DetTile* d_strips = nullptr;
     OctGeom* d_geom = nullptr;
     cdvs_keypoint* d_cand = nullptr;           // per image: cand_cap[i] records from cand_off[i]
     std::vector<int64_t> cand_off;
@@ -272,6 +274,7 @@ void cdvs_ctx_destroy(cdvs_ctx* ctx) {
     for (auto& e : ctx->ev) (void)hipEventDestroy(e);
     (void)hipFree(ctx->d_jobs);
     (void)hipFree(ctx->d_dtiles);
+    (void)hipFree(ctx->d_strips);
     (void)hipFree(ctx->d_blur_owner);
     (void)hipFree(ctx->d_cnn_owner);
     (void)hipFree(ctx->d_geom);
@@ -400,6 +403,36 @@ static cdvs_status build_layout(cdvs_ctx* c) {
         }
     }
     c->dtile_start[kMaxOctaves] = (int)c->dtiles.size();
+    // strips of the ungated detection, covering each octave's centres inside
+    // the border; image-major so that each XCD's contiguous share holds
+    // whole images (balanced work, and neighbouring strips share halo rows
+    // in that XCD's L2)
+    c->strips.clear();
+    for (int i = 0; i < c->n; ++i)
+        for (int o = 0; o < kMaxOctaves; ++o)
+            for (const OctJob& j : per_oct[o]) {
+                if (j.image != i) continue;
+                const int b = c->params.border;
+                const int cw = j.w - 2 * b, ch = j.h - 2 * b;
+                if (cw <= 0 || ch <= 0) continue;
+                const int sx = (cw + kDetStripW - 1) / kDetStripW, sy = (ch + kDetStripH - 1) / kDetStripH;
+                for (int t = 0; t < sx * sy; ++t) {
+                    DetTile r;
+                    memset(&r, 0, sizeof(r));
+                    r.plane0 = j.plane0;
+                    r.plane_stride = j.plane_stride;
+                    r.pitch = j.pitch;
+                    r.w = j.w;
+                    r.h = j.h;
+                    r.tx0 = b + (t % sx) * kDetStripW;
+                    r.ty0 = b + (t / sx) * kDetStripH;
+                    r.image = j.image;
+                    r.octave = j.octave;
+                    r.cand_cap = c->cand_cap[j.image];
+                    r.cand_blk = (int32_t)(c->cand_off[j.image] / kCandBlock);
+                    c->strips.push_back(r);
+                }
+            }
     c->job_start[kMaxOctaves] = (int)c->jobs.size();
     // surrogate CNN cells: 4x4-pixel cells of each base image
     c->cnn.assign(c->n, CnnImage{});
@@ -497,6 +530,7 @@ cdvs_status cdvs_ctx_create(const cdvs_params* params, const cdvs_image_desc* im
     } while (0)
     ALLOC(c->d_jobs, sizeof(OctJob) * std::max<size_t>(1, c->jobs.size()));
     ALLOC(c->d_dtiles, sizeof(DetTile) * std::max<size_t>(1, c->dtiles.size()));
+    ALLOC(c->d_strips, sizeof(DetTile) * std::max<size_t>(1, c->strips.size()));
     ALLOC(c->d_blur_owner, sizeof(int32_t) * std::max<size_t>(1, c->blur_owner.size()));
     ALLOC(c->d_cnn_owner, sizeof(int32_t) * std::max<size_t>(1, c->cnn_owner.size()));
     ALLOC(c->d_geom, sizeof(OctGeom) * c->geom.size());
@@ -523,6 +557,8 @@ cdvs_status cdvs_ctx_create(const cdvs_params* params, const cdvs_image_desc* im
     ALLOC(c->d_gate_state, sizeof(int32_t) * std::max<size_t>(1, c->dtiles.size()));
 #undef ALLOC
     if ((e = hipMemcpy(c->d_jobs, c->jobs.data(), sizeof(OctJob) * c->jobs.size(), hipMemcpyHostToDevice)) != hipSuccess ||
+        (e = hipMemcpy(c->d_strips, c->strips.data(), sizeof(DetTile) * c->strips.size(), hipMemcpyHostToDevice)) !=
+            hipSuccess ||
         (e = hipMemcpy(c->d_dtiles, c->dtiles.data(), sizeof(DetTile) * c->dtiles.size(), hipMemcpyHostToDevice)) !=
             hipSuccess ||
         (e = hipMemcpy(c->d_blur_owner, c->blur_owner.data(), sizeof(int32_t) * c->blur_owner.size(),
@@ -619,9 +655,15 @@ cdvs_status cdvs_alp_detect(cdvs_ctx* ctx, const float* d_pyr, const uint8_t* d_
         Bracket b(ctx, CDVS_KERNEL_CLEAR, s);
         HIP_OR_FAIL(ctx, launch_clear(ctx->d_cand_cnt, ctx->n, s));
     }
-    // one persistent launch per octave (measured faster than a single launch
-    // over all octaves); the finalisation does not rely on the order
-    for (int o = 0; o < ctx->max_oct; ++o) {
+    if (!d_mask) {
+        // ungated: one launch over the strips of every octave
+        Bracket b(ctx, CDVS_KERNEL_DETECT, s);
+        HIP_OR_FAIL(ctx, launch_detect_strips(d_pyr, ctx->d_strips, (int)ctx->strips.size(), ctx->det, ctx->d_cand,
+                                              ctx->d_cand_cnt, ctx->d_flags, s));
+    }
+    // gated: one persistent launch per octave over the tiles; the
+    // finalisation does not rely on the order
+    for (int o = 0; d_mask && o < ctx->max_oct; ++o) {
         Bracket b(ctx, CDVS_KERNEL_DETECT, s);
         GateParams go = gate;
         if (go.mask) {

@@ -160,6 +160,11 @@ hipError_t launch_gate_rows(const DetTile* tiles, int ntiles, const DetParams& d
 hipError_t launch_detect(const float* pyr, const DetTile* tiles, int ntiles, int grid, const DetParams& dp,
                          const GateParams& gate, cdvs_keypoint* cand, int32_t* cand_cnt, int32_t* flags,
                          hipStream_t stream);
+// Ungated detection over strips of 60 x kDetStripH centres inside the
+// detection border (tx0, ty0 = the strip's first centre), one wave each.
+constexpr int kDetStripW = 60, kDetStripH = 48;
+hipError_t launch_detect_strips(const float* pyr, const DetTile* strips, int nstrips, const DetParams& dp,
+                               cdvs_keypoint* cand, int32_t* cand_cnt, int32_t* flags, hipStream_t stream);
 hipError_t launch_select(const cdvs_keypoint* cand, const int32_t* cand_cnt, const int64_t* cand_off,
                          const int32_t* cand_capv, int n_images, cdvs_keypoint* sel, hipStream_t stream);
 hipError_t launch_finalize(const cdvs_keypoint* cand, const int32_t* cand_cnt, const int64_t* cand_off,

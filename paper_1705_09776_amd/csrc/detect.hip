@@ -114,22 +114,32 @@ __device__ __forceinline__ void store_tile(float* G, const float4 (&vals)[DNPER4
 
 // Scale-normalised 5-point Laplacians of the five planes at staged pixel
 // (ly, lx), folded into the four ALP coefficients (Eqs. (2)-(3)).
+// 5-point Laplacian sum (up + down + left + right - 4 centre), in one fixed
+// order of operations shared by both detection kernels.
+__device__ __forceinline__ float lap5(float c, float up, float dn, float lf, float rt) {
+    float s = up + dn;
+    s = s + lf;
+    s = s + rt;
+    s = s - 4.f * c;
+    return s;
+}
+
+// Adds scale k's normalised Laplacian to the ALP coefficients.
+__device__ __forceinline__ void alpha_acc(float4& a, float lap, int k, const DetParams& dp) {
+    const float L = dp.sig2[k] * lap;
+    a.x = fmaf(dp.beta[k][0], L, a.x);
+    a.y = fmaf(dp.beta[k][1], L, a.y);
+    a.z = fmaf(dp.beta[k][2], L, a.z);
+    a.w = fmaf(dp.beta[k][3], L, a.w);
+}
+
 __device__ __forceinline__ float4 alpha_at(const float (&G)[kScales][GH][GW], int ly, int lx, const DetParams& dp) {
-    float a0 = 0.f, a1 = 0.f, a2 = 0.f, a3 = 0.f;
+    float4 a = make_float4(0.f, 0.f, 0.f, 0.f);
 #pragma unroll
-    for (int k = 0; k < kScales; ++k) {
-        const float c = G[k][ly][lx];
-        float s = G[k][ly - 1][lx] + G[k][ly + 1][lx];
-        s = s + G[k][ly][lx - 1];
-        s = s + G[k][ly][lx + 1];
-        s = s - 4.f * c;
-        const float L = dp.sig2[k] * s;
-        a0 = fmaf(dp.beta[k][0], L, a0);
-        a1 = fmaf(dp.beta[k][1], L, a1);
-        a2 = fmaf(dp.beta[k][2], L, a2);
-        a3 = fmaf(dp.beta[k][3], L, a3);
-    }
-    return make_float4(a0, a1, a2, a3);
+    for (int k = 0; k < kScales; ++k)
+        alpha_acc(a, lap5(G[k][ly][lx], G[k][ly - 1][lx], G[k][ly + 1][lx], G[k][ly][lx - 1], G[k][ly][lx + 1]), k,
+                  dp);
+    return a;
 }
 
 struct Cand {
@@ -142,25 +152,20 @@ __device__ __forceinline__ bool centre_extremum(const float4 (&A)[AH][AW], int c
     return alp_extremum(A[cy + 1][cx + 1], dp.lo, dp.hi, s, p, pss) && fabsf(p) >= dp.contrast;
 }
 
-// Second half: strict 8-neighbour test at the centre's scale and one
-// quadratic refinement step (Algorithm 1 stages A-B).
-__device__ __forceinline__ bool centre_refine(const float4 (&A)[AH][AW], int cy, int cx, float s, float p, float pss,
-                                              const DetParams& dp, Cand& o) {
-    float v[9];
+// Strict extremum of the centre value p = v[4] against the eight
+// neighbours' cubics v[] evaluated at the centre's scale (Algorithm 1 stage A).
+__device__ __forceinline__ bool strict_extremum(const float (&v)[9], float p) {
     bool ext = true;
 #pragma unroll
-    for (int j = -1; j <= 1; ++j)
-#pragma unroll
-        for (int i = -1; i <= 1; ++i) {
-            if (i == 0 && j == 0) {
-                v[4] = p;
-                continue;
-            }
-            const float qv = horner(A[cy + 1 + j][cx + 1 + i], s);
-            v[(j + 1) * 3 + (i + 1)] = qv;
-            ext = ext && (p > 0.f ? (qv < p) : (qv > p));
-        }
-    if (!ext) return false;
+    for (int i = 0; i < 9; ++i)
+        if (i != 4) ext = ext && (p > 0.f ? (v[i] < p) : (v[i] > p));
+    return ext;
+}
+
+// One quadratic refinement step on the 3x3 values v[] (row-major, centre
+// v[4] = p): offset, edge test and interpolated response (Algorithm 1 stage B).
+__device__ __forceinline__ bool refine_v(const float (&v)[9], float s, float p, float pss, const DetParams& dp,
+                                         Cand& o) {
     const float c = v[4];
     const float gxd = (v[5] - v[3]) * 0.5f;
     const float gyd = (v[7] - v[1]) * 0.5f;
@@ -184,6 +189,18 @@ __device__ __forceinline__ bool centre_refine(const float4 (&A)[AH][AW], int cy,
     o.pr = c + (gxd * dx + gyd * dy) * 0.5f;
     o.rho = ratio;
     return true;
+}
+
+// Second half for a staged tile: strict 8-neighbour test at the centre's
+// scale and one quadratic refinement step (Algorithm 1 stages A-B).
+__device__ __forceinline__ bool centre_refine(const float4 (&A)[AH][AW], int cy, int cx, float s, float p, float pss,
+                                              const DetParams& dp, Cand& o) {
+    float v[9];
+#pragma unroll
+    for (int j = -1; j <= 1; ++j)
+#pragma unroll
+        for (int i = -1; i <= 1; ++i) v[(j + 1) * 3 + (i + 1)] = (i == 0 && j == 0) ? p : horner(A[cy + 1 + j][cx + 1 + i], s);
+    return strict_extremum(v, p) && refine_v(v, s, p, pss, dp, o);
 }
 
 // Appends (s, p, pss, centre index) of the lanes with `pass` to an LDS list
@@ -341,6 +358,204 @@ __global__ __launch_bounds__(256) void k_detect(const float* __restrict__ pyr, c
     }
     __syncthreads();
     refine_list(A, list, nlist, prev, dp, cand, cand_cnt, flags);
+}
+
+// ---------------------------------------------------------------------------
+// k_detect_strip: the ungated detection, one wave per strip of kStripW
+// centre columns x kStripH centre rows of one (image, octave) inside the
+// detection border; lane l holds image column x0 - 2 + l (lanes 0, 1, 62
+// and 63 are halo).  The wave walks down its strip one row at a time with
+// no LDS staging and no barriers: each row's five plane values arrive by one
+// coalesced dword load per plane, issued a chunk of rows ahead; the
+// Laplacians take their horizontal neighbours from the adjacent lanes (DPP
+// wave shifts) and their vertical ones from the previous two rows held in
+// registers, and the ALP coefficients of the last three rows stay in
+// registers for the centre tests.  For the strict 3x3 test each lane
+// evaluates its own column's cubics at its neighbours' scales and hands the
+// values over, so no lane needs another lane's coefficients.  Centres that
+// pass are queued in the wave's LDS list with their 3x3 values and refined
+// 64 at a time (dense lanes; one global atomic per 64 survivors).
+constexpr int kStripW = kDetStripW;
+constexpr int kStripH = kDetStripH;
+constexpr int kStripRing = 3;          // rows per ring period (three coefficient rows)
+constexpr int kStripChunk = 2;         // ring periods per prefetched chunk
+constexpr int kStripRows = kStripRing * kStripChunk;
+constexpr int kQCap = 128;             // < 64 pending + at most 60 from one row
+constexpr int kQFields = 13;           // v0..v8, s, p, pss, (x | y << 16)
+
+__device__ __forceinline__ float lane_from_left(float v) {   // lane l gets lane l-1's value (lane 0: 0)
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x138, 0xf, 0xf, false));
+}
+__device__ __forceinline__ float lane_from_right(float v) {  // lane l gets lane l+1's value (lane 63: 0)
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x130, 0xf, 0xf, false));
+}
+
+struct StripRow {
+    float g[kScales];
+};
+
+// Plane row y (clamped to the image) of this lane's column; rows past
+// `last` (the strip's last plane row) are not needed and not loaded.
+__device__ __forceinline__ void load_row(const float* __restrict__ col, const DetTile& job, int y, int last,
+                                         StripRow& r) {
+    if (y > last) return;   // uniform over the wave
+    const float* p = col + (int64_t)clampi(y, 0, job.h - 1) * job.pitch;
+#pragma unroll
+    for (int k = 0; k < kScales; ++k) r.g[k] = p[(int64_t)k * job.plane_stride];
+}
+
+// ALP coefficients of the middle row from three consecutive rows.
+__device__ __forceinline__ float4 strip_alpha(const StripRow& u, const StripRow& m, const StripRow& d,
+                                              const DetParams& dp) {
+    float4 a = make_float4(0.f, 0.f, 0.f, 0.f);
+#pragma unroll
+    for (int k = 0; k < kScales; ++k)
+        alpha_acc(a, lap5(m.g[k], u.g[k], d.g[k], lane_from_left(m.g[k]), lane_from_right(m.g[k])), k, dp);
+    return a;
+}
+
+// Refines the first n (<= 64) queued centres of this wave and appends the
+// survivors to the image's candidates.  Every lane of the wave calls it.
+__device__ __forceinline__ void strip_flush(float (*q)[kQCap], int n, const DetTile& job, const DetParams& dp,
+                                            cdvs_keypoint* __restrict__ cand, int32_t* __restrict__ cand_cnt,
+                                            int32_t* __restrict__ flags) {
+    const int lane = threadIdx.x & 63;
+    Cand c{};
+    bool keep = false;
+    int gx = 0, gy = 0;
+    if (lane < n) {
+        float v[9];
+#pragma unroll
+        for (int i = 0; i < 9; ++i) v[i] = q[i][lane];
+        const int xy = __float_as_int(q[12][lane]);
+        gx = xy & 0xffff;
+        gy = xy >> 16;
+        keep = refine_v(v, q[9][lane], q[10][lane], q[11][lane], dp, c);
+    }
+    emit(keep, c, gx, gy, job, dp, cand, cand_cnt, flags);
+}
+
+// Centre tests of one row y from the coefficients of rows y-1, y, y+1;
+// strict extrema are queued (qn: the wave's queue length, uniform).
+__device__ __forceinline__ void strip_centres(const float4& aU, const float4& aM, const float4& aD, bool col_ok, int gx,
+                                              int y, float (*q)[kQCap], int& qn, const DetTile& job,
+                                              const DetParams& dp, cdvs_keypoint* __restrict__ cand,
+                                              int32_t* __restrict__ cand_cnt, int32_t* __restrict__ flags) {
+    float s = 0.f, p = 0.f, pss = 0.f;
+    const bool pass = col_ok && alp_extremum(aM, dp.lo, dp.hi, s, p, pss) && fabsf(p) >= dp.contrast;
+    if (!__ballot(pass)) return;   // uniform over the wave
+    // this lane's column at the scale of the centre to its right (for which
+    // it is the left column) and of the centre to its left
+    const float s_r = lane_from_right(s), s_l = lane_from_left(s);
+    const float l0 = horner(aU, s_r), l1 = horner(aM, s_r), l2 = horner(aD, s_r);
+    const float r0 = horner(aU, s_l), r1 = horner(aM, s_l), r2 = horner(aD, s_l);
+    float v[9];
+    v[0] = lane_from_left(l0);
+    v[3] = lane_from_left(l1);
+    v[6] = lane_from_left(l2);
+    v[2] = lane_from_right(r0);
+    v[5] = lane_from_right(r1);
+    v[8] = lane_from_right(r2);
+    v[1] = horner(aU, s);
+    v[4] = p;
+    v[7] = horner(aD, s);
+    const bool keep = pass && strict_extremum(v, p);
+    const uint64_t m = __ballot(keep);
+    if (!m) return;
+    const int lane = threadIdx.x & 63;
+    if (keep) {
+        const int i = qn + __popcll(m & ((1ull << lane) - 1ull));
+#pragma unroll
+        for (int f = 0; f < 9; ++f) q[f][i] = v[f];
+        q[9][i] = s;
+        q[10][i] = p;
+        q[11][i] = pss;
+        q[12][i] = __int_as_float(gx | (y << 16));
+    }
+    qn += __popcll(m);
+    if (qn >= 64) {
+        strip_flush(q, 64, job, dp, cand, cand_cnt, flags);
+        // move the rest (fewer than 64) to the front; the source and
+        // destination ranges do not overlap
+        const int rest = qn - 64;
+        if (lane < rest) {
+            float t[kQFields];
+#pragma unroll
+            for (int f = 0; f < kQFields; ++f) t[f] = q[f][64 + lane];
+#pragma unroll
+            for (int f = 0; f < kQFields; ++f) q[f][lane] = t[f];
+        }
+        qn = rest;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_detect_strip(const float* __restrict__ pyr, const DetTile* __restrict__ strips,
+                                                      int nstrips, DetParams dp, cdvs_keypoint* __restrict__ cand,
+                                                      int32_t* __restrict__ cand_cnt, int32_t* __restrict__ flags) {
+    __shared__ float queue[4][kQFields][kQCap];
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int sidx = __builtin_amdgcn_readfirstlane(xcd_remap(blockIdx.x, gridDim.x) * 4 + wave);
+    if (sidx >= nstrips) return;   // uniform over the wave; there are no barriers
+    float (*q)[kQCap] = queue[wave];
+    const DetTile job = strips[sidx];
+    const int x0 = job.tx0, y0 = job.ty0;
+    const int xend = min(x0 + kStripW, job.w - dp.border), yend = min(y0 + kStripH, job.h - dp.border);
+    const int gx = x0 - 2 + lane;
+    const bool col_ok = lane >= 2 && gx < xend;
+    const float* col = pyr + job.plane0 + clampi(gx, 0, job.w - 1);
+
+    // rows y0-2 .. y0+1 give the coefficients of rows y0-1 and y0
+    const int last = yend + 1;
+    StripRow gA, gB, gC, gD;
+    load_row(col, job, y0 - 2, last, gA);
+    load_row(col, job, y0 - 1, last, gB);
+    load_row(col, job, y0, last, gC);
+    load_row(col, job, y0 + 1, last, gD);
+    StripRow cur[kStripRows];
+#pragma unroll
+    for (int r = 0; r < kStripRows; ++r) load_row(col, job, y0 + 2 + r, last, cur[r]);
+    float4 aA = strip_alpha(gA, gB, gC, dp);   // row y0-1
+    float4 aB = strip_alpha(gB, gC, gD, dp);   // row y0
+    gA = gC;
+    gB = gD;
+    int qn = 0;
+    // invariant at the top of each chunk (first centre row y): gA, gB hold
+    // plane rows y, y+1; aA, aB the coefficients of rows y-1, y; cur[] the
+    // plane rows y+2 .. y+1+kStripRows
+    for (int y = y0; y < yend; y += kStripRows) {
+        StripRow nxt[kStripRows];
+#pragma unroll
+        for (int r = 0; r < kStripRows; ++r) load_row(col, job, y + 2 + kStripRows + r, last, nxt[r]);
+#pragma unroll
+        for (int c3 = 0; c3 < kStripChunk; ++c3) {
+            const int yr = y + c3 * kStripRing;
+            const StripRow& r0 = cur[c3 * kStripRing];
+            const StripRow& r1 = cur[c3 * kStripRing + 1];
+            const StripRow& r2 = cur[c3 * kStripRing + 2];
+            if (yr < yend) {
+                const float4 aC = strip_alpha(gA, gB, r0, dp);   // row yr+1
+                strip_centres(aA, aB, aC, col_ok, gx, yr, q, qn, job, dp, cand, cand_cnt, flags);
+                aA = aC;   // row yr+1
+            }
+            if (yr + 1 < yend) {
+                const float4 aD = strip_alpha(gB, r0, r1, dp);   // row yr+2
+                strip_centres(aB, aA, aD, col_ok, gx, yr + 1, q, qn, job, dp, cand, cand_cnt, flags);
+                aB = aD;   // row yr+2
+            }
+            if (yr + 2 < yend) {
+                const float4 aE = strip_alpha(r0, r1, r2, dp);   // row yr+3
+                strip_centres(aA, aB, aE, col_ok, gx, yr + 2, q, qn, job, dp, cand, cand_cnt, flags);
+                // restore the invariant for row yr+3: coefficients of yr+2, yr+3
+                aA = aB;
+                aB = aE;
+            }
+            gA = r1;
+            gB = r2;
+        }
+#pragma unroll
+        for (int r = 0; r < kStripRows; ++r) cur[r] = nxt[r];
+    }
+    if (qn > 0) strip_flush(q, qn, job, dp, cand, cand_cnt, flags);
 }
 
 // Gating pre-pass, one wave per detection tile (all octaves in one
@@ -793,6 +1008,14 @@ hipError_t launch_gate_rows(const DetTile* tiles, int ntiles, const DetParams& d
                             uint64_t* rows, int32_t* state, hipStream_t stream) {
     if (ntiles <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_gate_rows, dim3((ntiles + 3) / 4), dim3(256), 0, stream, tiles, ntiles, dp, gate, rows, state);
+    return hipGetLastError();
+}
+
+hipError_t launch_detect_strips(const float* pyr, const DetTile* strips, int nstrips, const DetParams& dp,
+                               cdvs_keypoint* cand, int32_t* cand_cnt, int32_t* flags, hipStream_t stream) {
+    if (nstrips <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_detect_strip, dim3((nstrips + 3) / 4), dim3(256), 0, stream, pyr, strips, nstrips, dp, cand,
+                       cand_cnt, flags);
     return hipGetLastError();
 }
 
