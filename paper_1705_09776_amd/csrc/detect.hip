@@ -374,14 +374,13 @@ __global__ __launch_bounds__(256) void k_detect(const float* __restrict__ pyr, c
 // evaluates its own column's cubics at its neighbours' scales and hands the
 // values over, so no lane needs another lane's coefficients.  Centres that
 // pass are queued in the wave's LDS list with their 3x3 values and refined
-// 64 at a time (dense lanes; one global atomic per 64 survivors).
+// in passes of up to 64 once more than 36 are waiting (dense lanes; one
+// global atomic per pass).
 constexpr int kStripW = kDetStripW;
 constexpr int kStripH = kDetStripH;
-constexpr int kStripRing = 3;          // rows per ring period (three coefficient rows)
-constexpr int kStripChunk = 2;         // ring periods per prefetched chunk
-constexpr int kStripRows = kStripRing * kStripChunk;
-constexpr int kQCap = 128;             // < 64 pending + at most 60 from one row
-constexpr int kQFields = 13;           // v0..v8, s, p, pss, (x | y << 16)
+constexpr int kQCap = 96;              // flushed above 36, and one row adds at most 60
+constexpr int kQFlush = kQCap - 60;
+constexpr int kQFields = 12;           // the eight neighbour values, s, p, pss, (x | y << 16)
 
 __device__ __forceinline__ float lane_from_left(float v) {   // lane l gets lane l-1's value (lane 0: 0)
     return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x138, 0xf, 0xf, false));
@@ -394,11 +393,8 @@ struct StripRow {
     float g[kScales];
 };
 
-// Plane row y (clamped to the image) of this lane's column; rows past
-// `last` (the strip's last plane row) are not needed and not loaded.
-__device__ __forceinline__ void load_row(const float* __restrict__ col, const DetTile& job, int y, int last,
-                                         StripRow& r) {
-    if (y > last) return;   // uniform over the wave
+// Plane row y (clamped to the image) of this lane's column.
+__device__ __forceinline__ void load_row(const float* __restrict__ col, const DetTile& job, int y, StripRow& r) {
     const float* p = col + (int64_t)clampi(y, 0, job.h - 1) * job.pitch;
 #pragma unroll
     for (int k = 0; k < kScales; ++k) r.g[k] = p[(int64_t)k * job.plane_stride];
@@ -414,25 +410,38 @@ __device__ __forceinline__ float4 strip_alpha(const StripRow& u, const StripRow&
     return a;
 }
 
-// Refines the first n (<= 64) queued centres of this wave and appends the
-// survivors to the image's candidates.  Every lane of the wave calls it.
-__device__ __forceinline__ void strip_flush(float (*q)[kQCap], int n, const DetTile& job, const DetParams& dp,
-                                            cdvs_keypoint* __restrict__ cand, int32_t* __restrict__ cand_cnt,
-                                            int32_t* __restrict__ flags) {
+// Refines queued centres base .. base+n-1 (n <= 64) of this wave and
+// appends the survivors to the image's candidates.  Every lane of the wave
+// calls it.
+__device__ __forceinline__ void strip_flush(float (*q)[kQCap], int base, int n, const DetTile& job,
+                                            const DetParams& dp, cdvs_keypoint* __restrict__ cand,
+                                            int32_t* __restrict__ cand_cnt, int32_t* __restrict__ flags) {
     const int lane = threadIdx.x & 63;
     Cand c{};
     bool keep = false;
     int gx = 0, gy = 0;
     if (lane < n) {
+        const int e = base + lane;
         float v[9];
 #pragma unroll
-        for (int i = 0; i < 9; ++i) v[i] = q[i][lane];
-        const int xy = __float_as_int(q[12][lane]);
+        for (int i = 0; i < 4; ++i) v[i] = q[i][e];
+        v[4] = q[9][e];   // the centre: p
+#pragma unroll
+        for (int i = 5; i < 9; ++i) v[i] = q[i - 1][e];
+        const int xy = __float_as_int(q[11][e]);
         gx = xy & 0xffff;
         gy = xy >> 16;
-        keep = refine_v(v, q[9][lane], q[10][lane], q[11][lane], dp, c);
+        keep = refine_v(v, q[8][e], q[9][e], q[10][e], dp, c);
     }
     emit(keep, c, gx, gy, job, dp, cand, cand_cnt, flags);
+}
+
+// Refines everything queued (in passes of 64) and empties the queue.
+__device__ __forceinline__ void strip_drain(float (*q)[kQCap], int& qn, const DetTile& job, const DetParams& dp,
+                                            cdvs_keypoint* __restrict__ cand, int32_t* __restrict__ cand_cnt,
+                                            int32_t* __restrict__ flags) {
+    for (int base = 0; base < qn; base += 64) strip_flush(q, base, min(64, qn - base), job, dp, cand, cand_cnt, flags);
+    qn = 0;
 }
 
 // Centre tests of one row y from the coefficients of rows y-1, y, y+1;
@@ -466,27 +475,16 @@ __device__ __forceinline__ void strip_centres(const float4& aU, const float4& aM
     if (keep) {
         const int i = qn + __popcll(m & ((1ull << lane) - 1ull));
 #pragma unroll
-        for (int f = 0; f < 9; ++f) q[f][i] = v[f];
-        q[9][i] = s;
-        q[10][i] = p;
-        q[11][i] = pss;
-        q[12][i] = __int_as_float(gx | (y << 16));
+        for (int f = 0; f < 4; ++f) q[f][i] = v[f];
+#pragma unroll
+        for (int f = 5; f < 9; ++f) q[f - 1][i] = v[f];
+        q[8][i] = s;
+        q[9][i] = p;
+        q[10][i] = pss;
+        q[11][i] = __int_as_float(gx | (y << 16));
     }
     qn += __popcll(m);
-    if (qn >= 64) {
-        strip_flush(q, 64, job, dp, cand, cand_cnt, flags);
-        // move the rest (fewer than 64) to the front; the source and
-        // destination ranges do not overlap
-        const int rest = qn - 64;
-        if (lane < rest) {
-            float t[kQFields];
-#pragma unroll
-            for (int f = 0; f < kQFields; ++f) t[f] = q[f][64 + lane];
-#pragma unroll
-            for (int f = 0; f < kQFields; ++f) q[f][lane] = t[f];
-        }
-        qn = rest;
-    }
+    if (qn > kQFlush) strip_drain(q, qn, job, dp, cand, cand_cnt, flags);
 }
 
 __global__ __launch_bounds__(256) void k_detect_strip(const float* __restrict__ pyr, const DetTile* __restrict__ strips,
@@ -503,59 +501,35 @@ __global__ __launch_bounds__(256) void k_detect_strip(const float* __restrict__ 
     const int gx = x0 - 2 + lane;
     const bool col_ok = lane >= 2 && gx < xend;
     const float* col = pyr + job.plane0 + clampi(gx, 0, job.w - 1);
-
-    // rows y0-2 .. y0+1 give the coefficients of rows y0-1 and y0
+    // Plane rows live in a ring of kRing slots, row y in slot (y - y0 + 2) %
+    // kRing, and coefficient rows in a ring of three, row y in slot
+    // (y - y0 + 1) % 3.  Centre row y computes the coefficients of row y+1,
+    // which frees plane row y's slot for row y + kRing, loaded right away and
+    // first needed four rows later.  Loads past the strip's last plane row
+    // re-read that row (clamped; every load is unconditional, so the waits
+    // for them are exact).
+    constexpr int kRing = 6;
     const int last = yend + 1;
-    StripRow gA, gB, gC, gD;
-    load_row(col, job, y0 - 2, last, gA);
-    load_row(col, job, y0 - 1, last, gB);
-    load_row(col, job, y0, last, gC);
-    load_row(col, job, y0 + 1, last, gD);
-    StripRow cur[kStripRows];
+    StripRow g[kRing], t0, t1;
+    load_row(col, job, y0 - 2, t0);
+    load_row(col, job, y0 - 1, t1);
 #pragma unroll
-    for (int r = 0; r < kStripRows; ++r) load_row(col, job, y0 + 2 + r, last, cur[r]);
-    float4 aA = strip_alpha(gA, gB, gC, dp);   // row y0-1
-    float4 aB = strip_alpha(gB, gC, gD, dp);   // row y0
-    gA = gC;
-    gB = gD;
+    for (int r = 2; r < kRing + 2; ++r) load_row(col, job, min(y0 - 2 + r, last), g[r % kRing]);
+    float4 a[3];
+    a[0] = strip_alpha(t0, t1, g[2], dp);     // row y0-1
+    a[1] = strip_alpha(t1, g[2], g[3], dp);   // row y0
     int qn = 0;
-    // invariant at the top of each chunk (first centre row y): gA, gB hold
-    // plane rows y, y+1; aA, aB the coefficients of rows y-1, y; cur[] the
-    // plane rows y+2 .. y+1+kStripRows
-    for (int y = y0; y < yend; y += kStripRows) {
-        StripRow nxt[kStripRows];
+    for (int y = y0; y < yend; y += kRing) {
 #pragma unroll
-        for (int r = 0; r < kStripRows; ++r) load_row(col, job, y + 2 + kStripRows + r, last, nxt[r]);
-#pragma unroll
-        for (int c3 = 0; c3 < kStripChunk; ++c3) {
-            const int yr = y + c3 * kStripRing;
-            const StripRow& r0 = cur[c3 * kStripRing];
-            const StripRow& r1 = cur[c3 * kStripRing + 1];
-            const StripRow& r2 = cur[c3 * kStripRing + 2];
-            if (yr < yend) {
-                const float4 aC = strip_alpha(gA, gB, r0, dp);   // row yr+1
-                strip_centres(aA, aB, aC, col_ok, gx, yr, q, qn, job, dp, cand, cand_cnt, flags);
-                aA = aC;   // row yr+1
-            }
-            if (yr + 1 < yend) {
-                const float4 aD = strip_alpha(gB, r0, r1, dp);   // row yr+2
-                strip_centres(aB, aA, aD, col_ok, gx, yr + 1, q, qn, job, dp, cand, cand_cnt, flags);
-                aB = aD;   // row yr+2
-            }
-            if (yr + 2 < yend) {
-                const float4 aE = strip_alpha(r0, r1, r2, dp);   // row yr+3
-                strip_centres(aA, aB, aE, col_ok, gx, yr + 2, q, qn, job, dp, cand, cand_cnt, flags);
-                // restore the invariant for row yr+3: coefficients of yr+2, yr+3
-                aA = aB;
-                aB = aE;
-            }
-            gA = r1;
-            gB = r2;
+        for (int r = 0; r < kRing; ++r) {
+            a[(r + 2) % 3] = strip_alpha(g[(r + 2) % kRing], g[(r + 3) % kRing], g[(r + 4) % kRing], dp);
+            load_row(col, job, min(y + r + kRing, last), g[(r + 2) % kRing]);
+            if (y + r < yend)   // uniform over the wave
+                strip_centres(a[r % 3], a[(r + 1) % 3], a[(r + 2) % 3], col_ok, gx, y + r, q, qn, job, dp, cand,
+                              cand_cnt, flags);
         }
-#pragma unroll
-        for (int r = 0; r < kStripRows; ++r) cur[r] = nxt[r];
     }
-    if (qn > 0) strip_flush(q, qn, job, dp, cand, cand_cnt, flags);
+    strip_drain(q, qn, job, dp, cand, cand_cnt, flags);
 }
 
 // Gating pre-pass, one wave per detection tile (all octaves in one
