@@ -51,7 +51,8 @@ __device__ __forceinline__ KpGeom keypoint_geometry(const float* pyr, const OctG
 }
 
 // Angle of (x, y) in [0, 2 pi).  The octant symmetries of the arctangent
-// reduce the argument to t = min(|x|, |y|) / max(|x|, |y|) in [0, 1], where
+// reduce the argument to t = min(|x|, |y|) / max(|x|, |y|) in [0, 1] (its
+// rounding, under 2 ulp, moves the angle by less than 1e-7 rad), where
 // atan(t) is an odd polynomial t P(t^2) of degree 15 whose coefficients were
 // fitted here by (iteratively reweighted) least squares on Chebyshev nodes of
 // [0, 1]; in fp32 its error is below 2e-7 rad, and the reflections add at
@@ -60,7 +61,9 @@ __device__ __forceinline__ KpGeom keypoint_geometry(const float* pyr, const OctG
 __device__ __forceinline__ float angle_2pi(float y, float x) {
     const float ax = fabsf(x), ay = fabsf(y);
     const float mx = fmaxf(ax, ay), mn = fminf(ax, ay);
-    const float t = mx > 0.f ? __fdividef(mn, mx) : 0.f;
+    // mn / mx by the hardware reciprocal (1 ulp) and a multiply: a plain
+    // division is a full IEEE sequence on this target, several times longer
+    const float t = mx > 0.f ? mn * __builtin_amdgcn_rcpf(mx) : 0.f;
     const float s = t * t;
     float p = -0.004072779323905706f;
     p = fmaf(p, s, 0.021944405511021614f);
@@ -95,8 +98,17 @@ __device__ __forceinline__ void gradient(const KpGeom& g, int u, int v, float& m
 // Histogram copies per wave: lane l adds into copy l % kCopies; copies are
 // staggered by one bank.
 constexpr int kCopies = 8;
+// Orientation histogram copy: 36 bins plus bin 36, which takes the share of
+// bin 0 that wraps around from bin 35 (folded into bin 0 at the end); the
+// odd stride also starts the copies on different banks.
 constexpr int kOriStride = kOriBins + 1;
-constexpr int kDescStride = kDescDim + 1;
+// Descriptor histogram copy: 4 x 4 cells of 9 bins, bin 8 taking the share
+// of orientation bin 0 that wraps around from bin 7 (folded into bin 0 at
+// the end, which leaves every integer sum unchanged), so that the eight
+// adds of one pixel sit at fixed offsets from one base address; plus one
+// word so that copies start on different banks.
+constexpr int kDescCellBins = 9;
+constexpr int kDescStride = 16 * kDescCellBins + 1;
 
 // Walks the bounding box [u0, u0+bw) x [v0, ...) in row-major order, 64
 // pixels per step, without integer division in the loop.
@@ -161,9 +173,8 @@ __global__ __launch_bounds__(256) void k_orient(const float* __restrict__ pyr, c
                 const float fr = fb - f0;
                 int b0 = (int)f0;
                 b0 = b0 >= kOriBins ? b0 - kOriBins : b0;
-                const int b1 = b0 + 1 == kOriBins ? 0 : b0 + 1;
                 atomicAdd(hc + b0, (uint32_t)(wt - wt * fr + 0.5f));
-                atomicAdd(hc + b1, (uint32_t)(wt * fr + 0.5f));
+                atomicAdd(hc + b0 + 1, (uint32_t)(wt * fr + 0.5f));   // bin 36 is bin 0
             }
         }
     }
@@ -173,7 +184,8 @@ __global__ __launch_bounds__(256) void k_orient(const float* __restrict__ pyr, c
     auto bin = [&](int b) {
         uint32_t t = 0u;
 #pragma unroll
-        for (int c = 0; c < kCopies; ++c) t += hist[wave][c * kOriStride + b];
+        for (int c = 0; c < kCopies; ++c)
+            t += hist[wave][c * kOriStride + b] + (b == 0 ? hist[wave][c * kOriStride + kOriBins] : 0u);
         return (float)t / op.fix;
     };
     // every lane reads its bin and both neighbours from the summed copies
@@ -286,21 +298,27 @@ __global__ __launch_bounds__(256) void k_describe(const float* __restrict__ pyr,
                 const float x0f = floorf(fx), y0f = floorf(fy), o0f = floorf(fo);
                 const float ax = fx - x0f, ay = fy - y0f, ao = fo - o0f;
                 const int x0 = (int)x0f, y0 = (int)y0f;
-                const int o0 = (int)o0f & 7, o1 = (o0 + 1) & 7;
+                const int o0 = (int)o0f & 7;
+                // The two cells per axis are slots 0 and 1 from a base cell
+                // clamped to 0..2; a cell outside the 4 x 4 grid gets weight 0
+                // and the weights shift with the base, so each in-grid cell
+                // receives exactly its own trilinear share.
+                const int bx = min(max(x0, 0), 2), by = min(max(y0, 0), 2);
+                const float wx0 = x0 == bx ? 1.f - ax : (x0 == bx - 1 ? ax : 0.f);   // cell bx
+                const float wx1 = x0 == bx ? ax : (x0 == bx + 1 ? 1.f - ax : 0.f);   // cell bx + 1
+                const float wy0 = y0 == by ? 1.f - ay : (y0 == by - 1 ? ay : 0.f);
+                const float wy1 = y0 == by ? ay : (y0 == by + 1 ? 1.f - ay : 0.f);
+                uint32_t* cell = hc + (by * 4 + bx) * kDescCellBins + o0;
 #pragma unroll
                 for (int jy = 0; jy < 2; ++jy) {
-                    const int yy = y0 + jy;
-                    if ((unsigned)yy > 3u) continue;
-                    const float wy = wt * (jy ? ay : 1.f - ay);
+                    const float wy = wt * (jy ? wy1 : wy0);
 #pragma unroll
                     for (int jx = 0; jx < 2; ++jx) {
-                        const int xx = x0 + jx;
-                        if ((unsigned)xx > 3u) continue;
-                        const float wyx = wy * (jx ? ax : 1.f - ax);
+                        const float wyx = wy * (jx ? wx1 : wx0);
                         const float w1 = wyx * ao;
-                        uint32_t* cell = hc + (yy * 4 + xx) * 8;
-                        atomicAdd(cell + o0, (uint32_t)(wyx - w1 + 0.5f));
-                        atomicAdd(cell + o1, (uint32_t)(w1 + 0.5f));
+                        uint32_t* c = cell + (jy * 4 + jx) * kDescCellBins;
+                        atomicAdd(c, (uint32_t)(wyx - w1 + 0.5f));
+                        atomicAdd(c + 1, (uint32_t)(w1 + 0.5f));
                     }
                 }
             }
@@ -309,11 +327,15 @@ __global__ __launch_bounds__(256) void k_describe(const float* __restrict__ pyr,
     __syncthreads();
     if (!active) return;
 
+    // element e = cell * 8 + bin; bin 0 also takes the cell's wrap bin
     uint32_t i0 = 0u, i1 = 0u;
+    const int e0 = (lane >> 3) * kDescCellBins + (lane & 7), e1 = e0 + 8 * kDescCellBins;
+    const bool wrap = (lane & 7) == 0;
 #pragma unroll
     for (int c = 0; c < kCopies; ++c) {
-        i0 += hist[wave][c * kDescStride + lane];
-        i1 += hist[wave][c * kDescStride + lane + 64];
+        const uint32_t* h = &hist[wave][c * kDescStride];
+        i0 += h[e0] + (wrap ? h[e0 + 8] : 0u);
+        i1 += h[e1] + (wrap ? h[e1 + 8] : 0u);
     }
     const float h0 = (float)i0 / dp.fix, h1 = (float)i1 / dp.fix;
     float* out = desc + (((int64_t)img * dp.kp_cap + i) * kDescDim);
