@@ -80,11 +80,20 @@ __device__ __forceinline__ float angle_2pi(float y, float x) {
     return r >= kTwoPi ? 0.f : r;
 }
 
-// Gradient at an interior pixel: central differences, angle in [0, 2 pi).
-__device__ __forceinline__ void gradient(const KpGeom& g, int u, int v, float& mag, float& ang) {
+// The four neighbours of an interior pixel (u, v), and from them the
+// gradient by central differences, angle in [0, 2 pi).
+struct Nbrs {
+    float l, r, d, u;   // (u-1, v), (u+1, v), (u, v-1), (u, v+1)
+};
+
+__device__ __forceinline__ Nbrs load_nbrs(const KpGeom& g, int u, int v) {
     const float* row = g.plane + (int64_t)v * g.pitch;
-    const float gx = row[u + 1] - row[u - 1];
-    const float gy = row[u + g.pitch] - row[u - g.pitch];
+    return Nbrs{row[u - 1], row[u + 1], row[u - g.pitch], row[u + g.pitch]};
+}
+
+__device__ __forceinline__ void gradient(const Nbrs& n, float& mag, float& ang) {
+    const float gx = n.r - n.l;
+    const float gy = n.u - n.d;
     mag = __builtin_amdgcn_sqrtf(gx * gx + gy * gy);   // hardware square root (1 ulp)
     ang = angle_2pi(gy, gx);
 }
@@ -165,8 +174,9 @@ __global__ __launch_bounds__(256) void k_orient(const float* __restrict__ pyr, c
                 const float dx = (float)u - g.cx, dy = (float)v - g.cy;
                 const float d2 = dx * dx + dy * dy;
                 if (!(d2 < R2)) continue;
+                const Nbrs nb = load_nbrs(g, u, v);
                 float mag, ang;
-                gradient(g, u, v, mag, ang);
+                gradient(nb, mag, ang);
                 const float wt = mag * __expf(d2 * nid) * op.fix;   // in fixed-point units
                 const float fb = ang * ((float)kOriBins / kTwoPi);
                 const float f0 = floorf(fb);
@@ -286,10 +296,11 @@ __global__ __launch_bounds__(256) void k_describe(const float* __restrict__ pyr,
                 const float dx = (float)u - g.cx, dy = (float)v - g.cy;
                 const float d2 = dx * dx + dy * dy;
                 if (!(d2 < R2)) continue;
+                const Nbrs nb = load_nbrs(g, u, v);
                 const float rx = (ct * dx + st * dy) * icw;
                 const float ry = (ct * dy - st * dx) * icw;
                 float mag, ang;
-                gradient(g, u, v, mag, ang);
+                gradient(nb, mag, ang);
                 float rel = ang - th;
                 if (rel < 0.f) rel += kTwoPi;
                 if (rel >= kTwoPi) rel -= kTwoPi;
