@@ -23,10 +23,14 @@ sys.path.insert(0, ROOT)
 PEAK_HBM_GBS = 8000.0        # MI355X HBM3E
 PEAK_FP32_TFLOPS = 157.3     # MI355X FP32 vector (256 CU x 2.4 GHz x 256 FLOP/clk)
 
-# Minimum arithmetic per pixel, from the filter lengths: each of the four
-# scale images costs (2r+1) multiply-adds per pass and two passes, r = 5, 7, 9, 12.
-SCALES_FLOP_PER_PX = 2 * 2 * sum(2 * r + 1 for r in (5, 7, 9, 12))   # 280
-PREBLUR_FLOP_PER_PX = 2 * 2 * (2 * 7 + 1)                            # 60
+# Minimum arithmetic per pixel of the separable Gaussians with symmetric
+# taps: one pass of radius r is r pair additions and r+1 multiply-adds
+# (3r + 2 flops); the four scale images (r = 5, 7, 9, 12) take two passes
+# each, and their column passes share the pair sums of one input column
+# (12 additions, then r+1 multiply-adds per image).
+SCALES_FLOP_PER_PX = (12 + sum(2 * (r + 1) for r in (5, 7, 9, 12))) + sum(3 * r + 2 for r in (5, 7, 9, 12))  # 193
+PREBLUR_FLOP_PER_PX = 2 * (3 * 7 + 2)                                # 46
+RIDGE_FLOP_PER_BYTE = PEAK_FP32_TFLOPS * 1e12 / (PEAK_HBM_GBS * 1e9)  # 19.7
 
 
 def log(msg):
@@ -71,7 +75,7 @@ WEIGHTS = os.path.join(ROOT, "paper_1705_09776_amd", "weights", "surrogate_640x4
 WEIGHTS_HIRES = os.path.join(ROOT, "paper_1705_09776_amd", "weights", "surrogate_1280x960.npz")
 WEIGHTS_T4 = os.path.join(ROOT, "paper_1705_09776_amd", "weights", "surrogate_640x480_t4.npz")
 TRAFFIC = os.path.join(ROOT, "profiles", "traffic_plain_batch256_640x480.md")
-_PROFILE_NAME = {"detect": "k_detect", "describe": "k_describe", "scales": "k_blur<scales>", "orient": "k_orient",
+_PROFILE_NAME = {"detect": "k_detect_strip", "describe": "k_describe", "scales": "k_blur<scales>", "orient": "k_orient",
                  "finalize": "k_finalize", "preblur": "k_blur<preblur>"}
 
 
@@ -462,7 +466,7 @@ def main():
     a = alg[dom]
     # roofline of the dominant kernel: its algorithmic bytes (or flops) over its
     # own event-timed duration, per launch averaged over the timed region
-    if a["bytes"] is not None and a["flop"] is not None and a["flop"] / a["bytes"] > 9.8:
+    if a["bytes"] is not None and a["flop"] is not None and a["flop"] / a["bytes"] > RIDGE_FLOP_PER_BYTE:
         roof = {"bound": "alu", "achieved": round(a["flop"] / t_step_s / 1e12, 3), "peak": PEAK_FP32_TFLOPS,
                 "unit": "TFLOP/s"}
     elif a["bytes"] is not None:
