@@ -357,7 +357,7 @@ typedef enum {
     CDVS_KERNEL_PREBLUR = 0,  /* u8 input -> G_{0,0} */
     CDVS_KERNEL_SCALES,       /* G_{o,0} -> G_{o,1..4} and G_{o+1,0}, one launch per octave */
     CDVS_KERNEL_CLEAR,        /* candidate counters */
-    CDVS_KERNEL_DETECT,       /* LoG + ALP + NMS + refinement: one launch (gated: one per octave) */
+    CDVS_KERNEL_DETECT,       /* LoG + ALP + NMS + refinement: one launch over all octaves */
     CDVS_KERNEL_FINALIZE,     /* cross-octave duplicates, sort, top-k */
     CDVS_KERNEL_ORIENT,       /* orientation histograms and peaks */
     CDVS_KERNEL_ORIENT_COMPACT,

@@ -32,14 +32,12 @@ struct cdvs_ctx {
     int job_start[kMaxOctaves + 1] = {};
     int blur_tiles[kBlurVariants][kMaxOctaves] = {};
     int blur_variant = 0;  // scale-plane tile variant (cdvs_autotune)
-    int det_tiles[kMaxOctaves] = {};
     int64_t pyr_floats = 0;
     Taps taps{};
     DetParams det{};
     OriParams ori{};
     DescParams desc{};
     float dedup_ratio = 0.f;
-    int detect_grid = 0;  // persistent detection grid (workgroups)
     int wgrad_grid = 0;   // grid of the CNN weight-gradient kernels
     // surrogate CNN cell grid
     std::vector<CnnImage> cnn;
@@ -48,8 +46,6 @@ struct cdvs_ctx {
     CnnImage* d_cnn = nullptr;
     int32_t* d_active = nullptr;  // [n][kMaxOctaves] active mask cells
     short* d_cnn_frag = nullptr;  // packed weight fragments of the fused inference kernel
-    uint64_t* d_gate_rows = nullptr;  // [detection tile][16] active-centre rows (gated detection)
-    int32_t* d_gate_state = nullptr;  // [detection tile] skip / sparse / dense
     // device
     OctJob* d_jobs = nullptr;
     std::vector<int32_t> blur_owner;           // [variant][octave][tile] -> job (relative to job_start[octave])
@@ -57,9 +53,6 @@ struct cdvs_ctx {
     int32_t* d_blur_owner = nullptr;
     std::vector<int32_t> cnn_owner;            // fused CNN tile -> image
     int32_t* d_cnn_owner = nullptr;
-    std::vector<DetTile> dtiles;               // detection tiles, grouped by octave
-    int dtile_start[kMaxOctaves + 1] = {};
-    DetTile* d_dtiles = nullptr;
     std::vector<DetTile> strips;   // ungated detection: image-major, then octave, then row-major strips
     DetTile* d_strips = nullptr;
     OctGeom* d_geom = nullptr;
@@ -273,7 +266,6 @@ void cdvs_ctx_destroy(cdvs_ctx* ctx) {
     if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
     for (auto& e : ctx->ev) (void)hipEventDestroy(e);
     (void)hipFree(ctx->d_jobs);
-    (void)hipFree(ctx->d_dtiles);
     (void)hipFree(ctx->d_strips);
     (void)hipFree(ctx->d_blur_owner);
     (void)hipFree(ctx->d_cnn_owner);
@@ -289,8 +281,6 @@ void cdvs_ctx_destroy(cdvs_ctx* ctx) {
     (void)hipFree(ctx->d_cnn);
     (void)hipFree(ctx->d_active);
     (void)hipFree(ctx->d_cnn_frag);
-    (void)hipFree(ctx->d_gate_rows);
-    (void)hipFree(ctx->d_gate_state);
     delete ctx;
 }
 
@@ -336,7 +326,6 @@ static cdvs_status build_layout(cdvs_ctx* c) {
             j.image = i;
             j.octave = o;
             for (int v = 0; v < kBlurVariants; ++v) j.tiles_x_blur[v] = (ws[o] + blur_tw(v) - 1) / blur_tw(v);
-            j.tiles_x_det = (ws[o] + kDetTW - 1) / kDetTW;
             per_oct[o].push_back(j);
         }
     }
@@ -344,18 +333,15 @@ static cdvs_status build_layout(cdvs_ctx* c) {
     c->jobs.clear();
     for (int o = 0; o < kMaxOctaves; ++o) {
         c->job_start[o] = (int)c->jobs.size();
-        int tb[kBlurVariants] = {}, td = 0;
+        int tb[kBlurVariants] = {};
         for (OctJob& j : per_oct[o]) {
             for (int v = 0; v < kBlurVariants; ++v) {
                 j.tile0_blur[v] = tb[v];
                 tb[v] += j.tiles_x_blur[v] * ((j.h + blur_th(v) - 1) / blur_th(v));
             }
-            j.tile0_det = td;
-            td += j.tiles_x_det * ((j.h + kDetTH - 1) / kDetTH);
             c->jobs.push_back(j);
         }
         for (int v = 0; v < kBlurVariants; ++v) c->blur_tiles[v][o] = tb[v];
-        c->det_tiles[o] = td;
     }
     c->blur_owner.clear();
     for (int v = 0; v < kBlurVariants; ++v)
@@ -379,30 +365,6 @@ static cdvs_status build_layout(cdvs_ctx* c) {
         c->cand_off[i] = cand_total;
         cand_total += c->cand_cap[i];
     }
-    c->dtiles.clear();
-    for (int o = 0; o < kMaxOctaves; ++o) {
-        c->dtile_start[o] = (int)c->dtiles.size();
-        for (const OctJob& j : per_oct[o]) {
-            const int ty_n = (j.h + kDetTH - 1) / kDetTH;
-            for (int t = 0; t < j.tiles_x_det * ty_n; ++t) {
-                DetTile r;
-                memset(&r, 0, sizeof(r));
-                r.plane0 = j.plane0;
-                r.plane_stride = j.plane_stride;
-                r.pitch = j.pitch;
-                r.w = j.w;
-                r.h = j.h;
-                r.tx0 = (t % j.tiles_x_det) * kDetTW;
-                r.ty0 = (t / j.tiles_x_det) * kDetTH;
-                r.image = j.image;
-                r.octave = j.octave;
-                r.cand_cap = c->cand_cap[j.image];
-                r.cand_blk = (int32_t)(c->cand_off[j.image] / kCandBlock);
-                c->dtiles.push_back(r);
-            }
-        }
-    }
-    c->dtile_start[kMaxOctaves] = (int)c->dtiles.size();
     // strips of the ungated detection, covering each octave's centres inside
     // the border; image-major so that each XCD's contiguous share holds
     // whole images (balanced work, and neighbouring strips share halo rows
@@ -529,7 +491,6 @@ cdvs_status cdvs_ctx_create(const cdvs_params* params, const cdvs_image_desc* im
         }                                                                        \
     } while (0)
     ALLOC(c->d_jobs, sizeof(OctJob) * std::max<size_t>(1, c->jobs.size()));
-    ALLOC(c->d_dtiles, sizeof(DetTile) * std::max<size_t>(1, c->dtiles.size()));
     ALLOC(c->d_strips, sizeof(DetTile) * std::max<size_t>(1, c->strips.size()));
     ALLOC(c->d_blur_owner, sizeof(int32_t) * std::max<size_t>(1, c->blur_owner.size()));
     ALLOC(c->d_cnn_owner, sizeof(int32_t) * std::max<size_t>(1, c->cnn_owner.size()));
@@ -553,13 +514,9 @@ cdvs_status cdvs_ctx_create(const cdvs_params* params, const cdvs_image_desc* im
     ALLOC(c->d_cnn, sizeof(CnnImage) * n);
     ALLOC(c->d_active, sizeof(int32_t) * n * kMaxOctaves);
     ALLOC(c->d_cnn_frag, sizeof(short) * kCnnFragShorts);
-    ALLOC(c->d_gate_rows, sizeof(uint64_t) * kDetTH * std::max<size_t>(1, c->dtiles.size()));
-    ALLOC(c->d_gate_state, sizeof(int32_t) * std::max<size_t>(1, c->dtiles.size()));
 #undef ALLOC
     if ((e = hipMemcpy(c->d_jobs, c->jobs.data(), sizeof(OctJob) * c->jobs.size(), hipMemcpyHostToDevice)) != hipSuccess ||
         (e = hipMemcpy(c->d_strips, c->strips.data(), sizeof(DetTile) * c->strips.size(), hipMemcpyHostToDevice)) !=
-            hipSuccess ||
-        (e = hipMemcpy(c->d_dtiles, c->dtiles.data(), sizeof(DetTile) * c->dtiles.size(), hipMemcpyHostToDevice)) !=
             hipSuccess ||
         (e = hipMemcpy(c->d_blur_owner, c->blur_owner.data(), sizeof(int32_t) * c->blur_owner.size(),
                        hipMemcpyHostToDevice)) != hipSuccess ||
@@ -576,14 +533,11 @@ cdvs_status cdvs_ctx_create(const cdvs_params* params, const cdvs_image_desc* im
         cdvs_ctx_destroy(c);
         return CDVS_ERR_HIP;
     }
-    // persistent detection: three 256-lane workgroups per compute unit (the
-    // kernel's LDS allows three)
     int dev = 0, cus = 256;
     if (hipGetDevice(&dev) == hipSuccess) {
         int v = 0;
         if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && v > 0) cus = v;
     }
-    c->detect_grid = std::max(kXcds, (cus * 3) / kXcds * kXcds);
     c->wgrad_grid = std::max(kXcds, cus * 2);
     *out = c;
     return CDVS_OK;
@@ -643,35 +597,22 @@ cdvs_status cdvs_alp_detect(cdvs_ctx* ctx, const float* d_pyr, const uint8_t* d_
     if (!d_pyr || !d_kp || !d_count) return fail(ctx, CDVS_ERR_ARG, "cdvs_alp_detect: null device pointer");
     if (((uintptr_t)d_pyr & 255) != 0) return fail(ctx, CDVS_ERR_ARG, "cdvs_alp_detect: d_pyr not 256-byte aligned");
     hipStream_t s = (hipStream_t)stream;
-    GateParams gate{nullptr, nullptr, nullptr, 1.f, nullptr, nullptr};
+    GateParams gate{nullptr, nullptr, nullptr, 1.f};
     if (d_mask) {
         Bracket b(ctx, CDVS_KERNEL_MASK_COUNT, s);
         HIP_OR_FAIL(ctx, launch_mask_count(d_mask, ctx->d_cnn, ctx->n, ctx->d_active, s));
-        gate = GateParams{d_mask, ctx->d_active, ctx->d_cnn, ctx->params.mask_fmax, ctx->d_gate_rows, ctx->d_gate_state};
-        HIP_OR_FAIL(ctx, launch_gate_rows(ctx->d_dtiles, (int)ctx->dtiles.size(), ctx->det, gate, ctx->d_gate_rows,
-                                          ctx->d_gate_state, s));
+        gate = GateParams{d_mask, ctx->d_active, ctx->d_cnn, ctx->params.mask_fmax};
     }
     {
         Bracket b(ctx, CDVS_KERNEL_CLEAR, s);
         HIP_OR_FAIL(ctx, launch_clear(ctx->d_cand_cnt, ctx->n, s));
     }
-    if (!d_mask) {
-        // ungated: one launch over the strips of every octave
+    {
+        // one launch over the strips of every octave; the finalisation does
+        // not rely on the order in which candidates arrive
         Bracket b(ctx, CDVS_KERNEL_DETECT, s);
-        HIP_OR_FAIL(ctx, launch_detect_strips(d_pyr, ctx->d_strips, (int)ctx->strips.size(), ctx->det, ctx->d_cand,
-                                              ctx->d_cand_cnt, ctx->d_flags, s));
-    }
-    // gated: one persistent launch per octave over the tiles; the
-    // finalisation does not rely on the order
-    for (int o = 0; d_mask && o < ctx->max_oct; ++o) {
-        Bracket b(ctx, CDVS_KERNEL_DETECT, s);
-        GateParams go = gate;
-        if (go.mask) {
-            go.rows += (int64_t)kDetTH * ctx->dtile_start[o];
-            go.state += ctx->dtile_start[o];
-        }
-        HIP_OR_FAIL(ctx, launch_detect(d_pyr, ctx->d_dtiles + ctx->dtile_start[o], ctx->det_tiles[o],
-                                       ctx->detect_grid, ctx->det, go, ctx->d_cand, ctx->d_cand_cnt, ctx->d_flags, s));
+        HIP_OR_FAIL(ctx, launch_detect_strips(d_pyr, ctx->d_strips, (int)ctx->strips.size(), ctx->det, gate,
+                                              ctx->d_cand, ctx->d_cand_cnt, ctx->d_flags, s));
     }
     {
         Bracket b(ctx, CDVS_KERNEL_FINALIZE, s);

@@ -46,17 +46,16 @@ struct OctJob {
     int32_t image;
     int32_t octave;
     int32_t tiles_x_blur[4], tile0_blur[4];  // tiling of the blur kernels, per tile variant
-    int32_t tiles_x_det, tile0_det;    // tiling of the detection kernel
 };
 
-// One detection tile: everything the detection kernels need to stage and
-// label it, so that a tile costs one record load (no job search).
+// One detection strip: everything the detection kernel needs to load and
+// label it, so that a strip costs one record load (no job search).
 struct DetTile {
     int64_t plane0;        // float offset of G_{o,0}
     int32_t plane_stride;  // floats between G_{o,k} and G_{o,k+1}
     int32_t pitch;         // floats
     int32_t w, h;          // octave size
-    int32_t tx0, ty0;      // tile origin (octave pixels)
+    int32_t tx0, ty0;      // the strip's first centre (octave pixels)
     int32_t image, octave;
     int32_t cand_cap;      // the image's candidate capacity
     int32_t cand_blk;      // the image's first candidate slot / kCandBlock
@@ -135,10 +134,7 @@ struct GateParams {
     const int32_t* active;   // [image][kMaxOctaves] active cells of the mask
     const CnnImage* cells;   // per image cell grid
     float fmax;              // fraction of active cells above which detection is dense
-    const uint64_t* rows;    // per detection tile: 16 active-centre row masks (k_gate_rows)
-    const int32_t* state;    // per detection tile: kTileSkip, kTileSparse or kTileDense
 };
-constexpr int kTileSkip = 0, kTileSparse = 1, kTileDense = 2;
 
 // Kernel tile shapes.
 // Scale-plane kernel tile variants (width x height, autotuned); the
@@ -147,7 +143,6 @@ constexpr int kBlurVariants = 4;
 constexpr int kBlurV = 8;
 __host__ __device__ constexpr int blur_tw(int v) { return v == 1 ? 128 : v == 2 ? 32 : 64; }
 __host__ __device__ constexpr int blur_th(int v) { return v == 0 ? 32 : v == 1 ? 16 : v == 2 ? 32 : 16; }
-constexpr int kDetTW = 64, kDetTH = 16;
 
 // Launchers (each enqueues on `stream`, returns the launch error).
 hipError_t launch_preblur(const uint8_t* images, float* pyr, const OctJob* jobs, const int32_t* owner, int ntiles,
@@ -155,16 +150,13 @@ hipError_t launch_preblur(const uint8_t* images, float* pyr, const OctJob* jobs,
 hipError_t launch_scales(float* pyr, const OctJob* jobs, const int32_t* owner, int ntiles, int variant,
                          const Taps& taps, hipStream_t stream);
 hipError_t launch_clear(int32_t* p, int n, hipStream_t stream);
-hipError_t launch_gate_rows(const DetTile* tiles, int ntiles, const DetParams& dp, const GateParams& gate,
-                            uint64_t* rows, int32_t* state, hipStream_t stream);
-hipError_t launch_detect(const float* pyr, const DetTile* tiles, int ntiles, int grid, const DetParams& dp,
-                         const GateParams& gate, cdvs_keypoint* cand, int32_t* cand_cnt, int32_t* flags,
-                         hipStream_t stream);
-// Ungated detection over strips of 60 x kDetStripH centres inside the
-// detection border (tx0, ty0 = the strip's first centre), one wave each.
+// Detection over strips of 60 x kDetStripH centres inside the detection
+// border (tx0, ty0 = the strip's first centre), one wave each; gated by
+// gate.mask unless it is null.
 constexpr int kDetStripW = 60, kDetStripH = 48;
 hipError_t launch_detect_strips(const float* pyr, const DetTile* strips, int nstrips, const DetParams& dp,
-                               cdvs_keypoint* cand, int32_t* cand_cnt, int32_t* flags, hipStream_t stream);
+                                const GateParams& gate, cdvs_keypoint* cand, int32_t* cand_cnt, int32_t* flags,
+                                hipStream_t stream);
 hipError_t launch_select(const cdvs_keypoint* cand, const int32_t* cand_cnt, const int64_t* cand_off,
                          const int32_t* cand_capv, int n_images, cdvs_keypoint* sel, hipStream_t stream);
 hipError_t launch_finalize(const cdvs_keypoint* cand, const int32_t* cand_cnt, const int64_t* cand_off,

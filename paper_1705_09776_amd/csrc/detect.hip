@@ -1,14 +1,17 @@
 // ALP keypoint detection on gfx950 (Sec. III-A, Eqs. (2)-(3); Sec. IV-A,
 // Algorithm 1 stages A-C).
 //
-// k_detect: one 256-lane workgroup per 64x16 tile of one (image, octave).
-//   The five Gaussian images with a 2-pixel halo are staged in LDS; every
-//   lane computes the scale-normalised 5-point Laplacians and the four ALP
-//   coefficients of its pixels (tile + 1-pixel halo) into LDS; then per
-//   centre pixel: extremal scale, contrast test, strict 8-neighbour test at
-//   that scale, one quadratic refinement step.  Survivors are compacted with
-//   one wave ballot and one atomic per wave into the image's candidate list.
-//   One persistent launch per octave covers that octave of every image.
+// k_detect_strip: one wave per strip of 60 x 48 centres of one (image,
+//   octave), all octaves of all images in one launch; the wave streams the
+//   five Gaussian images down its strip in registers (details at the kernel).
+//   Per centre: scale-normalised 5-point Laplacians, the four ALP
+//   coefficients, extremal scale, contrast test, strict 8-neighbour test at
+//   that scale, one quadratic refinement step; survivors go to the image's
+//   candidate list with one ballot and one atomic per pass.  With a cell
+//   mask (the learned gate) only the centres of active cells are examined
+//   and strips without any are skipped before loading anything.
+// k_select (images with more candidates than k_finalize holds): their
+//   strongest kCandCap by |p|.
 // k_finalize: one workgroup per image.  Stage C (cross-octave duplicates)
 //   over adjacent-octave segments, then a bitonic sort in LDS on the 64-bit
 //   key (|p| desc, octave, iy, ix) and the top-k copy-out.
@@ -68,54 +71,6 @@ __device__ __forceinline__ bool alp_extremum(const float4 a, float lo, float hi,
     return found;
 }
 
-constexpr int DTW = kDetTW, DTH = kDetTH;
-// staged columns: tx0-4 .. tx0+DTW+3 (16-byte aligned start); rows ty0-2 .. ty0+DTH+1
-constexpr int GW = DTW + 8, GH = DTH + 4;
-constexpr int GX = 2;  // staged column of image column tx0-2
-constexpr int AW = DTW + 2, AH = DTH + 2;
-
-constexpr int DNV4 = kScales * GH * GW / 4;     // float4 chunks of the staged window
-constexpr int DNPER4 = (DNV4 + 255) / 256;      // chunks per lane
-static_assert(GW % 4 == 0, "staged rows are whole float4 chunks");
-// After the coefficients are computed the staging buffer holds the list of
-// contrast-passing centres (16 B each, at most one per centre).
-static_assert(kScales * GH * GW >= 4 * DTW * DTH, "the staging buffer holds the list of every centre");
-
-// Stage the five planes over the tile plus a clamped halo: rows are clamped
-// per chunk; a chunk lying inside the image is one aligned 16-byte load, and
-// only chunks crossing the left or right image edge load four clamped
-// scalars.  Every load of a lane is issued before its values are needed.
-__device__ __forceinline__ void load_tile(const float* __restrict__ pyr, const DetTile& job, float4 (&vals)[DNPER4]) {
-    const int tx0 = job.tx0, ty0 = job.ty0;
-#pragma unroll
-    for (int j = 0; j < DNPER4; ++j) {
-        const int t = threadIdx.x + j * 256;
-        if (t < DNV4) {
-            const int k = t / (GH * GW / 4), rem = t % (GH * GW / 4);
-            const int ly = rem / (GW / 4), c4 = rem % (GW / 4);
-            const int gy = clampi(ty0 - 2 + ly, 0, job.h - 1);
-            const int gx = tx0 - 4 + 4 * c4;
-            const float* row = pyr + job.plane0 + (int64_t)k * job.plane_stride + (int64_t)gy * job.pitch;
-            if (gx >= 0 && gx + 3 < job.w) {
-                vals[j] = *reinterpret_cast<const float4*>(row + gx);
-            } else {
-                vals[j] = make_float4(row[clampi(gx, 0, job.w - 1)], row[clampi(gx + 1, 0, job.w - 1)],
-                                      row[clampi(gx + 2, 0, job.w - 1)], row[clampi(gx + 3, 0, job.w - 1)]);
-            }
-        }
-    }
-}
-
-__device__ __forceinline__ void store_tile(float* G, const float4 (&vals)[DNPER4]) {
-#pragma unroll
-    for (int j = 0; j < DNPER4; ++j) {
-        const int t = threadIdx.x + j * 256;
-        if (t < DNV4) reinterpret_cast<float4*>(G)[t] = vals[j];
-    }
-}
-
-// Scale-normalised 5-point Laplacians of the five planes at staged pixel
-// (ly, lx), folded into the four ALP coefficients (Eqs. (2)-(3)).
 // 5-point Laplacian sum (up + down + left + right - 4 centre), in one fixed
 // order of operations shared by both detection kernels.
 __device__ __forceinline__ float lap5(float c, float up, float dn, float lf, float rt) {
@@ -135,24 +90,9 @@ __device__ __forceinline__ void alpha_acc(float4& a, float lap, int k, const Det
     a.w = fmaf(dp.beta[k][3], L, a.w);
 }
 
-__device__ __forceinline__ float4 alpha_at(const float (&G)[kScales][GH][GW], int ly, int lx, const DetParams& dp) {
-    float4 a = make_float4(0.f, 0.f, 0.f, 0.f);
-#pragma unroll
-    for (int k = 0; k < kScales; ++k)
-        alpha_acc(a, lap5(G[k][ly][lx], G[k][ly - 1][lx], G[k][ly + 1][lx], G[k][ly][lx - 1], G[k][ly][lx + 1]), k,
-                  dp);
-    return a;
-}
-
 struct Cand {
     float s, p, pss, ox, oy, pr, rho;
 };
-
-// Tile centre (cy, cx), first half: extremal scale and contrast.
-__device__ __forceinline__ bool centre_extremum(const float4 (&A)[AH][AW], int cy, int cx, const DetParams& dp,
-                                                float& s, float& p, float& pss) {
-    return alp_extremum(A[cy + 1][cx + 1], dp.lo, dp.hi, s, p, pss) && fabsf(p) >= dp.contrast;
-}
 
 // Strict extremum of the centre value p = v[4] against the eight
 // neighbours' cubics v[] evaluated at the centre's scale (Algorithm 1 stage A).
@@ -193,31 +133,6 @@ __device__ __forceinline__ bool refine_v(const float (&v)[9], float s, float p, 
     return true;
 }
 
-// Second half for a staged tile: strict 8-neighbour test at the centre's
-// scale and one quadratic refinement step (Algorithm 1 stages A-B).
-__device__ __forceinline__ bool centre_refine(const float4 (&A)[AH][AW], int cy, int cx, float s, float p, float pss,
-                                              const DetParams& dp, Cand& o) {
-    float v[9];
-#pragma unroll
-    for (int j = -1; j <= 1; ++j)
-#pragma unroll
-        for (int i = -1; i <= 1; ++i) v[(j + 1) * 3 + (i + 1)] = (i == 0 && j == 0) ? p : horner(A[cy + 1 + j][cx + 1 + i], s);
-    return strict_extremum(v, p) && refine_v(v, s, p, pss, dp, o);
-}
-
-// Appends (s, p, pss, centre index) of the lanes with `pass` to an LDS list
-// (one ballot and one LDS atomic per wave).  Every lane of the wave calls it.
-__device__ __forceinline__ void push_centre(bool pass, float s, float p, float pss, int q, float4* list, int* count) {
-    const int lane = threadIdx.x & 63;
-    const uint64_t m = __ballot(pass);
-    if (!m) return;
-    const int leader = __ffsll((unsigned long long)m) - 1;
-    int base = 0;
-    if (lane == leader) base = atomicAdd(count, __popcll(m));
-    base = __shfl(base, leader);
-    if (pass) list[base + __popcll(m & ((1ull << lane) - 1ull))] = make_float4(s, p, pss, __int_as_float(q));
-}
-
 // Wave-level compaction of survivors into the image's candidate list: one
 // ballot and one atomic per wave.  Every lane of the wave must call it.
 __device__ __forceinline__ void emit(bool keep, const Cand& c, int gx, int gy, const DetTile& job, const DetParams& dp,
@@ -253,117 +168,8 @@ __device__ __forceinline__ void emit(bool keep, const Cand& c, int gx, int gy, c
     cand[(int64_t)job.cand_blk * kCandBlock + slot] = r;
 }
 
-// Second phase over the LDS list of contrast-passing centres: dense lanes
-// for the 3x3 test and refinement, survivors appended to the candidates.
-__device__ __forceinline__ void refine_list(const float4 (&A)[AH][AW], const float4* list, int n, const DetTile& job,
-                                           const DetParams& dp, cdvs_keypoint* __restrict__ cand,
-                                           int32_t* __restrict__ cand_cnt, int32_t* __restrict__ flags) {
-    for (int i0 = 0; i0 < n; i0 += blockDim.x) {
-        const int i = i0 + threadIdx.x;
-        Cand c{};
-        bool keep = false;
-        int gx = 0, gy = 0;
-        if (i < n) {
-            const float4 r = list[i];
-            const int q = __float_as_int(r.w);
-            const int cy = q / DTW, cx = q % DTW;
-            gx = job.tx0 + cx;
-            gy = job.ty0 + cy;
-            keep = centre_refine(A, cy, cx, r.x, r.y, r.z, dp, c);
-        }
-        emit(keep, c, gx, gy, job, dp, cand, cand_cnt, flags);
-    }
-}
-
-// Tile records are fetched with vector loads, lane i holding dword i (the
-// wait for a scalar load would come at the next LDS access, since both are
-// counted together); as_uniform() moves the fields to scalar registers once
-// the record has arrived.
-typedef int RawTile;
-
-__device__ __forceinline__ RawTile fetch_tile(const DetTile* __restrict__ tiles, int idx) {
-    const int lane = threadIdx.x & 63;
-    constexpr int kWords = (int)sizeof(DetTile) / 4;
-    return reinterpret_cast<const int*>(tiles + idx)[min(lane, kWords - 1)];
-}
-
-__device__ __forceinline__ DetTile as_uniform(RawTile r) {
-    DetTile t;
-    t.plane0 = (int64_t)(uint32_t)__builtin_amdgcn_readlane(r, 0) | ((int64_t)__builtin_amdgcn_readlane(r, 1) << 32);
-    t.plane_stride = __builtin_amdgcn_readlane(r, 2);
-    t.pitch = __builtin_amdgcn_readlane(r, 3);
-    t.w = __builtin_amdgcn_readlane(r, 4);
-    t.h = __builtin_amdgcn_readlane(r, 5);
-    t.tx0 = __builtin_amdgcn_readlane(r, 6);
-    t.ty0 = __builtin_amdgcn_readlane(r, 7);
-    t.image = __builtin_amdgcn_readlane(r, 8);
-    t.octave = __builtin_amdgcn_readlane(r, 9);
-    t.cand_cap = __builtin_amdgcn_readlane(r, 10);
-    t.cand_blk = __builtin_amdgcn_readlane(r, 11);
-    return t;
-}
-
-// Persistent: the grid (a multiple of 8) is split evenly over the XCDs; each
-// workgroup walks its XCD's contiguous tile range with a stride, and the next
-// tile's loads are in flight while the current tile is computed.
-// The refinement of a tile's contrast-passing centres (which ends in global
-// atomics whose results are awaited) runs at the start of the next
-// iteration, before that iteration issues its prefetch: a wait on a global
-// atomic also waits for every vector load issued before it, so this way the
-// prefetched planes are in flight during the coefficients and extremal
-// scales, and the atomics only ever wait for loads about to be consumed.
-__global__ __launch_bounds__(256) void k_detect(const float* __restrict__ pyr, const DetTile* __restrict__ tiles,
-                                                int ntiles, DetParams dp, cdvs_keypoint* __restrict__ cand,
-                                                int32_t* __restrict__ cand_cnt, int32_t* __restrict__ flags) {
-    __shared__ __align__(16) float G[kScales][GH][GW];
-    __shared__ float4 A[AH][AW];
-    __shared__ int nlist;
-
-    const int x = blockIdx.x % kXcds, slot = blockIdx.x / kXcds, nslot = gridDim.x / kXcds;
-    const int per = ntiles / kXcds, rem = ntiles % kXcds;
-    const int tbase = x * per + min(x, rem), cnt = per + (x < rem ? 1 : 0);
-    if (slot >= cnt) return;   // uniform over the workgroup
-    float4* list = reinterpret_cast<float4*>(&G[0][0][0]);   // contrast-passing centres, after the coefficients
-    float4 vals[DNPER4];
-    DetTile cur = as_uniform(fetch_tile(tiles, tbase + slot));
-    DetTile prev = cur;
-    load_tile(pyr, cur, vals);
-    RawTile rn = fetch_tile(tiles, tbase + min(slot + nslot, cnt - 1));
-    for (int tj = slot; tj < cnt; tj += nslot) {
-        // the record two tiles ahead is fetched a whole tile before it is needed
-        const RawTile rnn = fetch_tile(tiles, tbase + min(tj + 2 * nslot, cnt - 1));
-        const DetTile nxt = as_uniform(rn);
-        __syncthreads();  // the previous tile's list and coefficients are complete
-        if (tj != slot) refine_list(A, list, nlist, prev, dp, cand, cand_cnt, flags);
-        __syncthreads();  // the previous tile is done with G, A and the list
-        store_tile(&G[0][0][0], vals);
-        if (threadIdx.x == 0) nlist = 0;
-        __syncthreads();
-        if (tj + nslot < cnt) load_tile(pyr, nxt, vals);
-        for (int t = threadIdx.x; t < AH * AW; t += blockDim.x) {
-            const int ay = t / AW, ax = t % AW;
-            A[ay][ax] = alpha_at(G, ay + 1, ax + 1 + GX, dp);
-        }
-        __syncthreads();
-        for (int it = 0; it < DTW * DTH / 256; ++it) {
-            const int q = threadIdx.x + it * 256;
-            const int cy = q / DTW, cx = q % DTW;
-            const int gx = cur.tx0 + cx, gy = cur.ty0 + cy;
-            float cs = 0.f, cp = 0.f, cpss = 0.f;
-            const bool pass = gx >= dp.border && gx <= cur.w - 1 - dp.border && gy >= dp.border &&
-                              gy <= cur.h - 1 - dp.border && centre_extremum(A, cy, cx, dp, cs, cp, cpss);
-            push_centre(pass, cs, cp, cpss, q, list, &nlist);
-        }
-        prev = cur;
-        cur = nxt;
-        rn = rnn;
-    }
-    __syncthreads();
-    refine_list(A, list, nlist, prev, dp, cand, cand_cnt, flags);
-}
-
 // ---------------------------------------------------------------------------
-// k_detect_strip: the ungated detection, one wave per strip of kStripW
+// k_detect_strip: the detection, one wave per strip of kStripW
 // centre columns x kStripH centre rows of one (image, octave) inside the
 // detection border; lane l holds image column x0 - 2 + l (lanes 0, 1, 62
 // and 63 are halo).  The wave walks down its strip one row at a time with
@@ -489,9 +295,15 @@ __device__ __forceinline__ void strip_centres(const float4& aU, const float4& aM
     if (qn > kQFlush) strip_drain(q, qn, job, dp, cand, cand_cnt, flags);
 }
 
+// GATED: an octave-o centre (x, y) is examined only when bit o of the mask
+// cell holding (x 2^o, y 2^o) / 4 is set, unless more than gate.fmax of the
+// image's cells have bit o set (then the octave is examined densely).
+template <bool GATED>
 __global__ __launch_bounds__(256) void k_detect_strip(const float* __restrict__ pyr, const DetTile* __restrict__ strips,
-                                                      int nstrips, DetParams dp, cdvs_keypoint* __restrict__ cand,
-                                                      int32_t* __restrict__ cand_cnt, int32_t* __restrict__ flags) {
+                                                      int nstrips, DetParams dp, GateParams gate,
+                                                      cdvs_keypoint* __restrict__ cand, int32_t* __restrict__ cand_cnt,
+                                                      int32_t* __restrict__ flags) {
+    static_assert(kStripH <= 64, "one activity bit per strip row");
     __shared__ float queue[4][kQFields][kQCap];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int sidx = __builtin_amdgcn_readfirstlane(xcd_remap(blockIdx.x, gridDim.x) * 4 + wave);
@@ -502,6 +314,24 @@ __global__ __launch_bounds__(256) void k_detect_strip(const float* __restrict__ 
     const int xend = min(x0 + kStripW, job.w - dp.border), yend = min(y0 + kStripH, job.h - dp.border);
     const int gx = x0 - 2 + lane;
     const bool col_ok = lane >= 2 && gx < xend;
+    // bit i: this lane's centre on row y0 + i is examined
+    uint64_t rows_on = ~0ull;
+    if constexpr (GATED) {
+        const CnnImage cg = gate.cells[job.image];
+        const bool dense =
+            (float)gate.active[job.image * kMaxOctaves + job.octave] > gate.fmax * (float)(cg.H4 * cg.W4);
+        if (!dense) {
+            rows_on = 0ull;
+            if (col_ok) {
+                const uint8_t* m = gate.mask + cg.cell0 + min((gx << job.octave) >> 2, cg.W4 - 1);
+                for (int y = y0; y < yend; ++y) {
+                    const int cy = min((y << job.octave) >> 2, cg.H4 - 1);
+                    rows_on |= (uint64_t)((m[(int64_t)cy * cg.W4] >> job.octave) & 1) << (y - y0);
+                }
+            }
+            if (!__ballot(rows_on != 0ull)) return;   // nothing active: the strip is not even loaded
+        }
+    }
     const float* col = pyr + job.plane0 + clampi(gx, 0, job.w - 1);
     // Plane rows live in a ring of kRing slots, row y in slot (y - y0 + 2) %
     // kRing, and coefficient rows in a ring of three, row y in slot
@@ -527,202 +357,11 @@ __global__ __launch_bounds__(256) void k_detect_strip(const float* __restrict__ 
             a[(r + 2) % 3] = strip_alpha(g[(r + 2) % kRing], g[(r + 3) % kRing], g[(r + 4) % kRing], dp);
             load_row(col, job, min(y + r + kRing, last), g[(r + 2) % kRing]);
             if (y + r < yend)   // uniform over the wave
-                strip_centres(a[r % 3], a[(r + 1) % 3], a[(r + 2) % 3], col_ok, gx, y + r, q, qn, job, dp, cand,
-                              cand_cnt, flags);
+                strip_centres(a[r % 3], a[(r + 1) % 3], a[(r + 2) % 3], col_ok && ((rows_on >> (y + r - y0)) & 1ull),
+                              gx, y + r, q, qn, job, dp, cand, cand_cnt, flags);
         }
     }
     strip_drain(q, qn, job, dp, cand, cand_cnt, flags);
-}
-
-// Gating pre-pass, one wave per detection tile (all octaves in one
-// launch): the tile's active-centre row masks (bit cx of row cy) and its
-// state.  An octave-o centre (x, y) is active when it lies inside the
-// detection border and bit o of the mask cell holding (x 2^o, y 2^o) / 4 is
-// set; when the image's active-cell fraction for that octave exceeds
-// gate.fmax the whole octave is dense (every border-valid centre active).
-__global__ __launch_bounds__(256) void k_gate_rows(const DetTile* __restrict__ tiles, int ntiles, DetParams dp,
-                                                   GateParams gate, uint64_t* __restrict__ rows_out,
-                                                   int32_t* __restrict__ state_out) {
-    // one wave per tile, lane = tile column
-    const int tile = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
-    if (tile >= ntiles) return;   // uniform over the wave
-    const DetTile job = tiles[tile];
-    const CnnImage& cg = gate.cells[job.image];
-    const bool dense = (float)gate.active[job.image * kMaxOctaves + job.octave] > gate.fmax * (float)(cg.H4 * cg.W4);
-    const int gx = job.tx0 + lane;
-    const int cx = min((gx << job.octave) >> 2, cg.W4 - 1);
-    const bool colok = gx >= dp.border && gx <= job.w - 1 - dp.border;
-    bool any = false;
-    for (int cy = 0; cy < DTH; ++cy) {
-        const int gy = job.ty0 + cy;
-        bool on = colok && gy >= dp.border && gy <= job.h - 1 - dp.border;
-        if (on && !dense) {
-            const int cyc = min((gy << job.octave) >> 2, cg.H4 - 1);
-            on = (gate.mask[cg.cell0 + (int64_t)cyc * cg.W4 + cx] >> job.octave) & 1;
-        }
-        const uint64_t m = __ballot(on);
-        if (lane == cy) rows_out[(int64_t)tile * DTH + cy] = m;
-        any |= m != 0;
-    }
-    if (lane == 0) state_out[tile] = !any ? kTileSkip : (dense ? kTileDense : kTileSparse);
-}
-
-// Exclusive prefix of the values held by the lanes of a wave.
-__device__ __forceinline__ int wave_excl_scan(int v) {
-    const int lane = threadIdx.x & 63;
-    int x = v;
-#pragma unroll
-    for (int d = 1; d < 64; d <<= 1) {
-        const int y = __shfl_up(x, d);
-        if (lane >= d) x += y;
-    }
-    return x - v;
-}
-
-// A tile's gating state and row masks, fetched with vector loads like the
-// tile record (lanes 0..15 each hold one row).
-struct RawGate {
-    int state;
-    uint64_t row;
-};
-
-__device__ __forceinline__ RawGate fetch_gate(const GateParams& gate, int idx) {
-    int z;
-    asm volatile("v_mov_b32 %0, 0" : "=v"(z));
-    const int lane = threadIdx.x & 63;
-    RawGate r;
-    r.state = gate.state[idx + z];
-    r.row = gate.rows[(int64_t)idx * DTH + min(lane, DTH - 1) + z];
-    return r;
-}
-
-// Mask-gated detection: the same results as k_detect on every active centre
-// (see k_gate_rows).  Tiles without an active centre are neither loaded nor
-// computed; dense tiles run k_detect's body; on the other tiles the active
-// centres, and the pixels whose coefficients they read (one pixel around
-// each), are compacted into LDS work lists so that every lane of every wave
-// does useful work in both phases.
-__global__ __launch_bounds__(256, 3) void k_detect_gated(const float* __restrict__ pyr, const DetTile* __restrict__ tiles,
-                                                      int ntiles, DetParams dp, GateParams gate,
-                                                      cdvs_keypoint* __restrict__ cand,
-                                                      int32_t* __restrict__ cand_cnt, int32_t* __restrict__ flags) {
-    __shared__ __align__(16) float G[kScales][GH][GW];
-    __shared__ float4 A[AH][AW];
-    __shared__ uint16_t alist[AH * AW];
-    __shared__ uint16_t clist[DTH * DTW];
-    __shared__ int nlist;
-
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int x = blockIdx.x % kXcds, slot = blockIdx.x / kXcds, nslot = gridDim.x / kXcds;
-    const int per = ntiles / kXcds, rem = ntiles % kXcds;
-    const int tbase = x * per + min(x, rem), cnt = per + (x < rem ? 1 : 0);
-    if (slot >= cnt) return;   // uniform over the workgroup
-    float4 vals[DNPER4];
-    DetTile cur = as_uniform(fetch_tile(tiles, tbase + slot));
-    RawGate gcur = fetch_gate(gate, tbase + slot);
-    int scur = __builtin_amdgcn_readfirstlane(gcur.state);
-    if (scur != kTileSkip) load_tile(pyr, cur, vals);
-    RawTile rn = fetch_tile(tiles, tbase + min(slot + nslot, cnt - 1));
-    RawGate gn = fetch_gate(gate, tbase + min(slot + nslot, cnt - 1));
-    for (int tj = slot; tj < cnt; tj += nslot) {
-        const int inn = tbase + min(tj + 2 * nslot, cnt - 1);
-        const RawTile rnn = fetch_tile(tiles, inn);
-        const RawGate gnn = fetch_gate(gate, inn);
-        const bool has_next = tj + nslot < cnt;
-        const DetTile nxt = as_uniform(rn);
-        const int snxt = has_next ? __builtin_amdgcn_readfirstlane(gn.state) : kTileSkip;
-        if (scur == kTileSkip) {
-            if (snxt != kTileSkip) load_tile(pyr, nxt, vals);
-        } else {
-            __syncthreads();  // the previous tile is done with G, A and the lists
-            store_tile(&G[0][0][0], vals);
-            if (threadIdx.x == 0) nlist = 0;
-            __syncthreads();
-            if (snxt != kTileSkip) load_tile(pyr, nxt, vals);
-            if (scur == kTileDense) {
-                for (int t = threadIdx.x; t < AH * AW; t += blockDim.x) {
-                    const int ay = t / AW, ax = t % AW;
-                    A[ay][ax] = alpha_at(G, ay + 1, ax + 1 + GX, dp);
-                }
-                __syncthreads();
-                float4* list = reinterpret_cast<float4*>(&G[0][0][0]);
-                for (int it = 0; it < DTW * DTH / 256; ++it) {
-                    const int q = threadIdx.x + it * 256;
-                    const int cy = q / DTW, cx = q % DTW;
-                    const int gx = cur.tx0 + cx, gy = cur.ty0 + cy;
-                    float cs = 0.f, cp = 0.f, cpss = 0.f;
-                    const bool pass = gx >= dp.border && gx <= cur.w - 1 - dp.border && gy >= dp.border &&
-                                      gy <= cur.h - 1 - dp.border && centre_extremum(A, cy, cx, dp, cs, cp, cpss);
-                    push_centre(pass, cs, cp, cpss, q, list, &nlist);
-                }
-                __syncthreads();
-                refine_list(A, list, nlist, cur, dp, cand, cand_cnt, flags);
-            } else {
-                // lanes 0..15 of every wave hold the row masks
-                const uint64_t myrow = lane < DTH ? gcur.row : 0ull;
-                // centre list: row bases from a wave scan of the row counts
-                const int rc = __popcll(myrow);
-                const int rb = wave_excl_scan(rc);
-                const int nc = __shfl(rb, DTH - 1) + __shfl(rc, DTH - 1);
-                for (int cy = wave; cy < DTH; cy += 4) {
-                    const uint64_t m = __shfl(myrow, cy);
-                    const int base = __shfl(rb, cy);
-                    if ((m >> lane) & 1)
-                        clist[base + __popcll(m & ((1ull << lane) - 1ull))] = (uint16_t)(cy * DTW + lane);
-                }
-                // coefficient list: alpha row ay is read by centre rows
-                // ay-2..ay, alpha column ax by centre columns ax-2..ax
-                const uint64_t r0 = __shfl(myrow, max(lane - 2, 0)), r1 = __shfl(myrow, max(lane - 1, 0));
-                const uint64_t r2 = __shfl(myrow, min(lane, 63));
-                uint64_t v = 0;
-                if (lane < AH) {
-                    if (lane - 2 >= 0 && lane - 2 < DTH) v |= r0;
-                    if (lane - 1 >= 0 && lane - 1 < DTH) v |= r1;
-                    if (lane < DTH) v |= r2;
-                }
-                const uint64_t vlo = v | (v << 1) | (v << 2);
-                const uint32_t vhi = (uint32_t)(((v >> 62) | (v >> 63)) & 1u) | (uint32_t)(((v >> 63) & 1u) << 1);
-                const int ac = __popcll(vlo) + __popc(vhi);
-                const int ab = wave_excl_scan(ac);
-                const int na = __shfl(ab, AH - 1) + __shfl(ac, AH - 1);
-                for (int ay = wave; ay < AH; ay += 4) {
-                    const uint64_t m = __shfl(vlo, ay);
-                    const uint32_t mh = __shfl(vhi, ay);
-                    const int base = __shfl(ab, ay);
-                    if ((m >> lane) & 1)
-                        alist[base + __popcll(m & ((1ull << lane) - 1ull))] = (uint16_t)(ay * AW + lane);
-                    if (lane < 2 && ((mh >> lane) & 1))
-                        alist[base + __popcll(m) + (lane == 1 ? (int)(mh & 1u) : 0)] = (uint16_t)(ay * AW + DTW + lane);
-                }
-                __syncthreads();
-                for (int i = threadIdx.x; i < na; i += blockDim.x) {
-                    const int idx = alist[i];
-                    const int ay = idx / AW, ax = idx % AW;
-                    A[ay][ax] = alpha_at(G, ay + 1, ax + 1 + GX, dp);
-                }
-                __syncthreads();
-                float4* list = reinterpret_cast<float4*>(&G[0][0][0]);
-                for (int i0 = 0; i0 < nc; i0 += blockDim.x) {
-                    const int i = i0 + threadIdx.x;
-                    float cs = 0.f, cp = 0.f, cpss = 0.f;
-                    int q = 0;
-                    bool pass = false;
-                    if (i < nc) {
-                        q = clist[i];
-                        pass = centre_extremum(A, q / DTW, q % DTW, dp, cs, cp, cpss);
-                    }
-                    push_centre(pass, cs, cp, cpss, q, list, &nlist);
-                }
-                __syncthreads();
-                refine_list(A, list, nlist, cur, dp, cand, cand_cnt, flags);
-            }
-        }
-        cur = nxt;
-        gcur = gn;
-        scur = snxt;
-        rn = rnn;
-        gn = gnn;
-    }
 }
 
 __global__ void k_clear(int32_t* p, int n) {
@@ -965,33 +604,16 @@ hipError_t launch_clear(int32_t* p, int n, hipStream_t stream) {
     return hipGetLastError();
 }
 
-hipError_t launch_detect(const float* pyr, const DetTile* tiles, int ntiles, int grid, const DetParams& dp,
-                         const GateParams& gate, cdvs_keypoint* cand, int32_t* cand_cnt, int32_t* flags,
-                         hipStream_t stream) {
-    if (ntiles <= 0) return hipSuccess;
-    // a multiple of the XCD count, no larger than needed
-    int g = std::min(grid, (ntiles + kXcds - 1) / kXcds * kXcds);
-    g = std::max(kXcds, g / kXcds * kXcds);
-    if (gate.mask)
-        hipLaunchKernelGGL(k_detect_gated, dim3(g), dim3(256), 0, stream, pyr, tiles, ntiles, dp, gate, cand, cand_cnt,
-                           flags);
-    else
-        hipLaunchKernelGGL(k_detect, dim3(g), dim3(256), 0, stream, pyr, tiles, ntiles, dp, cand, cand_cnt, flags);
-    return hipGetLastError();
-}
-
-hipError_t launch_gate_rows(const DetTile* tiles, int ntiles, const DetParams& dp, const GateParams& gate,
-                            uint64_t* rows, int32_t* state, hipStream_t stream) {
-    if (ntiles <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_gate_rows, dim3((ntiles + 3) / 4), dim3(256), 0, stream, tiles, ntiles, dp, gate, rows, state);
-    return hipGetLastError();
-}
-
 hipError_t launch_detect_strips(const float* pyr, const DetTile* strips, int nstrips, const DetParams& dp,
-                               cdvs_keypoint* cand, int32_t* cand_cnt, int32_t* flags, hipStream_t stream) {
+                                const GateParams& gate, cdvs_keypoint* cand, int32_t* cand_cnt, int32_t* flags,
+                                hipStream_t stream) {
     if (nstrips <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_detect_strip, dim3((nstrips + 3) / 4), dim3(256), 0, stream, pyr, strips, nstrips, dp, cand,
-                       cand_cnt, flags);
+    if (gate.mask)
+        hipLaunchKernelGGL(k_detect_strip<true>, dim3((nstrips + 3) / 4), dim3(256), 0, stream, pyr, strips, nstrips,
+                           dp, gate, cand, cand_cnt, flags);
+    else
+        hipLaunchKernelGGL(k_detect_strip<false>, dim3((nstrips + 3) / 4), dim3(256), 0, stream, pyr, strips, nstrips,
+                           dp, gate, cand, cand_cnt, flags);
     return hipGetLastError();
 }
 
