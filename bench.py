@@ -252,7 +252,8 @@ def sparse_leg(imgs, steps, contrast=4.0):
 def ragged_leg(steps, n=1024):
     """Uneven sizes: n images, long side 640, aspect drawn from {4:3, 3:2,
     16:9, 1:1, 3:4}, 100-400 blobs each, in one packed ragged context; the
-    scale-plane tile shape is picked by the autotuner, then K replays of the
+    scale-plane tile shape and the detection's launch form (one wave per
+    strip or persistent) are picked by the autotuner, then K replays of the
     captured pass are timed."""
     import tempfile
     import torch
@@ -284,7 +285,8 @@ def ragged_leg(steps, n=1024):
     npx = sum(octave_pixels(sizes))
     return {"value": round(n / (ms * 1e-3), 1), "unit": "images/s", "ms_per_step": round(ms, 4), "images": n,
             "octave_px_per_image": round(npx / n, 1),
-            "tile_variant": tune["variant"], "tile_variant_us": tune["us"], "autotune_s": round(t_tune, 3),
+            "tile_variant": tune["variant"], "tile_variant_us": tune["us"],
+            "detect_variant": tune["detect"], "detect_variant_us": tune["detect_us"], "autotune_s": round(t_tune, 3),
             "timing": "K hipGraph replays of the whole plain pass over the packed ragged batch"}
 
 

@@ -215,18 +215,24 @@ cdvs_status cdvs_graph_capture(cdvs_ctx* ctx, const uint8_t* d_images, float* d_
                                int32_t* d_count, cdvs_keypoint* d_kp_ori, int32_t* d_count_ori, float* d_desc);
 cdvs_status cdvs_graph_launch(cdvs_ctx* ctx, void* stream);
 
-/* Tile-shape autotuning of the scale-plane kernel (CDVS_KERNEL_SCALES has
- * CDVS_TUNE_VARIANTS tile shapes: 64x32, 128x16, 32x32, 64x16; every shape
- * produces bit-identical planes).  cdvs_autotune times each shape on the
- * context's batch (cdvs_pyramid on the given buffers, 1 warm-up + 3 timed
- * runs, median; blocking) and keeps the fastest.  With cache_path (may be
- * NULL) a JSON file keyed by (GPU arch, kernel, image size, batch-size
- * bucket) is read first (a hit skips the timing) and updated after timing.
- * cdvs_tune_get / cdvs_tune_set read and force the shape.  A captured graph
- * keeps the shape that was selected when it was captured.  The cache file is
- * a JSON object with one "key": {...} entry per line; an unreadable file is
- * treated as empty and rewritten. */
+/* Autotuning of two kernels on the context's batch.  CDVS_KERNEL_SCALES has
+ * CDVS_TUNE_VARIANTS tile shapes (64x32, 128x16, 32x32, 64x16; every shape
+ * produces bit-identical planes); CDVS_KERNEL_DETECT has
+ * CDVS_DETECT_VARIANTS launch forms (0: one wave per strip, dispatched by the
+ * hardware; 1: persistent, a fixed grid pulling strips from per-XCD work
+ * counters; both find the same candidates).  cdvs_autotune times each
+ * shape with cdvs_pyramid on the given buffers, then each launch form of the
+ * ungated detection on the resulting pyramid (candidates go to the
+ * context's scratch; d_pyr must be 256-byte aligned), 1 warm-up + 3 timed
+ * runs each, median; blocking; it keeps the fastest of each.  With
+ * cache_path (may be NULL) a JSON file keyed by (GPU arch, image size,
+ * batch-size bucket) is read first (a hit skips the timing) and updated
+ * after timing.  cdvs_tune_get / cdvs_tune_set read and force a kernel's
+ * variant.  A captured graph keeps the variants selected when it was
+ * captured.  The cache file is a JSON object with one "key": {...} entry per
+ * line; an unreadable file is treated as empty and rewritten. */
 #define CDVS_TUNE_VARIANTS 4
+#define CDVS_DETECT_VARIANTS 2
 cdvs_status cdvs_autotune(cdvs_ctx* ctx, const uint8_t* d_images, float* d_pyr, const char* cache_path,
                           void* stream);
 int32_t cdvs_tune_get(const cdvs_ctx* ctx, int32_t kernel);

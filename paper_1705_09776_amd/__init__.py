@@ -73,8 +73,10 @@ EXPORTS = ["cdvs_default_params", "cdvs_validate", "cdvs_ctx_create", "cdvs_ctx_
            "cdvs_cnn_adam", "cdvs_autotune", "cdvs_tune_get", "cdvs_tune_set",
            "cdvs_stream", "cdvs_standin_consume"]
 TUNE_VARIANTS = 4
+DETECT_VARIANTS = 2
 
 KERNEL_SCALES = 1
+KERNEL_DETECT = 3
 KERNEL_NAMES = ["preblur", "scales", "clear", "detect", "finalize", "orient", "orient_compact", "describe",
                 "cnn_forward", "mask_count"]
 

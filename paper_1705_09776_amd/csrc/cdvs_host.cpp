@@ -31,7 +31,8 @@ struct cdvs_ctx {
     int max_oct = 0;
     int job_start[kMaxOctaves + 1] = {};
     int blur_tiles[kBlurVariants][kMaxOctaves] = {};
-    int blur_variant = 0;  // scale-plane tile variant (cdvs_autotune)
+    int blur_variant = 0;    // scale-plane tile variant (cdvs_autotune)
+    int detect_variant = 0;  // detection launch form (cdvs_autotune)
     int64_t pyr_floats = 0;
     Taps taps{};
     DetParams det{};
@@ -39,6 +40,7 @@ struct cdvs_ctx {
     DescParams desc{};
     float dedup_ratio = 0.f;
     int wgrad_grid = 0;   // grid of the CNN weight-gradient kernels
+    int detect_grid = 0;  // persistent detection grid (workgroups)
     // surrogate CNN cell grid
     std::vector<CnnImage> cnn;
     int64_t ncells = 0;
@@ -62,7 +64,7 @@ struct cdvs_ctx {
     int64_t* d_cand_off = nullptr;
     int32_t* d_cand_capv = nullptr;
     cdvs_keypoint* d_sel = nullptr;            // [image][kCandCap] strongest candidates (only when needed)
-    int32_t* d_cand_cnt = nullptr;
+    int32_t* d_cand_cnt = nullptr;             // n per-image counts, then kXcds detection work counters
     cdvs_keypoint* d_ori = nullptr;
     int32_t* d_ori_cnt = nullptr;
     int32_t* d_flags = nullptr;
@@ -507,7 +509,7 @@ cdvs_status cdvs_ctx_create(const cdvs_params* params, const cdvs_image_desc* im
         ALLOC(c->d_cand_capv, sizeof(int32_t) * n);
         if (cmax > kCandCap) ALLOC(c->d_sel, sizeof(cdvs_keypoint) * n * kCandCap);
     }
-    ALLOC(c->d_cand_cnt, sizeof(int32_t) * n);
+    ALLOC(c->d_cand_cnt, sizeof(int32_t) * (n + kXcds));
     ALLOC(c->d_ori, sizeof(cdvs_keypoint) * n * kp_capacity * kMaxOri);
     ALLOC(c->d_ori_cnt, sizeof(int32_t) * n * kp_capacity);
     ALLOC(c->d_flags, sizeof(int32_t));
@@ -528,7 +530,7 @@ cdvs_status cdvs_ctx_create(const cdvs_params* params, const cdvs_image_desc* im
         (e = hipMemcpy(c->d_cand_capv, c->cand_cap.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice)) !=
             hipSuccess ||
         (e = hipMemset(c->d_flags, 0, sizeof(int32_t))) != hipSuccess ||
-        (e = hipMemset(c->d_cand_cnt, 0, sizeof(int32_t) * n)) != hipSuccess) {
+        (e = hipMemset(c->d_cand_cnt, 0, sizeof(int32_t) * (n + kXcds))) != hipSuccess) {
         fail(nullptr, CDVS_ERR_HIP, "context upload: %s", hipGetErrorString(e));
         cdvs_ctx_destroy(c);
         return CDVS_ERR_HIP;
@@ -539,6 +541,9 @@ cdvs_status cdvs_ctx_create(const cdvs_params* params, const cdvs_image_desc* im
         if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && v > 0) cus = v;
     }
     c->wgrad_grid = std::max(kXcds, cus * 2);
+    // persistent detection: five 256-lane workgroups per compute unit (its
+    // registers allow five waves per SIMD)
+    c->detect_grid = std::max(kXcds, cus * 5 / kXcds * kXcds);
     *out = c;
     return CDVS_OK;
 }
@@ -605,13 +610,14 @@ cdvs_status cdvs_alp_detect(cdvs_ctx* ctx, const float* d_pyr, const uint8_t* d_
     }
     {
         Bracket b(ctx, CDVS_KERNEL_CLEAR, s);
-        HIP_OR_FAIL(ctx, launch_clear(ctx->d_cand_cnt, ctx->n, s));
+        HIP_OR_FAIL(ctx, launch_clear(ctx->d_cand_cnt, ctx->n + kXcds, s));   // counts and work counters
     }
     {
         // one launch over the strips of every octave; the finalisation does
         // not rely on the order in which candidates arrive
         Bracket b(ctx, CDVS_KERNEL_DETECT, s);
-        HIP_OR_FAIL(ctx, launch_detect_strips(d_pyr, ctx->d_strips, (int)ctx->strips.size(), ctx->det, gate,
+        HIP_OR_FAIL(ctx, launch_detect_strips(d_pyr, ctx->d_strips, (int)ctx->strips.size(), ctx->detect_variant,
+                                              ctx->detect_grid, ctx->det, gate, ctx->d_cand_cnt + ctx->n,
                                               ctx->d_cand, ctx->d_cand_cnt, ctx->d_flags, s));
     }
     {
@@ -782,19 +788,32 @@ cdvs_status cdvs_graph_launch(cdvs_ctx* ctx, void* stream) {
 }
 
 int32_t cdvs_tune_get(const cdvs_ctx* ctx, int32_t kernel) {
-    if (!ctx || kernel != CDVS_KERNEL_SCALES) return -1;
-    return ctx->blur_variant;
+    if (!ctx) return -1;
+    if (kernel == CDVS_KERNEL_SCALES) return ctx->blur_variant;
+    if (kernel == CDVS_KERNEL_DETECT) return ctx->detect_variant;
+    return -1;
 }
-
 cdvs_status cdvs_tune_set(cdvs_ctx* ctx, int32_t kernel, int32_t variant) {
     if (!ctx) return CDVS_ERR_STATE;
-    if (kernel != CDVS_KERNEL_SCALES) return fail(ctx, CDVS_ERR_ARG, "cdvs_tune_set: only CDVS_KERNEL_SCALES is tunable");
-    if (variant < 0 || variant >= kBlurVariants) return fail(ctx, CDVS_ERR_ARG, "cdvs_tune_set: variant out of range");
-    ctx->blur_variant = variant;
-    return CDVS_OK;
+    if (kernel == CDVS_KERNEL_SCALES) {
+        if (variant < 0 || variant >= kBlurVariants)
+            return fail(ctx, CDVS_ERR_ARG, "cdvs_tune_set: variant out of range");
+        ctx->blur_variant = variant;
+        return CDVS_OK;
+    }
+    if (kernel == CDVS_KERNEL_DETECT) {
+        if (variant < 0 || variant >= kDetectVariants)
+            return fail(ctx, CDVS_ERR_ARG, "cdvs_tune_set: variant out of range");
+        ctx->detect_variant = variant;
+        return CDVS_OK;
+    }
+    return fail(ctx, CDVS_ERR_ARG, "cdvs_tune_set: only CDVS_KERNEL_SCALES and CDVS_KERNEL_DETECT are tunable");
 }
 
-// Cache key: arch, kernel, size of the first image, batch size rounded up to a power of two.
+// Cache key: arch, size of the first image, batch size rounded up to a power of two.
+static_assert(CDVS_TUNE_VARIANTS == kBlurVariants && CDVS_DETECT_VARIANTS == kDetectVariants,
+              "tunable variant counts agree with the header");
+
 static std::string tune_key(const cdvs_ctx* ctx) {
     std::string arch = "unknown";
     int dev = 0;
@@ -806,28 +825,30 @@ static std::string tune_key(const cdvs_ctx* ctx) {
     int nb = 1;
     while (nb < ctx->n) nb <<= 1;
     char buf[160];
-    snprintf(buf, sizeof(buf), "%s:scales:%dx%d:n%d", arch.c_str(), ctx->images[0].width, ctx->images[0].height, nb);
+    snprintf(buf, sizeof(buf), "%s:pass:%dx%d:n%d", arch.c_str(), ctx->images[0].width, ctx->images[0].height, nb);
     return buf;
 }
 
 // The cache is a JSON object with one "key": {...} entry per line.
-static bool tune_cache_lookup(const char* path, const std::string& key, int* variant) {
+static bool tune_cache_lookup(const char* path, const std::string& key, int* variant, int* dvariant) {
     std::ifstream f(path);
     if (!f) return false;
     std::string line, pat = "\"" + key + "\"";
     while (std::getline(f, line)) {
         if (line.find(pat) == std::string::npos) continue;
-        size_t p = line.find("\"variant\":");
-        if (p == std::string::npos) return false;
-        int v = atoi(line.c_str() + p + 10);
-        if (v < 0 || v >= kBlurVariants) return false;
+        const size_t p = line.find("\"variant\":"), d = line.find("\"detect\":");
+        if (p == std::string::npos || d == std::string::npos) return false;
+        const int v = atoi(line.c_str() + p + 10), dv = atoi(line.c_str() + d + 9);
+        if (v < 0 || v >= kBlurVariants || dv < 0 || dv >= kDetectVariants) return false;
         *variant = v;
+        *dvariant = dv;
         return true;
     }
     return false;
 }
 
-static void tune_cache_store(const char* path, const std::string& key, int variant, const float* us) {
+static void tune_cache_store(const char* path, const std::string& key, int variant, const float* us, int dvariant,
+                             const float* dus) {
     std::vector<std::string> entries;
     std::ifstream f(path);
     std::string line, pat = "\"" + key + "\"";
@@ -835,14 +856,17 @@ static void tune_cache_store(const char* path, const std::string& key, int varia
         size_t q = line.find('"');
         if (q == std::string::npos || line.find(pat) != std::string::npos) continue;
         // keep only well-formed entries of other keys; anything else is dropped
-        if (line.find("\"variant\": ") == std::string::npos || line.find("\"us\": [") == std::string::npos) continue;
+        if (line.find("\"variant\": ") == std::string::npos || line.find("\"us\": [") == std::string::npos ||
+            line.find("\"detect\": ") == std::string::npos)
+            continue;
         size_t e = line.find_last_of('}');
         if (e == std::string::npos) continue;
         entries.push_back(line.substr(q, e - q + 1));
     }
-    char buf[512];
-    snprintf(buf, sizeof(buf), "\"%s\": {\"variant\": %d, \"us\": [%.1f, %.1f, %.1f, %.1f]}", key.c_str(), variant, us[0],
-             us[1], us[2], us[3]);
+    char buf[640];
+    snprintf(buf, sizeof(buf),
+             "\"%s\": {\"variant\": %d, \"us\": [%.1f, %.1f, %.1f, %.1f], \"detect\": %d, \"detect_us\": [%.1f, %.1f]}",
+             key.c_str(), variant, us[0], us[1], us[2], us[3], dvariant, dus[0], dus[1]);
     entries.push_back(buf);
     std::ofstream o(path, std::ios::trunc);
     o << "{\n";
@@ -853,10 +877,12 @@ static void tune_cache_store(const char* path, const std::string& key, int varia
 cdvs_status cdvs_autotune(cdvs_ctx* ctx, const uint8_t* d_images, float* d_pyr, const char* cache_path, void* stream) {
     if (!ctx) return CDVS_ERR_STATE;
     if (!d_images || !d_pyr) return fail(ctx, CDVS_ERR_ARG, "cdvs_autotune: null device pointer");
+    if (((uintptr_t)d_pyr & 255) != 0) return fail(ctx, CDVS_ERR_ARG, "cdvs_autotune: d_pyr not 256-byte aligned");
     const std::string key = tune_key(ctx);
-    int v = 0;
-    if (cache_path && tune_cache_lookup(cache_path, key, &v)) {
+    int v = 0, dv = 0;
+    if (cache_path && tune_cache_lookup(cache_path, key, &v, &dv)) {
         ctx->blur_variant = v;
+        ctx->detect_variant = dv;
         return CDVS_OK;
     }
     hipStream_t s = (hipStream_t)stream;
@@ -865,16 +891,13 @@ cdvs_status cdvs_autotune(cdvs_ctx* ctx, const uint8_t* d_images, float* d_pyr, 
     HIP_OR_FAIL(ctx, hipEventCreate(&e1));
     const bool prof = ctx->prof;
     ctx->prof = false;
-    float best = 1e30f, us[kBlurVariants];
-    int best_v = ctx->blur_variant;
-    cdvs_status st = CDVS_OK;
-    for (int var = 0; var < kBlurVariants && st == CDVS_OK; ++var) {
-        ctx->blur_variant = var;
-        float t[3];
-        st = cdvs_pyramid(ctx, d_images, d_pyr, stream);
+    // median of three timed runs after one warm-up
+    auto median3 = [&](auto&& run, float* out) -> cdvs_status {
+        float t[3] = {0.f, 0.f, 0.f};
+        cdvs_status st = run();
         for (int r = 0; r < 3 && st == CDVS_OK; ++r) {
             (void)hipEventRecord(e0, s);
-            st = cdvs_pyramid(ctx, d_images, d_pyr, stream);
+            st = run();
             (void)hipEventRecord(e1, s);
             (void)hipEventSynchronize(e1);
             float ms = 0.f;
@@ -882,18 +905,46 @@ cdvs_status cdvs_autotune(cdvs_ctx* ctx, const uint8_t* d_images, float* d_pyr, 
             t[r] = ms * 1e3f;
         }
         std::sort(t, t + 3);
-        us[var] = t[1];
+        *out = t[1];
+        return st;
+    };
+    float us[kBlurVariants] = {}, dus[kDetectVariants] = {};
+    int best_v = ctx->blur_variant, best_dv = ctx->detect_variant;
+    cdvs_status st = CDVS_OK;
+    float best = 1e30f;
+    for (int var = 0; var < kBlurVariants && st == CDVS_OK; ++var) {
+        ctx->blur_variant = var;
+        st = median3([&] { return cdvs_pyramid(ctx, d_images, d_pyr, stream); }, &us[var]);
         if (us[var] < best) {
             best = us[var];
             best_v = var;
+        }
+    }
+    // the detection's launch forms on the pyramid just built (every tile
+    // shape writes the same planes), candidates into the context's scratch
+    best = 1e30f;
+    for (int var = 0; var < kDetectVariants && st == CDVS_OK; ++var) {
+        auto run = [&]() -> cdvs_status {
+            const GateParams gate{nullptr, nullptr, nullptr, 1.f};
+            HIP_OR_FAIL(ctx, launch_clear(ctx->d_cand_cnt, ctx->n + kXcds, s));
+            HIP_OR_FAIL(ctx, launch_detect_strips(d_pyr, ctx->d_strips, (int)ctx->strips.size(), var,
+                                                  ctx->detect_grid, ctx->det, gate, ctx->d_cand_cnt + ctx->n,
+                                                  ctx->d_cand, ctx->d_cand_cnt, ctx->d_flags, s));
+            return CDVS_OK;
+        };
+        st = median3(run, &dus[var]);
+        if (dus[var] < best) {
+            best = dus[var];
+            best_dv = var;
         }
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     ctx->prof = prof;
     ctx->blur_variant = best_v;
+    ctx->detect_variant = best_dv;
     if (st != CDVS_OK) return st;
-    if (cache_path) tune_cache_store(cache_path, key, best_v, us);
+    if (cache_path) tune_cache_store(cache_path, key, best_v, us, best_dv, dus);
     return CDVS_OK;
 }
 

@@ -151,12 +151,16 @@ hipError_t launch_scales(float* pyr, const OctJob* jobs, const int32_t* owner, i
                          const Taps& taps, hipStream_t stream);
 hipError_t launch_clear(int32_t* p, int n, hipStream_t stream);
 // Detection over strips of 60 x kDetStripH centres inside the detection
-// border (tx0, ty0 = the strip's first centre), one wave each; gated by
-// gate.mask unless it is null.
+// border (tx0, ty0 = the strip's first centre), one wave at a time each;
+// gated by gate.mask unless it is null.
 constexpr int kDetStripW = 60, kDetStripH = 48;
-hipError_t launch_detect_strips(const float* pyr, const DetTile* strips, int nstrips, const DetParams& dp,
-                                const GateParams& gate, cdvs_keypoint* cand, int32_t* cand_cnt, int32_t* flags,
-                                hipStream_t stream);
+// Launch forms (the detection's tunable variant): one wave per strip, or
+// persistent: `grid` workgroups (rounded to a multiple of 8) pulling strips
+// from per-XCD counters work[0..7], which must be zero at launch.
+constexpr int kDetectPerStrip = 0, kDetectPersistent = 1, kDetectVariants = 2;
+hipError_t launch_detect_strips(const float* pyr, const DetTile* strips, int nstrips, int variant, int grid,
+                                const DetParams& dp, const GateParams& gate, int32_t* work, cdvs_keypoint* cand,
+                                int32_t* cand_cnt, int32_t* flags, hipStream_t stream);
 hipError_t launch_select(const cdvs_keypoint* cand, const int32_t* cand_cnt, const int64_t* cand_off,
                          const int32_t* cand_capv, int n_images, cdvs_keypoint* sel, hipStream_t stream);
 hipError_t launch_finalize(const cdvs_keypoint* cand, const int32_t* cand_cnt, const int64_t* cand_off,

@@ -299,17 +299,12 @@ __device__ __forceinline__ void strip_centres(const float4& aU, const float4& aM
 // cell holding (x 2^o, y 2^o) / 4 is set, unless more than gate.fmax of the
 // image's cells have bit o set (then the octave is examined densely).
 template <bool GATED>
-__global__ __launch_bounds__(256) void k_detect_strip(const float* __restrict__ pyr, const DetTile* __restrict__ strips,
-                                                      int nstrips, DetParams dp, GateParams gate,
-                                                      cdvs_keypoint* __restrict__ cand, int32_t* __restrict__ cand_cnt,
-                                                      int32_t* __restrict__ flags) {
+__device__ __forceinline__ void detect_strip(const float* __restrict__ pyr, const DetTile& job, const DetParams& dp,
+                                             const GateParams& gate, float (*q)[kQCap],
+                                             cdvs_keypoint* __restrict__ cand, int32_t* __restrict__ cand_cnt,
+                                             int32_t* __restrict__ flags) {
     static_assert(kStripH <= 64, "one activity bit per strip row");
-    __shared__ float queue[4][kQFields][kQCap];
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int sidx = __builtin_amdgcn_readfirstlane(xcd_remap(blockIdx.x, gridDim.x) * 4 + wave);
-    if (sidx >= nstrips) return;   // uniform over the wave; there are no barriers
-    float (*q)[kQCap] = queue[wave];
-    const DetTile job = strips[sidx];
+    const int lane = threadIdx.x & 63;
     const int x0 = job.tx0, y0 = job.ty0;
     const int xend = min(x0 + kStripW, job.w - dp.border), yend = min(y0 + kStripH, job.h - dp.border);
     const int gx = x0 - 2 + lane;
@@ -362,6 +357,58 @@ __global__ __launch_bounds__(256) void k_detect_strip(const float* __restrict__ 
         }
     }
     strip_drain(q, qn, job, dp, cand, cand_cnt, flags);
+}
+
+// Requests one strip index from this XCD's work counter; the value arrives
+// in lane 0 and is read (made uniform) only when it is needed.  (An
+// increment rather than an add: the compiler rewrites a single-lane add into
+// a wave-wide one whose result it consumes at once, stalling on the round
+// trip; the counter never comes near the wrap limit.)
+__device__ __forceinline__ int fetch_strip(int32_t* __restrict__ ctr) {
+    unsigned t = 0u;
+    if ((threadIdx.x & 63) == 0) t = atomicInc(reinterpret_cast<unsigned*>(ctr), 0xffffffffu);
+    return (int)t;
+}
+
+// Two launch forms (picked by the autotuner):
+// PERSISTENT = false: one wave per strip, the hardware dispatching the
+//   workgroups (xcd_remap gives each XCD one contiguous range of strips).
+// PERSISTENT = true: the grid (a multiple of 8, sized to the waves the chip
+//   holds) is split evenly over the XCDs, and every XCD owns one contiguous
+//   range of strips with a work counter in `work` (zeroed before the
+//   launch); each wave pulls its next strip from the counter until the range
+//   is used up, so uneven strips (octaves, ragged images, skipped gated
+//   strips) balance by themselves.  The next index is requested when a
+//   strip starts and read when it ends, so the atomic's round trip overlaps
+//   the strip's work.
+// Either way neighbouring strips run close together in time on one XCD and
+// share their halo rows through its L2.
+template <bool GATED, bool PERSISTENT>
+__global__ __launch_bounds__(256) void k_detect_strip(const float* __restrict__ pyr, const DetTile* __restrict__ strips,
+                                                      int nstrips, DetParams dp, GateParams gate,
+                                                      int32_t* __restrict__ work, cdvs_keypoint* __restrict__ cand,
+                                                      int32_t* __restrict__ cand_cnt, int32_t* __restrict__ flags) {
+    __shared__ float queue[4][kQFields][kQCap];
+    const int wave = threadIdx.x >> 6;
+    if constexpr (!PERSISTENT) {
+        const int sidx = __builtin_amdgcn_readfirstlane(xcd_remap(blockIdx.x, gridDim.x) * 4 + wave);
+        if (sidx >= nstrips) return;   // uniform over the wave; there are no barriers
+        const DetTile job = strips[sidx];
+        detect_strip<GATED>(pyr, job, dp, gate, queue[wave], cand, cand_cnt, flags);
+    } else {
+        const int x = blockIdx.x % kXcds;
+        const int per = nstrips / kXcds, rem = nstrips % kXcds;
+        const int base = x * per + min(x, rem), cnt = per + (x < rem ? 1 : 0);
+        int32_t* ctr = work + x;
+        int pending = fetch_strip(ctr);
+        for (;;) {
+            const int t = __builtin_amdgcn_readfirstlane(pending);
+            if (t >= cnt) break;   // uniform over the wave; there are no barriers
+            pending = fetch_strip(ctr);
+            const DetTile job = strips[base + t];
+            detect_strip<GATED>(pyr, job, dp, gate, queue[wave], cand, cand_cnt, flags);
+        }
+    }
 }
 
 __global__ void k_clear(int32_t* p, int n) {
@@ -604,16 +651,29 @@ hipError_t launch_clear(int32_t* p, int n, hipStream_t stream) {
     return hipGetLastError();
 }
 
-hipError_t launch_detect_strips(const float* pyr, const DetTile* strips, int nstrips, const DetParams& dp,
-                                const GateParams& gate, cdvs_keypoint* cand, int32_t* cand_cnt, int32_t* flags,
-                                hipStream_t stream) {
+hipError_t launch_detect_strips(const float* pyr, const DetTile* strips, int nstrips, int variant, int grid,
+                                const DetParams& dp, const GateParams& gate, int32_t* work, cdvs_keypoint* cand,
+                                int32_t* cand_cnt, int32_t* flags, hipStream_t stream) {
     if (nstrips <= 0) return hipSuccess;
-    if (gate.mask)
-        hipLaunchKernelGGL(k_detect_strip<true>, dim3((nstrips + 3) / 4), dim3(256), 0, stream, pyr, strips, nstrips,
-                           dp, gate, cand, cand_cnt, flags);
-    else
-        hipLaunchKernelGGL(k_detect_strip<false>, dim3((nstrips + 3) / 4), dim3(256), 0, stream, pyr, strips, nstrips,
-                           dp, gate, cand, cand_cnt, flags);
+#define DETECT_LAUNCH(G, P, NB)                                                                                    \
+    hipLaunchKernelGGL((k_detect_strip<G, P>), dim3(NB), dim3(256), 0, stream, pyr, strips, nstrips, dp, gate, work, \
+                       cand, cand_cnt, flags)
+    if (variant == kDetectPersistent) {
+        // a multiple of the XCD count, no larger than one wave per strip
+        int g = std::min(grid, (nstrips + 4 * kXcds - 1) / (4 * kXcds) * kXcds);
+        g = std::max(kXcds, g / kXcds * kXcds);
+        if (gate.mask)
+            DETECT_LAUNCH(true, true, g);
+        else
+            DETECT_LAUNCH(false, true, g);
+    } else {
+        const int nb = (nstrips + 3) / 4;
+        if (gate.mask)
+            DETECT_LAUNCH(true, false, nb);
+        else
+            DETECT_LAUNCH(false, false, nb);
+    }
+#undef DETECT_LAUNCH
     return hipGetLastError();
 }
 

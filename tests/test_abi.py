@@ -113,6 +113,8 @@ def test_pack_images():
 def test_tune_api_host_checks():
     L = cd.lib()
     assert L.cdvs_tune_get(None, cd.KERNEL_SCALES) == -1
+    assert L.cdvs_tune_get(None, cd.KERNEL_DETECT) == -1
+    assert L.cdvs_tune_set(None, cd.KERNEL_DETECT, 1) == cd.CDVS_ERR_STATE
     assert L.cdvs_tune_set(None, cd.KERNEL_SCALES, 0) == cd.CDVS_ERR_STATE
     assert L.cdvs_autotune(None, None, None, None, None) == cd.CDVS_ERR_STATE
 

@@ -298,14 +298,17 @@ def test_scale_tile_variants_identical(tmp_path):
     cache = str(tmp_path / "tune.json")
     cd.cdvs_autotune(pipe.ctx, pipe.d_images, pipe.d_pyr, cache)
     v = cd.cdvs_tune_get(pipe.ctx, cd.KERNEL_SCALES)
-    assert 0 <= v < cd.TUNE_VARIANTS
+    dv = cd.cdvs_tune_get(pipe.ctx, cd.KERNEL_DETECT)
+    assert 0 <= v < cd.TUNE_VARIANTS and 0 <= dv < cd.DETECT_VARIANTS
     import json
     entries = json.load(open(cache))
-    assert len(entries) == 1 and list(entries.values())[0]["variant"] == v
-    other = (v + 1) % cd.TUNE_VARIANTS
-    cd.cdvs_tune_set(pipe.ctx, cd.KERNEL_SCALES, other)
+    e = list(entries.values())[0]
+    assert len(entries) == 1 and e["variant"] == v and e["detect"] == dv and len(e["detect_us"]) == cd.DETECT_VARIANTS
+    cd.cdvs_tune_set(pipe.ctx, cd.KERNEL_SCALES, (v + 1) % cd.TUNE_VARIANTS)
+    cd.cdvs_tune_set(pipe.ctx, cd.KERNEL_DETECT, (dv + 1) % cd.DETECT_VARIANTS)
     cd.cdvs_autotune(pipe.ctx, pipe.d_images, pipe.d_pyr, cache)   # cache hit
     assert cd.cdvs_tune_get(pipe.ctx, cd.KERNEL_SCALES) == v
+    assert cd.cdvs_tune_get(pipe.ctx, cd.KERNEL_DETECT) == dv
     # a corrupt cache is replaced by a valid one
     bad = str(tmp_path / "bad.json")
     open(bad, "w").write("not json {\n\"x\": }\n")
@@ -442,3 +445,32 @@ def test_max_side_images(O32):
         r1, r2, _ = rates(sel, kps[i])
         assert min(r1, r2) >= KP_RATE
         assert pipe.num_octaves(i) == O32.num_octaves(im.shape[1], im.shape[0])
+
+
+@pytest.mark.parametrize("gated", [False, True])
+def test_detect_launch_forms_identical(gated):
+    """Both launch forms of the detection (one wave per strip; persistent
+    with per-XCD work counters) give the same keypoints, plain and gated, on
+    a ragged batch (partial strips, several octaves)."""
+    imgs = [synth.image(synth.SEED_RAGGED, i, w, h, nblobs=60)
+            for i, (w, h) in enumerate([(640, 480), (333, 217), (97, 61), (480, 640), (1280, 96)])]
+    pipe = cd.Pipeline([(im.shape[1], im.shape[0]) for im in imgs])
+    pipe.upload(imgs)
+    pipe.pyramid()
+    mask = None
+    if gated:
+        rng = np.random.default_rng(5)
+        ncell = cd.cdvs_cnn_cells(pipe.ctx)
+        mask = torch.from_numpy(rng.integers(0, 256, size=ncell, dtype=np.uint8)).cuda()
+    got = []
+    for v in range(cd.DETECT_VARIANTS):
+        cd.cdvs_tune_set(pipe.ctx, cd.KERNEL_DETECT, v)
+        pipe.d_kp.zero_()
+        pipe.detect(mask=mask)
+        torch.cuda.synchronize()
+        assert pipe.sync_status() == cd.CDVS_OK
+        got.append(pipe.keypoints())
+    for a, b in zip(got[0], got[1]):
+        assert len(a) == len(b) > 0
+        for f in ("x", "y", "sigma", "p", "octave", "ix", "iy"):
+            np.testing.assert_array_equal(a[f], b[f])
