@@ -131,15 +131,33 @@ __global__ __launch_bounds__(256) void k_blur(const uint8_t* __restrict__ images
         const int gx = clampi(tx0 - HALO + col, 0, w - 1);
         const int gy0 = ty0 + grp * V - HALO;
         float win[V + 2 * HALO];
+        // A window inside the image (all but the top and bottom tiles) is
+        // read with one 32-bit byte offset from the uniform plane base,
+        // advanced by the pitch per row; edge windows clamp every row.
+        const bool inside = gy0 >= 0 && gy0 + V + 2 * HALO <= h;
         if constexpr (U8) {
-            const uint8_t* src = images + job.src + gx;
+            const uint8_t* base = images + job.src;
+            if (inside) {
+                uint32_t off = (uint32_t)(gy0 * job.src_pitch + gx);
 #pragma unroll
-            for (int r = 0; r < V + 2 * HALO; ++r)
-                win[r] = (float)src[(int64_t)clampi(gy0 + r, 0, h - 1) * job.src_pitch];
+                for (int r = 0; r < V + 2 * HALO; ++r, off += (uint32_t)job.src_pitch) win[r] = (float)base[off];
+            } else {
+#pragma unroll
+                for (int r = 0; r < V + 2 * HALO; ++r)
+                    win[r] = (float)base[(int64_t)clampi(gy0 + r, 0, h - 1) * job.src_pitch + gx];
+            }
         } else {
-            const float* src = pyr + job.plane0 + gx;
+            const char* base = reinterpret_cast<const char*>(pyr + job.plane0);
+            if (inside) {
+                uint32_t off = (uint32_t)(gy0 * job.pitch + gx) * 4u;
 #pragma unroll
-            for (int r = 0; r < V + 2 * HALO; ++r) win[r] = src[(int64_t)clampi(gy0 + r, 0, h - 1) * job.pitch];
+                for (int r = 0; r < V + 2 * HALO; ++r, off += 4u * (uint32_t)job.pitch)
+                    win[r] = *reinterpret_cast<const float*>(base + off);
+            } else {
+#pragma unroll
+                for (int r = 0; r < V + 2 * HALO; ++r)
+                    win[r] = reinterpret_cast<const float*>(base)[(int64_t)clampi(gy0 + r, 0, h - 1) * job.pitch + gx];
+            }
         }
         if constexpr (NK == 1) {
             float out[V];
