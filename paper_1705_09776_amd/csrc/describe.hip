@@ -1,7 +1,7 @@
 // Orientation assignment and local descriptors on gfx950 (Sec. III-B and
 // Sec. IV-B, Algorithm 2 stages A and B).
 //
-// One 64-lane wave per keypoint, four keypoints per workgroup.  The lanes
+// One 64-lane wave (and workgroup) per keypoint.  The lanes
 // sweep the bounding box of the keypoint's disk in row-major order (64
 // pixels per step, the paper's pixel-level parallelism over a patch of
 // variable size), and each in-disk pixel adds its weighted gradient to the
@@ -107,6 +107,18 @@ __device__ __forceinline__ void gradient(const Nbrs& n, float& mag, float& ang) 
 // Histogram copies per wave: lane l adds into copy l % kCopies; copies are
 // staggered by one bank.
 constexpr int kCopies = 8;
+
+// Keypoints (waves) per workgroup.  Each wave owns its keypoint's histogram
+// outright, so waves never wait for each other: wave_sync() only orders one
+// wave's own LDS accesses.  One wave per workgroup measured fastest (a
+// workgroup's resources are released only when its slowest keypoint, the
+// one with the largest window, is done).
+constexpr int kKpWaves = 1;
+
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+}
 // Orientation histogram copy: 36 bins plus bin 36, which takes the share of
 // bin 0 that wraps around from bin 35 (folded into bin 0 at the end); the
 // odd stride also starts the copies on different banks.
@@ -140,13 +152,13 @@ struct BoxWalk {
     }
 };
 
-__global__ __launch_bounds__(256) void k_orient(const float* __restrict__ pyr, const OctGeom* __restrict__ geom,
+__global__ __launch_bounds__(64 * kKpWaves) void k_orient(const float* __restrict__ pyr, const OctGeom* __restrict__ geom,
                                                 const cdvs_keypoint* __restrict__ kp,
                                                 const int32_t* __restrict__ count, int n_images, OriParams op,
                                                 cdvs_keypoint* __restrict__ ori, int32_t* __restrict__ ori_cnt) {
-    __shared__ uint32_t hist[4][kCopies * kOriStride];
+    __shared__ uint32_t hist[kKpWaves][kCopies * kOriStride];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int64_t slot = (int64_t)xcd_remap(blockIdx.x, gridDim.x) * 4 + wave;
+    const int64_t slot = (int64_t)xcd_remap(blockIdx.x, gridDim.x) * kKpWaves + wave;
     const int img = (int)(slot / op.kp_cap), i = (int)(slot % op.kp_cap);
     cdvs_keypoint k;
     bool active = img < n_images && i < count[img];
@@ -154,10 +166,11 @@ __global__ __launch_bounds__(256) void k_orient(const float* __restrict__ pyr, c
         k = kp[(int64_t)img * op.kp_cap + i];
         active = k.octave >= 0 && k.octave < kMaxOctaves;
     }
+    if (!active) return;   // uniform over the wave
     for (int j = lane; j < kCopies * kOriStride; j += 64) hist[wave][j] = 0u;
-    __syncthreads();
+    wave_sync();
 
-    if (active) {
+    {
         uint32_t* hc = &hist[wave][(lane & (kCopies - 1)) * kOriStride];
         const KpGeom g = keypoint_geometry(pyr, geom, img, k, op.sigma0);
         const float R = op.radius * g.s;
@@ -188,8 +201,7 @@ __global__ __launch_bounds__(256) void k_orient(const float* __restrict__ pyr, c
             }
         }
     }
-    __syncthreads();
-    if (!active) return;
+    wave_sync();
 
     auto bin = [&](int b) {
         uint32_t t = 0u;
@@ -259,13 +271,13 @@ __global__ __launch_bounds__(256) void k_orient_compact(const cdvs_keypoint* __r
     if (tid == 255) count_out[img] = min(part[255], limit);
 }
 
-__global__ __launch_bounds__(256) void k_describe(const float* __restrict__ pyr, const OctGeom* __restrict__ geom,
+__global__ __launch_bounds__(64 * kKpWaves) void k_describe(const float* __restrict__ pyr, const OctGeom* __restrict__ geom,
                                                   const cdvs_keypoint* __restrict__ kp,
                                                   const int32_t* __restrict__ count, int n_images, DescParams dp,
                                                   float* __restrict__ desc) {
-    __shared__ uint32_t hist[4][kCopies * kDescStride];
+    __shared__ uint32_t hist[kKpWaves][kCopies * kDescStride];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int64_t slot = (int64_t)xcd_remap(blockIdx.x, gridDim.x) * 4 + wave;
+    const int64_t slot = (int64_t)xcd_remap(blockIdx.x, gridDim.x) * kKpWaves + wave;
     const int img = (int)(slot / dp.kp_cap), i = (int)(slot % dp.kp_cap);
     cdvs_keypoint k;
     bool active = img < n_images && i < count[img];
@@ -273,10 +285,11 @@ __global__ __launch_bounds__(256) void k_describe(const float* __restrict__ pyr,
         k = kp[(int64_t)img * dp.kp_cap + i];
         active = k.octave >= 0 && k.octave < kMaxOctaves;
     }
+    if (!active) return;   // uniform over the wave
     for (int j = lane; j < kCopies * kDescStride; j += 64) hist[wave][j] = 0u;
-    __syncthreads();
+    wave_sync();
 
-    if (active) {
+    {
         uint32_t* hc = &hist[wave][(lane & (kCopies - 1)) * kDescStride];
         const KpGeom g = keypoint_geometry(pyr, geom, img, k, dp.sigma0);
         const float th = k.theta;
@@ -335,8 +348,7 @@ __global__ __launch_bounds__(256) void k_describe(const float* __restrict__ pyr,
             }
         }
     }
-    __syncthreads();
-    if (!active) return;
+    wave_sync();
 
     // element e = cell * 8 + bin; bin 0 also takes the cell's wrap bin
     uint32_t i0 = 0u, i1 = 0u;
@@ -365,7 +377,7 @@ __global__ __launch_bounds__(256) void k_describe(const float* __restrict__ pyr,
 
 int blocks_for(int n_images, int kp_cap) {
     const int64_t waves = (int64_t)n_images * kp_cap;
-    return (int)((waves + 3) / 4);
+    return (int)((waves + kKpWaves - 1) / kKpWaves);
 }
 
 }  // namespace
@@ -374,7 +386,7 @@ hipError_t launch_orient(const float* pyr, const OctGeom* geom, const cdvs_keypo
                          int n_images, const OriParams& op, cdvs_keypoint* ori, int32_t* ori_cnt,
                          hipStream_t stream) {
     if (n_images <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_orient, dim3(blocks_for(n_images, op.kp_cap)), dim3(256), 0, stream, pyr, geom, kp, count,
+    hipLaunchKernelGGL(k_orient, dim3(blocks_for(n_images, op.kp_cap)), dim3(64 * kKpWaves), 0, stream, pyr, geom, kp, count,
                        n_images, op, ori, ori_cnt);
     return hipGetLastError();
 }
@@ -392,7 +404,7 @@ hipError_t launch_orient_compact(const cdvs_keypoint* ori, const int32_t* ori_cn
 hipError_t launch_describe(const float* pyr, const OctGeom* geom, const cdvs_keypoint* kp, const int32_t* count,
                            int n_images, const DescParams& dp, float* desc, hipStream_t stream) {
     if (n_images <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_describe, dim3(blocks_for(n_images, dp.kp_cap)), dim3(256), 0, stream, pyr, geom, kp, count,
+    hipLaunchKernelGGL(k_describe, dim3(blocks_for(n_images, dp.kp_cap)), dim3(64 * kKpWaves), 0, stream, pyr, geom, kp, count,
                        n_images, dp, desc);
     return hipGetLastError();
 }
