@@ -293,7 +293,9 @@ __global__ __launch_bounds__(64 * kKpWaves) void k_describe(const float* __restr
         uint32_t* hc = &hist[wave][(lane & (kCopies - 1)) * kDescStride];
         const KpGeom g = keypoint_geometry(pyr, geom, img, k, dp.sigma0);
         const float th = k.theta;
-        const float ct = cosf(th), st = sinf(th);
+        // hardware sine and cosine: theta is in [0, 2 pi), where they are
+        // accurate to ~1e-6, far below what the cell weights can resolve
+        const float ct = __cosf(th), st = __sinf(th);
         const float R = dp.radius * g.s;
         const float R2 = R * R;
         const float icw = 1.f / (dp.cell * g.s);    // cell units

@@ -34,18 +34,19 @@ __device__ __forceinline__ bool alp_extremum(const float4 a, float lo, float hi,
     const float A = 3.f * a.w, B = 2.f * a.z, C = a.y;
     float r[2];
     int nr = 0;
-    // quotients by the hardware reciprocal (1 ulp) and a multiply: a plain
-    // division is a full IEEE sequence on this target, several times longer
+    // correctly rounded quotients: the extremal scale is ill-conditioned
+    // (a 1-ulp change moves it, and the refined position, measurably), so it
+    // is computed exactly as the fp32 reference does
     if (A == 0.f) {
-        if (B != 0.f) r[nr++] = -(C * __builtin_amdgcn_rcpf(B));
+        if (B != 0.f) r[nr++] = -(C / B);
     } else {
         const float disc = B * B - 4.f * A * C;
         if (disc < 0.f) return false;
         const float sq = __builtin_amdgcn_sqrtf(disc);   // hardware square root (1 ulp)
         const float q = (B >= 0.f) ? -(B + sq) * 0.5f : -(B - sq) * 0.5f;
         if (q != 0.f) {
-            r[nr++] = q * __builtin_amdgcn_rcpf(A);
-            r[nr++] = C * __builtin_amdgcn_rcpf(q);
+            r[nr++] = q / A;
+            r[nr++] = C / q;
         } else {
             r[nr++] = 0.f;
         }
