@@ -42,7 +42,7 @@ __device__ __forceinline__ void column_pass(const float (&win)[V + 2 * HALO], co
 // all four sets (49 operations per pixel instead of 70).
 template <int HALO, int V, int CP, int TH>
 __device__ __forceinline__ void column_pass_scales(const float (&win)[V + 2 * HALO], const Taps& taps, int row0,
-                                                   int col, float (*T)[TH][CP]) {
+                                                   int scol, float (*T)[TH][CP]) {
     static_assert(HALO >= kR4 && kR4 >= kR3 && kR3 >= kR2 && kR2 >= kR1, "radii");
 #pragma unroll
     for (int r = 0; r < V; ++r) {
@@ -58,21 +58,29 @@ __device__ __forceinline__ void column_pass_scales(const float (&win)[V + 2 * HA
             if (p <= kR3) a3 = fmaf(taps.g[3][kR3 + p], pr[p], a3);
             a4 = fmaf(taps.g[4][kR4 + p], pr[p], a4);
         }
-        T[0][row0 + r][col] = a1;
-        T[1][row0 + r][col] = a2;
-        T[2][row0 + r][col] = a3;
-        T[3][row0 + r][col] = a4;
+        T[0][row0 + r][scol] = a1;
+        T[1][row0 + r][scol] = a2;
+        T[2][row0 + r][scol] = a3;
+        T[3][row0 + r][scol] = a4;
     }
 }
 
-// Row pass of tap set K for 8 outputs of one LDS row (row points at column 0
-// of the T buffer, whose column c is image column x0 - HALO + c).
+// LDS rows of the column-pass output are skewed: column c is stored at
+// c + c / 8, so the 16 lanes of a row, which read from columns 8 apart, hit
+// 16 different banks (a stride of 9 words instead of 8).
+__device__ __forceinline__ constexpr int skew(int c) { return c + (c >> 3); }
+
+// Row pass of tap set K for outputs 8 cg .. 8 cg + 7 of one LDS row (row
+// points at column 0 of the T buffer, whose column c is image column
+// x0 - HALO + c).  Column 8 cg + j sits at 9 cg + skew(j), so every offset
+// below is a constant.
 template <int K, int HALO>
-__device__ __forceinline__ void row_pass(const float* row, int c0, const Taps& taps, float (&out)[8]) {
+__device__ __forceinline__ void row_pass(const float* row, int cg, const Taps& taps, float (&out)[8]) {
     constexpr int R = radius_of(K);
+    const float* base = row + 9 * cg;
     float in[8 + 2 * R];
 #pragma unroll
-    for (int i = 0; i < 8 + 2 * R; ++i) in[i] = row[c0 + HALO - R + i];
+    for (int i = 0; i < 8 + 2 * R; ++i) in[i] = base[skew(HALO - R + i)];
 #pragma unroll
     for (int c = 0; c < 8; ++c) {
         float acc = 0.f;
@@ -115,7 +123,7 @@ __global__ __launch_bounds__(256) void k_blur(const uint8_t* __restrict__ images
     constexpr int TW = blur_tw(VAR), TH = blur_th(VAR), V = kBlurV;
     static_assert(TH % V == 0 && TW % 8 == 0, "tile shape");
     constexpr int C = TW + 2 * HALO;
-    constexpr int CP = C + 1;
+    constexpr int CP = skew(C - 1) + 2;   // skewed row, one spare word
     constexpr int NG = TH / V;
     __shared__ float T[NK][TH][CP];
 
@@ -126,11 +134,18 @@ __global__ __launch_bounds__(256) void k_blur(const uint8_t* __restrict__ images
     const int ty0 = (lt / job.tiles_x_blur[VAR]) * TH;
     const int w = job.w, h = job.h;
 
-    for (int t = threadIdx.x; t < C * NG; t += blockDim.x) {
+    // Every column window this thread owns is loaded before any is filtered,
+    // so a thread with two windows does not wait twice for memory (and the
+    // workgroup's barrier does not wait for that second round trip).
+    constexpr int NI = (C * NG + 255) / 256;   // windows per thread (256 lanes)
+    float win[NI][V + 2 * HALO];
+#pragma unroll
+    for (int ii = 0; ii < NI; ++ii) {
+        const int t = threadIdx.x + ii * 256;
+        if (t >= C * NG) break;
         const int col = t % C, grp = t / C;
         const int gx = clampi(tx0 - HALO + col, 0, w - 1);
         const int gy0 = ty0 + grp * V - HALO;
-        float win[V + 2 * HALO];
         // A window inside the image (all but the top and bottom tiles) is
         // read with one 32-bit byte offset from the uniform plane base,
         // advanced by the pitch per row; edge windows clamp every row.
@@ -140,11 +155,11 @@ __global__ __launch_bounds__(256) void k_blur(const uint8_t* __restrict__ images
             if (inside) {
                 uint32_t off = (uint32_t)(gy0 * job.src_pitch + gx);
 #pragma unroll
-                for (int r = 0; r < V + 2 * HALO; ++r, off += (uint32_t)job.src_pitch) win[r] = (float)base[off];
+                for (int r = 0; r < V + 2 * HALO; ++r, off += (uint32_t)job.src_pitch) win[ii][r] = (float)base[off];
             } else {
 #pragma unroll
                 for (int r = 0; r < V + 2 * HALO; ++r)
-                    win[r] = (float)base[(int64_t)clampi(gy0 + r, 0, h - 1) * job.src_pitch + gx];
+                    win[ii][r] = (float)base[(int64_t)clampi(gy0 + r, 0, h - 1) * job.src_pitch + gx];
             }
         } else {
             const char* base = reinterpret_cast<const char*>(pyr + job.plane0);
@@ -152,21 +167,28 @@ __global__ __launch_bounds__(256) void k_blur(const uint8_t* __restrict__ images
                 uint32_t off = (uint32_t)(gy0 * job.pitch + gx) * 4u;
 #pragma unroll
                 for (int r = 0; r < V + 2 * HALO; ++r, off += 4u * (uint32_t)job.pitch)
-                    win[r] = *reinterpret_cast<const float*>(base + off);
+                    win[ii][r] = *reinterpret_cast<const float*>(base + off);
             } else {
 #pragma unroll
                 for (int r = 0; r < V + 2 * HALO; ++r)
-                    win[r] = reinterpret_cast<const float*>(base)[(int64_t)clampi(gy0 + r, 0, h - 1) * job.pitch + gx];
+                    win[ii][r] =
+                        reinterpret_cast<const float*>(base)[(int64_t)clampi(gy0 + r, 0, h - 1) * job.pitch + gx];
             }
         }
+    }
+#pragma unroll
+    for (int ii = 0; ii < NI; ++ii) {
+        const int t = threadIdx.x + ii * 256;
+        if (t >= C * NG) break;
+        const int col = t % C, grp = t / C;
         if constexpr (NK == 1) {
             float out[V];
-            column_pass<KFIRST, HALO, V>(win, taps, out);
+            column_pass<KFIRST, HALO, V>(win[ii], taps, out);
 #pragma unroll
-            for (int r = 0; r < V; ++r) T[0][grp * V + r][col] = out[r];
+            for (int r = 0; r < V; ++r) T[0][grp * V + r][skew(col)] = out[r];
         } else {
             static_assert(KFIRST == 1 && NK == 4, "the scale kernel applies tap sets 1..4");
-            column_pass_scales<HALO, V, CP, TH>(win, taps, grp * V, col, T);
+            column_pass_scales<HALO, V, CP, TH>(win[ii], taps, grp * V, skew(col), T);
         }
     }
     __syncthreads();
@@ -177,17 +199,17 @@ __global__ __launch_bounds__(256) void k_blur(const uint8_t* __restrict__ images
         if (gy >= h || gx0 >= w) continue;
         float out[8];
         if constexpr (U8) {
-            row_pass<KFIRST, HALO>(&T[0][row][0], cg * 8, taps, out);
+            row_pass<KFIRST, HALO>(&T[0][row][0], cg, taps, out);
             store8(pyr + job.plane0 + (int64_t)gy * job.pitch, gx0, w, out);
         } else {
             float* base = pyr + job.plane0 + (int64_t)gy * job.pitch;
-            row_pass<KFIRST, HALO>(&T[0][row][0], cg * 8, taps, out);
+            row_pass<KFIRST, HALO>(&T[0][row][0], cg, taps, out);
             store8(base + (int64_t)1 * job.plane_stride, gx0, w, out);
-            row_pass<KFIRST + 1, HALO>(&T[1 % NK][row][0], cg * 8, taps, out);
+            row_pass<KFIRST + 1, HALO>(&T[1 % NK][row][0], cg, taps, out);
             store8(base + (int64_t)2 * job.plane_stride, gx0, w, out);
-            row_pass<KFIRST + 2, HALO>(&T[2 % NK][row][0], cg * 8, taps, out);
+            row_pass<KFIRST + 2, HALO>(&T[2 % NK][row][0], cg, taps, out);
             store8(base + (int64_t)3 * job.plane_stride, gx0, w, out);
-            row_pass<KFIRST + 3, HALO>(&T[3 % NK][row][0], cg * 8, taps, out);
+            row_pass<KFIRST + 3, HALO>(&T[3 % NK][row][0], cg, taps, out);
             store8(base + (int64_t)4 * job.plane_stride, gx0, w, out);
             if (job.next0 >= 0 && (gy & 1) == 0)
                 store_decimated(pyr + job.next0 + (int64_t)(gy >> 1) * job.next_pitch, gx0, job.next_w, out);
