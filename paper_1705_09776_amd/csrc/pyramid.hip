@@ -65,22 +65,17 @@ __device__ __forceinline__ void column_pass_scales(const float (&win)[V + 2 * HA
     }
 }
 
-// LDS rows of the column-pass output are skewed: column c is stored at
-// c + c / 8, so the 16 lanes of a row, which read from columns 8 apart, hit
-// 16 different banks (a stride of 9 words instead of 8).
-__device__ __forceinline__ constexpr int skew(int c) { return c + (c >> 3); }
-
 // Row pass of tap set K for outputs 8 cg .. 8 cg + 7 of one LDS row (row
 // points at column 0 of the T buffer, whose column c is image column
-// x0 - HALO + c).  Column 8 cg + j sits at 9 cg + skew(j), so every offset
-// below is a constant.
+// x0 - HALO + c).  (A row layout skewed against bank conflicts measured
+// slower: its extra LDS cost a workgroup per CU.)
 template <int K, int HALO>
 __device__ __forceinline__ void row_pass(const float* row, int cg, const Taps& taps, float (&out)[8]) {
     constexpr int R = radius_of(K);
-    const float* base = row + 9 * cg;
+    const float* base = row + 8 * cg;
     float in[8 + 2 * R];
 #pragma unroll
-    for (int i = 0; i < 8 + 2 * R; ++i) in[i] = base[skew(HALO - R + i)];
+    for (int i = 0; i < 8 + 2 * R; ++i) in[i] = base[HALO - R + i];
 #pragma unroll
     for (int c = 0; c < 8; ++c) {
         float acc = 0.f;
@@ -123,7 +118,7 @@ __global__ __launch_bounds__(256) void k_blur(const uint8_t* __restrict__ images
     constexpr int TW = blur_tw(VAR), TH = blur_th(VAR), V = kBlurV;
     static_assert(TH % V == 0 && TW % 8 == 0, "tile shape");
     constexpr int C = TW + 2 * HALO;
-    constexpr int CP = skew(C - 1) + 2;   // skewed row, one spare word
+    constexpr int CP = C + 1;
     constexpr int NG = TH / V;
     __shared__ float T[NK][TH][CP];
 
@@ -185,10 +180,10 @@ __global__ __launch_bounds__(256) void k_blur(const uint8_t* __restrict__ images
             float out[V];
             column_pass<KFIRST, HALO, V>(win[ii], taps, out);
 #pragma unroll
-            for (int r = 0; r < V; ++r) T[0][grp * V + r][skew(col)] = out[r];
+            for (int r = 0; r < V; ++r) T[0][grp * V + r][col] = out[r];
         } else {
             static_assert(KFIRST == 1 && NK == 4, "the scale kernel applies tap sets 1..4");
-            column_pass_scales<HALO, V, CP, TH>(win[ii], taps, grp * V, skew(col), T);
+            column_pass_scales<HALO, V, CP, TH>(win[ii], taps, grp * V, col, T);
         }
     }
     __syncthreads();
