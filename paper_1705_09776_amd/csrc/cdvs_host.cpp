@@ -583,7 +583,8 @@ cdvs_status cdvs_pyramid(cdvs_ctx* ctx, const uint8_t* d_images, float* d_pyr, v
     {
         Bracket b(ctx, CDVS_KERNEL_PREBLUR, s);
         HIP_OR_FAIL(ctx, launch_preblur(d_images, d_pyr, ctx->d_jobs + ctx->job_start[0],
-                                        ctx->d_blur_owner + ctx->blur_owner_start[0][0], ctx->blur_tiles[0][0],
+                                        ctx->d_blur_owner + ctx->blur_owner_start[kPreblurVariant][0],
+                                        ctx->blur_tiles[kPreblurVariant][0],
                                         ctx->taps, s));
     }
     for (int o = 0; o < ctx->max_oct; ++o) {

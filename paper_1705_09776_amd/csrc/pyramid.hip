@@ -217,8 +217,8 @@ __global__ __launch_bounds__(256) void k_blur(const uint8_t* __restrict__ images
 hipError_t launch_preblur(const uint8_t* images, float* pyr, const OctJob* jobs, const int32_t* owner, int ntiles,
                           const Taps& taps, hipStream_t stream) {
     if (ntiles <= 0) return hipSuccess;
-    hipLaunchKernelGGL((k_blur<0, 1, kR0, true, 0>), dim3(ntiles), dim3(256), 0, stream, images, pyr, jobs, owner,
-                       taps);
+    hipLaunchKernelGGL((k_blur<0, 1, kR0, true, kPreblurVariant>), dim3(ntiles), dim3(256), 0, stream, images, pyr,
+                       jobs, owner, taps);
     return hipGetLastError();
 }
 
