@@ -1,14 +1,16 @@
 // Gaussian scale space on gfx950 (Sec. III-A, Eq. (1); Sec. IV-A,
 // Algorithm 1 stage A and its final downsampling step).
 //
-// One 256-lane workgroup per 64x32 output tile of one (image, octave).  The
-// vertical pass reads input columns straight from global memory (adjacent
-// lanes = adjacent columns, so every load is a contiguous 256-byte row
-// segment; the halo rows are L1/L2 hits), keeps an 8-row window plus halo in
-// registers, and produces the column-filtered rows T_k of every scale at once
-// into LDS.  The horizontal pass reads T_k from LDS and writes each output
-// row with 16-byte stores.  The scale kernel also writes the even samples of
-// G_{o,4}, which is G_{o+1,0}, so no separate downsampling pass exists.
+// One 256-lane workgroup per output tile of one (image, octave) (tile shape
+// autotuned for the scale kernel).  The vertical pass reads input columns
+// straight from global memory (adjacent lanes = adjacent columns, so every
+// load is a contiguous 256-byte row segment; the halo rows are L1/L2 hits),
+// all of a thread's column windows (8 output rows plus halo; 16 for the
+// pre-blur) before filtering any, and produces the column-filtered rows T_k
+// of every scale at once into LDS.  The horizontal pass reads T_k from LDS
+// and writes each output row with 16-byte stores.  The scale kernel also
+// writes the even samples of G_{o,4}, which is G_{o+1,0}, so no separate
+// downsampling pass exists.
 #include "cdvs_internal.h"
 
 namespace cdvs {
@@ -115,7 +117,10 @@ template <int KFIRST, int NK, int HALO, bool U8, int VAR>
 __global__ __launch_bounds__(256) void k_blur(const uint8_t* __restrict__ images, float* __restrict__ pyr,
                                               const OctJob* __restrict__ jobs, const int32_t* __restrict__ owner,
                                               Taps taps) {
-    constexpr int TW = blur_tw(VAR), TH = blur_th(VAR), V = kBlurV;
+    // column window: 8 output rows for the scale planes, 16 for the pre-blur
+    // (its single radius-7 filter leaves room for the longer window; each
+    // was the faster of 4, 8 and 16 rows)
+    constexpr int TW = blur_tw(VAR), TH = blur_th(VAR), V = U8 ? 2 * kBlurV : kBlurV;
     static_assert(TH % V == 0 && TW % 8 == 0, "tile shape");
     constexpr int C = TW + 2 * HALO;
     constexpr int CP = C + 1;
