@@ -1,6 +1,6 @@
 """GPU (HIP path through the C ABI) vs the CPU oracle on the same seeded inputs.
 
-Bars (stated by the build's target):
+Bars:
   * keypoints: >= 99% of oracle keypoints have a GPU keypoint in the same image
     and octave within 0.5 base-image px, and the reverse;
   * descriptors: over matched oriented keypoints (|d theta| <= 1e-2 rad),
