@@ -28,47 +28,33 @@ __device__ __forceinline__ int clampi(int v, int lo, int hi) { return min(max(v,
 __device__ __forceinline__ float horner(const float4 a, float s) { return fmaf(fmaf(fmaf(a.w, s, a.z), s, a.y), s, a.x); }
 
 // Extremal scale of p(s) = a.x + a.y s + a.z s^2 + a.w s^3 in [lo, hi) where
-// |p| has a maximum (p p'' < 0); larger |p| wins, then the smaller s.
+// |p| has a maximum (p p'' < 0); larger |p| wins, then the smaller s.  The
+// roots of p'(s) = A s^2 + B s + C come from the stable quadratic formula,
+// s0 = q / A and s1 = C / q; when A = 0, q = -B and s1 is the linear root.
+// Both candidates are evaluated and the choice is made by selects (no
+// branches: every lane of a wave runs this), with correctly rounded
+// quotients (the extremal scale is ill-conditioned, so it is computed as
+// the fp32 reference computes it).
 __device__ __forceinline__ bool alp_extremum(const float4 a, float lo, float hi, float& s_out, float& p_out,
                                              float& pss_out) {
     const float A = 3.f * a.w, B = 2.f * a.z, C = a.y;
-    float r[2];
-    int nr = 0;
-    // correctly rounded quotients: the extremal scale is ill-conditioned
-    // (a 1-ulp change moves it, and the refined position, measurably), so it
-    // is computed exactly as the fp32 reference does
-    if (A == 0.f) {
-        if (B != 0.f) r[nr++] = -(C / B);
-    } else {
-        const float disc = B * B - 4.f * A * C;
-        if (disc < 0.f) return false;
-        const float sq = __builtin_amdgcn_sqrtf(disc);   // hardware square root (1 ulp)
-        const float q = (B >= 0.f) ? -(B + sq) * 0.5f : -(B - sq) * 0.5f;
-        if (q != 0.f) {
-            r[nr++] = q / A;
-            r[nr++] = C / q;
-        } else {
-            r[nr++] = 0.f;
-        }
-    }
-    bool found = false;
-    float bs = 0.f, bp = 0.f, bpss = 0.f;
-    for (int i = 0; i < nr; ++i) {
-        const float s = r[i];
-        if (!(s >= lo && s < hi)) continue;
-        const float p = horner(a, s);
-        const float pss = 6.f * a.w * s + 2.f * a.z;
-        if (!(p * pss < 0.f)) continue;
-        if (!found || fabsf(p) > fabsf(bp) || (fabsf(p) == fabsf(bp) && s < bs)) {
-            bs = s;
-            bp = p;
-            bpss = pss;
-            found = true;
-        }
-    }
-    s_out = bs;
-    p_out = bp;
-    pss_out = bpss;
+    const bool lin = A == 0.f;
+    const float disc = B * B - 4.f * A * C;
+    const float sq = __builtin_amdgcn_sqrtf(fmaxf(disc, 0.f));   // hardware square root (1 ulp)
+    const float q = (B >= 0.f) ? -(B + sq) * 0.5f : -(B - sq) * 0.5f;
+    const float s0 = q / A;
+    const float s1 = C / (lin ? -B : q);
+    const bool real = lin || disc >= 0.f;
+    const float p0 = horner(a, s0), p1 = horner(a, s1);
+    const float pss0 = 6.f * a.w * s0 + 2.f * a.z, pss1 = 6.f * a.w * s1 + 2.f * a.z;
+    const bool ok0 = real & !lin & (s0 >= lo) & (s0 < hi) & (p0 * pss0 < 0.f);
+    const bool ok1 = real & (s1 >= lo) & (s1 < hi) & (p1 * pss1 < 0.f);
+    const float a0 = fabsf(p0), a1 = fabsf(p1);
+    const bool take1 = ok1 & (!ok0 | (a1 > a0) | ((a1 == a0) & (s1 < s0)));
+    const bool found = ok0 | ok1;
+    s_out = found ? (take1 ? s1 : s0) : 0.f;
+    p_out = found ? (take1 ? p1 : p0) : 0.f;
+    pss_out = found ? (take1 ? pss1 : pss0) : 0.f;
     return found;
 }
 
@@ -260,7 +246,8 @@ __device__ __forceinline__ void strip_centres(const float4& aU, const float4& aM
                                               const DetParams& dp, cdvs_keypoint* __restrict__ cand,
                                               int32_t* __restrict__ cand_cnt, int32_t* __restrict__ flags) {
     float s = 0.f, p = 0.f, pss = 0.f;
-    const bool pass = col_ok && alp_extremum(aM, dp.lo, dp.hi, s, p, pss) && fabsf(p) >= dp.contrast;
+    const bool found = alp_extremum(aM, dp.lo, dp.hi, s, p, pss);
+    const bool pass = col_ok & found & (fabsf(p) >= dp.contrast);   // no branch: every lane evaluates
     if (!__ballot(pass)) return;   // uniform over the wave
     // this lane's column at the scale of the centre to its right (for which
     // it is the left column) and of the centre to its left
