@@ -83,12 +83,17 @@ struct Cand {
 
 // Strict extremum of the centre value p = v[4] against the eight
 // neighbours' cubics v[] evaluated at the centre's scale (Algorithm 1 stage A).
+// (All eight below p for a maximum, above it for a minimum: compared through
+// their max and min, without branches; the values are finite.)
 __device__ __forceinline__ bool strict_extremum(const float (&v)[9], float p) {
-    bool ext = true;
+    float mx = v[0], mn = v[0];
 #pragma unroll
-    for (int i = 0; i < 9; ++i)
-        if (i != 4) ext = ext && (p > 0.f ? (v[i] < p) : (v[i] > p));
-    return ext;
+    for (int i = 1; i < 9; ++i)
+        if (i != 4) {
+            mx = fmaxf(mx, v[i]);
+            mn = fminf(mn, v[i]);
+        }
+    return p > 0.f ? (mx < p) : (mn > p);
 }
 
 // One quadratic refinement step on the 3x3 values v[] (row-major, centre
