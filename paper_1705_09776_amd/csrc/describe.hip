@@ -43,10 +43,16 @@ __device__ __forceinline__ KpGeom keypoint_geometry(const float* pyr, const OctG
     g.s = k.sigma * sc;
     // nearest scale image: round(4 log2(s / sigma0)), clamped to 0..4
     const int ks = min(max((int)floorf(4.f * log2f(g.s / sigma0) + 0.5f), 0), kScales - 1);
-    g.plane = pyr + og.plane0 + (int64_t)ks * og.plane_stride;
+    // one keypoint per wave: the plane pointer and pitch are the same in
+    // every lane, and kept in scalar registers so that pixel addresses are
+    // a 32-bit offset from them
+    const uint64_t po = (uint64_t)(og.plane0 + (int64_t)ks * og.plane_stride);
+    const uint32_t plo = __builtin_amdgcn_readfirstlane((uint32_t)po);
+    const uint32_t phi = __builtin_amdgcn_readfirstlane((uint32_t)(po >> 32));
+    g.plane = pyr + (int64_t)(((uint64_t)phi << 32) | plo);
     g.w = og.w;
     g.h = og.h;
-    g.pitch = og.pitch;
+    g.pitch = __builtin_amdgcn_readfirstlane(og.pitch);
     return g;
 }
 
@@ -86,9 +92,13 @@ struct Nbrs {
     float l, r, d, u;   // (u-1, v), (u+1, v), (u, v-1), (u, v+1)
 };
 
+// (A 32-bit byte offset from the keypoint's plane base: one offset and two
+// additions per pixel instead of four 64-bit addresses.)
 __device__ __forceinline__ Nbrs load_nbrs(const KpGeom& g, int u, int v) {
-    const float* row = g.plane + (int64_t)v * g.pitch;
-    return Nbrs{row[u - 1], row[u + 1], row[u - g.pitch], row[u + g.pitch]};
+    const char* base = reinterpret_cast<const char*>(g.plane);
+    const uint32_t off = (uint32_t)(v * g.pitch + u) * 4u, dy = 4u * (uint32_t)g.pitch;
+    return Nbrs{*reinterpret_cast<const float*>(base + (off - 4u)), *reinterpret_cast<const float*>(base + (off + 4u)),
+                *reinterpret_cast<const float*>(base + (off - dy)), *reinterpret_cast<const float*>(base + (off + dy))};
 }
 
 __device__ __forceinline__ void gradient(const Nbrs& n, float& mag, float& ang) {
@@ -322,18 +332,20 @@ __global__ __launch_bounds__(64 * kKpWaves) void k_describe(const float* __restr
                 const float wt = mag * __expf(d2 * nid) * dp.fix;   // in fixed-point units
                 const float fx = rx + 1.5f, fy = ry + 1.5f, fo = rel * (8.f / kTwoPi);
                 const float x0f = floorf(fx), y0f = floorf(fy), o0f = floorf(fo);
-                const float ax = fx - x0f, ay = fy - y0f, ao = fo - o0f;
+                const float ao = fo - o0f;
                 const int x0 = (int)x0f, y0 = (int)y0f;
                 const int o0 = (int)o0f & 7;
                 // The two cells per axis are slots 0 and 1 from a base cell
-                // clamped to 0..2; a cell outside the 4 x 4 grid gets weight 0
-                // and the weights shift with the base, so each in-grid cell
-                // receives exactly its own trilinear share.
+                // clamped to 0..2.  Cell c's trilinear weight along an axis is
+                // max(0, 1 - |f - c|): the usual 1 - a and a for the two cells
+                // around f, 0 for any other, so a base shifted by the clamp, or
+                // a cell outside the 4 x 4 grid, gets exactly its share.
                 const int bx = min(max(x0, 0), 2), by = min(max(y0, 0), 2);
-                const float wx0 = x0 == bx ? 1.f - ax : (x0 == bx - 1 ? ax : 0.f);   // cell bx
-                const float wx1 = x0 == bx ? ax : (x0 == bx + 1 ? 1.f - ax : 0.f);   // cell bx + 1
-                const float wy0 = y0 == by ? 1.f - ay : (y0 == by - 1 ? ay : 0.f);
-                const float wy1 = y0 == by ? ay : (y0 == by + 1 ? 1.f - ay : 0.f);
+                const float cx0 = (float)bx, cy0 = (float)by;
+                const float wx0 = fmaxf(0.f, 1.f - fabsf(fx - cx0));          // cell bx
+                const float wx1 = fmaxf(0.f, 1.f - fabsf(fx - (cx0 + 1.f)));  // cell bx + 1
+                const float wy0 = fmaxf(0.f, 1.f - fabsf(fy - cy0));
+                const float wy1 = fmaxf(0.f, 1.f - fabsf(fy - (cy0 + 1.f)));
                 uint32_t* cell = hc + (by * 4 + bx) * kDescCellBins + o0;
 #pragma unroll
                 for (int jy = 0; jy < 2; ++jy) {
