@@ -31,7 +31,7 @@ struct cdvs_ctx {
     int max_oct = 0;
     int job_start[kMaxOctaves + 1] = {};
     int blur_tiles[kBlurVariants][kMaxOctaves] = {};
-    int blur_variant = 0;    // scale-plane tile variant (cdvs_autotune)
+    int blur_variant = 1;    // scale-plane tile variant (cdvs_autotune; 128 x 16 measured best untuned)
     int detect_variant = 0;  // detection launch form (cdvs_autotune)
     int64_t pyr_floats = 0;
     Taps taps{};
