@@ -223,8 +223,9 @@ cdvs_status cdvs_graph_launch(cdvs_ctx* ctx, void* stream);
  * counters; both find the same candidates).  cdvs_autotune times each
  * shape with cdvs_pyramid on the given buffers, then each launch form of the
  * ungated detection on the resulting pyramid (candidates go to the
- * context's scratch; d_pyr must be 256-byte aligned), 1 warm-up + 3 timed
- * runs each, median; blocking; it keeps the fastest of each.  With
+ * context's scratch; d_pyr must be 256-byte aligned), 2 warm-ups + 7
+ * timed runs each, the variants taken in turn, median; blocking; it keeps
+ * the fastest of each.  With
  * cache_path (may be NULL) a JSON file keyed by (GPU arch, image size,
  * batch-size bucket) is read first (a hit skips the timing) and updated
  * after timing.  cdvs_tune_get / cdvs_tune_set read and force a kernel's

@@ -892,52 +892,64 @@ cdvs_status cdvs_autotune(cdvs_ctx* ctx, const uint8_t* d_images, float* d_pyr, 
     HIP_OR_FAIL(ctx, hipEventCreate(&e1));
     const bool prof = ctx->prof;
     ctx->prof = false;
-    // median of three timed runs after one warm-up
-    auto median3 = [&](auto&& run, float* out) -> cdvs_status {
-        float t[3] = {0.f, 0.f, 0.f};
-        cdvs_status st = run();
-        for (int r = 0; r < 3 && st == CDVS_OK; ++r) {
-            (void)hipEventRecord(e0, s);
-            st = run();
-            (void)hipEventRecord(e1, s);
-            (void)hipEventSynchronize(e1);
-            float ms = 0.f;
-            (void)hipEventElapsedTime(&ms, e0, e1);
-            t[r] = ms * 1e3f;
+    // Each variant is warmed up twice, then timed seven times with the
+    // variants taken in turn inside each round, so a clock that is still
+    // settling favours none of them; the median of each is kept.  Shapes can
+    // be within 10% of each other, closer than a few samples separate.
+    constexpr int kRuns = 7;
+    auto time_variants = [&](int nvar, auto&& run, float* out) -> cdvs_status {
+        std::vector<float> t((size_t)nvar * kRuns, 0.f);
+        cdvs_status st = CDVS_OK;
+        for (int w = 0; w < 2 && st == CDVS_OK; ++w)
+            for (int var = 0; var < nvar && st == CDVS_OK; ++var) st = run(var);
+        for (int r = 0; r < kRuns && st == CDVS_OK; ++r)
+            for (int var = 0; var < nvar && st == CDVS_OK; ++var) {
+                (void)hipEventRecord(e0, s);
+                st = run(var);
+                (void)hipEventRecord(e1, s);
+                (void)hipEventSynchronize(e1);
+                float ms = 0.f;
+                (void)hipEventElapsedTime(&ms, e0, e1);
+                t[(size_t)var * kRuns + r] = ms * 1e3f;
+            }
+        for (int var = 0; var < nvar; ++var) {
+            float* tv = t.data() + (size_t)var * kRuns;
+            std::sort(tv, tv + kRuns);
+            out[var] = tv[kRuns / 2];
         }
-        std::sort(t, t + 3);
-        *out = t[1];
         return st;
+    };
+    auto argmin = [](const float* x, int n) {
+        int b = 0;
+        for (int i = 1; i < n; ++i)
+            if (x[i] < x[b]) b = i;
+        return b;
     };
     float us[kBlurVariants] = {}, dus[kDetectVariants] = {};
     int best_v = ctx->blur_variant, best_dv = ctx->detect_variant;
-    cdvs_status st = CDVS_OK;
-    float best = 1e30f;
-    for (int var = 0; var < kBlurVariants && st == CDVS_OK; ++var) {
-        ctx->blur_variant = var;
-        st = median3([&] { return cdvs_pyramid(ctx, d_images, d_pyr, stream); }, &us[var]);
-        if (us[var] < best) {
-            best = us[var];
-            best_v = var;
-        }
-    }
-    // the detection's launch forms on the pyramid just built (every tile
-    // shape writes the same planes), candidates into the context's scratch
-    best = 1e30f;
-    for (int var = 0; var < kDetectVariants && st == CDVS_OK; ++var) {
-        auto run = [&]() -> cdvs_status {
-            const GateParams gate{nullptr, nullptr, nullptr, 1.f};
-            HIP_OR_FAIL(ctx, launch_clear(ctx->d_cand_cnt, ctx->n + kXcds, s));
-            HIP_OR_FAIL(ctx, launch_detect_strips(d_pyr, ctx->d_strips, (int)ctx->strips.size(), var,
-                                                  ctx->detect_grid, ctx->det, gate, ctx->d_cand_cnt + ctx->n,
-                                                  ctx->d_cand, ctx->d_cand_cnt, ctx->d_flags, s));
-            return CDVS_OK;
-        };
-        st = median3(run, &dus[var]);
-        if (dus[var] < best) {
-            best = dus[var];
-            best_dv = var;
-        }
+    cdvs_status st = time_variants(
+        kBlurVariants,
+        [&](int var) {
+            ctx->blur_variant = var;
+            return cdvs_pyramid(ctx, d_images, d_pyr, stream);
+        },
+        us);
+    if (st == CDVS_OK) {
+        best_v = argmin(us, kBlurVariants);
+        // the detection's launch forms on the pyramid just built (every tile
+        // shape writes the same planes), candidates into the context's scratch
+        st = time_variants(
+            kDetectVariants,
+            [&](int var) -> cdvs_status {
+                const GateParams gate{nullptr, nullptr, nullptr, 1.f};
+                HIP_OR_FAIL(ctx, launch_clear(ctx->d_cand_cnt, ctx->n + kXcds, s));
+                HIP_OR_FAIL(ctx, launch_detect_strips(d_pyr, ctx->d_strips, (int)ctx->strips.size(), var,
+                                                      ctx->detect_grid, ctx->det, gate, ctx->d_cand_cnt + ctx->n,
+                                                      ctx->d_cand, ctx->d_cand_cnt, ctx->d_flags, s));
+                return CDVS_OK;
+            },
+            dus);
+        if (st == CDVS_OK) best_dv = argmin(dus, kDetectVariants);
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
