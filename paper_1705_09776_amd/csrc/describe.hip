@@ -56,7 +56,9 @@ __device__ __forceinline__ KpGeom keypoint_geometry(const float* pyr, const OctG
     return g;
 }
 
-// Angle of (x, y) in [0, 2 pi).  The octant symmetries of the arctangent
+// Angle of (x, y) in [0, 2 pi], 2 pi itself only by rounding for angles
+// just below it (both histograms take their bin index modulo the bin
+// count, so 2 pi falls into bin 0 as 0 does).  The octant symmetries of the arctangent
 // reduce the argument to t = min(|x|, |y|) / max(|x|, |y|) in [0, 1] (its
 // rounding, under 2 ulp, moves the angle by less than 1e-7 rad), where
 // atan(t) is an odd polynomial t P(t^2) of degree 15 whose coefficients were
@@ -83,7 +85,7 @@ __device__ __forceinline__ float angle_2pi(float y, float x) {
     if (ay > ax) r = 1.5707963267948966f - r;          // first quadrant
     if (x < 0.f) r = 3.141592653589793f - r;           // upper half plane
     if (y < 0.f) r = kTwoPi - r;                       // lower half plane
-    return r >= kTwoPi ? 0.f : r;
+    return r;
 }
 
 // The four neighbours of an interior pixel (u, v), and from them the
@@ -186,7 +188,8 @@ __global__ __launch_bounds__(64 * kKpWaves) void k_orient(const float* __restric
         const float R = op.radius * g.s;
         const float R2 = R * R;
         const float ws = op.wsigma * g.s;
-        const float nid = -1.f / (2.f * ws * ws);   // Gaussian weight exp(-d^2 / (2 ws^2))
+        // Gaussian weight exp(-d^2 / (2 ws^2)) = 2^(d^2 nid)
+        const float nid = -1.4426950408889634f / (2.f * ws * ws);
         const int u0 = max((int)ceilf(g.cx - R), 1), u1 = min((int)floorf(g.cx + R), g.w - 2);
         const int v0 = max((int)ceilf(g.cy - R), 1), v1 = min((int)floorf(g.cy + R), g.h - 2);
         const int bw = u1 - u0 + 1, bh = v1 - v0 + 1;
@@ -200,7 +203,7 @@ __global__ __launch_bounds__(64 * kKpWaves) void k_orient(const float* __restric
                 const Nbrs nb = load_nbrs(g, u, v);
                 float mag, ang;
                 gradient(nb, mag, ang);
-                const float wt = mag * __expf(d2 * nid) * op.fix;   // in fixed-point units
+                const float wt = mag * __builtin_amdgcn_exp2f(d2 * nid) * op.fix;   // in fixed-point units
                 const float fb = ang * ((float)kOriBins / kTwoPi);
                 const float f0 = floorf(fb);
                 const float fr = fb - f0;
@@ -310,7 +313,7 @@ __global__ __launch_bounds__(64 * kKpWaves) void k_describe(const float* __restr
         const float R2 = R * R;
         const float icw = 1.f / (dp.cell * g.s);    // cell units
         const float ws = dp.wsigma * g.s;
-        const float nid = -1.f / (2.f * ws * ws);
+        const float nid = -1.4426950408889634f / (2.f * ws * ws);   // exp(-d^2 / (2 ws^2)) = 2^(d^2 nid)
         const int u0 = max((int)ceilf(g.cx - R), 1), u1 = min((int)floorf(g.cx + R), g.w - 2);
         const int v0 = max((int)ceilf(g.cy - R), 1), v1 = min((int)floorf(g.cy + R), g.h - 2);
         const int bw = u1 - u0 + 1, bh = v1 - v0 + 1;
@@ -326,26 +329,28 @@ __global__ __launch_bounds__(64 * kKpWaves) void k_describe(const float* __restr
                 const float ry = (ct * dy - st * dx) * icw;
                 float mag, ang;
                 gradient(nb, mag, ang);
-                float rel = ang - th;
-                if (rel < 0.f) rel += kTwoPi;
-                if (rel >= kTwoPi) rel -= kTwoPi;
-                const float wt = mag * __expf(d2 * nid) * dp.fix;   // in fixed-point units
-                const float fx = rx + 1.5f, fy = ry + 1.5f, fo = rel * (8.f / kTwoPi);
-                const float x0f = floorf(fx), y0f = floorf(fy), o0f = floorf(fo);
-                const float ao = fo - o0f;
-                const int x0 = (int)x0f, y0 = (int)y0f;
+                const float wt = mag * __builtin_amdgcn_exp2f(d2 * nid) * dp.fix;   // in fixed-point units
+                // Orientation relative to theta in eighths of a turn: ang - th
+                // lies in (-2 pi, 2 pi], and the bin is floor(fo) modulo 8
+                // (a mask by 7, right for either sign), so no wrap is needed.
+                const float fo = (ang - th) * (8.f / kTwoPi);
+                const float o0f = floorf(fo);
+                const float ao = fo - o0f, bo = 1.f - ao;
                 const int o0 = (int)o0f & 7;
                 // The two cells per axis are slots 0 and 1 from a base cell
                 // clamped to 0..2.  Cell c's trilinear weight along an axis is
                 // max(0, 1 - |f - c|): the usual 1 - a and a for the two cells
                 // around f, 0 for any other, so a base shifted by the clamp, or
                 // a cell outside the 4 x 4 grid, gets exactly its share.
-                const int bx = min(max(x0, 0), 2), by = min(max(y0, 0), 2);
-                const float cx0 = (float)bx, cy0 = (float)by;
-                const float wx0 = fmaxf(0.f, 1.f - fabsf(fx - cx0));          // cell bx
-                const float wx1 = fmaxf(0.f, 1.f - fabsf(fx - (cx0 + 1.f)));  // cell bx + 1
-                const float wy0 = fmaxf(0.f, 1.f - fabsf(fy - cy0));
-                const float wy1 = fmaxf(0.f, 1.f - fabsf(fy - (cy0 + 1.f)));
+                const float fx = rx + 1.5f, fy = ry + 1.5f;
+                const float cx0 = __builtin_amdgcn_fmed3f(floorf(fx), 0.f, 2.f);
+                const float cy0 = __builtin_amdgcn_fmed3f(floorf(fy), 0.f, 2.f);
+                const float tx = fx - cx0, ty = fy - cy0;
+                const float wx0 = fmaxf(0.f, 1.f - fabsf(tx));         // cell bx
+                const float wx1 = fmaxf(0.f, 1.f - fabsf(tx - 1.f));   // cell bx + 1
+                const float wy0 = fmaxf(0.f, 1.f - fabsf(ty));
+                const float wy1 = fmaxf(0.f, 1.f - fabsf(ty - 1.f));
+                const int bx = (int)cx0, by = (int)cy0;
                 uint32_t* cell = hc + (by * 4 + bx) * kDescCellBins + o0;
 #pragma unroll
                 for (int jy = 0; jy < 2; ++jy) {
@@ -353,10 +358,9 @@ __global__ __launch_bounds__(64 * kKpWaves) void k_describe(const float* __restr
 #pragma unroll
                     for (int jx = 0; jx < 2; ++jx) {
                         const float wyx = wy * (jx ? wx1 : wx0);
-                        const float w1 = wyx * ao;
                         uint32_t* c = cell + (jy * 4 + jx) * kDescCellBins;
-                        atomicAdd(c, (uint32_t)(wyx - w1 + 0.5f));
-                        atomicAdd(c + 1, (uint32_t)(w1 + 0.5f));
+                        atomicAdd(c, (uint32_t)fmaf(wyx, bo, 0.5f));      // rounded to nearest
+                        atomicAdd(c + 1, (uint32_t)fmaf(wyx, ao, 0.5f));
                     }
                 }
             }
