@@ -68,10 +68,12 @@ __device__ __forceinline__ KpGeom keypoint_geometry(const float* pyr, const OctG
 // can resolve.  (0, 0) gives 0.
 __device__ __forceinline__ float angle_2pi(float y, float x) {
     const float ax = fabsf(x), ay = fabsf(y);
-    const float mx = fmaxf(ax, ay), mn = fminf(ax, ay);
+    // mx is kept at least the smallest normal float, so (0, 0) gives
+    // t = 0 * finite = 0 with no test
+    const float mx = fmaxf(fmaxf(ax, ay), 1.17549435e-38f), mn = fminf(ax, ay);
     // mn / mx by the hardware reciprocal (1 ulp) and a multiply: a plain
     // division is a full IEEE sequence on this target, several times longer
-    const float t = mx > 0.f ? mn * __builtin_amdgcn_rcpf(mx) : 0.f;
+    const float t = mn * __builtin_amdgcn_rcpf(mx);
     const float s = t * t;
     float p = -0.004072779323905706f;
     p = fmaf(p, s, 0.021944405511021614f);
@@ -95,10 +97,12 @@ struct Nbrs {
 };
 
 // (A 32-bit byte offset from the keypoint's plane base: one offset and two
-// additions per pixel instead of four 64-bit addresses.)
+// additions per pixel instead of four 64-bit addresses.  Row and pitch are
+// below 2^24 (image sides are at most CDVS_MAX_SIDE), so the row offset is a
+// full-rate 24-bit multiply.)
 __device__ __forceinline__ Nbrs load_nbrs(const KpGeom& g, int u, int v) {
     const char* base = reinterpret_cast<const char*>(g.plane);
-    const uint32_t off = (uint32_t)(v * g.pitch + u) * 4u, dy = 4u * (uint32_t)g.pitch;
+    const uint32_t off = (__umul24((uint32_t)v, (uint32_t)g.pitch) + (uint32_t)u) * 4u, dy = 4u * (uint32_t)g.pitch;
     return Nbrs{*reinterpret_cast<const float*>(base + (off - 4u)), *reinterpret_cast<const float*>(base + (off + 4u)),
                 *reinterpret_cast<const float*>(base + (off - dy)), *reinterpret_cast<const float*>(base + (off + dy))};
 }
@@ -188,8 +192,9 @@ __global__ __launch_bounds__(64 * kKpWaves) void k_orient(const float* __restric
         const float R = op.radius * g.s;
         const float R2 = R * R;
         const float ws = op.wsigma * g.s;
-        // Gaussian weight exp(-d^2 / (2 ws^2)) = 2^(d^2 nid)
-        const float nid = -1.4426950408889634f / (2.f * ws * ws);
+        // Gaussian weight in fixed-point units: fix exp(-d^2 / (2 ws^2)) =
+        // 2^(d^2 nid + log2 fix), fix being a power of two
+        const float nid = -1.4426950408889634f / (2.f * ws * ws), lfix = log2f(op.fix);
         const int u0 = max((int)ceilf(g.cx - R), 1), u1 = min((int)floorf(g.cx + R), g.w - 2);
         const int v0 = max((int)ceilf(g.cy - R), 1), v1 = min((int)floorf(g.cy + R), g.h - 2);
         const int bw = u1 - u0 + 1, bh = v1 - v0 + 1;
@@ -203,7 +208,7 @@ __global__ __launch_bounds__(64 * kKpWaves) void k_orient(const float* __restric
                 const Nbrs nb = load_nbrs(g, u, v);
                 float mag, ang;
                 gradient(nb, mag, ang);
-                const float wt = mag * __builtin_amdgcn_exp2f(d2 * nid) * op.fix;   // in fixed-point units
+                const float wt = mag * __builtin_amdgcn_exp2f(fmaf(d2, nid, lfix));
                 const float fb = ang * ((float)kOriBins / kTwoPi);
                 const float f0 = floorf(fb);
                 const float fr = fb - f0;
@@ -313,7 +318,9 @@ __global__ __launch_bounds__(64 * kKpWaves) void k_describe(const float* __restr
         const float R2 = R * R;
         const float icw = 1.f / (dp.cell * g.s);    // cell units
         const float ws = dp.wsigma * g.s;
-        const float nid = -1.4426950408889634f / (2.f * ws * ws);   // exp(-d^2 / (2 ws^2)) = 2^(d^2 nid)
+        // Gaussian weight in fixed-point units: fix exp(-d^2 / (2 ws^2)) =
+        // 2^(d^2 nid + log2 fix), fix being a power of two
+        const float nid = -1.4426950408889634f / (2.f * ws * ws), lfix = log2f(dp.fix);
         const int u0 = max((int)ceilf(g.cx - R), 1), u1 = min((int)floorf(g.cx + R), g.w - 2);
         const int v0 = max((int)ceilf(g.cy - R), 1), v1 = min((int)floorf(g.cy + R), g.h - 2);
         const int bw = u1 - u0 + 1, bh = v1 - v0 + 1;
@@ -329,7 +336,7 @@ __global__ __launch_bounds__(64 * kKpWaves) void k_describe(const float* __restr
                 const float ry = (ct * dy - st * dx) * icw;
                 float mag, ang;
                 gradient(nb, mag, ang);
-                const float wt = mag * __builtin_amdgcn_exp2f(d2 * nid) * dp.fix;   // in fixed-point units
+                const float wt = mag * __builtin_amdgcn_exp2f(fmaf(d2, nid, lfix));
                 // Orientation relative to theta in eighths of a turn: ang - th
                 // lies in (-2 pi, 2 pi], and the bin is floor(fo) modulo 8
                 // (a mask by 7, right for either sign), so no wrap is needed.
@@ -350,8 +357,9 @@ __global__ __launch_bounds__(64 * kKpWaves) void k_describe(const float* __restr
                 const float wx1 = fmaxf(0.f, 1.f - fabsf(tx - 1.f));   // cell bx + 1
                 const float wy0 = fmaxf(0.f, 1.f - fabsf(ty));
                 const float wy1 = fmaxf(0.f, 1.f - fabsf(ty - 1.f));
-                const int bx = (int)cx0, by = (int)cy0;
-                uint32_t* cell = hc + (by * 4 + bx) * kDescCellBins + o0;
+                // base cell's first bin: (4 by + bx) x 9, exact in float
+                const int cell0 = (int)fmaf(cy0, 4.f * kDescCellBins, cx0 * (float)kDescCellBins);
+                uint32_t* cell = hc + cell0 + o0;
 #pragma unroll
                 for (int jy = 0; jy < 2; ++jy) {
                     const float wy = wt * (jy ? wy1 : wy0);

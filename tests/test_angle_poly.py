@@ -24,8 +24,9 @@ def _coeffs():
 def _angle(y, x):
     f = np.float32
     ax, ay = np.abs(x), np.abs(y)
-    mx, mn = np.maximum(ax, ay), np.minimum(ax, ay)
-    t = np.where(mx > 0, mn / np.where(mx > 0, mx, f(1)), f(0)).astype(np.float32)
+    mx = np.maximum(np.maximum(ax, ay), f(1.17549435e-38))
+    mn = np.minimum(ax, ay)
+    t = (mn / mx).astype(np.float32)
     s = (t * t).astype(np.float32)
     c = _coeffs()
     p = np.full_like(t, c[0])
