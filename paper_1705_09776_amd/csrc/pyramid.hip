@@ -148,7 +148,9 @@ __global__ __launch_bounds__(256) void k_blur(const uint8_t* __restrict__ images
         const int gy0 = ty0 + grp * V - HALO;
         // A window inside the image (all but the top and bottom tiles) is
         // read with one 32-bit byte offset from the uniform plane base,
-        // advanced by the pitch per row; edge windows clamp every row.
+        // advanced by the pitch per row; edge windows clamp every row (a
+        // 24-bit multiply: rows and pitches are below 2^24, and a plane's
+        // bytes below 2^32, as sides are at most CDVS_MAX_SIDE).
         const bool inside = gy0 >= 0 && gy0 + V + 2 * HALO <= h;
         if constexpr (U8) {
             const uint8_t* base = images + job.src;
@@ -159,7 +161,8 @@ __global__ __launch_bounds__(256) void k_blur(const uint8_t* __restrict__ images
             } else {
 #pragma unroll
                 for (int r = 0; r < V + 2 * HALO; ++r)
-                    win[ii][r] = (float)base[(int64_t)clampi(gy0 + r, 0, h - 1) * job.src_pitch + gx];
+                    win[ii][r] = (float)base[__umul24((uint32_t)clampi(gy0 + r, 0, h - 1), (uint32_t)job.src_pitch) +
+                                             (uint32_t)gx];
             }
         } else {
             const char* base = reinterpret_cast<const char*>(pyr + job.plane0);
@@ -171,8 +174,8 @@ __global__ __launch_bounds__(256) void k_blur(const uint8_t* __restrict__ images
             } else {
 #pragma unroll
                 for (int r = 0; r < V + 2 * HALO; ++r)
-                    win[ii][r] =
-                        reinterpret_cast<const float*>(base)[(int64_t)clampi(gy0 + r, 0, h - 1) * job.pitch + gx];
+                    win[ii][r] = *reinterpret_cast<const float*>(
+                        base + (__umul24((uint32_t)clampi(gy0 + r, 0, h - 1), (uint32_t)job.pitch) + (uint32_t)gx) * 4u);
             }
         }
     }
