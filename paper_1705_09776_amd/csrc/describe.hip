@@ -58,9 +58,10 @@ __device__ __forceinline__ KpGeom keypoint_geometry(const float* pyr, const OctG
 
 // Angle of (x, y) in [0, 2 pi], 2 pi itself only by rounding for angles
 // just below it (both histograms take their bin index modulo the bin
-// count, so 2 pi falls into bin 0 as 0 does).  The octant symmetries of the arctangent
-// reduce the argument to t = min(|x|, |y|) / max(|x|, |y|) in [0, 1] (its
-// rounding, under 2 ulp, moves the angle by less than 1e-7 rad), where
+// count, so 2 pi falls into bin 0 as 0 does).  The octant symmetries of
+// the arctangent reduce the argument to t = min(|x|, |y|) / max(|x|, |y|)
+// in [0, 1] (its rounding, under 2 ulp, moves the angle by less than
+// 1e-7 rad), where
 // atan(t) is an odd polynomial t P(t^2) of degree 15 whose coefficients were
 // fitted here by (iteratively reweighted) least squares on Chebyshev nodes of
 // [0, 1]; in fp32 its error is below 2e-7 rad, and the reflections add at
@@ -353,8 +354,8 @@ __global__ __launch_bounds__(64 * kKpWaves) void k_describe(const float* __restr
                 const float cx0 = __builtin_amdgcn_fmed3f(floorf(fx), 0.f, 2.f);
                 const float cy0 = __builtin_amdgcn_fmed3f(floorf(fy), 0.f, 2.f);
                 const float tx = fx - cx0, ty = fy - cy0;
-                const float wx0 = fmaxf(0.f, 1.f - fabsf(tx));         // cell bx
-                const float wx1 = fmaxf(0.f, 1.f - fabsf(tx - 1.f));   // cell bx + 1
+                const float wx0 = fmaxf(0.f, 1.f - fabsf(tx));         // base cell column
+                const float wx1 = fmaxf(0.f, 1.f - fabsf(tx - 1.f));   // the column after it
                 const float wy0 = fmaxf(0.f, 1.f - fabsf(ty));
                 const float wy1 = fmaxf(0.f, 1.f - fabsf(ty - 1.f));
                 // base cell's first bin: (4 by + bx) x 9, exact in float
