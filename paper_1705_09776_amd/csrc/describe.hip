@@ -136,10 +136,12 @@ __device__ __forceinline__ void wave_sync() {
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
     __builtin_amdgcn_wave_barrier();
 }
-// Orientation histogram copy: 36 bins plus bin 36, which takes the share of
-// bin 0 that wraps around from bin 35 (folded into bin 0 at the end); the
-// odd stride also starts the copies on different banks.
-constexpr int kOriStride = kOriBins + 1;
+// Orientation histogram copy: 36 bins plus bins 36 and 37, which take the
+// shares of bins 0 and 1 that wrap around (from bin 35, and from an angle
+// of 2 pi, which rounding can give), folded into bins 0 and 1 at the end,
+// so no bin index is wrapped per pixel; the stride of 38 words starts the
+// eight copies on eight different banks.
+constexpr int kOriStride = kOriBins + 2;
 // Descriptor histogram copy: 4 x 4 cells of 9 bins, bin 8 taking the share
 // of orientation bin 0 that wraps around from bin 7 (folded into bin 0 at
 // the end, which leaves every integer sum unchanged), so that the eight
@@ -213,10 +215,9 @@ __global__ __launch_bounds__(64 * kKpWaves) void k_orient(const float* __restric
                 const float fb = ang * ((float)kOriBins / kTwoPi);
                 const float f0 = floorf(fb);
                 const float fr = fb - f0;
-                int b0 = (int)f0;
-                b0 = b0 >= kOriBins ? b0 - kOriBins : b0;
+                const int b0 = (int)f0;   // 0 .. 36 (36 only for an angle of 2 pi)
                 atomicAdd(hc + b0, (uint32_t)(wt - wt * fr + 0.5f));
-                atomicAdd(hc + b0 + 1, (uint32_t)(wt * fr + 0.5f));   // bin 36 is bin 0
+                atomicAdd(hc + b0 + 1, (uint32_t)(wt * fr + 0.5f));   // bins 36, 37 are bins 0, 1
             }
         }
     }
@@ -226,7 +227,7 @@ __global__ __launch_bounds__(64 * kKpWaves) void k_orient(const float* __restric
         uint32_t t = 0u;
 #pragma unroll
         for (int c = 0; c < kCopies; ++c)
-            t += hist[wave][c * kOriStride + b] + (b == 0 ? hist[wave][c * kOriStride + kOriBins] : 0u);
+            t += hist[wave][c * kOriStride + b] + (b < 2 ? hist[wave][c * kOriStride + kOriBins + b] : 0u);
         return (float)t / op.fix;
     };
     // every lane reads its bin and both neighbours from the summed copies
