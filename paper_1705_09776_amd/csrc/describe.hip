@@ -319,6 +319,11 @@ __global__ __launch_bounds__(64 * kKpWaves) void k_describe(const float* __restr
         const float R = dp.radius * g.s;
         const float R2 = R * R;
         const float icw = 1.f / (dp.cell * g.s);    // cell units
+        // rotation by -theta and the scale to cell units in one 2 x 2 matrix,
+        // the cell-grid centre (1.5, 1.5) added by the same multiply-adds
+        const float cti = ct * icw, sti = st * icw;
+        // theta in eighths of a turn
+        const float th8 = th * (8.f / kTwoPi);
         const float ws = dp.wsigma * g.s;
         // Gaussian weight in fixed-point units: fix exp(-d^2 / (2 ws^2)) =
         // 2^(d^2 nid + log2 fix), fix being a power of two
@@ -334,15 +339,15 @@ __global__ __launch_bounds__(64 * kKpWaves) void k_describe(const float* __restr
                 const float d2 = dx * dx + dy * dy;
                 if (!(d2 < R2)) continue;
                 const Nbrs nb = load_nbrs(g, u, v);
-                const float rx = (ct * dx + st * dy) * icw;
-                const float ry = (ct * dy - st * dx) * icw;
+                const float fx = fmaf(cti, dx, fmaf(sti, dy, 1.5f));    // cell units, grid from 0
+                const float fy = fmaf(cti, dy, fmaf(-sti, dx, 1.5f));
                 float mag, ang;
                 gradient(nb, mag, ang);
                 const float wt = mag * __builtin_amdgcn_exp2f(fmaf(d2, nid, lfix));
                 // Orientation relative to theta in eighths of a turn: ang - th
                 // lies in (-2 pi, 2 pi], and the bin is floor(fo) modulo 8
                 // (a mask by 7, right for either sign), so no wrap is needed.
-                const float fo = (ang - th) * (8.f / kTwoPi);
+                const float fo = fmaf(ang, 8.f / kTwoPi, -th8);
                 const float o0f = floorf(fo);
                 const float ao = fo - o0f, bo = 1.f - ao;
                 const int o0 = (int)o0f & 7;
@@ -351,7 +356,6 @@ __global__ __launch_bounds__(64 * kKpWaves) void k_describe(const float* __restr
                 // max(0, 1 - |f - c|): the usual 1 - a and a for the two cells
                 // around f, 0 for any other, so a base shifted by the clamp, or
                 // a cell outside the 4 x 4 grid, gets exactly its share.
-                const float fx = rx + 1.5f, fy = ry + 1.5f;
                 const float cx0 = __builtin_amdgcn_fmed3f(floorf(fx), 0.f, 2.f);
                 const float cy0 = __builtin_amdgcn_fmed3f(floorf(fy), 0.f, 2.f);
                 const float tx = fx - cx0, ty = fy - cy0;
