@@ -452,8 +452,10 @@ static void build_constants(cdvs_ctx* c) {
     }
     double sig[kScales];
     for (int k = 0; k < kScales; ++k) sig[k] = s0 * pow(2.0, k / 4.0);
-    make_beta(sig, c->det.beta);
-    for (int k = 0; k < kScales; ++k) c->det.sig2[k] = (float)(sig[k] * sig[k]);
+    float beta[kScales][4];
+    make_beta(sig, beta);
+    for (int k = 0; k < kScales; ++k)
+        for (int i = 0; i < 4; ++i) c->det.bsig[k][i] = (float)((double)beta[k][i] * sig[k] * sig[k]);
     c->det.lo = (float)sig[0];
     c->det.hi = (float)sig[kScales - 1];
     c->det.contrast = p.contrast;

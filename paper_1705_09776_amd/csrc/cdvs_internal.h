@@ -70,8 +70,9 @@ struct OctGeom {
 };
 
 struct DetParams {
-    float beta[kScales][4];  // alpha_i = sum_k beta[k][i] L_k
-    float sig2[kScales];     // sigma_k^2 (octave units)
+    // alpha_i = sum_k beta[k][i] L_k with L_k = sigma_k^2 lap_k, taken as
+    // sum_k bsig[k][i] lap_k: bsig[k][i] = sigma_k^2 beta[k][i] (octave units)
+    float bsig[kScales][4];
     float lo, hi;            // extremal scale range [sigma_0, sigma_4)
     float contrast;
     float edge_lim;          // (r+1)^2 / r

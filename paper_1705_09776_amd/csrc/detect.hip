@@ -68,13 +68,13 @@ __device__ __forceinline__ float lap5(float c, float up, float dn, float lf, flo
     return s;
 }
 
-// Adds scale k's normalised Laplacian to the ALP coefficients.
+// Adds scale k's normalised Laplacian sigma_k^2 lap to the ALP coefficients
+// (sigma_k^2 is folded into the fitting weights on the host).
 __device__ __forceinline__ void alpha_acc(float4& a, float lap, int k, const DetParams& dp) {
-    const float L = dp.sig2[k] * lap;
-    a.x = fmaf(dp.beta[k][0], L, a.x);
-    a.y = fmaf(dp.beta[k][1], L, a.y);
-    a.z = fmaf(dp.beta[k][2], L, a.z);
-    a.w = fmaf(dp.beta[k][3], L, a.w);
+    a.x = fmaf(dp.bsig[k][0], lap, a.x);
+    a.y = fmaf(dp.bsig[k][1], lap, a.y);
+    a.z = fmaf(dp.bsig[k][2], lap, a.z);
+    a.w = fmaf(dp.bsig[k][3], lap, a.w);
 }
 
 struct Cand {
