@@ -33,8 +33,8 @@ __device__ __forceinline__ float horner(const float4 a, float s) { return fmaf(f
 // s0 = q / A and s1 = C / q; when A = 0, q = -B and s1 is the linear root.
 // Both candidates are evaluated and the choice is made by selects (no
 // branches: every lane of a wave runs this), with correctly rounded
-// quotients (the extremal scale is ill-conditioned, so it is computed as
-// the fp32 reference computes it).
+// quotients (the extremal scale is ill-conditioned, so the quotients are
+// not replaced by reciprocal approximations).
 __device__ __forceinline__ bool alp_extremum(const float4 a, float lo, float hi, float& s_out, float& p_out,
                                              float& pss_out) {
     const float A = 3.f * a.w, B = 2.f * a.z, C = a.y;
@@ -59,7 +59,7 @@ __device__ __forceinline__ bool alp_extremum(const float4 a, float lo, float hi,
 }
 
 // 5-point Laplacian sum (up + down + left + right - 4 centre), in one fixed
-// order of operations shared by both detection kernels.
+// order of operations for the plain and the gated detection.
 __device__ __forceinline__ float lap5(float c, float up, float dn, float lf, float rt) {
     float s = up + dn;
     s = s + lf;
