@@ -51,11 +51,12 @@ __device__ __forceinline__ bool alp_extremum(const float4 a, float lo, float hi,
     const bool ok1 = real & (s1 >= lo) & (s1 < hi) & (p1 * pss1 < 0.f);
     const float a0 = fabsf(p0), a1 = fabsf(p1);
     const bool take1 = ok1 & (!ok0 | (a1 > a0) | ((a1 == a0) & (s1 < s0)));
-    const bool found = ok0 | ok1;
-    s_out = found ? (take1 ? s1 : s0) : 0.f;
-    p_out = found ? (take1 ? p1 : p0) : 0.f;
-    pss_out = found ? (take1 ? pss1 : pss0) : 0.f;
-    return found;
+    // without an extremum the outputs are left as they fall (possibly not
+    // finite): they then only feed this centre's own tests, which it fails
+    s_out = take1 ? s1 : s0;
+    p_out = take1 ? p1 : p0;
+    pss_out = take1 ? pss1 : pss0;
+    return ok0 | ok1;
 }
 
 // 5-point Laplacian sum (up + down + left + right - 4 centre), in one fixed
