@@ -194,11 +194,36 @@ struct StripRow {
     float g[kScales];
 };
 
-// Plane row y (clamped to the image) of this lane's column.
-__device__ __forceinline__ void load_row(const float* __restrict__ col, const DetTile& job, int y, StripRow& r) {
-    const float* p = col + (int64_t)clampi(y, 0, job.h - 1) * job.pitch;
+// The five planes of a strip's (image, octave): their bases are the same in
+// every lane and kept in scalar registers, and a lane reads a row as one
+// 32-bit byte offset from each (an octave's planes span less than 2^32
+// bytes, as sides are at most CDVS_MAX_SIDE), so a row costs one vector add
+// for its address instead of a 64-bit address per plane.
+struct StripPlanes {
+    const char* base[kScales];
+    uint32_t col4;   // this lane's (clamped) column, in bytes
+};
+
+__device__ __forceinline__ StripPlanes strip_planes(const float* __restrict__ pyr, const DetTile& job, int gx) {
+    StripPlanes sp;
+    // (the offset, not the pointer, goes through the scalar unit: a pointer
+    // rebuilt from an integer would lose its global address space)
 #pragma unroll
-    for (int k = 0; k < kScales; ++k) r.g[k] = p[(int64_t)k * job.plane_stride];
+    for (int k = 0; k < kScales; ++k) {
+        const uint64_t o = (uint64_t)(job.plane0 + (int64_t)k * job.plane_stride);
+        const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)o);
+        const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(o >> 32));
+        sp.base[k] = reinterpret_cast<const char*>(pyr + (int64_t)(((uint64_t)hi << 32) | lo));
+    }
+    sp.col4 = (uint32_t)clampi(gx, 0, job.w - 1) * 4u;
+    return sp;
+}
+
+// Plane row y (clamped to the image) of this lane's column.
+__device__ __forceinline__ void load_row(const StripPlanes& sp, const DetTile& job, int y, StripRow& r) {
+    const uint32_t off = (uint32_t)clampi(y, 0, job.h - 1) * (uint32_t)job.pitch * 4u + sp.col4;
+#pragma unroll
+    for (int k = 0; k < kScales; ++k) r.g[k] = *reinterpret_cast<const float*>(sp.base[k] + off);
 }
 
 // ALP coefficients of the middle row from three consecutive rows.
@@ -321,7 +346,7 @@ __device__ __forceinline__ void detect_strip(const float* __restrict__ pyr, cons
             if (!__ballot(rows_on != 0ull)) return;   // nothing active: the strip is not even loaded
         }
     }
-    const float* col = pyr + job.plane0 + clampi(gx, 0, job.w - 1);
+    const StripPlanes col = strip_planes(pyr, job, gx);
     // Plane rows live in a ring of kRing slots, row y in slot (y - y0 + 2) %
     // kRing, and coefficient rows in a ring of three, row y in slot
     // (y - y0 + 1) % 3.  Centre row y computes the coefficients of row y+1,
