@@ -151,7 +151,8 @@ constexpr int kDescCellBins = 9;
 constexpr int kDescStride = 16 * kDescCellBins + 1;
 
 // Walks the bounding box [u0, u0+bw) x [v0, ...) in row-major order, 64
-// pixels per step, without integer division in the loop.
+// pixels per step, without integer division in the loop; a lane is past the
+// box's last row exactly when its pixel index is past the box.
 struct BoxWalk {
     int u, v, du, dv, u1;
     __device__ __forceinline__ BoxWalk(int lane, int u0, int v0, int bw) {
@@ -203,7 +204,7 @@ __global__ __launch_bounds__(64 * kKpWaves) void k_orient(const float* __restric
         const int bw = u1 - u0 + 1, bh = v1 - v0 + 1;
         if (bw > 0 && bh > 0) {
             BoxWalk bwk(lane, u0, v0, bw);
-            for (int q = lane; q < bw * bh; q += 64, bwk.next(bw)) {
+            for (; bwk.v <= v1; bwk.next(bw)) {   // row-major: past the box once v > v1
                 const int u = bwk.u, v = bwk.v;
                 const float dx = (float)u - g.cx, dy = (float)v - g.cy;
                 const float d2 = dx * dx + dy * dy;
@@ -333,7 +334,7 @@ __global__ __launch_bounds__(64 * kKpWaves) void k_describe(const float* __restr
         const int bw = u1 - u0 + 1, bh = v1 - v0 + 1;
         if (bw > 0 && bh > 0) {
             BoxWalk bwk(lane, u0, v0, bw);
-            for (int q = lane; q < bw * bh; q += 64, bwk.next(bw)) {
+            for (; bwk.v <= v1; bwk.next(bw)) {   // row-major: past the box once v > v1
                 const int u = bwk.u, v = bwk.v;
                 const float dx = (float)u - g.cx, dy = (float)v - g.cy;
                 const float d2 = dx * dx + dy * dy;
@@ -359,10 +360,11 @@ __global__ __launch_bounds__(64 * kKpWaves) void k_describe(const float* __restr
                 const float cx0 = __builtin_amdgcn_fmed3f(floorf(fx), 0.f, 2.f);
                 const float cy0 = __builtin_amdgcn_fmed3f(floorf(fy), 0.f, 2.f);
                 const float tx = fx - cx0, ty = fy - cy0;
-                const float wx0 = fmaxf(0.f, 1.f - fabsf(tx));         // base cell column
-                const float wx1 = fmaxf(0.f, 1.f - fabsf(tx - 1.f));   // the column after it
+                // (max(0, 1 - |t - 1|) is the median of t, 2 - t and 0)
+                const float wx0 = fmaxf(0.f, 1.f - fabsf(tx));                    // base cell column
+                const float wx1 = __builtin_amdgcn_fmed3f(tx, 2.f - tx, 0.f);     // the column after it
                 const float wy0 = fmaxf(0.f, 1.f - fabsf(ty));
-                const float wy1 = fmaxf(0.f, 1.f - fabsf(ty - 1.f));
+                const float wy1 = __builtin_amdgcn_fmed3f(ty, 2.f - ty, 0.f);
                 // base cell's first bin: (4 by + bx) x 9, exact in float
                 const int cell0 = (int)fmaf(cy0, 4.f * kDescCellBins, cx0 * (float)kDescCellBins);
                 uint32_t* cell = hc + cell0 + o0;
