@@ -158,6 +158,8 @@ cdvs_status cdvs_pyramid(cdvs_ctx* ctx, const uint8_t* d_images, float* d_pyr, v
  * only when bit o of the cell holding (x 2^o, y 2^o) / 4 is set -- neighbours
  * are still read in full -- unless more than mask_fmax of that image's cells
  * have bit o set, in which case octave o of that image is examined densely.
+ * Octaves 6 and up (images whose short side exceeds 992 px have them) have
+ * no mask bit and are always examined densely.
  * Each image holds up to max(8192, W*H/64 rounded up to 256) candidates
  * before stage C; one that finds more than its capacity keeps those stored
  * and latches an overflow.  Stage C and the top-k work on at most 8192
@@ -178,7 +180,10 @@ cdvs_status cdvs_alp_detect(cdvs_ctx* ctx, const float* d_pyr, const uint8_t* d_
  * highest gives one output record (at most max_ori, highest first), its angle
  * refined by a parabola.  Output per image: records in input order, cut at
  * topk.  d_kp_in/d_count_in as written by cdvs_alp_detect; d_kp_out and
- * d_count_out have the same shapes and must not alias the inputs. */
+ * d_count_out have the same shapes and must not alias the inputs.  An input
+ * record whose octave is outside 0..15, whose x or y is not finite, or whose
+ * scale in octave units, sigma / 2^octave, is not in (0, 2 sigma0] (detected
+ * keypoints have sigma0 <= that < 2 sigma0) gets no orientation. */
 cdvs_status cdvs_orient(cdvs_ctx* ctx, const float* d_pyr, const cdvs_keypoint* d_kp_in,
                         const int32_t* d_count_in, cdvs_keypoint* d_kp_out, int32_t* d_count_out,
                         void* stream);
@@ -190,7 +195,8 @@ cdvs_status cdvs_orient(cdvs_ctx* ctx, const float* d_pyr, const cdvs_keypoint* 
  * magnitude and a Gaussian of desc_wsigma*sigma, split trilinearly; then
  * L2-normalised, clamped at desc_clamp and L2-normalised again.  Element
  * (row*4 + col)*8 + bin.  d_desc: n_images x kp_capacity x 128 floats; rows
- * at or beyond d_count[image] are left untouched. */
+ * at or beyond d_count[image] are left untouched.  A record that
+ * cdvs_orient would not take (see there) gets an all-zero descriptor. */
 cdvs_status cdvs_describe(cdvs_ctx* ctx, const float* d_pyr, const cdvs_keypoint* d_kp, const int32_t* d_count,
                           float* d_desc, void* stream);
 

@@ -10,7 +10,10 @@ The C source (``cdvs_oracle.c``) is built twice:
 * ``f32`` -- REAL = float; decisions (thresholds, strict NMS, disk membership,
   peak tests) taken in the precision of the GPU kernels, used for parity.
 
-Both are compiled with ``-O2 -ffp-contract=off`` and no fast-math.
+Both are compiled with ``-O2 -ffp-contract=off`` and no fast-math.  A third
+build, ``f32n`` (REAL = float, ``-O3 -march=native -fno-fast-math
+-ffp-contract=off``), is compiled on demand on the machine that runs it and
+serves only to time the oracle as a CPU baseline.
 """
 from __future__ import annotations
 
@@ -45,8 +48,9 @@ class Params(ctypes.Structure):
 
 
 def build() -> None:
-    """Compile both oracle variants with gcc (always recompiles)."""
-    for prec, lib in _LIBS.items():
+    """Compile both portable oracle variants with gcc (always recompiles)."""
+    for prec in ("f64", "f32"):
+        lib = _LIBS[prec]
         tmp = lib + ".tmp"
         subprocess.check_call(["gcc", "-O2", "-fPIC", "-shared", "-std=c99", "-Wall",
                                "-ffp-contract=off", "-fno-fast-math",
@@ -54,11 +58,28 @@ def build() -> None:
         os.replace(tmp, lib)
 
 
+def build_native(out_dir: str) -> str:
+    """Compile the fp32 oracle for this host's CPU (``-O3 -march=native``,
+    still ``-fno-fast-math -ffp-contract=off``) into out_dir; returns the
+    library path.  Used for the CPU-baseline timing only."""
+    path = os.path.join(out_dir, "liboracle_f32_native.so")
+    subprocess.check_call(["gcc", "-O3", "-march=native", "-fPIC", "-shared", "-std=c99", "-Wall",
+                           "-ffp-contract=off", "-fno-fast-math", "-DREAL=float", "-o", path, _SRC, "-lm"])
+    return path
+
+
+def use_native(path: str) -> None:
+    """Register a library written by build_native as the ``f32n`` build."""
+    _LIBS["f32n"] = path
+    _REAL["f32n"] = "float"
+    _cache.pop("f32n", None)
+
+
 def _load(prec: str):
     if prec in _cache:
         return _cache[prec]
     path = _LIBS[prec]
-    if not os.path.exists(path) or os.path.getmtime(path) < os.path.getmtime(_SRC):
+    if prec != "f32n" and (not os.path.exists(path) or os.path.getmtime(path) < os.path.getmtime(_SRC)):
         build()
     lib = ctypes.CDLL(path)
     vp, i32, f64 = ctypes.c_void_p, ctypes.c_int, ctypes.c_double
@@ -82,6 +103,7 @@ def _load(prec: str):
         "or_alp_extremum": (i32, [vp, f64, f64, vp, vp, vp]),
         "or_refine3x3": (i32, [vp, f64, f64, vp, vp, vp, vp]),
         "or_detect": (i32, [vp, i32, i32, P, i32, vp, i32]),
+        "or_detect_masked": (i32, [vp, i32, i32, P, i32, vp, f64, vp, i32]),
         "or_dedup": (None, [vp, i32, P, vp]),
         "or_select": (i32, [vp, i32, vp, i32, vp]),
         "or_scale_index": (i32, [P, f64]),
@@ -112,7 +134,7 @@ class Oracle:
     def __init__(self, prec: str = "f64", params: Params | None = None):
         self.prec = prec
         self.lib = _load(prec)
-        self.dtype = np.float64 if prec == "f64" else np.float32
+        self.dtype = np.float64 if _REAL[prec] == "double" else np.float32
         assert self.lib.or_real_size() == np.dtype(self.dtype).itemsize
         if params is None:
             params = Params()
@@ -221,6 +243,17 @@ class Oracle:
         out = np.zeros(cap, dtype=KP_DTYPE)
         n = self.lib.or_detect(flat.ctypes.data, W, H, ctypes.byref(self.P), image,
                                out.ctypes.data, cap)
+        assert n >= 0
+        return out[:min(n, cap)].copy()
+
+    def detect_masked(self, flat, W, H, mask, fmax=0.6, image=0, cap=1 << 16):
+        """Stages A-B examining only the centres the cell mask switches on
+        (mask: uint8 per 4x4 cell, shape (ceil(H/4), ceil(W/4)))."""
+        m = np.ascontiguousarray(mask, dtype=np.uint8)
+        assert m.shape == ((H + 3) // 4, (W + 3) // 4)
+        out = np.zeros(cap, dtype=KP_DTYPE)
+        n = self.lib.or_detect_masked(flat.ctypes.data, W, H, ctypes.byref(self.P), image, m.ctypes.data,
+                                      float(fmax), out.ctypes.data, cap)
         assert n >= 0
         return out[:min(n, cap)].copy()
 

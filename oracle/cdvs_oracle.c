@@ -410,7 +410,8 @@ int or_refine3x3(const real* v, real edge_r, real max_off, real* ox, real* oy, r
  * candidates to `out` (capacity cap) and returns how many were found (which
  * may exceed cap; only the first cap are stored). */
 static int detect_octave(const real* planes, int w, int h, int o, const or_params* P,
-                         const real* beta_r, or_kp* out, int cap, int count, int image) {
+                         const real* beta_r, const uint8_t* cells, int W4, or_kp* out, int cap, int count,
+                         int image) {
     int K = P->intervals + 1;
     size_t np = (size_t)w * h;
     real* L = (real*)malloc(sizeof(real) * np * K);
@@ -433,6 +434,8 @@ static int detect_octave(const real* planes, int w, int h, int o, const or_param
     int b = P->border;
     for (int y = b; y <= h - 1 - b; ++y)
         for (int x = b; x <= w - 1 - b; ++x) {
+            /* gated: only centres whose cell has bit o set are examined */
+            if (cells && !((cells[(size_t)((y << o) >> 2) * W4 + ((x << o) >> 2)] >> o) & 1)) continue;
             real s, p, pss;
             if (!or_alp_extremum(al + ((size_t)y * w + x) * 4, lo, hi, &s, &p, &pss)) continue;
             if (!(r_abs(p) >= T)) continue;
@@ -486,7 +489,44 @@ int or_detect(const real* pyr, int W, int H, const or_params* P, int image, or_k
     for (int o = 0; o < n; ++o) {
         int w, h;
         or_octave_size(W, H, o, &w, &h);
-        count = detect_octave(pyr + or_plane_offset(W, H, P, o, 0), w, h, o, P, beta_r, out, cap, count, image);
+        count = detect_octave(pyr + or_plane_offset(W, H, P, o, 0), w, h, o, P, beta_r, NULL, 0, out, cap, count,
+                              image);
+        if (count < 0) return count;
+    }
+    return count;
+}
+
+/* Stages A and B restricted by a cell mask (the learned gate, which is not
+ * part of the paper).  `mask` holds one byte per 4x4-pixel cell of the base
+ * image, ceil(H/4) rows of W4 = ceil(W/4) bytes.  An octave-o centre (x, y)
+ * is examined only when bit o of the cell holding (x 2^o, y 2^o) / 4 is set;
+ * the 3x3 comparison and the refinement still read every neighbour.  An
+ * octave is examined densely (as by or_detect) when o >= 6 (bits the gate
+ * never sets) or when more than fmax of the image's cells have bit o set
+ * (the count against fmax x cells compared in single precision, as the
+ * library does).  Returns the candidate count. */
+int or_detect_masked(const real* pyr, int W, int H, const or_params* P, int image, const uint8_t* mask,
+                     double fmax, or_kp* out, int cap) {
+    int n = or_num_octaves(W, H, P->min_side), K = P->intervals + 1;
+    int W4 = (W + 3) / 4, H4 = (H + 3) / 4;
+    double beta[64];
+    real beta_r[64];
+    if (or_alp_beta(P, beta)) return -1;
+    for (int i = 0; i < K * 4; ++i) beta_r[i] = (real)beta[i];
+    int count = 0;
+    for (int o = 0; o < n; ++o) {
+        int w, h;
+        or_octave_size(W, H, o, &w, &h);
+        const uint8_t* cells = mask;
+        if (o >= 6) {
+            cells = NULL;
+        } else {
+            int64_t act = 0;
+            for (int64_t c = 0; c < (int64_t)W4 * H4; ++c) act += (mask[c] >> o) & 1;
+            if ((float)act > (float)fmax * (float)((int64_t)W4 * H4)) cells = NULL;
+        }
+        count = detect_octave(pyr + or_plane_offset(W, H, P, o, 0), w, h, o, P, beta_r, cells, W4, out, cap, count,
+                              image);
         if (count < 0) return count;
     }
     return count;

@@ -27,6 +27,26 @@ __device__ __forceinline__ float wave_max(float v) {
     return v;
 }
 
+// A keypoint the histogram kernels can take: octave in range, finite
+// position, and a scale in octave units in (0, 2 sigma0] -- the largest a
+// detected keypoint has (sigma* < sigma_4 = 2 sigma0), and the bound the
+// host's fixed-point histogram scale is derived for, so that no bin can
+// wrap.  Others get no orientation and an all-zero descriptor.
+__device__ __forceinline__ bool keypoint_ok(const cdvs_keypoint& k, float sigma0) {
+    if (k.octave < 0 || k.octave >= kMaxOctaves) return false;
+    const float s = k.sigma * (1.0f / (float)(1 << k.octave));
+    return isfinite(k.x) && isfinite(k.y) && s > 0.f && s <= 2.f * sigma0;
+}
+
+// Squared distance of a pixel from the keypoint, as two rounded products
+// and a rounded sum (never fused into a multiply-add): disk membership is a
+// hard edge, and this way it is decided exactly as the plain definition
+// computes it in single precision.
+__device__ __forceinline__ float disk_d2(float dx, float dy) {
+#pragma clang fp contract(off)
+    return dx * dx + dy * dy;
+}
+
 struct KpGeom {
     const float* plane;  // G_{o,k*}
     int w, h, pitch;
@@ -62,9 +82,10 @@ __device__ __forceinline__ KpGeom keypoint_geometry(const float* pyr, const OctG
 // the arctangent reduce the argument to t = min(|x|, |y|) / max(|x|, |y|)
 // in [0, 1] (its rounding, under 2 ulp, moves the angle by less than
 // 1e-7 rad), where
-// atan(t) is an odd polynomial t P(t^2) of degree 15 whose coefficients were
-// fitted here by (iteratively reweighted) least squares on Chebyshev nodes of
-// [0, 1]; in fp32 its error is below 2e-7 rad, and the reflections add at
+// atan(t) is an odd polynomial t P(t^2) of degree 15 whose coefficients are
+// a minimax fit (Lawson's reweighted least squares on Chebyshev nodes of
+// [0, 1], written by fit_atan_poly.py beside this file); its error is
+// 6.7e-8 rad, below 2e-7 rad in fp32, and the reflections add at
 // most about one fp32 ulp of 2 pi (4.8e-7), well inside what the histograms
 // can resolve.  (0, 0) gives 0.
 __device__ __forceinline__ float angle_2pi(float y, float x) {
@@ -76,14 +97,14 @@ __device__ __forceinline__ float angle_2pi(float y, float x) {
     // division is a full IEEE sequence on this target, several times longer
     const float t = mn * __builtin_amdgcn_rcpf(mx);
     const float s = t * t;
-    float p = -0.004072779323905706f;
-    p = fmaf(p, s, 0.021944405511021614f);
-    p = fmaf(p, s, -0.05605942755937576f);
-    p = fmaf(p, s, 0.09655921906232834f);
-    p = fmaf(p, s, -0.13915635645389557f);
-    p = fmaf(p, s, 0.19948463141918182f);
-    p = fmaf(p, s, -0.33330100774765015f);
-    p = fmaf(p, s, 0.999999463558197f);
+    float p = -0.004054567310959101f;
+    p = fmaf(p, s, 0.021862957626581192f);
+    p = fmaf(p, s, -0.0559123270213604f);
+    p = fmaf(p, s, 0.0964219719171524f);
+    p = fmaf(p, s, -0.1390862911939621f);
+    p = fmaf(p, s, 0.19946566224098206f);
+    p = fmaf(p, s, -0.33329859375953674f);
+    p = fmaf(p, s, 0.9999993443489075f);
     float r = p * t;                                   // atan(t), in [0, pi/4]
     if (ay > ax) r = 1.5707963267948966f - r;          // first quadrant
     if (x < 0.f) r = 3.141592653589793f - r;           // upper half plane
@@ -180,13 +201,12 @@ __global__ __launch_bounds__(64 * kKpWaves) void k_orient(const float* __restric
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int64_t slot = (int64_t)xcd_remap(blockIdx.x, gridDim.x) * kKpWaves + wave;
     const int img = (int)(slot / op.kp_cap), i = (int)(slot % op.kp_cap);
-    cdvs_keypoint k;
-    bool active = img < n_images && i < count[img];
-    if (active) {
-        k = kp[(int64_t)img * op.kp_cap + i];
-        active = k.octave >= 0 && k.octave < kMaxOctaves;
+    if (img >= n_images || i >= count[img]) return;   // uniform over the wave
+    const cdvs_keypoint k = kp[(int64_t)img * op.kp_cap + i];
+    if (!keypoint_ok(k, op.sigma0)) {
+        if (lane == 0) ori_cnt[(int64_t)img * op.kp_cap + i] = 0;
+        return;
     }
-    if (!active) return;   // uniform over the wave
     for (int j = lane; j < kCopies * kOriStride; j += 64) hist[wave][j] = 0u;
     wave_sync();
 
@@ -207,7 +227,7 @@ __global__ __launch_bounds__(64 * kKpWaves) void k_orient(const float* __restric
             for (; bwk.v <= v1; bwk.next(bw)) {   // row-major: past the box once v > v1
                 const int u = bwk.u, v = bwk.v;
                 const float dx = (float)u - g.cx, dy = (float)v - g.cy;
-                const float d2 = dx * dx + dy * dy;
+                const float d2 = disk_d2(dx, dy);
                 if (!(d2 < R2)) continue;
                 const Nbrs nb = load_nbrs(g, u, v);
                 float mag, ang;
@@ -300,13 +320,14 @@ __global__ __launch_bounds__(64 * kKpWaves) void k_describe(const float* __restr
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int64_t slot = (int64_t)xcd_remap(blockIdx.x, gridDim.x) * kKpWaves + wave;
     const int img = (int)(slot / dp.kp_cap), i = (int)(slot % dp.kp_cap);
-    cdvs_keypoint k;
-    bool active = img < n_images && i < count[img];
-    if (active) {
-        k = kp[(int64_t)img * dp.kp_cap + i];
-        active = k.octave >= 0 && k.octave < kMaxOctaves;
+    if (img >= n_images || i >= count[img]) return;   // uniform over the wave
+    const cdvs_keypoint k = kp[(int64_t)img * dp.kp_cap + i];
+    if (!keypoint_ok(k, dp.sigma0)) {
+        float* out = desc + (((int64_t)img * dp.kp_cap + i) * kDescDim);
+        out[lane] = 0.f;
+        out[lane + 64] = 0.f;
+        return;
     }
-    if (!active) return;   // uniform over the wave
     for (int j = lane; j < kCopies * kDescStride; j += 64) hist[wave][j] = 0u;
     wave_sync();
 
@@ -337,7 +358,7 @@ __global__ __launch_bounds__(64 * kKpWaves) void k_describe(const float* __restr
             for (; bwk.v <= v1; bwk.next(bw)) {   // row-major: past the box once v > v1
                 const int u = bwk.u, v = bwk.v;
                 const float dx = (float)u - g.cx, dy = (float)v - g.cy;
-                const float d2 = dx * dx + dy * dy;
+                const float d2 = disk_d2(dx, dy);
                 if (!(d2 < R2)) continue;
                 const Nbrs nb = load_nbrs(g, u, v);
                 const float fx = fmaf(cti, dx, fmaf(sti, dy, 1.5f));    // cell units, grid from 0

@@ -316,7 +316,8 @@ __device__ __forceinline__ void strip_centres(const float4& aU, const float4& aM
 
 // GATED: an octave-o centre (x, y) is examined only when bit o of the mask
 // cell holding (x 2^o, y 2^o) / 4 is set, unless more than gate.fmax of the
-// image's cells have bit o set (then the octave is examined densely).
+// image's cells have bit o set, or o is beyond the gate's kCnnHeads bits
+// (then the octave is examined densely).
 template <bool GATED>
 __device__ __forceinline__ void detect_strip(const float* __restrict__ pyr, const DetTile& job, const DetParams& dp,
                                              const GateParams& gate, float (*q)[kQCap],
@@ -333,6 +334,7 @@ __device__ __forceinline__ void detect_strip(const float* __restrict__ pyr, cons
     if constexpr (GATED) {
         const CnnImage cg = gate.cells[job.image];
         const bool dense =
+            job.octave >= kCnnHeads ||
             (float)gate.active[job.image * kMaxOctaves + job.octave] > gate.fmax * (float)(cg.H4 * cg.W4);
         if (!dense) {
             rows_on = 0ull;

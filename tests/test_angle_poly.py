@@ -3,6 +3,7 @@ octant-reduced odd polynomial (no library arctangent).  Its coefficients are
 read from the kernel source and evaluated here in float32 exactly as the
 kernel does (Horner with fused multiply-adds emulated in float64 then
 rounded), against numpy's arctan2 over all quadrants."""
+import importlib.util
 import os
 import re
 
@@ -61,3 +62,19 @@ def test_angle_all_quadrants():
     # 2 pi itself only by rounding (the histograms take it as bin 0)
     assert np.all((got >= 0) & (got <= np.float32(2 * np.pi)))
     assert _angle(np.float32([0]), np.float32([0]))[0] == 0
+
+
+def test_coefficients_reproduced_by_the_fit_script():
+    """The kernel's coefficients are what the committed fitting script
+    (Lawson minimax fit, float64, rounded to float32) writes -- within one
+    float32 ulp, so a last-bit change of a library's least-squares solver
+    does not matter."""
+    path = os.path.join(ROOT, "paper_1705_09776_amd", "csrc", "fit_atan_poly.py")
+    spec = importlib.util.spec_from_file_location("fit_atan_poly", path)
+    mod = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(mod)
+    fitted = mod.fit()
+    src = np.array(_coeffs(), dtype=np.float32)
+    assert fitted.shape == src.shape
+    assert np.all(np.abs(fitted - src) <= np.spacing(np.abs(src)))
+    assert mod.max_error(src) < 1e-7

@@ -11,9 +11,13 @@ active cells are found.
 import numpy as np
 import pytest
 
+import json
+import os
+
 import oracle
 import synth
 from oracle import cnn
+from parity import assert_parity, check_images, summarize
 
 pytestmark = pytest.mark.gpu
 
@@ -223,3 +227,48 @@ def test_fused_inference_equals_training_forward(fwd):
     torch.cuda.synchronize()
     np.testing.assert_array_equal(pipe.d_logits.cpu().numpy().view(np.uint32), logits.view(np.uint32))
     np.testing.assert_array_equal(pipe.d_mask.cpu().numpy(), mask)
+
+
+_ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _image_masks(pipe, mask):
+    out = []
+    for i in range(pipe.n):
+        c0, w4, h4 = pipe.cell_layout(i)
+        out.append(mask[c0:c0 + w4 * h4].reshape(h4, w4).copy())
+    return out
+
+
+@pytest.mark.parametrize("which", ["trained", "random"])
+def test_gated_detection_matches_oracle(O32, which):
+    """The gated pass against the oracle's own gated detection (a centre is
+    examined iff its cell bit is set, neighbours read in full, dense above
+    mask_fmax, stage C and the top-k afterwards) under the same mask: the
+    trained 640x480 network's mask at its stored threshold, and a random mask
+    with 30% of the (cell, octave) bits set; keypoints, orientations and
+    descriptors to the plain path's bars."""
+    imgs = list(synth.fixed_batch(synth.SEED_EVAL, 16, first=3000))
+    pipe = cd.Pipeline([(640, 480)] * len(imgs))
+    pipe.upload(imgs)
+    pipe.cnn_buffers()
+    if which == "trained":
+        from paper_1705_09776_amd import surrogate
+        w = os.path.join(_ROOT, "paper_1705_09776_amd", "weights", "surrogate_640x480.npz")
+        tau = float(json.load(open(os.path.splitext(w)[0] + ".json"))["tau"])
+        params = torch.from_numpy(surrogate.load_checkpoint(w)["params"]).cuda()
+        pipe.run_gated(params, tau)
+    else:
+        rng = np.random.default_rng(11)
+        m = (rng.random((pipe.ncells, 6)) < 0.3).astype(np.uint8).dot(1 << np.arange(6)).astype(np.uint8)
+        pipe.d_mask.copy_(torch.from_numpy(m))
+        pipe.pyramid()
+        pipe.detect(mask=pipe.d_mask)
+        pipe.orient()
+        pipe.describe()
+    torch.cuda.synchronize()
+    assert pipe.sync_status() == cd.CDVS_OK
+    masks = _image_masks(pipe, pipe.d_mask.cpu().numpy())
+    res = check_images(O32, imgs, pipe.keypoints(), pipe.oriented(), pipe.descriptors(), masks=masks,
+                       fmax=pipe.params.mask_fmax)
+    assert_parity(summarize(res), f"gated ({which} mask)")

@@ -4,7 +4,11 @@ Bars:
   * keypoints: >= 99% of oracle keypoints have a GPU keypoint in the same image
     and octave within 0.5 base-image px, and the reverse;
   * descriptors: over matched oriented keypoints (|d theta| <= 1e-2 rad),
-    >= 99% have max |d| <= 1e-3 after normalisation;
+    every descriptor is within max |d| <= 1e-3 of the oracle's after
+    normalisation -- end to end, or, where the two keypoints' fp32 geometry
+    differs enough to move a pixel across the disk edge, at the GPU's own
+    (x, y, sigma, theta) (tests/parity.py describe_check); at most 1e-4 of
+    the pairs may miss both (an fp32 tie in the nearest-scale-image choice);
   * pyramid planes: max |d| <= 1e-3 on the 0..255 scale against the fp64
     oracle (fp32 sums of <= 25 taps per pass, two passes, values <= 255:
     the accumulated rounding stays near 1e-4).
@@ -18,7 +22,7 @@ import pytest
 
 import oracle
 import synth
-from parity import match, rates
+from parity import KP_RATE, assert_parity, check_images, describe_check, match, rates, summarize
 
 pytestmark = pytest.mark.gpu
 
@@ -28,7 +32,6 @@ if not torch.cuda.is_available():
 
 import paper_1705_09776_amd as cd  # noqa: E402
 
-KP_RATE = 0.99
 DESC_TOL = 1e-3
 DESC_RATE = 0.99
 PLANE_TOL = 1e-3
@@ -102,36 +105,18 @@ def test_keypoints_match_oracle(single, single_oracle):
     assert np.all(np.diff(np.abs(got["p"])) <= 0)
 
 
-def _desc_agreement(ref_kp, ref_desc, kp, desc):
-    r1, r2, pairs = rates(ref_kp, kp, oriented=True)
-    err = np.array([np.abs(ref_desc[i] - desc[j]).max() for i, j in pairs])
-    return r1, r2, err
-
-
-def test_descriptors_match_oracle(single, single_oracle, O64, O32):
-    """End to end.  sigma* and the refined position carry fp32 rounding of
-    ~1e-3 (relative) and ~1e-3 px, which moves the hard 6 sigma disk edge of
-    the descriptor across a pixel centre for about one keypoint in ten; the
-    oracle's own fp32 and fp64 builds disagree that way too, while at the same
-    keypoint geometry they agree to ~1e-6.  So end to end the GPU must agree
-    with the fp32 oracle at least as well as the fp32 oracle agrees with the
-    fp64 oracle (less 3 points), every matched pair must stay within one
-    boundary-pixel flip (5e-2), and the 1e-3 bar is applied per stage (next
-    test), where the keypoint geometry is shared."""
+def test_descriptors_match_oracle(single, single_oracle, O32):
+    """End to end on the single image: every matched descriptor within 1e-3
+    of the oracle's, or, where it is not, within 1e-3 of the oracle's
+    descriptor at the GPU keypoint's own geometry."""
     img, pipe = single
-    _, ori, desc, _ = single_oracle
+    _, ori, desc, flat = single_oracle
     got = pipe.oriented()[0]
     gdesc = pipe.descriptors()[0]
-    r_ref, r_got, err = _desc_agreement(ori, desc, got, gdesc)
-    k64, d64, _ = O64.run(img)
-    _, _, self_err = _desc_agreement(k64, d64, ori, desc)
-    frac, frac_self = np.mean(err <= DESC_TOL), np.mean(self_err <= DESC_TOL)
-    print(f"oriented match: oracle->gpu {r_ref:.4f}, gpu->oracle {r_got:.4f}")
-    print(f"descriptor max|d| <= 1e-3: gpu-vs-oracle32 {frac:.4f}, oracle32-vs-oracle64 {frac_self:.4f}; "
-          f"max {err.max():.2e} p99.9 {np.quantile(err, 0.999):.2e} mean {err.mean():.2e}")
-    assert r_ref >= KP_RATE and r_got >= KP_RATE
-    assert frac >= frac_self - 0.03
-    assert err.max() <= 5e-2 and err.mean() <= 1e-3
+    d = describe_check(O32, flat, 640, 480, ori, desc, got, gdesc)
+    d.update(r1=1.0, r2=1.0, n_ref=1, n_got=1)
+    assert_parity(summarize([d]), "single image")
+    assert d["q1"] >= KP_RATE and d["q2"] >= KP_RATE
     np.testing.assert_allclose(np.linalg.norm(gdesc, axis=1), 1.0, atol=1e-5)
     assert gdesc.min() >= 0
 
@@ -168,10 +153,9 @@ def test_orient_and_describe_on_oracle_keypoints(single, single_oracle, O32):
     assert np.mean(err <= DESC_TOL) >= DESC_RATE
 
 
-def test_full_batch_sampled(O32):
-    """256 x 640x480 in one context (the benchmark's launch configuration);
-    sampled images are checked against the oracle, all of them for the
-    invariants that hold at any size."""
+def test_full_batch_every_image(O32):
+    """256 x 640x480 in one context (the benchmark's launch configuration),
+    every image against the oracle."""
     n = 256
     imgs = synth.fixed_batch(synth.SEED_BATCH, n)
     pipe = _run(list(imgs))
@@ -181,14 +165,7 @@ def test_full_batch_sampled(O32):
         assert np.all(kps[i]["image"] == i)
         assert np.all(np.diff(np.abs(kps[i]["p"])) <= 0)
         np.testing.assert_allclose(np.linalg.norm(descs[i], axis=1), 1.0, atol=1e-5)
-    for i in (0, 97, 255):
-        sel, ori, desc, _ = _oracle_stages(O32, imgs[i])
-        r1, r2, _ = rates(sel, kps[i])
-        q1, q2, err = _desc_agreement(ori, desc, oris[i], descs[i])
-        print(f"image {i}: kp {r1:.4f}/{r2:.4f} ori {q1:.4f}/{q2:.4f} desc<=1e-3 {np.mean(err <= DESC_TOL):.4f} "
-              f"max {err.max():.2e}")
-        assert min(r1, r2, q1, q2) >= KP_RATE
-        assert err.max() <= 5e-2 and err.mean() <= 1e-3
+    assert_parity(summarize(check_images(O32, list(imgs), kps, oris, descs)), "256-image batch")
 
 
 def test_ragged_batch_equals_single_runs(O32):
@@ -316,10 +293,10 @@ def test_scale_tile_variants_identical(tmp_path):
     assert len(json.load(open(bad))) == 1
 
 
-def test_ragged_1024_sampled(O32):
+def test_ragged_1024_every_image(O32):
     """The uneven-size workload at its full size (1024 images, one packed
-    context, captured graph, autotuned tile shape): invariants on every
-    image, oracle parity on sampled ones."""
+    context, captured graph, autotuned tile shape), every image against the
+    oracle."""
     imgs = synth.ragged_batch(synth.SEED_RAGGED, 1024)
     pipe = cd.Pipeline([(im.shape[1], im.shape[0]) for im in imgs])
     pipe.upload(imgs)
@@ -334,14 +311,7 @@ def test_ragged_1024_sampled(O32):
         assert np.all(kps[i]["image"] == i)
         assert np.all(np.diff(np.abs(kps[i]["p"])) <= 0)
         np.testing.assert_allclose(np.linalg.norm(descs[i], axis=1), 1.0, atol=1e-5)
-    for i in (0, 517, 1023):
-        sel, ori, desc, _ = _oracle_stages(O32, imgs[i])
-        r1, r2, _ = rates(sel, kps[i])
-        q1, q2, err = _desc_agreement(ori, desc, oris[i], descs[i])
-        print(f"ragged image {i} {imgs[i].shape}: kp {r1:.4f}/{r2:.4f} ori {q1:.4f}/{q2:.4f} "
-              f"desc<=1e-3 {np.mean(err <= DESC_TOL):.4f}")
-        assert min(r1, r2, q1, q2) >= KP_RATE
-        assert err.max() <= 5e-2 and err.mean() <= 1e-3
+    assert_parity(summarize(check_images(O32, imgs, kps, oris, descs)), "1024-image ragged batch")
 
 
 def test_misaligned_pyramid_rejected():
@@ -474,3 +444,51 @@ def test_detect_launch_forms_identical(gated):
         assert len(a) == len(b) > 0
         for f in ("x", "y", "sigma", "p", "octave", "ix", "iy"):
             np.testing.assert_array_equal(a[f], b[f])
+
+
+def test_keypoints_outside_the_histogram_bounds(single, single_oracle):
+    """Caller-supplied records the histogram kernels cannot take (scale in
+    octave units above 2 sigma0 -- the bound the fixed-point histograms are
+    sized for --, zero scale, a non-finite position, an octave out of range)
+    get no orientation and an all-zero descriptor; a valid record among them
+    is unaffected."""
+    img, _ = single
+    pipe = _run([img])
+    sel = single_oracle[0]
+    good = sel[0]
+    rec = np.zeros((1, pipe.kp_capacity), dtype=cd.KP_DTYPE)
+
+    def put(j, **kw):
+        for f in ("x", "y", "sigma", "p", "rho", "octave", "ix", "iy"):
+            rec[f][0, j] = good[f]
+        for f, v in kw.items():
+            rec[f][0, j] = v
+
+    o = int(good["octave"])
+    put(0)
+    put(1, sigma=3.3 * 2 ** o)
+    put(2, sigma=0.0)
+    put(3, x=np.float32("nan"))
+    put(4, octave=20)
+    put(5)
+    pipe.d_kp.copy_(torch.from_numpy(rec.view(np.int32).reshape(1, pipe.kp_capacity, 12)))
+    pipe.d_count.fill_(6)
+    pipe.d_kp_ori.zero_()
+    pipe.orient()
+    torch.cuda.synchronize()
+    ori = pipe.oriented()[0]
+    n1 = len(ori) // 2
+    assert len(ori) == 2 * n1 and n1 >= 1
+    np.testing.assert_array_equal(ori["x"][:n1], ori["x"][n1:])
+    # the same records as oriented input to the descriptor kernel
+    for j in range(6):
+        rec["theta"][0, j] = 0.5
+    pipe.d_kp_ori.copy_(torch.from_numpy(rec.view(np.int32).reshape(1, pipe.kp_capacity, 12)))
+    pipe.d_count_ori.fill_(6)
+    pipe.d_desc.fill_(7.0)
+    pipe.describe()
+    torch.cuda.synchronize()
+    d = pipe.descriptors()[0]
+    assert abs(np.linalg.norm(d[0]) - 1) < 1e-5
+    np.testing.assert_array_equal(d[0], d[5])
+    assert np.all(d[1:5] == 0)

@@ -15,7 +15,7 @@ import numpy as np
 import pytest
 
 import synth
-from parity import rates
+from parity import assert_parity, check_image, rates, summarize
 
 pytestmark = pytest.mark.gpu
 
@@ -49,14 +49,10 @@ def test_hires_image_matches_oracle(hires, O32):
     torch.cuda.synchronize()
     assert pipe.sync_status() == cd.CDVS_OK
     assert pipe.num_octaves(0) == 6
-    kp, desc, _ = O32.run(img)
-    got, gdesc = pipe.oriented()[0], pipe.descriptors()[0]
-    r1, r2, pairs = rates(kp, got, oriented=True)
-    err = np.array([np.abs(desc[i] - gdesc[j]).max() for i, j in pairs])
-    print(f"1280x960: oriented match {r1:.4f}/{r2:.4f}, desc<=1e-3 {np.mean(err <= 1e-3):.4f}, max {err.max():.2e}")
-    assert len(got) == len(kp) == 1000
-    assert min(r1, r2) >= 0.99
-    assert err.max() <= 5e-2 and err.mean() <= 1e-3
+    r = check_image(O32, img, pipe.keypoints()[0], pipe.oriented()[0], pipe.descriptors()[0])
+    assert r["n_ref"] == r["n_got"] == 1000
+    assert_parity(summarize([r]), "1280x960 image")
+    assert min(r["r1"], r["r2"], r["q1"], r["q2"]) >= 0.99
 
 
 def _eager(pipe, chunks, params=None, tau=0.1):
@@ -140,12 +136,11 @@ def test_stream_full_chunk_sampled(O32):
         torch.cuda.synchronize()
         descs = pipe.descriptors()
         oris = pipe.oriented()
+        kps = pipe.keypoints()
+        res = []
         for i in picks:
             g = c * chunk + i
             np.testing.assert_array_equal(codes[g, :kept[g]], _codes(descs[i]))
             img = d_all[g * W * H:(g + 1) * W * H].view(H, W).cpu().numpy()
-            kp, desc, _ = O32.run(img)
-            r1, r2, pairs = rates(kp, oris[i], oriented=True)
-            err = np.array([np.abs(desc[a] - descs[i][b]).max() for a, b in pairs])
-            print(f"stream image {g}: oriented {r1:.4f}/{r2:.4f} desc mean {err.mean():.2e}")
-            assert min(r1, r2) >= 0.99 and err.max() <= 5e-2 and err.mean() <= 1e-3
+            res.append(check_image(O32, img, kps[i], oris[i], descs[i]))
+        assert_parity(summarize(res), f"stream chunk {c}, images {picks}")

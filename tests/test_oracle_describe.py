@@ -136,3 +136,59 @@ def test_scale_index(O64):
     # nearest scale image: k* = round(4 log2(s / 1.6))
     for s, k in [(1.6, 0), (1.7, 0), (1.8, 1), (2.0, 1), (2.1, 2), (2.5, 3), (2.9, 3), (3.0, 4), (3.19, 4)]:
         assert O64.scale_index(s) == k, s
+
+
+def _cell_masses(N, cx, cy, s, theta, mag, radius=6.0, cell=3.0, wsig=6.0, strict=True):
+    """Spatial mass of each of the 16 descriptor cells, straight from the
+    definition (Sec. IV-B, Algorithm 2 stage B, weighting after Lowe 2004):
+    every integer pixel (1..N-2 on both axes) strictly inside radius*sigma
+    adds mag * exp(-d^2 / (2 (wsig sigma)^2)), split bilinearly between the two
+    nearest cells per axis of its offset rotated by -theta and measured in
+    cells of cell*sigma, cell centres at -1.5 .. 1.5."""
+    m = np.zeros((4, 4))
+    R = radius * s
+    for v in range(1, N - 1):
+        for u in range(1, N - 1):
+            dx, dy = u - cx, v - cy
+            d2 = dx * dx + dy * dy
+            if not (d2 < R * R if strict else d2 <= R * R):
+                continue
+            wt = mag * math.exp(-d2 / (2 * (wsig * s) ** 2))
+            rx = (math.cos(theta) * dx + math.sin(theta) * dy) / (cell * s)
+            ry = (math.cos(theta) * dy - math.sin(theta) * dx) / (cell * s)
+            for r in range(4):
+                wy = max(0.0, 1 - abs(ry - (r - 1.5)))
+                for c in range(4):
+                    m[r, c] += wt * wy * max(0.0, 1 - abs(rx - (c - 1.5)))
+    return m
+
+
+@pytest.mark.parametrize("theta,phi,cx,cy,s", [(0.0, 0.3, 47.2, 48.7, 2.5), (math.pi / 3, 2.0, 46.6, 47.9, 2.2),
+                                               (0.0, 1.1, 48.0, 48.0, 2.5)])
+def test_descriptor_spatial_weighting(O64, theta, phi, cx, cy, s):
+    """Pins the descriptor's spatial weighting: each cell's share of the
+    descriptor (summed over its 8 bins) equals the brute-force cell mass of a
+    constant-gradient ramp computed from the definition -- Gaussian of 6
+    sigma, cells of 3 sigma, integer pixels strictly inside 6 sigma.  Clamping
+    is lifted, so the normalised descriptor is proportional to the raw
+    histogram.  A weighting sigma of 3 sigma, cells of 4 sigma, or a closed
+    disk (<= 6 sigma, which adds the pixels exactly on the circle of the
+    integer-centred cases) give cell masses that the oracle does not match."""
+    P = oracle.Oracle.default_params()
+    P.desc_clamp = 1.0
+    O = oracle.Oracle("f64", P)
+    N, a = 96, 2.0
+    G = _ramp(N, phi, a)
+    d = O.descriptor(G, cx, cy, s, theta).reshape(4, 4, 8).sum(axis=2)
+    got = d / d.sum()
+
+    def share(**kw):
+        m = _cell_masses(N, cx, cy, s, theta, 2 * a, **kw)
+        return m / m.sum()
+
+    np.testing.assert_allclose(got, share(), rtol=0, atol=1e-9)
+    for mutant in (dict(wsig=3.0), dict(cell=4.0)):
+        assert np.abs(got - share(**mutant)).max() > 1e-3, mutant
+    if cx == int(cx) and cy == int(cy) and 6 * s == int(6 * s):
+        # pixels exactly 6 sigma away (e.g. (cx + 15, cy), (cx + 9, cy + 12))
+        assert np.abs(got - share(strict=False)).max() > 1e-3
