@@ -246,6 +246,46 @@ int32_t cdvs_tune_get(const cdvs_ctx* ctx, int32_t kernel);
 cdvs_status cdvs_tune_set(cdvs_ctx* ctx, int32_t kernel, int32_t variant);
 
 /* ---------------------------------------------------------------------- */
+/* Global aggregation: SCFV (Sec. III-D, Eqs. (6)-(8); Sec. IV-C, Eqs. (9)-(14)) */
+/* ---------------------------------------------------------------------- */
+#define CDVS_SCFV_COMPONENTS 512
+#define CDVS_SCFV_DIM 32
+
+/* The aggregation model, device buffers of float32 owned by the caller:
+ * PCA mean (128) and matrix (32 x 128, row r = principal direction r), and
+ * a diagonal GMM of CDVS_SCFV_COMPONENTS components: weights (positive, sum
+ * 1), means and variances (positive), each components x 32 row-major.  The
+ * PCA mean must be 16-byte aligned. */
+typedef struct {
+    const float* d_pca_mean;
+    const float* d_pca_matrix;
+    const float* d_weights;
+    const float* d_means;
+    const float* d_variances;
+} cdvs_scfv_model;
+
+/* Scalable compressed Fisher vector of each image's descriptors: the first
+ * d_count[image] rows of d_desc[image] (as cdvs_describe writes them:
+ * n_images x kp_capacity x 128, 16-byte aligned; counts clamped to
+ * 0..kp_capacity) are projected by the PCA, x_t = A (d_t - m), and
+ * aggregated over the GMM: posteriors gamma_t(i) (Eq. (6)), then per
+ * component i and dimension k
+ *   d_gm[image][i][k] = sum_t gamma_t(i) (x_tk - mu_ik) / sigma_ik / (K sqrt(w_i))           (Eq. (7))
+ *   d_gv[image][i][k] = sum_t gamma_t(i) ((x_tk - mu_ik)^2 / sigma_ik^2 - 1) / (K sqrt(2 w_i))
+ * (K = the image's count; all zero when K = 0), computed in the matrix form
+ * of Eqs. (10), (12), (14) on FP32 matrix cores;
+ *   d_delta[image][i] = population standard deviation of d_gm[image][i][.] (Eq. (8));
+ *   d_order[image][0..511] = components by delta, descending (ties: lower index
+ *     first) -- the order in which a bit budget keeps them;
+ *   d_bits[image][i][0], [1] = sign bits of d_gm[image][i][.] and
+ *     d_gv[image][i][.], bit k set when entry k is positive.
+ * Shapes: d_gm, d_gv n_images x 512 x 32 floats; d_delta n_images x 512;
+ * d_order n_images x 512 int32; d_bits n_images x 512 x 2 uint32.  Uses
+ * 196 KB of context scratch (so calls on one context must not overlap). */
+cdvs_status cdvs_scfv(cdvs_ctx* ctx, const cdvs_scfv_model* model, const float* d_desc, const int32_t* d_count,
+                      float* d_gm, float* d_gv, float* d_delta, int32_t* d_order, uint32_t* d_bits, void* stream);
+
+/* ---------------------------------------------------------------------- */
 /* Surrogate candidate mask (a small learned CNN; not from the paper).       */
 /* ---------------------------------------------------------------------- */
 /* Each base image is seen as H4 x W4 cells of 4x4 pixels (H4 = ceil(H/4),
@@ -377,6 +417,7 @@ typedef enum {
     CDVS_KERNEL_DESCRIBE,     /* 4x4x8 descriptors */
     CDVS_KERNEL_CNN_FORWARD,  /* surrogate CNN: four convolutions and the head */
     CDVS_KERNEL_MASK_COUNT,   /* active cells of a gating mask */
+    CDVS_KERNEL_SCFV,         /* SCFV aggregation (model constants + one workgroup per image) */
     CDVS_KERNEL_COUNT
 } cdvs_kernel_id;
 

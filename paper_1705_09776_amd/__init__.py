@@ -71,14 +71,21 @@ EXPORTS = ["cdvs_default_params", "cdvs_validate", "cdvs_ctx_create", "cdvs_ctx_
            "cdvs_graph_capture", "cdvs_graph_launch", "cdvs_profile_enable", "cdvs_profile_read",
            "cdvs_cnn_cells", "cdvs_cnn_cell_layout", "cdvs_cnn_forward", "cdvs_cnn_labels", "cdvs_cnn_backward",
            "cdvs_cnn_adam", "cdvs_autotune", "cdvs_tune_get", "cdvs_tune_set",
-           "cdvs_stream", "cdvs_standin_consume"]
+           "cdvs_stream", "cdvs_standin_consume", "cdvs_scfv"]
 TUNE_VARIANTS = 4
 DETECT_VARIANTS = 2
 
 KERNEL_SCALES = 1
 KERNEL_DETECT = 3
 KERNEL_NAMES = ["preblur", "scales", "clear", "detect", "finalize", "orient", "orient_compact", "describe",
-                "cnn_forward", "mask_count"]
+                "cnn_forward", "mask_count", "scfv"]
+SCFV_COMPONENTS = 512
+SCFV_DIM = 32
+
+
+class ScfvModel(ctypes.Structure):
+    _fields_ = [("d_pca_mean", ctypes.c_void_p), ("d_pca_matrix", ctypes.c_void_p), ("d_weights", ctypes.c_void_p),
+                ("d_means", ctypes.c_void_p), ("d_variances", ctypes.c_void_p)]
 
 
 def build() -> str:
@@ -128,6 +135,7 @@ def lib():
         "cdvs_graph_launch": (i32, [vp, vp]),
         "cdvs_profile_enable": (i32, [vp, i32]),
         "cdvs_profile_read": (i32, [vp, vp, vp]),
+        "cdvs_scfv": (i32, [vp, ctypes.POINTER(ScfvModel), vp, vp, vp, vp, vp, vp, vp, vp]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(L, name)
@@ -267,6 +275,41 @@ def cdvs_profile_read(ctx):
     n = np.zeros(len(KERNEL_NAMES), dtype=np.int32)
     _check(ctx, lib().cdvs_profile_read(ctx, ms.ctypes.data, n.ctypes.data))
     return {k: (float(ms[i]), int(n[i])) for i, k in enumerate(KERNEL_NAMES)}
+
+
+class Scfv:
+    """Device copy of an SCFV model (PCA mean and matrix, GMM weights, means
+    and variances; see include/cdvs.h) and the output buffers of cdvs_scfv
+    for n images."""
+
+    def __init__(self, model: dict, n_images: int, device="cuda"):
+        import torch
+        t = lambda a: torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).to(device)
+        self.tensors = {k: t(model[k]) for k in ("pca_mean", "pca_matrix", "weights", "means", "variances")}
+        assert self.tensors["pca_mean"].shape == (DESC_DIM,)
+        assert self.tensors["pca_matrix"].shape == (SCFV_DIM, DESC_DIM)
+        assert self.tensors["weights"].shape == (SCFV_COMPONENTS,)
+        assert self.tensors["means"].shape == self.tensors["variances"].shape == (SCFV_COMPONENTS, SCFV_DIM)
+        tt = self.tensors
+        self.model = ScfvModel(_ptr(tt["pca_mean"]), _ptr(tt["pca_matrix"]), _ptr(tt["weights"]),
+                               _ptr(tt["means"]), _ptr(tt["variances"]))
+        n, C, Dm = n_images, SCFV_COMPONENTS, SCFV_DIM
+        self.gm = torch.zeros((n, C, Dm), dtype=torch.float32, device=device)
+        self.gv = torch.zeros((n, C, Dm), dtype=torch.float32, device=device)
+        self.delta = torch.zeros((n, C), dtype=torch.float32, device=device)
+        self.order = torch.zeros((n, C), dtype=torch.int32, device=device)
+        self.bits = torch.zeros((n, C, 2), dtype=torch.int32, device=device)
+
+    def outputs(self):
+        """(gm, gv, delta, order, bits) as numpy arrays (bits as uint32)."""
+        return (self.gm.cpu().numpy(), self.gv.cpu().numpy(), self.delta.cpu().numpy(), self.order.cpu().numpy(),
+                self.bits.cpu().numpy().view(np.uint32))
+
+
+def cdvs_scfv(ctx, scfv: Scfv, d_desc, d_count, stream=None):
+    _check(ctx, lib().cdvs_scfv(ctx, ctypes.byref(scfv.model), _ptr(d_desc), _ptr(d_count), _ptr(scfv.gm),
+                                _ptr(scfv.gv), _ptr(scfv.delta), _ptr(scfv.order), _ptr(scfv.bits),
+                                _stream(stream)))
 
 
 def cdvs_plane_layout(ctx, image: int, octave: int, k: int):

@@ -48,6 +48,7 @@ struct cdvs_ctx {
     CnnImage* d_cnn = nullptr;
     int32_t* d_active = nullptr;  // [n][kMaxOctaves] active mask cells
     short* d_cnn_frag = nullptr;  // packed weight fragments of the fused inference kernel
+    float* d_scfv_prep = nullptr; // SCFV per-call model constants (kScfvPrepFloats)
     // device
     OctJob* d_jobs = nullptr;
     std::vector<int32_t> blur_owner;           // [variant][octave][tile] -> job (relative to job_start[octave])
@@ -283,6 +284,7 @@ void cdvs_ctx_destroy(cdvs_ctx* ctx) {
     (void)hipFree(ctx->d_cnn);
     (void)hipFree(ctx->d_active);
     (void)hipFree(ctx->d_cnn_frag);
+    (void)hipFree(ctx->d_scfv_prep);
     delete ctx;
 }
 
@@ -518,6 +520,7 @@ cdvs_status cdvs_ctx_create(const cdvs_params* params, const cdvs_image_desc* im
     ALLOC(c->d_cnn, sizeof(CnnImage) * n);
     ALLOC(c->d_active, sizeof(int32_t) * n * kMaxOctaves);
     ALLOC(c->d_cnn_frag, sizeof(short) * kCnnFragShorts);
+    ALLOC(c->d_scfv_prep, sizeof(float) * kScfvPrepFloats);
 #undef ALLOC
     if ((e = hipMemcpy(c->d_jobs, c->jobs.data(), sizeof(OctJob) * c->jobs.size(), hipMemcpyHostToDevice)) != hipSuccess ||
         (e = hipMemcpy(c->d_strips, c->strips.data(), sizeof(DetTile) * c->strips.size(), hipMemcpyHostToDevice)) !=
@@ -682,6 +685,24 @@ cdvs_status cdvs_sync_status(cdvs_ctx* ctx, void* stream) {
                     "an image with more than %d candidates kept keypoints as weak as the weakest of its %d "
                     "strongest; its top-k may differ from the exact one", kCandCap, kCandCap);
     }
+    return CDVS_OK;
+}
+
+static_assert(CDVS_SCFV_COMPONENTS == kScfvComponents && CDVS_SCFV_DIM == kScfvDim, "SCFV shape");
+
+cdvs_status cdvs_scfv(cdvs_ctx* ctx, const cdvs_scfv_model* model, const float* d_desc, const int32_t* d_count,
+                      float* d_gm, float* d_gv, float* d_delta, int32_t* d_order, uint32_t* d_bits, void* stream) {
+    if (!ctx) return CDVS_ERR_STATE;
+    if (!model || !model->d_pca_mean || !model->d_pca_matrix || !model->d_weights || !model->d_means ||
+        !model->d_variances || !d_desc || !d_count || !d_gm || !d_gv || !d_delta || !d_order || !d_bits)
+        return fail(ctx, CDVS_ERR_ARG, "cdvs_scfv: null pointer");
+    if ((((uintptr_t)d_desc | (uintptr_t)model->d_pca_mean) & 15) != 0)
+        return fail(ctx, CDVS_ERR_ARG, "cdvs_scfv: d_desc and the PCA mean must be 16-byte aligned");
+    hipStream_t s = (hipStream_t)stream;
+    Bracket b(ctx, CDVS_KERNEL_SCFV, s);
+    HIP_OR_FAIL(ctx, launch_scfv(d_desc, d_count, ctx->n, ctx->kp_cap, model->d_pca_mean, model->d_pca_matrix,
+                                 model->d_weights, model->d_means, model->d_variances, ctx->d_scfv_prep, d_gm, d_gv,
+                                 d_delta, d_order, d_bits, s));
     return CDVS_OK;
 }
 

@@ -194,4 +194,18 @@ hipError_t launch_cnn_labels(const cdvs_keypoint* kp, const int32_t* count, int 
                              int64_t ncells, uint32_t* labels, hipStream_t s);
 hipError_t launch_mask_count(const uint8_t* mask, const CnnImage* imgs, int nimg, int32_t* active, hipStream_t s);
 
+// SCFV aggregation: 512 components of 32 dimensions; per-call constants
+// derived from the model (B = [M./V, -1/(2V)] per component, c, 1/sqrt(w),
+// 1/sigma) at these float offsets of a scratch block of kScfvPrepFloats.
+constexpr int kScfvComponents = 512, kScfvDim = 32;
+constexpr int kScfvPrepB = 0;
+constexpr int kScfvPrepC = kScfvPrepB + kScfvComponents * 64;
+constexpr int kScfvPrepRsw = kScfvPrepC + kScfvComponents;
+constexpr int kScfvPrepIsig = kScfvPrepRsw + kScfvComponents;
+constexpr int kScfvPrepFloats = kScfvPrepIsig + kScfvComponents * kScfvDim;   // 50176
+hipError_t launch_scfv(const float* desc, const int32_t* count, int n_images, int kp_cap, const float* pca_mean,
+                       const float* pca_matrix, const float* weights, const float* means, const float* vars,
+                       float* prep, float* gm, float* gv, float* delta, int32_t* order, uint32_t* bits,
+                       hipStream_t s);
+
 }  // namespace cdvs

@@ -1,0 +1,100 @@
+"""Writes the SCFV stand-in parameters: a PCA (128 -> 32) and a 512-component
+diagonal GMM fitted on oracle descriptors of seeded synthetic images.
+
+They stand in for the MPEG-CDVS normative PCA and GMM (Sec. III-D), which
+are not available here: same shapes, fitted the usual way (PCA by the
+eigenvectors of the descriptor covariance; GMM by expectation-maximisation
+in float64), but on synthetic blob images, so they carry no claim about
+real images.  Only the oracle computes the descriptors they are fitted on.
+
+Run from the repository root (about a minute):
+    python tests/golden/fit_scfv_standin.py
+Writes paper_1705_09776_amd/weights/scfv_standin.npz (float32) and a .json
+note beside it.
+"""
+import json
+import os
+import sys
+import time
+from concurrent.futures import ThreadPoolExecutor
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+sys.path.insert(0, ROOT)
+import oracle  # noqa: E402
+import synth  # noqa: E402
+
+SEED_FIT = 8          # seed base of the fitting images (no other workload uses it)
+N_IMAGES = 48
+COMPONENTS = 512
+PDIM = 32
+EM_ITERATIONS = 30
+OUT = os.path.join(ROOT, "paper_1705_09776_amd", "weights", "scfv_standin.npz")
+
+
+def descriptors():
+    O = oracle.Oracle("f64")
+    imgs = synth.fixed_batch(SEED_FIT, N_IMAGES)
+    with ThreadPoolExecutor(min(16, os.cpu_count() or 1)) as ex:
+        out = list(ex.map(lambda i: O.run(imgs[i], image=i)[1], range(N_IMAGES)))
+    return np.concatenate(out)
+
+
+def fit_pca(D):
+    m = D.mean(axis=0)
+    C = np.cov((D - m).T)
+    ev, V = np.linalg.eigh(C)
+    A = V[:, np.argsort(ev)[::-1][:PDIM]].T
+    # fix each direction's sign: its largest-magnitude entry is positive
+    A *= np.sign(A[np.arange(PDIM), np.abs(A).argmax(axis=1)])[:, None]
+    return m, A
+
+
+def fit_gmm(X, rng):
+    n = len(X)
+    mu = X[rng.choice(n, COMPONENTS, replace=False)].copy()
+    floor = 1e-3 * X.var(axis=0).mean()
+    var = np.tile(X.var(axis=0), (COMPONENTS, 1))
+    w = np.full(COMPONENTS, 1.0 / COMPONENTS)
+    for _ in range(EM_ITERATIONS):
+        # E step: log w_i + log N(x; mu_i, var_i), normalised per descriptor
+        L = (np.log(w)[None, :] - 0.5 * np.sum(np.log(2 * np.pi * var), axis=1)[None, :]
+             - 0.5 * ((X * X) @ (1 / var).T - 2 * X @ (mu / var).T + np.sum(mu * mu / var, axis=1)[None, :]))
+        L -= L.max(axis=1, keepdims=True)
+        G = np.exp(L)
+        G /= G.sum(axis=1, keepdims=True)
+        # M step; a component that lost all its mass is re-seeded on a random point
+        nk = G.sum(axis=0)
+        dead = nk < 1e-8
+        nk = np.maximum(nk, 1e-12)
+        mu = (G.T @ X) / nk[:, None]
+        var = np.maximum((G.T @ (X * X)) / nk[:, None] - mu * mu, floor)
+        if dead.any():
+            mu[dead] = X[rng.choice(n, int(dead.sum()), replace=False)]
+            var[dead] = X.var(axis=0)
+        w = nk / nk.sum()
+    return w, mu, var
+
+
+def main():
+    t0 = time.time()
+    D = descriptors()
+    m, A = fit_pca(D)
+    X = (D - m) @ A.T
+    w, mu, var = fit_gmm(X, np.random.default_rng(SEED_FIT))
+    np.savez(OUT, pca_mean=m.astype(np.float32), pca_matrix=A.astype(np.float32), weights=w.astype(np.float32),
+             means=mu.astype(np.float32), variances=var.astype(np.float32))
+    note = {"what": "stand-in SCFV parameters (PCA 128->32, 512-component diagonal GMM), fitted on oracle "
+                    "descriptors of seeded synthetic images; not the MPEG-CDVS normative parameters",
+            "images": N_IMAGES, "seed_base": SEED_FIT, "descriptors": int(len(D)), "em_iterations": EM_ITERATIONS,
+            "min_weight": float(w.min()), "max_weight": float(w.max()),
+            "pca_variance_kept": float(np.var(X, axis=0).sum() / np.var(D, axis=0).sum()),
+            "fit_s": round(time.time() - t0, 1)}
+    with open(os.path.splitext(OUT)[0] + ".json", "w") as f:
+        json.dump(note, f, indent=1)
+    print(json.dumps(note))
+
+
+if __name__ == "__main__":
+    main()

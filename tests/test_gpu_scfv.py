@@ -1,0 +1,141 @@
+"""SCFV aggregation on the GPU (cdvs_scfv, FP32 matrix cores) against the
+float64 oracle (oracle/scfv.py) on the same descriptors, with the stand-in
+PCA/GMM model.
+
+Tolerance, derived from the arithmetic: the logits log w_j p_j(x_t) are
+sums of 64 products each of magnitude up to ~1e2, so FP32 carries an
+absolute error of ~1e-4 in them and a relative error of that size in the
+posteriors; the gradients are posterior-weighted sums, so their error is a
+few 1e-5 of the image's largest gradient entry (an FP32 emulation of the
+same expanded form measured 2e-5).  The bar is 1e-3 of the image's largest
+|entry| for the mean and variance gradients and for delta.  The ranking is
+compared where it is unique: the GPU order sorts the GPU's own delta
+exactly, and at every rank the oracle's delta of the GPU's component is
+within the delta tolerance of the oracle's delta at that rank.  Sign bits
+are compared where the oracle's entry is farther than the tolerance from
+zero."""
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from oracle import scfv
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+import paper_1705_09776_amd as cd  # noqa: E402
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+MODEL = os.path.join(ROOT, "paper_1705_09776_amd", "weights", "scfv_standin.npz")
+TOL = 1e-3
+
+
+@pytest.fixture(scope="module")
+def model():
+    return dict(np.load(MODEL))
+
+
+def _check(ref, gm, gv, dl, order, bits):
+    gmax, vmax, dmax = np.abs(ref["gm"]).max(), np.abs(ref["gv"]).max(), ref["delta"].max()
+    if gmax == 0:
+        assert not gm.any() and not gv.any() and not dl.any()
+        np.testing.assert_array_equal(order, np.arange(512))
+        return 0.0
+    e_m = np.abs(gm - ref["gm"]).max() / gmax
+    e_v = np.abs(gv - ref["gv"]).max() / vmax
+    e_d = np.abs(dl - ref["delta"]).max() / dmax
+    assert e_m <= TOL and e_v <= TOL and e_d <= TOL, (e_m, e_v, e_d)
+    # order: a permutation sorting the GPU's delta (desc, ties by index) ...
+    assert sorted(order) == list(range(512))
+    np.testing.assert_array_equal(order, scfv.rank(dl))
+    # ... and a valid ranking of the oracle's delta within the tolerance
+    assert np.abs(ref["delta"][order] - ref["delta"][ref["order"]]).max() <= TOL * dmax
+    for b, g, gmx in ((bits[:, 0], ref["gm"], gmax), (bits[:, 1], ref["gv"], vmax)):
+        sure = np.abs(g) > TOL * gmx
+        got = ((b[:, None] >> np.arange(32, dtype=np.uint32)[None, :]) & 1).astype(bool)
+        np.testing.assert_array_equal(got[sure], (g > 0)[sure])
+    return max(e_m, e_v, e_d)
+
+
+def _run(model, descs, counts, kp_cap):
+    """descs: list of (count_i x 128) arrays -> GPU outputs per image."""
+    n = len(descs)
+    pipe = cd.Pipeline([(64, 64)] * n, kp_capacity=kp_cap)
+    host = np.zeros((n, kp_cap, 128), dtype=np.float32)
+    for i, d in enumerate(descs):
+        host[i, :len(d)] = d
+    pipe.d_desc.copy_(torch.from_numpy(host))
+    pipe.d_count_ori.copy_(torch.from_numpy(np.asarray(counts, dtype=np.int32)))
+    S = cd.Scfv(model, n)
+    cd.cdvs_scfv(pipe.ctx, S, pipe.d_desc, pipe.d_count_ori)
+    torch.cuda.synchronize()
+    return S.outputs()
+
+
+def test_scfv_on_oracle_descriptors(model, O32):
+    """Descriptors of real (synthetic-scene) images from the oracle, with
+    ragged counts: the full 1000, a partial last tile, one, and none."""
+    imgs = synth.fixed_batch(synth.SEED_BATCH, 3)
+    descs = [O32.run(im)[1].astype(np.float32) for im in imgs]
+    counts = [len(descs[0]), 33, 1, 0]
+    descs = [descs[0], descs[1][:33], descs[2][:1], np.zeros((0, 128), np.float32)]
+    gm, gv, dl, order, bits = _run(model, descs, counts, 1000)
+    worst = 0.0
+    for i, d in enumerate(descs):
+        ref = scfv.scfv(d.astype(np.float64), {k: v.astype(np.float64) for k, v in model.items()})
+        worst = max(worst, _check(ref, gm[i], gv[i], dl[i], order[i], bits[i]))
+    print(f"SCFV on oracle descriptors: worst relative error {worst:.2e} (bar {TOL})")
+
+
+def test_scfv_counts_beyond_capacity_and_random_descriptors(model):
+    """Seeded random unit-norm descriptors (non-negative, clamped as a
+    descriptor is); a count above the capacity is clamped to it."""
+    rng = np.random.default_rng(3)
+    cap = 96
+    descs = []
+    for k in (96, 64, 31):
+        d = rng.gamma(0.5, 1.0, (k, 128))
+        d /= np.linalg.norm(d, axis=1, keepdims=True)
+        d = np.minimum(d, 0.2)
+        d /= np.linalg.norm(d, axis=1, keepdims=True)
+        descs.append(d.astype(np.float32))
+    counts = [500, 64, 31]            # 500 > capacity: clamped to 96
+    gm, gv, dl, order, bits = _run(model, descs, counts, cap)
+    for i, d in enumerate(descs):
+        ref = scfv.scfv(d.astype(np.float64), {k: v.astype(np.float64) for k, v in model.items()})
+        _check(ref, gm[i], gv[i], dl[i], order[i], bits[i])
+
+
+def test_scfv_full_batch_sampled(model, O32):
+    """The benchmark's launch configuration: 256 images' descriptors from the
+    plain pass (1000 each).  Sampled images against the oracle on the same
+    descriptors; on every image, the order sorts delta and the sign bits are
+    those of the gradients written."""
+    imgs = synth.fixed_batch(synth.SEED_BATCH, 256)
+    pipe = cd.Pipeline([(640, 480)] * 256)
+    pipe.upload(list(imgs))
+    pipe.run()
+    S = cd.Scfv(model, 256)
+    cd.cdvs_scfv(pipe.ctx, S, pipe.d_desc, pipe.d_count_ori)
+    torch.cuda.synchronize()
+    gm, gv, dl, order, bits = S.outputs()
+    descs = pipe.descriptors()
+    for i in range(256):
+        np.testing.assert_array_equal(order[i], scfv.rank(dl[i]))
+        np.testing.assert_array_equal(bits[i, :, 0], scfv.sign_bits(gm[i]))
+        np.testing.assert_array_equal(bits[i, :, 1], scfv.sign_bits(gv[i]))
+        assert np.isfinite(gm[i]).all() and np.isfinite(gv[i]).all()
+    for i in (0, 101, 255):
+        # the oracle aggregates the oracle's own descriptors of image i,
+        # uploaded in place of the GPU's
+        d = O32.run(imgs[i])[1].astype(np.float32)
+        one = _run(model, [d], [len(d)], 1000)
+        ref = scfv.scfv(d.astype(np.float64), {k: v.astype(np.float64) for k, v in model.items()})
+        _check(ref, *(x[0] for x in one))
+        assert len(descs[i]) == 1000
