@@ -246,6 +246,41 @@ int32_t cdvs_tune_get(const cdvs_ctx* ctx, int32_t kernel);
 cdvs_status cdvs_tune_set(cdvs_ctx* ctx, int32_t kernel, int32_t variant);
 
 /* ---------------------------------------------------------------------- */
+/* Descriptor compression: transform coding and ternary quantisation        */
+/* (Sec. III-C)                                                              */
+/* ---------------------------------------------------------------------- */
+#define CDVS_TQ_WORDS 8   /* 32-bit code words per descriptor (up to 128 elements x 2 bits) */
+
+/* The quantiser, device buffers owned by the caller: per transformed
+ * element e (0..127), thresholds d_lo[e] <= d_hi[e] (float32), and a
+ * priority order d_order[0..127] (int32, a permutation of 0..127). */
+typedef struct {
+    const float* d_lo;
+    const float* d_hi;
+    const int32_t* d_order;
+} cdvs_tq_model;
+
+/* Codes the first d_count[image] descriptors of every image (d_desc as
+ * cdvs_describe writes it, 16-byte aligned).  Cell c = 4 row + col of a
+ * descriptor (bins h_0..h_7 at elements 8c..8c+7) is transformed by set A
+ * when row + col is even and by set B otherwise:
+ *   A: v0 = (h2-h6)/2, v1 = (h3-h7)/2, v2 = (h0-h1)/2, v3 = (h2-h3)/2,
+ *      v4 = (h4-h5)/2, v5 = (h6-h7)/2, v6 = ((h0+h4)-(h2+h6))/4,
+ *      v7 = ((h0+h2+h4+h6)-(h1+h3+h5+h7))/8;
+ *   B: v0 = (h0-h4)/2, v1 = (h1-h5)/2, v2 = (h7-h0)/2, v3 = (h1-h2)/2,
+ *      v4 = (h3-h4)/2, v5 = (h5-h6)/2, v6 = ((h1+h5)-(h3+h7))/4,
+ *      v7 = ((h0+h1+h2+h3)-(h4+h5+h6+h7))/8
+ * (each evaluated left to right in single precision), element 8c + k being
+ * v_k; element e becomes +1 if v > d_hi[e], -1 if v < d_lo[e], else 0.
+ * Positions p = 0..n_elements-1 (1 <= n_elements <= 128) code element
+ * d_order[p] with two bits (01 = +1, 10 = -1, 00 = 0) at bit 2 (p % 16) of
+ * word p / 16 of d_codes[image][k][0..7] (n_images x kp_capacity x 8
+ * uint32; other bits zero); the code is 2 n_elements bits.  Rows at or
+ * beyond the count are left untouched. */
+cdvs_status cdvs_encode(cdvs_ctx* ctx, const cdvs_tq_model* model, int32_t n_elements, const float* d_desc,
+                        const int32_t* d_count, uint32_t* d_codes, void* stream);
+
+/* ---------------------------------------------------------------------- */
 /* Global aggregation: SCFV (Sec. III-D, Eqs. (6)-(8); Sec. IV-C, Eqs. (9)-(14)) */
 /* ---------------------------------------------------------------------- */
 #define CDVS_SCFV_COMPONENTS 512
@@ -418,6 +453,7 @@ typedef enum {
     CDVS_KERNEL_CNN_FORWARD,  /* surrogate CNN: four convolutions and the head */
     CDVS_KERNEL_MASK_COUNT,   /* active cells of a gating mask */
     CDVS_KERNEL_SCFV,         /* SCFV aggregation (model constants + one workgroup per image) */
+    CDVS_KERNEL_ENCODE,       /* transform coding and ternary quantisation */
     CDVS_KERNEL_COUNT
 } cdvs_kernel_id;
 

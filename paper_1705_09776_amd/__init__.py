@@ -71,16 +71,21 @@ EXPORTS = ["cdvs_default_params", "cdvs_validate", "cdvs_ctx_create", "cdvs_ctx_
            "cdvs_graph_capture", "cdvs_graph_launch", "cdvs_profile_enable", "cdvs_profile_read",
            "cdvs_cnn_cells", "cdvs_cnn_cell_layout", "cdvs_cnn_forward", "cdvs_cnn_labels", "cdvs_cnn_backward",
            "cdvs_cnn_adam", "cdvs_autotune", "cdvs_tune_get", "cdvs_tune_set",
-           "cdvs_stream", "cdvs_standin_consume", "cdvs_scfv"]
+           "cdvs_stream", "cdvs_standin_consume", "cdvs_scfv", "cdvs_encode"]
 TUNE_VARIANTS = 4
 DETECT_VARIANTS = 2
 
 KERNEL_SCALES = 1
 KERNEL_DETECT = 3
 KERNEL_NAMES = ["preblur", "scales", "clear", "detect", "finalize", "orient", "orient_compact", "describe",
-                "cnn_forward", "mask_count", "scfv"]
+                "cnn_forward", "mask_count", "scfv", "encode"]
+TQ_WORDS = 8
 SCFV_COMPONENTS = 512
 SCFV_DIM = 32
+
+
+class TqModel(ctypes.Structure):
+    _fields_ = [("d_lo", ctypes.c_void_p), ("d_hi", ctypes.c_void_p), ("d_order", ctypes.c_void_p)]
 
 
 class ScfvModel(ctypes.Structure):
@@ -136,6 +141,7 @@ def lib():
         "cdvs_profile_enable": (i32, [vp, i32]),
         "cdvs_profile_read": (i32, [vp, vp, vp]),
         "cdvs_scfv": (i32, [vp, ctypes.POINTER(ScfvModel), vp, vp, vp, vp, vp, vp, vp, vp]),
+        "cdvs_encode": (i32, [vp, ctypes.POINTER(TqModel), i32, vp, vp, vp, vp]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(L, name)
@@ -304,6 +310,24 @@ class Scfv:
         """(gm, gv, delta, order, bits) as numpy arrays (bits as uint32)."""
         return (self.gm.cpu().numpy(), self.gv.cpu().numpy(), self.delta.cpu().numpy(), self.order.cpu().numpy(),
                 self.bits.cpu().numpy().view(np.uint32))
+
+
+class Tq:
+    """Device copy of a ternary-quantiser model (thresholds lo, hi and the
+    element priority order; see include/cdvs.h)."""
+
+    def __init__(self, model: dict, device="cuda"):
+        import torch
+        self.lo = torch.from_numpy(np.ascontiguousarray(model["lo"], dtype=np.float32)).to(device)
+        self.hi = torch.from_numpy(np.ascontiguousarray(model["hi"], dtype=np.float32)).to(device)
+        self.order = torch.from_numpy(np.ascontiguousarray(model["order"], dtype=np.int32)).to(device)
+        assert self.lo.shape == self.hi.shape == self.order.shape == (DESC_DIM,)
+        self.model = TqModel(_ptr(self.lo), _ptr(self.hi), _ptr(self.order))
+
+
+def cdvs_encode(ctx, tq: Tq, n_elements, d_desc, d_count, d_codes, stream=None):
+    _check(ctx, lib().cdvs_encode(ctx, ctypes.byref(tq.model), int(n_elements), _ptr(d_desc), _ptr(d_count),
+                                  _ptr(d_codes), _stream(stream)))
 
 
 def cdvs_scfv(ctx, scfv: Scfv, d_desc, d_count, stream=None):

@@ -706,6 +706,23 @@ cdvs_status cdvs_scfv(cdvs_ctx* ctx, const cdvs_scfv_model* model, const float* 
     return CDVS_OK;
 }
 
+static_assert(CDVS_TQ_WORDS == kTqWords, "code words");
+
+cdvs_status cdvs_encode(cdvs_ctx* ctx, const cdvs_tq_model* model, int32_t n_elements, const float* d_desc,
+                        const int32_t* d_count, uint32_t* d_codes, void* stream) {
+    if (!ctx) return CDVS_ERR_STATE;
+    if (!model || !model->d_lo || !model->d_hi || !model->d_order || !d_desc || !d_count || !d_codes)
+        return fail(ctx, CDVS_ERR_ARG, "cdvs_encode: null pointer");
+    if (n_elements < 1 || n_elements > kDescDim)
+        return fail(ctx, CDVS_ERR_ARG, "cdvs_encode: n_elements %d outside 1..%d", n_elements, kDescDim);
+    if (((uintptr_t)d_desc & 15) != 0) return fail(ctx, CDVS_ERR_ARG, "cdvs_encode: d_desc not 16-byte aligned");
+    hipStream_t s = (hipStream_t)stream;
+    Bracket b(ctx, CDVS_KERNEL_ENCODE, s);
+    HIP_OR_FAIL(ctx, launch_tq_encode(d_desc, d_count, ctx->n, ctx->kp_cap, model->d_lo, model->d_hi, model->d_order,
+                                      n_elements, d_codes, s));
+    return CDVS_OK;
+}
+
 int64_t cdvs_cnn_cells(const cdvs_ctx* ctx) { return ctx ? ctx->ncells : -1; }
 
 cdvs_status cdvs_cnn_cell_layout(const cdvs_ctx* ctx, int32_t image, int64_t* cell0, int32_t* w4, int32_t* h4) {

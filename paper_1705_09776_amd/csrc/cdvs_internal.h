@@ -208,4 +208,9 @@ hipError_t launch_scfv(const float* desc, const int32_t* count, int n_images, in
                        float* prep, float* gm, float* gv, float* delta, int32_t* order, uint32_t* bits,
                        hipStream_t s);
 
+// Transform coding and ternary quantisation: eight code words per descriptor.
+constexpr int kTqWords = 8;
+hipError_t launch_tq_encode(const float* desc, const int32_t* count, int n_images, int kp_cap, const float* lo,
+                            const float* hi, const int32_t* order, int n_elem, uint32_t* codes, hipStream_t s);
+
 }  // namespace cdvs

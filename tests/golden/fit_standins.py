@@ -1,16 +1,23 @@
-"""Writes the SCFV stand-in parameters: a PCA (128 -> 32) and a 512-component
-diagonal GMM fitted on oracle descriptors of seeded synthetic images.
+"""Writes the stand-in parameters of the descriptor coding and aggregation
+steps, fitted on oracle descriptors of seeded synthetic images:
 
-They stand in for the MPEG-CDVS normative PCA and GMM (Sec. III-D), which
-are not available here: same shapes, fitted the usual way (PCA by the
-eigenvectors of the descriptor covariance; GMM by expectation-maximisation
-in float64), but on synthetic blob images, so they carry no claim about
-real images.  Only the oracle computes the descriptors they are fitted on.
+* SCFV (Sec. III-D): a PCA (128 -> 32) and a 512-component diagonal GMM,
+  fitted the usual way (PCA by the eigenvectors of the descriptor
+  covariance; GMM by expectation-maximisation in float64);
+* transform coding (Sec. III-C): per transformed element, the two ternary
+  thresholds at its 1/3 and 2/3 quantiles (so that each symbol is about
+  equally likely), and a priority order of the elements by the entropy of
+  their symbols, highest first (ties: lower element first).
+
+They stand in for the MPEG-CDVS normative parameters, which are not
+available here: same shapes, but fitted on synthetic blob images, so they
+carry no claim about real images.  Only the oracle computes the
+descriptors they are fitted on.
 
 Run from the repository root (about a minute):
-    python tests/golden/fit_scfv_standin.py
-Writes paper_1705_09776_amd/weights/scfv_standin.npz (float32) and a .json
-note beside it.
+    python tests/golden/fit_standins.py
+Writes paper_1705_09776_amd/weights/scfv_standin.npz and tq_standin.npz
+(float32 / int32) with a .json note beside each.
 """
 import json
 import os
@@ -24,6 +31,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.dirname(os.path.abspath(__file__)
 sys.path.insert(0, ROOT)
 import oracle  # noqa: E402
 import synth  # noqa: E402
+from oracle import tq  # noqa: E402
 
 SEED_FIT = 8          # seed base of the fitting images (no other workload uses it)
 N_IMAGES = 48
@@ -31,6 +39,7 @@ COMPONENTS = 512
 PDIM = 32
 EM_ITERATIONS = 30
 OUT = os.path.join(ROOT, "paper_1705_09776_amd", "weights", "scfv_standin.npz")
+OUT_TQ = os.path.join(ROOT, "paper_1705_09776_amd", "weights", "tq_standin.npz")
 
 
 def descriptors():
@@ -77,6 +86,19 @@ def fit_gmm(X, rng):
     return w, mu, var
 
 
+def fit_tq(D):
+    V = tq.transform(D.astype(np.float32)).astype(np.float64)
+    lo = np.quantile(V, 1.0 / 3.0, axis=0)
+    hi = np.quantile(V, 2.0 / 3.0, axis=0)
+    q = tq.quantise(V, lo.astype(np.float32), hi.astype(np.float32))
+    ent = np.zeros(128)
+    for s in (-1, 0, 1):
+        p = (q == s).mean(axis=0)
+        ent -= np.where(p > 0, p * np.log2(np.where(p > 0, p, 1.0)), 0.0)
+    order = np.lexsort((np.arange(128), -np.round(ent, 12)))
+    return lo, hi, order, ent
+
+
 def main():
     t0 = time.time()
     D = descriptors()
@@ -92,6 +114,17 @@ def main():
             "pca_variance_kept": float(np.var(X, axis=0).sum() / np.var(D, axis=0).sum()),
             "fit_s": round(time.time() - t0, 1)}
     with open(os.path.splitext(OUT)[0] + ".json", "w") as f:
+        json.dump(note, f, indent=1)
+    print(json.dumps(note))
+    lo, hi, order, ent = fit_tq(D)
+    np.savez(OUT_TQ, lo=lo.astype(np.float32), hi=hi.astype(np.float32), order=order.astype(np.int32))
+    note = {"what": "stand-in ternary-quantisation thresholds (1/3 and 2/3 quantiles of each transformed element) "
+                    "and element priority (symbol entropy, highest first) fitted on oracle descriptors of seeded "
+                    "synthetic images; not the MPEG-CDVS normative thresholds",
+            "images": N_IMAGES, "seed_base": SEED_FIT, "descriptors": int(len(D)),
+            "entropy_bits_first_16": [round(float(e), 4) for e in ent[order[:16]]],
+            "entropy_bits_total": round(float(ent.sum()), 2)}
+    with open(os.path.splitext(OUT_TQ)[0] + ".json", "w") as f:
         json.dump(note, f, indent=1)
     print(json.dumps(note))
 
