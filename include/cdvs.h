@@ -246,6 +246,38 @@ int32_t cdvs_tune_get(const cdvs_ctx* ctx, int32_t kernel);
 cdvs_status cdvs_tune_set(cdvs_ctx* ctx, int32_t kernel, int32_t variant);
 
 /* ---------------------------------------------------------------------- */
+/* Keypoint selection by relevance (Sec. III-B, Eqs. (4)-(5))               */
+/* ---------------------------------------------------------------------- */
+#define CDVS_REL_FEATURES 5
+#define CDVS_REL_EDGES 15
+#define CDVS_REL_BINS 16
+
+/* The relevance tables, device buffers (float32) owned by the caller: for
+ * characteristic c = 0..4 (sigma in base pixels, |p|, distance to the image
+ * centre, rho, p_ss -- in that order), d_edges[c][0..14] increasing bin
+ * edges and d_values[c][0..15] table values (positive). */
+typedef struct {
+    const float* d_edges;
+    const float* d_values;
+} cdvs_relevance_model;
+
+/* Keeps, per image, the n_keep keypoints of highest relevance
+ *   r = f_0(sigma) f_1(|p|) f_2(d) f_3(rho) f_4(p_ss),
+ * f_c(v) = d_values[c][b], b = the number of d_edges[c] entries <= v,
+ * d = distance of (x, y) from ((W-1)/2, (H-1)/2) over that point's distance
+ * to a corner, all in single precision (the product left to right).  Input:
+ * the first d_count_in[image] records of d_kp_in[image] (clamped to
+ * 0..kp_capacity; e.g. cdvs_alp_detect's output with a large topk).
+ * Output: the kept records in order of r, descending (equal r: input
+ * order), in d_kp_out[image][0..], their number min(count, n_keep) in
+ * d_count_out[image], and (d_score may be NULL) their r in
+ * d_score[image][0..] (n_images x kp_capacity floats).  Outputs must not
+ * alias inputs; 1 <= n_keep. */
+cdvs_status cdvs_relevance_select(cdvs_ctx* ctx, const cdvs_relevance_model* model, const cdvs_keypoint* d_kp_in,
+                                  const int32_t* d_count_in, int32_t n_keep, cdvs_keypoint* d_kp_out,
+                                  int32_t* d_count_out, float* d_score, void* stream);
+
+/* ---------------------------------------------------------------------- */
 /* Descriptor compression: transform coding and ternary quantisation        */
 /* (Sec. III-C)                                                              */
 /* ---------------------------------------------------------------------- */
@@ -454,6 +486,7 @@ typedef enum {
     CDVS_KERNEL_MASK_COUNT,   /* active cells of a gating mask */
     CDVS_KERNEL_SCFV,         /* SCFV aggregation (model constants + one workgroup per image) */
     CDVS_KERNEL_ENCODE,       /* transform coding and ternary quantisation */
+    CDVS_KERNEL_RELEVANCE,    /* relevance scores and per-image selection */
     CDVS_KERNEL_COUNT
 } cdvs_kernel_id;
 

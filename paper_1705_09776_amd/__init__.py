@@ -71,17 +71,22 @@ EXPORTS = ["cdvs_default_params", "cdvs_validate", "cdvs_ctx_create", "cdvs_ctx_
            "cdvs_graph_capture", "cdvs_graph_launch", "cdvs_profile_enable", "cdvs_profile_read",
            "cdvs_cnn_cells", "cdvs_cnn_cell_layout", "cdvs_cnn_forward", "cdvs_cnn_labels", "cdvs_cnn_backward",
            "cdvs_cnn_adam", "cdvs_autotune", "cdvs_tune_get", "cdvs_tune_set",
-           "cdvs_stream", "cdvs_standin_consume", "cdvs_scfv", "cdvs_encode"]
+           "cdvs_stream", "cdvs_standin_consume", "cdvs_scfv", "cdvs_encode",
+           "cdvs_relevance_select"]
 TUNE_VARIANTS = 4
 DETECT_VARIANTS = 2
 
 KERNEL_SCALES = 1
 KERNEL_DETECT = 3
 KERNEL_NAMES = ["preblur", "scales", "clear", "detect", "finalize", "orient", "orient_compact", "describe",
-                "cnn_forward", "mask_count", "scfv", "encode"]
+                "cnn_forward", "mask_count", "scfv", "encode", "relevance"]
 TQ_WORDS = 8
 SCFV_COMPONENTS = 512
 SCFV_DIM = 32
+
+
+class RelevanceModel(ctypes.Structure):
+    _fields_ = [("d_edges", ctypes.c_void_p), ("d_values", ctypes.c_void_p)]
 
 
 class TqModel(ctypes.Structure):
@@ -142,6 +147,7 @@ def lib():
         "cdvs_profile_read": (i32, [vp, vp, vp]),
         "cdvs_scfv": (i32, [vp, ctypes.POINTER(ScfvModel), vp, vp, vp, vp, vp, vp, vp, vp]),
         "cdvs_encode": (i32, [vp, ctypes.POINTER(TqModel), i32, vp, vp, vp, vp]),
+        "cdvs_relevance_select": (i32, [vp, ctypes.POINTER(RelevanceModel), vp, vp, i32, vp, vp, vp, vp]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(L, name)
@@ -310,6 +316,24 @@ class Scfv:
         """(gm, gv, delta, order, bits) as numpy arrays (bits as uint32)."""
         return (self.gm.cpu().numpy(), self.gv.cpu().numpy(), self.delta.cpu().numpy(), self.order.cpu().numpy(),
                 self.bits.cpu().numpy().view(np.uint32))
+
+
+class Relevance:
+    """Device copy of relevance tables (edges 5 x 15, values 5 x 16)."""
+
+    def __init__(self, model: dict, device="cuda"):
+        import torch
+        self.edges = torch.from_numpy(np.ascontiguousarray(model["edges"], dtype=np.float32)).to(device)
+        self.values = torch.from_numpy(np.ascontiguousarray(model["values"], dtype=np.float32)).to(device)
+        assert self.edges.shape == (5, 15) and self.values.shape == (5, 16)
+        self.model = RelevanceModel(_ptr(self.edges), _ptr(self.values))
+
+
+def cdvs_relevance_select(ctx, rel: Relevance, d_kp_in, d_count_in, n_keep, d_kp_out, d_count_out, d_score=None,
+                          stream=None):
+    _check(ctx, lib().cdvs_relevance_select(ctx, ctypes.byref(rel.model), _ptr(d_kp_in), _ptr(d_count_in),
+                                            int(n_keep), _ptr(d_kp_out), _ptr(d_count_out), _ptr(d_score),
+                                            _stream(stream)))
 
 
 class Tq:

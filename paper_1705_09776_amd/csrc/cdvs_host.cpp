@@ -49,6 +49,7 @@ struct cdvs_ctx {
     int32_t* d_active = nullptr;  // [n][kMaxOctaves] active mask cells
     short* d_cnn_frag = nullptr;  // packed weight fragments of the fused inference kernel
     float* d_scfv_prep = nullptr; // SCFV per-call model constants (kScfvPrepFloats)
+    int32_t* d_wh = nullptr;      // per image: width, height
     // device
     OctJob* d_jobs = nullptr;
     std::vector<int32_t> blur_owner;           // [variant][octave][tile] -> job (relative to job_start[octave])
@@ -285,6 +286,7 @@ void cdvs_ctx_destroy(cdvs_ctx* ctx) {
     (void)hipFree(ctx->d_active);
     (void)hipFree(ctx->d_cnn_frag);
     (void)hipFree(ctx->d_scfv_prep);
+    (void)hipFree(ctx->d_wh);
     delete ctx;
 }
 
@@ -521,7 +523,13 @@ cdvs_status cdvs_ctx_create(const cdvs_params* params, const cdvs_image_desc* im
     ALLOC(c->d_active, sizeof(int32_t) * n * kMaxOctaves);
     ALLOC(c->d_cnn_frag, sizeof(short) * kCnnFragShorts);
     ALLOC(c->d_scfv_prep, sizeof(float) * kScfvPrepFloats);
+    ALLOC(c->d_wh, sizeof(int32_t) * 2 * n);
 #undef ALLOC
+    std::vector<int32_t> wh(2 * n);
+    for (size_t i = 0; i < n; ++i) {
+        wh[2 * i] = images[i].width;
+        wh[2 * i + 1] = images[i].height;
+    }
     if ((e = hipMemcpy(c->d_jobs, c->jobs.data(), sizeof(OctJob) * c->jobs.size(), hipMemcpyHostToDevice)) != hipSuccess ||
         (e = hipMemcpy(c->d_strips, c->strips.data(), sizeof(DetTile) * c->strips.size(), hipMemcpyHostToDevice)) !=
             hipSuccess ||
@@ -531,6 +539,7 @@ cdvs_status cdvs_ctx_create(const cdvs_params* params, const cdvs_image_desc* im
                        hipMemcpyHostToDevice)) != hipSuccess ||
         (e = hipMemcpy(c->d_geom, c->geom.data(), sizeof(OctGeom) * c->geom.size(), hipMemcpyHostToDevice)) != hipSuccess ||
         (e = hipMemcpy(c->d_cnn, c->cnn.data(), sizeof(CnnImage) * n, hipMemcpyHostToDevice)) != hipSuccess ||
+        (e = hipMemcpy(c->d_wh, wh.data(), sizeof(int32_t) * 2 * n, hipMemcpyHostToDevice)) != hipSuccess ||
         (e = hipMemcpy(c->d_cand_off, c->cand_off.data(), sizeof(int64_t) * n, hipMemcpyHostToDevice)) != hipSuccess ||
         (e = hipMemcpy(c->d_cand_capv, c->cand_cap.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice)) !=
             hipSuccess ||
@@ -703,6 +712,25 @@ cdvs_status cdvs_scfv(cdvs_ctx* ctx, const cdvs_scfv_model* model, const float* 
     HIP_OR_FAIL(ctx, launch_scfv(d_desc, d_count, ctx->n, ctx->kp_cap, model->d_pca_mean, model->d_pca_matrix,
                                  model->d_weights, model->d_means, model->d_variances, ctx->d_scfv_prep, d_gm, d_gv,
                                  d_delta, d_order, d_bits, s));
+    return CDVS_OK;
+}
+
+static_assert(CDVS_REL_FEATURES == kRelFeatures && CDVS_REL_EDGES == kRelEdges && CDVS_REL_BINS == kRelBins,
+              "relevance tables");
+
+cdvs_status cdvs_relevance_select(cdvs_ctx* ctx, const cdvs_relevance_model* model, const cdvs_keypoint* d_kp_in,
+                                  const int32_t* d_count_in, int32_t n_keep, cdvs_keypoint* d_kp_out,
+                                  int32_t* d_count_out, float* d_score, void* stream) {
+    if (!ctx) return CDVS_ERR_STATE;
+    if (!model || !model->d_edges || !model->d_values || !d_kp_in || !d_count_in || !d_kp_out || !d_count_out)
+        return fail(ctx, CDVS_ERR_ARG, "cdvs_relevance_select: null pointer");
+    if (n_keep < 1) return fail(ctx, CDVS_ERR_ARG, "cdvs_relevance_select: n_keep %d < 1", n_keep);
+    if ((const void*)d_kp_in == (const void*)d_kp_out || (const void*)d_count_in == (const void*)d_count_out)
+        return fail(ctx, CDVS_ERR_ARG, "cdvs_relevance_select: outputs must not alias inputs");
+    hipStream_t s = (hipStream_t)stream;
+    Bracket b(ctx, CDVS_KERNEL_RELEVANCE, s);
+    HIP_OR_FAIL(ctx, launch_relevance(d_kp_in, d_count_in, ctx->d_wh, ctx->n, ctx->kp_cap, model->d_edges,
+                                      model->d_values, n_keep, d_kp_out, d_count_out, d_score, s));
     return CDVS_OK;
 }
 

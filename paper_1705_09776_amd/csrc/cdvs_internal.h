@@ -208,6 +208,13 @@ hipError_t launch_scfv(const float* desc, const int32_t* count, int n_images, in
                        float* prep, float* gm, float* gv, float* delta, int32_t* order, uint32_t* bits,
                        hipStream_t s);
 
+// Keypoint relevance: five characteristics, 15 bin edges and 16 table
+// values each.
+constexpr int kRelFeatures = 5, kRelEdges = 15, kRelBins = 16;
+hipError_t launch_relevance(const cdvs_keypoint* kp_in, const int32_t* count_in, const int32_t* wh, int n_images,
+                            int kp_cap, const float* edges, const float* values, int n_keep, cdvs_keypoint* kp_out,
+                            int32_t* count_out, float* score_out, hipStream_t s);
+
 // Transform coding and ternary quantisation: eight code words per descriptor.
 constexpr int kTqWords = 8;
 hipError_t launch_tq_encode(const float* desc, const int32_t* count, int n_images, int kp_cap, const float* lo,

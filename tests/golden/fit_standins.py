@@ -4,6 +4,12 @@ steps, fitted on oracle descriptors of seeded synthetic images:
 * SCFV (Sec. III-D): a PCA (128 -> 32) and a 512-component diagonal GMM,
   fitted the usual way (PCA by the eigenvectors of the descriptor
   covariance; GMM by expectation-maximisation in float64);
+* keypoint relevance (Sec. III-B, Eqs. (4)-(5)): per characteristic
+  (sigma, |p|, distance to the centre, rho, p_ss), 15 bin edges at its
+  quantiles over all detected keypoints, and per bin the rate at which a
+  keypoint is found again (same octave, within 1 base pixel) when the same
+  image gets fresh pixel noise (uniform +-6 levels, added here, rounded
+  and clipped) -- the stand-in for "correctly matched" (Laplace-smoothed);
 * transform coding (Sec. III-C): per transformed element, the two ternary
   thresholds at its 1/3 and 2/3 quantiles (so that each symbol is about
   equally likely), and a priority order of the elements by the entropy of
@@ -16,8 +22,8 @@ descriptors they are fitted on.
 
 Run from the repository root (about a minute):
     python tests/golden/fit_standins.py
-Writes paper_1705_09776_amd/weights/scfv_standin.npz and tq_standin.npz
-(float32 / int32) with a .json note beside each.
+Writes paper_1705_09776_amd/weights/scfv_standin.npz, tq_standin.npz and
+relevance_standin.npz (float32 / int32) with a .json note beside each.
 """
 import json
 import os
@@ -31,7 +37,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.dirname(os.path.abspath(__file__)
 sys.path.insert(0, ROOT)
 import oracle  # noqa: E402
 import synth  # noqa: E402
-from oracle import tq  # noqa: E402
+from oracle import relevance, tq  # noqa: E402
 
 SEED_FIT = 8          # seed base of the fitting images (no other workload uses it)
 N_IMAGES = 48
@@ -40,6 +46,9 @@ PDIM = 32
 EM_ITERATIONS = 30
 OUT = os.path.join(ROOT, "paper_1705_09776_amd", "weights", "scfv_standin.npz")
 OUT_TQ = os.path.join(ROOT, "paper_1705_09776_amd", "weights", "tq_standin.npz")
+OUT_REL = os.path.join(ROOT, "paper_1705_09776_amd", "weights", "relevance_standin.npz")
+REL_IMAGES = 32
+NOISE = 6
 
 
 def descriptors():
@@ -99,6 +108,45 @@ def fit_tq(D):
     return lo, hi, order, ent
 
 
+def _all_keypoints(O, img):
+    H, W = img.shape
+    _, flat = O.pyramid(img)
+    cand = O.detect(flat, W, H)
+    return O.select(cand, O.dedup(cand), 0)
+
+
+def fit_relevance():
+    O = oracle.Oracle("f64")
+    imgs = synth.fixed_batch(SEED_FIT, REL_IMAGES)
+    rng = np.random.default_rng(SEED_FIT + 1)
+    views = [np.clip(np.rint(im.astype(np.float64) + rng.uniform(-NOISE, NOISE, im.shape)), 0, 255).astype(np.uint8)
+             for im in imgs]
+    with ThreadPoolExecutor(min(16, os.cpu_count() or 1)) as ex:
+        a = list(ex.map(lambda im: _all_keypoints(O, im), imgs))
+        b = list(ex.map(lambda im: _all_keypoints(O, im), views))
+    F, hit = [], []
+    for ka, kb in zip(a, b):
+        H, W = imgs[0].shape
+        F.append(relevance.features(ka, W, H))
+        m = np.zeros(len(ka), bool)
+        for o in np.unique(ka["octave"]):
+            ia, jb = np.nonzero(ka["octave"] == o)[0], np.nonzero(kb["octave"] == o)[0]
+            if len(jb):
+                d = np.hypot(ka["x"][ia, None] - kb["x"][None, jb], ka["y"][ia, None] - kb["y"][None, jb])
+                m[ia] = d.min(axis=1) <= 1.0
+        hit.append(m)
+    F, hit = np.concatenate(F), np.concatenate(hit)
+    edges = np.stack([np.quantile(F[:, k].astype(np.float64), np.arange(1, 16) / 16.0) for k in range(5)])
+    edges = edges.astype(np.float32)
+    b = relevance.bins(F, edges)
+    values = np.zeros((5, 16))
+    for k in range(5):
+        for j in range(16):
+            sel = b[:, k] == j
+            values[k, j] = (hit[sel].sum() + 1.0) / (sel.sum() + 2.0)
+    return edges, values.astype(np.float32), len(F), float(hit.mean())
+
+
 def main():
     t0 = time.time()
     D = descriptors()
@@ -125,6 +173,17 @@ def main():
             "entropy_bits_first_16": [round(float(e), 4) for e in ent[order[:16]]],
             "entropy_bits_total": round(float(ent.sum()), 2)}
     with open(os.path.splitext(OUT_TQ)[0] + ".json", "w") as f:
+        json.dump(note, f, indent=1)
+    print(json.dumps(note))
+    edges, values, nkp, rate = fit_relevance()
+    np.savez(OUT_REL, edges=edges, values=values)
+    note = {"what": "stand-in relevance tables (per characteristic sigma, |p|, centre distance, rho, p_ss: 15 "
+                    "quantile bin edges and 16 repeat rates) fitted on oracle keypoints of seeded synthetic images "
+                    "against a re-noised copy; not the MPEG-CDVS normative tables",
+            "images": REL_IMAGES, "seed_base": SEED_FIT, "keypoints": nkp, "noise_levels": NOISE,
+            "repeat_rate": round(rate, 4),
+            "value_range": [[round(float(v.min()), 4), round(float(v.max()), 4)] for v in values]}
+    with open(os.path.splitext(OUT_REL)[0] + ".json", "w") as f:
         json.dump(note, f, indent=1)
     print(json.dumps(note))
 
