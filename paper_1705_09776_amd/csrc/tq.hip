@@ -33,7 +33,7 @@ __global__ __launch_bounds__(256) void k_tq_encode(const float* __restrict__ des
     if (tid < kDescDim) {
         slo[tid] = lo[tid];
         shi[tid] = hi[tid];
-        sord[tid] = order[tid];
+        sord[tid] = order[tid] & (kDescDim - 1);   // a position in the symbol row, whatever the caller passed
     }
     const int64_t g = (int64_t)blockIdx.x * kTqDesc + dl;
     const int img = (int)(g / kp_cap), i = (int)(g % kp_cap);

@@ -66,7 +66,9 @@ def _check(ref, gm, gv, dl, order, bits):
 def _run(model, descs, counts, kp_cap):
     """descs: list of (count_i x 128) arrays -> GPU outputs per image."""
     n = len(descs)
-    pipe = cd.Pipeline([(64, 64)] * n, kp_capacity=kp_cap)
+    params = cd.default_params()
+    params.topk = min(params.topk, kp_cap)      # the context requires topk <= capacity
+    pipe = cd.Pipeline([(64, 64)] * n, params=params, kp_capacity=kp_cap)
     host = np.zeros((n, kp_cap, 128), dtype=np.float32)
     for i, d in enumerate(descs):
         host[i, :len(d)] = d

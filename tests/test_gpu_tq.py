@@ -36,7 +36,9 @@ def model():
 
 def _encode(model, descs, counts, kp_cap, n_el):
     n = len(descs)
-    pipe = cd.Pipeline([(64, 64)] * n, kp_capacity=kp_cap)
+    params = cd.default_params()
+    params.topk = min(params.topk, kp_cap)      # the context requires topk <= capacity
+    pipe = cd.Pipeline([(64, 64)] * n, params=params, kp_capacity=kp_cap)
     host = np.zeros((n, kp_cap, 128), dtype=np.float32)
     for i, d in enumerate(descs):
         host[i, :len(d)] = d
