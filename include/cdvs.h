@@ -352,6 +352,32 @@ typedef struct {
 cdvs_status cdvs_scfv(cdvs_ctx* ctx, const cdvs_scfv_model* model, const float* d_desc, const int32_t* d_count,
                       float* d_gm, float* d_gv, float* d_delta, int32_t* d_order, uint32_t* d_bits, void* stream);
 
+/* For callers that cannot allocate device memory (code under graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc): cdvs_scfv without a
+ * context.  It allocates nothing -- no hipMalloc, hipFree or allocating
+ * library call -- and keeps its scratch in one file-scope device array of
+ * CDVS_SCFV_STATIC_BYTES (8.7 MB) per GPU, held until the process ends: the
+ * model's derived constants (196 KB) and 64 blocks of per-part sums
+ * (130 KB each).  Its device address is looked up on the first call on each
+ * device.  Batches of at most 32 images are split into parts (as many as fit
+ * in the 64 blocks, at most one per 32-descriptor tile of kp_capacity) whose
+ * sums a second kernel adds up; larger batches take one workgroup per image
+ * and use only the constants.  The outputs are those of cdvs_scfv (same
+ * definitions, shapes and layouts; sums in another order, so equal up to
+ * single-precision rounding).  d_desc is n_images x kp_capacity x 128 floats
+ * (16-byte aligned), d_count n_images int32 (clamped to 0..kp_capacity).
+ * Argument errors (null pointers, n_images outside 0..CDVS_MAX_IMAGES,
+ * kp_capacity outside 1..CDVS_MAX_KP_CAPACITY, misalignment) return
+ * CDVS_ERR_ARG before anything is enqueued, with a message from
+ * cdvs_last_error(NULL) (per thread).  Every call on one GPU shares that
+ * GPU's array and overwrites what it needs before reading it, so calls that
+ * overlap on one GPU (other streams, other threads) race and must be
+ * serialised by the caller. */
+#define CDVS_SCFV_STATIC_BYTES 8720384
+cdvs_status cdvs_scfv_noalloc(const cdvs_scfv_model* model, const float* d_desc, const int32_t* d_count,
+                              int32_t n_images, int32_t kp_capacity, float* d_gm, float* d_gv, float* d_delta,
+                              int32_t* d_order, uint32_t* d_bits, void* stream);
+
 /* ---------------------------------------------------------------------- */
 /* Surrogate candidate mask (a small learned CNN; not from the paper).       */
 /* ---------------------------------------------------------------------- */

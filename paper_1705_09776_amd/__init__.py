@@ -32,6 +32,7 @@ CNN_CHANNELS = 16
 CNN_HEADS = 6
 CNN_LAYERS = 4
 DESC_DIM = 128
+MAX_KP_CAPACITY = 8192      # CDVS_MAX_KP_CAPACITY
 
 _STATUS = {0: "CDVS_OK", -1: "CDVS_ERR_ARG", -2: "CDVS_ERR_SHAPE", -3: "CDVS_ERR_CAPACITY",
            -4: "CDVS_ERR_HIP", -5: "CDVS_ERR_STATE", -6: "CDVS_ERR_VERSION"}
@@ -71,7 +72,7 @@ EXPORTS = ["cdvs_default_params", "cdvs_validate", "cdvs_ctx_create", "cdvs_ctx_
            "cdvs_graph_capture", "cdvs_graph_launch", "cdvs_profile_enable", "cdvs_profile_read",
            "cdvs_cnn_cells", "cdvs_cnn_cell_layout", "cdvs_cnn_forward", "cdvs_cnn_labels", "cdvs_cnn_backward",
            "cdvs_cnn_adam", "cdvs_autotune", "cdvs_tune_get", "cdvs_tune_set",
-           "cdvs_stream", "cdvs_standin_consume", "cdvs_scfv", "cdvs_encode",
+           "cdvs_stream", "cdvs_standin_consume", "cdvs_scfv", "cdvs_scfv_noalloc", "cdvs_encode",
            "cdvs_relevance_select"]
 TUNE_VARIANTS = 4
 DETECT_VARIANTS = 2
@@ -146,6 +147,7 @@ def lib():
         "cdvs_profile_enable": (i32, [vp, i32]),
         "cdvs_profile_read": (i32, [vp, vp, vp]),
         "cdvs_scfv": (i32, [vp, ctypes.POINTER(ScfvModel), vp, vp, vp, vp, vp, vp, vp, vp]),
+        "cdvs_scfv_noalloc": (i32, [ctypes.POINTER(ScfvModel), vp, vp, i32, i32, vp, vp, vp, vp, vp, vp]),
         "cdvs_encode": (i32, [vp, ctypes.POINTER(TqModel), i32, vp, vp, vp, vp]),
         "cdvs_relevance_select": (i32, [vp, ctypes.POINTER(RelevanceModel), vp, vp, i32, vp, vp, vp, vp]),
     }
@@ -358,6 +360,14 @@ def cdvs_scfv(ctx, scfv: Scfv, d_desc, d_count, stream=None):
     _check(ctx, lib().cdvs_scfv(ctx, ctypes.byref(scfv.model), _ptr(d_desc), _ptr(d_count), _ptr(scfv.gm),
                                 _ptr(scfv.gv), _ptr(scfv.delta), _ptr(scfv.order), _ptr(scfv.bits),
                                 _stream(stream)))
+
+
+def cdvs_scfv_noalloc(scfv: Scfv, d_desc, d_count, n_images: int, kp_capacity: int, stream=None):
+    """cdvs_scfv without a context, on the library's static scratch (no
+    device allocation); outputs to scfv's buffers."""
+    _check(None, lib().cdvs_scfv_noalloc(ctypes.byref(scfv.model), _ptr(d_desc), _ptr(d_count), int(n_images),
+                                         int(kp_capacity), _ptr(scfv.gm), _ptr(scfv.gv), _ptr(scfv.delta),
+                                         _ptr(scfv.order), _ptr(scfv.bits), _stream(stream)))
 
 
 def cdvs_plane_layout(ctx, image: int, octave: int, k: int):

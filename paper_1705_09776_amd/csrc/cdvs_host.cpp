@@ -715,6 +715,39 @@ cdvs_status cdvs_scfv(cdvs_ctx* ctx, const cdvs_scfv_model* model, const float* 
     return CDVS_OK;
 }
 
+static_assert(CDVS_SCFV_STATIC_BYTES == kScfvStaticFloats * 4, "static scratch size");
+
+cdvs_status cdvs_scfv_noalloc(const cdvs_scfv_model* model, const float* d_desc, const int32_t* d_count,
+                              int32_t n_images, int32_t kp_capacity, float* d_gm, float* d_gv, float* d_delta,
+                              int32_t* d_order, uint32_t* d_bits, void* stream) {
+    if (!model || !model->d_pca_mean || !model->d_pca_matrix || !model->d_weights || !model->d_means ||
+        !model->d_variances || !d_desc || !d_count || !d_gm || !d_gv || !d_delta || !d_order || !d_bits)
+        return fail(nullptr, CDVS_ERR_ARG, "cdvs_scfv_noalloc: null pointer");
+    if (n_images < 0 || n_images > CDVS_MAX_IMAGES)
+        return fail(nullptr, CDVS_ERR_ARG, "cdvs_scfv_noalloc: n_images %d outside 0..%d", n_images, CDVS_MAX_IMAGES);
+    if (kp_capacity < 1 || kp_capacity > CDVS_MAX_KP_CAPACITY)
+        return fail(nullptr, CDVS_ERR_ARG, "cdvs_scfv_noalloc: kp_capacity %d outside 1..%d (the maximum)",
+                    kp_capacity, CDVS_MAX_KP_CAPACITY);
+    if ((((uintptr_t)d_desc | (uintptr_t)model->d_pca_mean) & 15) != 0)
+        return fail(nullptr, CDVS_ERR_ARG, "cdvs_scfv_noalloc: d_desc and the PCA mean must be 16-byte aligned");
+    if (n_images == 0) return CDVS_OK;
+    const int splits = scfv_static_splits(n_images, kp_capacity);
+    if (splits > 1 && (int64_t)n_images * splits > kScfvStaticPartials)
+        return fail(nullptr, CDVS_ERR_CAPACITY,
+                    "cdvs_scfv_noalloc: %d images in %d parts need %lld partial blocks, the static scratch holds %d",
+                    n_images, splits, (long long)n_images * splits, kScfvStaticPartials);
+    float* scr = nullptr;
+    hipError_t e = scfv_static_scratch(&scr);
+    if (e != hipSuccess)
+        return fail(nullptr, CDVS_ERR_HIP, "cdvs_scfv_noalloc: device address of the static scratch: %s",
+                    hipGetErrorString(e));
+    e = launch_scfv_static(scr, splits, d_desc, d_count, n_images, kp_capacity, model->d_pca_mean,
+                           model->d_pca_matrix, model->d_weights, model->d_means, model->d_variances, d_gm, d_gv,
+                           d_delta, d_order, d_bits, (hipStream_t)stream);
+    if (e != hipSuccess) return fail(nullptr, CDVS_ERR_HIP, "cdvs_scfv_noalloc: launch: %s", hipGetErrorString(e));
+    return CDVS_OK;
+}
+
 static_assert(CDVS_REL_FEATURES == kRelFeatures && CDVS_REL_EDGES == kRelEdges && CDVS_REL_BINS == kRelBins,
               "relevance tables");
 

@@ -207,6 +207,24 @@ hipError_t launch_scfv(const float* desc, const int32_t* count, int n_images, in
                        const float* pca_matrix, const float* weights, const float* means, const float* vars,
                        float* prep, float* gm, float* gv, float* delta, int32_t* order, uint32_t* bits,
                        hipStream_t s);
+// The allocation-free form keeps the same constants and, for small
+// batches, per-part sums S0, S1, S2 (kScfvPartialFloats each) of images
+// split into parts, in one file-scope device array per GPU: the constants
+// first, then kScfvStaticPartials partial blocks.
+constexpr int kScfvPartialFloats = kScfvComponents * (1 + 2 * kScfvDim);                   // 33280
+constexpr int kScfvStaticPartials = 64;
+constexpr int kScfvStaticPrepFloats = (kScfvPrepFloats + 63) / 64 * 64;
+constexpr int64_t kScfvStaticFloats = kScfvStaticPrepFloats + (int64_t)kScfvStaticPartials * kScfvPartialFloats;
+// Parts per image for a batch: 1 (one workgroup per image, no partial sums)
+// unless the batch is at most half the partial blocks, then as many parts
+// as fit, at most one per 32-descriptor tile.
+int scfv_static_splits(int n_images, int kp_cap);
+// Device address of this GPU's array (looked up once per device).
+hipError_t scfv_static_scratch(float** out);
+hipError_t launch_scfv_static(float* scr, int splits, const float* desc, const int32_t* count, int n_images,
+                              int kp_cap, const float* pca_mean, const float* pca_matrix, const float* weights,
+                              const float* means, const float* vars, float* gm, float* gv, float* delta,
+                              int32_t* order, uint32_t* bits, hipStream_t s);
 
 // Keypoint relevance: five characteristics, 15 bin edges and 16 table
 // values each.

@@ -24,6 +24,9 @@
 // MFMA layouts (wave64): 32x32x2 f32: lane l holds A[l%32][l/32] and
 // B[l/32][l%32], and D[8(i/4) + 4(l/32) + i%4][l%32] in register i = 0..15;
 // 16x16x4 f32: A[l%16][l/16], B[l/16][l%16], D[4(l/16) + r][l%16], r = 0..3.
+#include <algorithm>
+#include <mutex>
+
 #include "cdvs_internal.h"
 
 namespace cdvs {
@@ -81,16 +84,85 @@ __device__ __forceinline__ float half_sum(float v) {
     return v;
 }
 
-// One workgroup of 8 waves per image.  Wave w owns components
-// [64 w, 64 w + 64): their logits and their gradient accumulators live in
-// its registers for the whole image.
+// Output stage of one image, shared by the one-workgroup-per-image kernel
+// and the kernel that completes split images: s0s[] holds S0 of every
+// component, acc1/acc2 this lane's S1/S2 entries in the 32x32 MFMA
+// accumulator layout (component 64 wave + 32 t + 8 (i/4) + 4 (lane/32) +
+// i%4, dimension lane%32).  Writes the gradients (Eqs. (7), (12), (14)),
+// delta (Eq. (8)), the sign bits and the component order.
+__device__ __forceinline__ void scfv_output(int img, int K, int wave, int lane, const float* s0s,
+                                            const f16v (&acc1)[2], const f16v (&acc2)[2],
+                                            const float* __restrict__ means, const float* __restrict__ vars,
+                                            const float* __restrict__ prep, float* __restrict__ gm_out,
+                                            float* __restrict__ gv_out, float* __restrict__ delta_out,
+                                            int32_t* __restrict__ order_out, uint32_t* __restrict__ bits_out,
+                                            float* skey, int* sidx) {
+    const int tid = threadIdx.x, h = lane >> 5, k = lane & 31;
+    const float invK = K > 0 ? 1.f / (float)K : 0.f;
+#pragma unroll
+    for (int t = 0; t < 2; ++t)
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+            const int comp = CPW * wave + 32 * t + 8 * (i >> 2) + 4 * h + (i & 3);
+            const float S0 = s0s[comp], S1 = acc1[t][i], S2 = acc2[t][i];
+            const float m = means[comp * PD + k], v = vars[comp * PD + k];
+            const float isg = prep[kScfvPrepIsig + comp * PD + k], rsw = prep[kScfvPrepRsw + comp];
+            const float gm = (S1 - S0 * m) * isg * (invK * rsw);
+            const float gv = (S2 - 2.f * S1 * m + S0 * (m * m - v)) * (isg * isg) * (invK * rsw * 0.70710678118654752f);
+            const int64_t o = ((int64_t)img * NC + comp) * PD + k;
+            gm_out[o] = gm;
+            gv_out[o] = gv;
+            const float mean = half_sum(gm) * (1.f / PD);
+            const float dv = gm - mean;
+            const float dl = sqrtf(half_sum(dv * dv) * (1.f / PD));
+            const uint64_t bm = __ballot(gm > 0.f), bv = __ballot(gv > 0.f);
+            if (k == 0) {
+                delta_out[(int64_t)img * NC + comp] = dl;
+                bits_out[((int64_t)img * NC + comp) * 2] = (uint32_t)(bm >> (32 * h));
+                bits_out[((int64_t)img * NC + comp) * 2 + 1] = (uint32_t)(bv >> (32 * h));
+                skey[comp] = dl;
+                sidx[comp] = comp;
+            }
+        }
+    __syncthreads();
+    // rank by delta, descending, ties by lower index: bitonic sort of 512
+    // (key, index) pairs, one per thread
+    for (int size = 2; size <= NC; size <<= 1)
+        for (int stride = size >> 1; stride > 0; stride >>= 1) {
+            const int j = tid ^ stride;
+            if (j > tid) {
+                const float ka = skey[tid], kb = skey[j];
+                const int ia = sidx[tid], ib = sidx[j];
+                // a before b: larger key, or equal key and lower index
+                const bool a_first = ka > kb || (ka == kb && ia < ib);
+                const bool up = (tid & size) == 0;
+                if (up != a_first) {
+                    skey[tid] = kb;
+                    skey[j] = ka;
+                    sidx[tid] = ib;
+                    sidx[j] = ia;
+                }
+            }
+            __syncthreads();
+        }
+    order_out[(int64_t)img * NC + tid] = sidx[tid];
+}
+
+// One workgroup of 8 waves per image (SPLIT = false), or per part of an
+// image (SPLIT = true: image blockIdx.x / splits takes descriptor tiles
+// [part * tiles_per_part, (part + 1) * tiles_per_part) and writes its sums
+// S0, S1, S2 to partial block blockIdx.x, which k_scfv_join adds up).
+// Wave w owns components [64 w, 64 w + 64): their logits and their
+// gradient accumulators live in its registers for the whole range.
+template <bool SPLIT>
 __global__ __launch_bounds__(512) void k_scfv(const float* __restrict__ desc, const int32_t* __restrict__ count,
-                                              int kp_cap, const float* __restrict__ pca_mean,
+                                              int kp_cap, int splits, int tiles_per_part,
+                                              const float* __restrict__ pca_mean,
                                               const float* __restrict__ pca_matrix, const float* __restrict__ means,
                                               const float* __restrict__ vars, const float* __restrict__ prep,
-                                              float* __restrict__ gm_out, float* __restrict__ gv_out,
-                                              float* __restrict__ delta_out, int32_t* __restrict__ order_out,
-                                              uint32_t* __restrict__ bits_out) {
+                                              float* __restrict__ partial, float* __restrict__ gm_out,
+                                              float* __restrict__ gv_out, float* __restrict__ delta_out,
+                                              int32_t* __restrict__ order_out, uint32_t* __restrict__ bits_out) {
     __shared__ float Dl[TD * DSTR];        // descriptor tile minus the PCA mean
     __shared__ float XXt[64 * TD];         // [X | X.*X] by columns: [k][descriptor]
     __shared__ float XXr[TD * XRS];        // [X | X.*X] by rows: [descriptor][k]
@@ -100,9 +172,12 @@ __global__ __launch_bounds__(512) void k_scfv(const float* __restrict__ desc, co
     __shared__ float skey[NC];
     __shared__ int sidx[NC];
 
-    const int img = blockIdx.x;
+    const int img = SPLIT ? blockIdx.x / splits : blockIdx.x;
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, h = lane >> 5, c32 = lane & 31;
     const int K = min(max(count[img], 0), kp_cap);
+    // descriptor range of this workgroup: [tbeg, tend)
+    const int tbeg = SPLIT ? min(K, (blockIdx.x % splits) * tiles_per_part * TD) : 0;
+    const int tend = SPLIT ? min(K, tbeg + tiles_per_part * TD) : K;
     const float* D = desc + (int64_t)img * kp_cap * kDescDim;
     const float* Bp = prep + kScfvPrepB;
 
@@ -124,12 +199,12 @@ __global__ __launch_bounds__(512) void k_scfv(const float* __restrict__ desc, co
     }
     float s0[2] = {0.f, 0.f};
 
-    for (int t0 = 0; t0 < K; t0 += TD) {
+    for (int t0 = tbeg; t0 < tend; t0 += TD) {
         __syncthreads();   // the previous tile's readers are done
         for (int e = tid; e < TD * 32; e += NW * 64) {
             const int r = e >> 5, q = e & 31;
             float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
-            if (t0 + r < K) {
+            if (t0 + r < tend) {
                 v = *reinterpret_cast<const float4*>(D + (int64_t)(t0 + r) * kDescDim + 4 * q);
                 const float4 m = *reinterpret_cast<const float4*>(pca_mean + 4 * q);
                 v.x -= m.x;
@@ -196,7 +271,7 @@ __global__ __launch_bounds__(512) void k_scfv(const float* __restrict__ desc, co
 #pragma unroll
             for (int w = 0; w < NW; ++w) S += reds[w][tid] * __expf(redm[w][tid] - M);
             rowq[tid][0] = M;
-            rowq[tid][1] = (t0 + tid < K) ? 1.f / S : 0.f;
+            rowq[tid][1] = (t0 + tid < tend) ? 1.f / S : 0.f;
         }
         __syncthreads();
 #pragma unroll
@@ -222,63 +297,69 @@ __global__ __launch_bounds__(512) void k_scfv(const float* __restrict__ desc, co
         }
     }
 
-    // epilogue: S0 per component (this lane's logit column), then the
-    // gradients of the rows this lane's accumulators hold
+    // S0 per component (this lane's logit column), then either the sums of
+    // this part to its partial block or the image's outputs
 #pragma unroll
     for (int t = 0; t < 2; ++t) {
         const float v = s0[t] + __shfl_xor(s0[t], 32);
-        if (h == 0) s0s[CPW * wave + 32 * t + c32] = v;
+        if (h == 0) {
+            if constexpr (SPLIT) partial[(int64_t)blockIdx.x * kScfvPartialFloats + CPW * wave + 32 * t + c32] = v;
+            else s0s[CPW * wave + 32 * t + c32] = v;
+        }
     }
-    __syncthreads();
-    const float invK = K > 0 ? 1.f / (float)K : 0.f;
-    const int k = c32;
+    if constexpr (SPLIT) {
+        float* P = partial + (int64_t)blockIdx.x * kScfvPartialFloats + NC;
+#pragma unroll
+        for (int t = 0; t < 2; ++t)
+#pragma unroll
+            for (int i = 0; i < 16; ++i) {
+                const int comp = CPW * wave + 32 * t + 8 * (i >> 2) + 4 * h + (i & 3);
+                P[comp * PD + c32] = acc1[t][i];
+                P[NC * PD + comp * PD + c32] = acc2[t][i];
+            }
+    } else {
+        __syncthreads();
+        scfv_output(img, K, wave, lane, s0s, acc1, acc2, means, vars, prep, gm_out, gv_out, delta_out, order_out,
+                    bits_out, skey, sidx);
+    }
+}
+
+// Completes images aggregated in `splits` parts: adds up their partial
+// blocks (in part order) and writes the outputs as k_scfv does.
+__global__ __launch_bounds__(512) void k_scfv_join(const float* __restrict__ partial, int splits,
+                                                   const int32_t* __restrict__ count, int kp_cap,
+                                                   const float* __restrict__ means, const float* __restrict__ vars,
+                                                   const float* __restrict__ prep, float* __restrict__ gm_out,
+                                                   float* __restrict__ gv_out, float* __restrict__ delta_out,
+                                                   int32_t* __restrict__ order_out, uint32_t* __restrict__ bits_out) {
+    __shared__ float s0s[NC];
+    __shared__ float skey[NC];
+    __shared__ int sidx[NC];
+    const int img = blockIdx.x;
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, h = lane >> 5, c32 = lane & 31;
+    const int K = min(max(count[img], 0), kp_cap);
+    const float* P0 = partial + (int64_t)img * splits * kScfvPartialFloats;
+    float s = 0.f;
+    for (int p = 0; p < splits; ++p) s += P0[(int64_t)p * kScfvPartialFloats + tid];
+    s0s[tid] = s;
+    f16v acc1[2], acc2[2];
 #pragma unroll
     for (int t = 0; t < 2; ++t)
 #pragma unroll
         for (int i = 0; i < 16; ++i) {
             const int comp = CPW * wave + 32 * t + 8 * (i >> 2) + 4 * h + (i & 3);
-            const float S0 = s0s[comp], S1 = acc1[t][i], S2 = acc2[t][i];
-            const float m = means[comp * PD + k], v = vars[comp * PD + k];
-            const float isg = prep[kScfvPrepIsig + comp * PD + k], rsw = prep[kScfvPrepRsw + comp];
-            const float gm = (S1 - S0 * m) * isg * (invK * rsw);
-            const float gv = (S2 - 2.f * S1 * m + S0 * (m * m - v)) * (isg * isg) * (invK * rsw * 0.70710678118654752f);
-            const int64_t o = ((int64_t)img * NC + comp) * PD + k;
-            gm_out[o] = gm;
-            gv_out[o] = gv;
-            const float mean = half_sum(gm) * (1.f / PD);
-            const float dv = gm - mean;
-            const float dl = sqrtf(half_sum(dv * dv) * (1.f / PD));
-            const uint64_t bm = __ballot(gm > 0.f), bv = __ballot(gv > 0.f);
-            if (c32 == 0) {
-                delta_out[(int64_t)img * NC + comp] = dl;
-                bits_out[((int64_t)img * NC + comp) * 2] = (uint32_t)(bm >> (32 * h));
-                bits_out[((int64_t)img * NC + comp) * 2 + 1] = (uint32_t)(bv >> (32 * h));
-                skey[comp] = dl;
-                sidx[comp] = comp;
+            float a = 0.f, b = 0.f;
+            for (int p = 0; p < splits; ++p) {
+                const float* P = P0 + (int64_t)p * kScfvPartialFloats + NC;
+                a += P[comp * PD + c32];
+                b += P[NC * PD + comp * PD + c32];
             }
+            acc1[t][i] = a;
+            acc2[t][i] = b;
         }
     __syncthreads();
-    // rank by delta, descending, ties by lower index: bitonic sort of 512
-    // (key, index) pairs, one per thread
-    for (int size = 2; size <= NC; size <<= 1)
-        for (int stride = size >> 1; stride > 0; stride >>= 1) {
-            const int j = tid ^ stride;
-            if (j > tid) {
-                const float ka = skey[tid], kb = skey[j];
-                const int ia = sidx[tid], ib = sidx[j];
-                // a before b: larger key, or equal key and lower index
-                const bool a_first = ka > kb || (ka == kb && ia < ib);
-                const bool up = (tid & size) == 0;
-                if (up != a_first) {
-                    skey[tid] = kb;
-                    skey[j] = ka;
-                    sidx[tid] = ib;
-                    sidx[j] = ia;
-                }
-            }
-            __syncthreads();
-        }
-    order_out[(int64_t)img * NC + tid] = sidx[tid];
+    scfv_output(img, K, wave, lane, s0s, acc1, acc2, means, vars, prep, gm_out, gv_out, delta_out, order_out,
+                bits_out, skey, sidx);
 }
 
 }  // namespace
@@ -289,8 +370,66 @@ hipError_t launch_scfv(const float* desc, const int32_t* count, int n_images, in
                        hipStream_t s) {
     if (n_images <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_scfv_prep, dim3(NC / 8), dim3(256), 0, s, weights, means, vars, prep);
-    hipLaunchKernelGGL(k_scfv, dim3(n_images), dim3(NW * 64), 0, s, desc, count, kp_cap, pca_mean, pca_matrix, means,
-                       vars, prep, gm, gv, delta, order, bits);
+    hipLaunchKernelGGL(k_scfv<false>, dim3(n_images), dim3(NW * 64), 0, s, desc, count, kp_cap, 1, 0, pca_mean,
+                       pca_matrix, means, vars, prep, nullptr, gm, gv, delta, order, bits);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------
+// The allocation-free form: its scratch is this file-scope array, one copy
+// per GPU, looked up once per device with hipGetSymbolAddress.  In host
+// code `scratch` names a host-side stand-in, never the device memory: only
+// the looked-up address is passed to kernels.
+static __device__ __align__(256) float scratch[kScfvStaticFloats];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+float* g_scratch_dev[kMaxDevices] = {};
+}  // namespace
+
+int scfv_static_splits(int n_images, int kp_cap) {
+    if (n_images <= 0 || n_images > kScfvStaticPartials / 2) return 1;
+    const int tiles = (kp_cap + TD - 1) / TD;
+    return std::max(1, std::min(tiles, kScfvStaticPartials / n_images));
+}
+
+hipError_t scfv_static_scratch(float** out) {
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_dev[dev]) {
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        g_scratch_dev[dev] = static_cast<float*>(p);
+    }
+    *out = g_scratch_dev[dev];
+    return hipSuccess;
+}
+
+hipError_t launch_scfv_static(float* scr, int splits, const float* desc, const int32_t* count, int n_images,
+                              int kp_cap, const float* pca_mean, const float* pca_matrix, const float* weights,
+                              const float* means, const float* vars, float* gm, float* gv, float* delta,
+                              int32_t* order, uint32_t* bits, hipStream_t s) {
+    if (n_images <= 0) return hipSuccess;
+    float* prep = scr;
+    hipLaunchKernelGGL(k_scfv_prep, dim3(NC / 8), dim3(256), 0, s, weights, means, vars, prep);
+    if (splits <= 1) {
+        hipLaunchKernelGGL(k_scfv<false>, dim3(n_images), dim3(NW * 64), 0, s, desc, count, kp_cap, 1, 0, pca_mean,
+                           pca_matrix, means, vars, prep, nullptr, gm, gv, delta, order, bits);
+    } else {
+        float* partial = scr + kScfvStaticPrepFloats;
+        const int tiles = (kp_cap + TD - 1) / TD;
+        const int per = (tiles + splits - 1) / splits;
+        hipLaunchKernelGGL(k_scfv<true>, dim3(n_images * splits), dim3(NW * 64), 0, s, desc, count, kp_cap, splits,
+                           per, pca_mean, pca_matrix, means, vars, prep, partial, nullptr, nullptr, nullptr, nullptr,
+                           nullptr);
+        hipLaunchKernelGGL(k_scfv_join, dim3(n_images), dim3(NW * 64), 0, s, partial, splits, count, kp_cap, means,
+                           vars, prep, gm, gv, delta, order, bits);
+    }
     return hipGetLastError();
 }
 

@@ -142,3 +142,26 @@ def test_standin_consumer_on_host():
     # a chunk past the sink's size is refused
     assert L.cdvs_standin_consume(ctypes.addressof(sink), 2, n, cap, counts.ctypes.data, None, desc.ctypes.data) != 0
     assert L.cdvs_stream(None, None, 0, 0, None, None, None, None) == cd.CDVS_ERR_STATE
+
+
+def test_scfv_noalloc_rejects_arguments_without_a_gpu():
+    """The allocation-free SCFV entry point checks its arguments on the host
+    before any device call: null pointers, a capacity beyond the maximum,
+    an image count out of range and misalignment, each with a message."""
+    import ctypes
+    import paper_1705_09776_amd as cd
+    L = cd.lib()
+    m = cd.ScfvModel(16, 16, 16, 16, 16)       # fake, never dereferenced
+    fake = ctypes.c_void_p(4096)
+
+    def call(model, desc, n, cap):
+        return L.cdvs_scfv_noalloc(model, desc, fake, n, cap, fake, fake, fake, fake, fake, None)
+
+    assert call(None, fake, 1, 100) == cd.CDVS_ERR_ARG
+    assert b"null" in L.cdvs_last_error(None)
+    assert call(ctypes.byref(m), fake, 1, cd.MAX_KP_CAPACITY + 1) == cd.CDVS_ERR_ARG
+    assert b"maximum" in L.cdvs_last_error(None)
+    assert call(ctypes.byref(m), fake, -1, 100) == cd.CDVS_ERR_ARG
+    assert call(ctypes.byref(m), ctypes.c_void_p(4100), 1, 100) == cd.CDVS_ERR_ARG
+    assert b"aligned" in L.cdvs_last_error(None)
+    assert call(ctypes.byref(m), fake, 0, 100) == cd.CDVS_OK       # nothing to do, nothing enqueued
