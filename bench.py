@@ -366,6 +366,129 @@ def stream_leg(n_images=4096, chunk=256, threads=16):
                       "finished the last chunk); gpu_only: the same chunks gated, eager, no hand-off"}
 
 
+SCFV_MODEL = os.path.join(ROOT, "paper_1705_09776_amd", "weights", "scfv_standin.npz")
+TQ_MODEL = os.path.join(ROOT, "paper_1705_09776_amd", "weights", "tq_standin.npz")
+REL_MODEL = os.path.join(ROOT, "paper_1705_09776_amd", "weights", "relevance_standin.npz")
+PEAK_FP32_MFMA_TFLOPS = 157.3    # MI355X dense FP32 matrix rate
+# SCFV arithmetic per descriptor: PCA 32 x 128, then logits and gradient
+# sums against 512 components over the 64 columns [x | x.*x] (multiply-adds
+# as two flops)
+SCFV_FLOP_PER_DESC = 2 * 32 * 128 + 2 * 512 * 64 + 2 * 512 * 64
+
+
+def _timed(fn, steps):
+    """Mean ms of fn() over `steps` runs on torch's current stream (events)."""
+    import torch
+    fn()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(steps):
+        fn()
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / steps
+
+
+def aggregate_leg(pipe, steps, B):
+    """The steps the paper places beside description (Sec. III-B to III-D)
+    on the plain pass's outputs, each kernel timed with events on its own
+    stream: relevance selection of 300 of each image's 1000 detected
+    keypoints, transform coding of the 1000 descriptors per image (all 128
+    elements), SCFV aggregation of the same descriptors (stand-in models);
+    and the allocation-free SCFV on one image (split over workgroups)
+    against the context form on one image."""
+    import numpy as np
+    import torch
+    import paper_1705_09776_amd as cd
+    rel = cd.Relevance(dict(np.load(REL_MODEL)))
+    tq = cd.Tq(dict(np.load(TQ_MODEL)))
+    S = cd.Scfv(dict(np.load(SCFV_MODEL)), B)
+    kp_out, cnt_out = torch.zeros_like(pipe.d_kp), torch.zeros_like(pipe.d_count)
+    codes = torch.zeros((B, pipe.kp_capacity, cd.TQ_WORDS), dtype=torch.int32, device="cuda")
+    n_keep = 300
+
+    def one():
+        cd.cdvs_relevance_select(pipe.ctx, rel, pipe.d_kp, pipe.d_count, n_keep, kp_out, cnt_out)
+        cd.cdvs_encode(pipe.ctx, tq, 128, pipe.d_desc, pipe.d_count_ori, codes)
+        cd.cdvs_scfv(pipe.ctx, S, pipe.d_desc, pipe.d_count_ori)
+
+    one()
+    torch.cuda.synchronize()
+    cd.cdvs_profile_enable(pipe.ctx, True)
+    for _ in range(steps):
+        one()
+    torch.cuda.synchronize()
+    prof = cd.cdvs_profile_read(pipe.ctx)
+    cd.cdvs_profile_enable(pipe.ctx, False)
+    n_kp = int(pipe.d_count.sum().item())
+    n_desc = int(pipe.d_count_ori.sum().item())
+    ms = {k: prof[k][0] / steps for k in ("relevance", "encode", "scfv")}
+    rel_bytes = n_kp * 48 + int(cnt_out.sum().item()) * (48 + 4)
+    enc_bytes = n_desc * (512 + 4 * cd.TQ_WORDS)
+    scfv_flop = n_desc * SCFV_FLOP_PER_DESC
+    out = {
+        "relevance": {"ms": round(ms["relevance"], 4), "images_per_s": round(B / (ms["relevance"] * 1e-3), 1),
+                      "keep": n_keep,
+                      "roofline": {"bound": "hbm", "achieved": round(rel_bytes / (ms["relevance"] * 1e-3) / 1e9, 1),
+                                   "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                                   "frac": round(rel_bytes / (ms["relevance"] * 1e-3) / 1e9 / PEAK_HBM_GBS, 4)}},
+        "encode": {"ms": round(ms["encode"], 4), "descriptors_per_s": round(n_desc / (ms["encode"] * 1e-3), 1),
+                   "roofline": {"bound": "hbm", "achieved": round(enc_bytes / (ms["encode"] * 1e-3) / 1e9, 1),
+                                "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                                "frac": round(enc_bytes / (ms["encode"] * 1e-3) / 1e9 / PEAK_HBM_GBS, 4)}},
+        "scfv": {"ms": round(ms["scfv"], 4), "images_per_s": round(B / (ms["scfv"] * 1e-3), 1),
+                 "roofline": {"bound": "mfma", "achieved": round(scfv_flop / (ms["scfv"] * 1e-3) / 1e12, 2),
+                              "peak": PEAK_FP32_MFMA_TFLOPS, "unit": "TFLOP/s",
+                              "frac": round(scfv_flop / (ms["scfv"] * 1e-3) / 1e12 / PEAK_FP32_MFMA_TFLOPS, 4)}},
+        "descriptors_per_image": round(n_desc / B, 1),
+    }
+    # one image: the context form (one workgroup) and the allocation-free
+    # form (the image split into parts over workgroups)
+    S1 = cd.Scfv(dict(np.load(SCFV_MODEL)), 1)
+    d1, c1 = pipe.d_desc[:1].contiguous(), pipe.d_count_ori[:1].contiguous()
+    one_ctx = cd.Pipeline([(640, 480)])
+    out["scfv_one_image_ms"] = {
+        "context_form": round(_timed(lambda: cd.cdvs_scfv(one_ctx.ctx, S1, d1, c1), 50), 4),
+        "noalloc_split": round(_timed(lambda: cd.cdvs_scfv_noalloc(S1, d1, c1, 1, pipe.kp_capacity), 50), 4)}
+    out["timing"] = (f"{steps} rounds of the three calls, per-kernel events; one-image SCFV: mean of 50 calls "
+                     "between events (model constants included)")
+    return out
+
+
+def front_leg(steps, n=256):
+    """The front end on n images 1280x960 (the high-resolution recipe,
+    rendered on the device) brought down to 640x480, then the plain pass:
+    the front-end kernel's rate and the whole pass's images/s from the
+    high-resolution inputs."""
+    import torch
+    import paper_1705_09776_amd as cd
+    import synth
+    W, H = 1280, 960
+    src = synth.device_batch(synth.SEED_HIRES, n, W, H, 400, 1200, smax=40.0)
+    sdesc = [cd.ImageDesc(i * W * H, W, H, W, 0) for i in range(n)]
+    d_sd = cd.descs_to_device(sdesc)
+    wo, ho = cd.cdvs_front_size(W, H)
+    pipe = cd.Pipeline([(wo, ho)] * n)
+    pipe.front_end(src, d_sd)
+    if pipe.sync_status() != cd.CDVS_OK:
+        raise RuntimeError("front end rejected the batch")
+    front_ms = _timed(lambda: pipe.front_end(src, d_sd), steps)
+
+    def whole():
+        pipe.front_end(src, d_sd)
+        pipe.run()
+
+    whole_ms = _timed(whole, steps)
+    fb = n * (W * H + wo * ho)
+    return {"images": n, "source": f"{W}x{H}", "output": f"{wo}x{ho}", "front_ms": round(front_ms, 4),
+            "front_images_per_s": round(n / (front_ms * 1e-3), 1),
+            "roofline": {"bound": "hbm", "achieved": round(fb / (front_ms * 1e-3) / 1e9, 1), "peak": PEAK_HBM_GBS,
+                         "unit": "GB/s", "frac": round(fb / (front_ms * 1e-3) / 1e9 / PEAK_HBM_GBS, 4)},
+            "front_plus_plain_images_per_s": round(n / (whole_ms * 1e-3), 1),
+            "timing": f"mean of {steps} eager runs between events (inputs resident in HBM)"}
+
+
 def host_cpu():
     """CPU model name (from /proc/cpuinfo) and logical CPU counts."""
     model = None
@@ -441,6 +564,8 @@ def main():
     ap.add_argument("--no-single", action="store_true")
     ap.add_argument("--no-sparse", action="store_true")
     ap.add_argument("--stream-images", type=int, default=4096)
+    ap.add_argument("--no-aggregate", action="store_true")
+    ap.add_argument("--no-front", action="store_true")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -572,6 +697,12 @@ def main():
         plain_kp = [k.copy() for k in pipe.keypoints()]
         out["plain_eager_images_per_s"] = round(B / (eager_ms * 1e-3), 1)
         out["gated"] = gated_leg(pipe, args.steps, B, plain_kp)
+    if not args.no_aggregate and os.path.exists(SCFV_MODEL):
+        log("[bench] relevance, transform coding and SCFV on the plain pass's outputs")
+        out["aggregate"] = aggregate_leg(pipe, args.steps, B)
+    if not args.no_front:
+        log("[bench] front end (1280x960 -> 640x480) and plain pass")
+        out["front"] = front_leg(args.steps)
     if not args.no_single:
         log("[bench] single image latency")
         out["single"] = single_leg()

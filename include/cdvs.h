@@ -200,10 +200,11 @@ cdvs_status cdvs_orient(cdvs_ctx* ctx, const float* d_pyr, const cdvs_keypoint* 
 cdvs_status cdvs_describe(cdvs_ctx* ctx, const float* d_pyr, const cdvs_keypoint* d_kp, const int32_t* d_count,
                           float* d_desc, void* stream);
 
-/* Synchronise `stream`, then return CDVS_ERR_CAPACITY if any call since the
- * last cdvs_sync_status latched a candidate overflow or an inexact top-k
- * (see cdvs_alp_detect), else CDVS_OK; clears the latch.  The only blocking
- * call. */
+/* Synchronise `stream`, then return CDVS_ERR_SHAPE if any call since the
+ * last cdvs_sync_status latched a front-end source that does not fit (see
+ * cdvs_front_end), else CDVS_ERR_CAPACITY if one latched a candidate
+ * overflow or an inexact top-k (see cdvs_alp_detect), else CDVS_OK; clears
+ * the latch.  The only blocking call. */
 cdvs_status cdvs_sync_status(cdvs_ctx* ctx, void* stream);
 
 /* Smallest candidate capacity over the context's images (pre-deduplication
@@ -244,6 +245,33 @@ cdvs_status cdvs_autotune(cdvs_ctx* ctx, const uint8_t* d_images, float* d_pyr, 
                           void* stream);
 int32_t cdvs_tune_get(const cdvs_ctx* ctx, int32_t kernel);
 cdvs_status cdvs_tune_set(cdvs_ctx* ctx, int32_t kernel, int32_t variant);
+
+/* ---------------------------------------------------------------------- */
+/* Front end (Sec. III: inputs reduced to a longer side of at most 640)     */
+/* ---------------------------------------------------------------------- */
+#define CDVS_FRONT_LONG_SIDE 640
+
+/* Output size of the front end for a width x height input (1..CDVS_MAX_SIDE
+ * per side, else CDVS_ERR_SHAPE): unchanged when the longer side L is at
+ * most 640; otherwise the longer side becomes 640 and the shorter one
+ * round(S * 640 / L) (half up), at least 1.  A context for front-end output
+ * is created with these sizes. */
+cdvs_status cdvs_front_size(int32_t width, int32_t height, int32_t* out_width, int32_t* out_height);
+
+/* Brings source image i (d_src_desc[i], a device array of the context's
+ * image count; offsets into d_src) down to the context's image i, written
+ * into d_images at that image's offset and pitch.  Area averaging: every
+ * output pixel is the mean of the source over its footprint, each source
+ * pixel weighted by its overlap area, computed in exact integers and
+ * rounded half up (along an axis of n source and m output pixels, source
+ * pixel i spans [i m, (i+1) m) and output pixel j spans [j n, (j+1) n);
+ * output = floor((2 N + W H) / (2 W H)) for the integer weighted sum N).
+ * An image whose longer side is at most 640 is copied.  A source whose size
+ * (by cdvs_front_size) is not the context's image size, or whose
+ * descriptor is invalid, is skipped and latched: cdvs_sync_status returns
+ * CDVS_ERR_SHAPE.  d_images must not alias d_src. */
+cdvs_status cdvs_front_end(cdvs_ctx* ctx, const uint8_t* d_src, const cdvs_image_desc* d_src_desc,
+                           uint8_t* d_images, void* stream);
 
 /* ---------------------------------------------------------------------- */
 /* Keypoint selection by relevance (Sec. III-B, Eqs. (4)-(5))               */
@@ -513,6 +541,7 @@ typedef enum {
     CDVS_KERNEL_SCFV,         /* SCFV aggregation (model constants + one workgroup per image) */
     CDVS_KERNEL_ENCODE,       /* transform coding and ternary quantisation */
     CDVS_KERNEL_RELEVANCE,    /* relevance scores and per-image selection */
+    CDVS_KERNEL_FRONT,        /* front-end downsampling to a longer side of 640 */
     CDVS_KERNEL_COUNT
 } cdvs_kernel_id;
 

@@ -23,9 +23,11 @@ size rule nor the filter; the readings taken here are:
   3. Rounding.  The u8 output is the mean rounded half up,
      floor((2 N + W H) / (2 W H)), an exact integer decision.
 
-The result is written with library integer matrix products (the overlap
-matrices applied on both sides), which is the definition above evaluated
-exactly.
+The weighted sums are library matrix products (the overlap matrices applied
+on both sides), evaluated in float64: every term and every partial sum is
+an integer no larger than 255 W H < 2^53 (sides up to 8192), so float64
+represents each exactly and the products are exact whatever their order of
+summation -- the definition above evaluated exactly, at BLAS speed.
 """
 from __future__ import annotations
 
@@ -66,6 +68,7 @@ def front(img: np.ndarray, long_side: int = LONG_SIDE) -> np.ndarray:
         return img.astype(np.uint8).copy()
     oy = overlap_matrix(H, ho)               # ho x H
     ox = overlap_matrix(W, wo)               # wo x W
-    N = oy @ img.astype(np.int64) @ ox.T     # exact integer weighted sums
+    assert 255 * W * H < 2 ** 53
+    N = np.rint((oy.astype(np.float64) @ img.astype(np.float64)) @ ox.T.astype(np.float64)).astype(np.int64)
     d = np.int64(W) * np.int64(H)
     return ((2 * N + d) // (2 * d)).astype(np.uint8)

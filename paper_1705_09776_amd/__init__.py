@@ -72,7 +72,7 @@ EXPORTS = ["cdvs_default_params", "cdvs_validate", "cdvs_ctx_create", "cdvs_ctx_
            "cdvs_graph_capture", "cdvs_graph_launch", "cdvs_profile_enable", "cdvs_profile_read",
            "cdvs_cnn_cells", "cdvs_cnn_cell_layout", "cdvs_cnn_forward", "cdvs_cnn_labels", "cdvs_cnn_backward",
            "cdvs_cnn_adam", "cdvs_autotune", "cdvs_tune_get", "cdvs_tune_set",
-           "cdvs_stream", "cdvs_standin_consume", "cdvs_scfv", "cdvs_scfv_noalloc", "cdvs_encode",
+           "cdvs_stream", "cdvs_standin_consume", "cdvs_scfv", "cdvs_scfv_noalloc", "cdvs_encode", "cdvs_front_size", "cdvs_front_end",
            "cdvs_relevance_select"]
 TUNE_VARIANTS = 4
 DETECT_VARIANTS = 2
@@ -80,7 +80,7 @@ DETECT_VARIANTS = 2
 KERNEL_SCALES = 1
 KERNEL_DETECT = 3
 KERNEL_NAMES = ["preblur", "scales", "clear", "detect", "finalize", "orient", "orient_compact", "describe",
-                "cnn_forward", "mask_count", "scfv", "encode", "relevance"]
+                "cnn_forward", "mask_count", "scfv", "encode", "relevance", "front"]
 TQ_WORDS = 8
 SCFV_COMPONENTS = 512
 SCFV_DIM = 32
@@ -147,6 +147,8 @@ def lib():
         "cdvs_profile_enable": (i32, [vp, i32]),
         "cdvs_profile_read": (i32, [vp, vp, vp]),
         "cdvs_scfv": (i32, [vp, ctypes.POINTER(ScfvModel), vp, vp, vp, vp, vp, vp, vp, vp]),
+        "cdvs_front_size": (i32, [i32, i32, ctypes.POINTER(i32), ctypes.POINTER(i32)]),
+        "cdvs_front_end": (i32, [vp, vp, vp, vp, vp]),
         "cdvs_scfv_noalloc": (i32, [ctypes.POINTER(ScfvModel), vp, vp, i32, i32, vp, vp, vp, vp, vp, vp]),
         "cdvs_encode": (i32, [vp, ctypes.POINTER(TqModel), i32, vp, vp, vp, vp]),
         "cdvs_relevance_select": (i32, [vp, ctypes.POINTER(RelevanceModel), vp, vp, i32, vp, vp, vp, vp]),
@@ -216,8 +218,10 @@ def cdvs_describe(ctx, d_pyr, d_kp, d_count, d_desc, stream=None):
 
 
 def cdvs_sync_status(ctx, stream=None) -> int:
+    """The latched device-side status (CDVS_OK, CDVS_ERR_CAPACITY or
+    CDVS_ERR_SHAPE); raises on any other error."""
     st = lib().cdvs_sync_status(ctx, _stream(stream))
-    if st not in (CDVS_OK, CDVS_ERR_CAPACITY):
+    if st not in (CDVS_OK, CDVS_ERR_CAPACITY, CDVS_ERR_SHAPE):
         _check(ctx, st)
     return st
 
@@ -362,6 +366,19 @@ def cdvs_scfv(ctx, scfv: Scfv, d_desc, d_count, stream=None):
                                 _stream(stream)))
 
 
+def cdvs_front_size(width: int, height: int):
+    """(width, height) of the front end's output for a width x height image."""
+    w, h = ctypes.c_int32(), ctypes.c_int32()
+    _check(None, lib().cdvs_front_size(int(width), int(height), ctypes.byref(w), ctypes.byref(h)))
+    return w.value, h.value
+
+
+def cdvs_front_end(ctx, d_src, d_src_desc, d_images, stream=None):
+    """Front end into the context's image layout (d_src_desc: device tensor
+    of n x 24-byte cdvs_image_desc records)."""
+    _check(ctx, lib().cdvs_front_end(ctx, _ptr(d_src), _ptr(d_src_desc), _ptr(d_images), _stream(stream)))
+
+
 def cdvs_scfv_noalloc(scfv: Scfv, d_desc, d_count, n_images: int, kp_capacity: int, stream=None):
     """cdvs_scfv without a context, on the library's static scratch (no
     device allocation); outputs to scfv's buffers."""
@@ -391,6 +408,15 @@ def pack_images(images):
         chunks.append(buf.reshape(-1))
         off += buf.size
     return np.concatenate(chunks), descs
+
+
+def descs_to_device(descs, device="cuda"):
+    """A list of ImageDesc as a device tensor of 24-byte records (the
+    cdvs_image_desc array cdvs_front_end takes)."""
+    import torch
+    arr = (ImageDesc * len(descs))(*descs)
+    host = np.frombuffer(bytes(arr), dtype=np.uint8).copy()
+    return torch.from_numpy(host).to(device)
 
 
 class StreamBuffers(ctypes.Structure):
@@ -476,6 +502,12 @@ class Pipeline:
 
     def upload(self, images):
         self.d_images.copy_(self.torch.from_numpy(self.pack(images)))
+
+    def front_end(self, d_src, d_src_desc, stream=None):
+        """cdvs_front_end: sources (packed u8 on the device, descriptors from
+        descs_to_device) brought down into this batch's images; the context
+        must have been made with cdvs_front_size of each source."""
+        cdvs_front_end(self.ctx, d_src, d_src_desc, self.d_images, stream)
 
     # -- streaming ----------------------------------------------------------
     def stream(self, d_all, n_chunks, params=None, tau=0.1, consumer=None, user=None, keep=None, threads=8,

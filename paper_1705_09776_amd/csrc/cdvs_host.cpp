@@ -50,6 +50,7 @@ struct cdvs_ctx {
     short* d_cnn_frag = nullptr;  // packed weight fragments of the fused inference kernel
     float* d_scfv_prep = nullptr; // SCFV per-call model constants (kScfvPrepFloats)
     int32_t* d_wh = nullptr;      // per image: width, height
+    cdvs_image_desc* d_img = nullptr;  // the image table (front-end output layout)
     // device
     OctJob* d_jobs = nullptr;
     std::vector<int32_t> blur_owner;           // [variant][octave][tile] -> job (relative to job_start[octave])
@@ -287,6 +288,7 @@ void cdvs_ctx_destroy(cdvs_ctx* ctx) {
     (void)hipFree(ctx->d_cnn_frag);
     (void)hipFree(ctx->d_scfv_prep);
     (void)hipFree(ctx->d_wh);
+    (void)hipFree(ctx->d_img);
     delete ctx;
 }
 
@@ -524,6 +526,7 @@ cdvs_status cdvs_ctx_create(const cdvs_params* params, const cdvs_image_desc* im
     ALLOC(c->d_cnn_frag, sizeof(short) * kCnnFragShorts);
     ALLOC(c->d_scfv_prep, sizeof(float) * kScfvPrepFloats);
     ALLOC(c->d_wh, sizeof(int32_t) * 2 * n);
+    ALLOC(c->d_img, sizeof(cdvs_image_desc) * n);
 #undef ALLOC
     std::vector<int32_t> wh(2 * n);
     for (size_t i = 0; i < n; ++i) {
@@ -540,6 +543,7 @@ cdvs_status cdvs_ctx_create(const cdvs_params* params, const cdvs_image_desc* im
         (e = hipMemcpy(c->d_geom, c->geom.data(), sizeof(OctGeom) * c->geom.size(), hipMemcpyHostToDevice)) != hipSuccess ||
         (e = hipMemcpy(c->d_cnn, c->cnn.data(), sizeof(CnnImage) * n, hipMemcpyHostToDevice)) != hipSuccess ||
         (e = hipMemcpy(c->d_wh, wh.data(), sizeof(int32_t) * 2 * n, hipMemcpyHostToDevice)) != hipSuccess ||
+        (e = hipMemcpy(c->d_img, images, sizeof(cdvs_image_desc) * n, hipMemcpyHostToDevice)) != hipSuccess ||
         (e = hipMemcpy(c->d_cand_off, c->cand_off.data(), sizeof(int64_t) * n, hipMemcpyHostToDevice)) != hipSuccess ||
         (e = hipMemcpy(c->d_cand_capv, c->cand_cap.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice)) !=
             hipSuccess ||
@@ -686,6 +690,10 @@ cdvs_status cdvs_sync_status(cdvs_ctx* ctx, void* stream) {
     HIP_OR_FAIL(ctx, hipMemcpy(&flags, ctx->d_flags, sizeof(flags), hipMemcpyDeviceToHost));
     if (flags) {
         HIP_OR_FAIL(ctx, hipMemset(ctx->d_flags, 0, sizeof(int32_t)));
+        if (flags & kFlagFrontShape)
+            return fail(ctx, CDVS_ERR_SHAPE,
+                        "cdvs_front_end: a source image's size does not map onto the context's image of the "
+                        "same index (or its descriptor is invalid); that image was not written");
         if (flags & kFlagCandOverflow)
             return fail(ctx, CDVS_ERR_CAPACITY,
                         "candidate scratch overflowed (an image found more candidates than its capacity, "
@@ -712,6 +720,32 @@ cdvs_status cdvs_scfv(cdvs_ctx* ctx, const cdvs_scfv_model* model, const float* 
     HIP_OR_FAIL(ctx, launch_scfv(d_desc, d_count, ctx->n, ctx->kp_cap, model->d_pca_mean, model->d_pca_matrix,
                                  model->d_weights, model->d_means, model->d_variances, ctx->d_scfv_prep, d_gm, d_gv,
                                  d_delta, d_order, d_bits, s));
+    return CDVS_OK;
+}
+
+static_assert(CDVS_FRONT_LONG_SIDE == kFrontLongSide, "front-end long side");
+
+cdvs_status cdvs_front_size(int32_t width, int32_t height, int32_t* out_width, int32_t* out_height) {
+    if (!out_width || !out_height) return fail(nullptr, CDVS_ERR_ARG, "cdvs_front_size: null pointer");
+    if (width < 1 || height < 1 || width > CDVS_MAX_SIDE || height > CDVS_MAX_SIDE)
+        return fail(nullptr, CDVS_ERR_SHAPE, "cdvs_front_size: %d x %d outside 1..%d per side", width, height,
+                    CDVS_MAX_SIDE);
+    int w = 0, h = 0;
+    front_size(width, height, &w, &h);
+    *out_width = w;
+    *out_height = h;
+    return CDVS_OK;
+}
+
+cdvs_status cdvs_front_end(cdvs_ctx* ctx, const uint8_t* d_src, const cdvs_image_desc* d_src_desc,
+                           uint8_t* d_images, void* stream) {
+    if (!ctx) return CDVS_ERR_STATE;
+    if (!d_src || !d_src_desc || !d_images) return fail(ctx, CDVS_ERR_ARG, "cdvs_front_end: null pointer");
+    if ((const void*)d_src == (const void*)d_images)
+        return fail(ctx, CDVS_ERR_ARG, "cdvs_front_end: output must not alias the sources");
+    hipStream_t s = (hipStream_t)stream;
+    Bracket b(ctx, CDVS_KERNEL_FRONT, s);
+    HIP_OR_FAIL(ctx, launch_front(d_src, d_src_desc, d_images, ctx->d_img, ctx->n, ctx->d_flags, s));
     return CDVS_OK;
 }
 

@@ -110,6 +110,7 @@ __device__ __forceinline__ int xcd_remap(int b, int n) {
 // Bits of the device status word.
 constexpr int kFlagCandOverflow = 1;
 constexpr int kFlagSelectInexact = 2;   // a reduced image's top-k reached its selection threshold
+constexpr int kFlagFrontShape = 4;      // a front-end source image does not map onto the context's image
 
 // Surrogate CNN geometry: one entry per image.
 constexpr int kCnnChannels = 16, kCnnHeads = 6, kCnnLayers = 4;
@@ -232,6 +233,24 @@ constexpr int kRelFeatures = 5, kRelEdges = 15, kRelBins = 16;
 hipError_t launch_relevance(const cdvs_keypoint* kp_in, const int32_t* count_in, const int32_t* wh, int n_images,
                             int kp_cap, const float* edges, const float* values, int n_keep, cdvs_keypoint* kp_out,
                             int32_t* count_out, float* score_out, hipStream_t s);
+
+// Front end: longer side brought down to kFrontLongSide; the output size
+// (the longer side 640, the shorter rounded half up, at least 1; images
+// already within 640 unchanged).  Host and device share this rule.
+constexpr int kFrontLongSide = 640;
+__host__ __device__ inline void front_size(int w, int h, int* ow, int* oh) {
+    const int L = w > h ? w : h;
+    if (L <= kFrontLongSide) {
+        *ow = w;
+        *oh = h;
+        return;
+    }
+    const int sw = (2 * kFrontLongSide * w + L) / (2 * L), sh = (2 * kFrontLongSide * h + L) / (2 * L);
+    *ow = sw > 1 ? sw : 1;
+    *oh = sh > 1 ? sh : 1;
+}
+hipError_t launch_front(const uint8_t* src, const cdvs_image_desc* sdesc, uint8_t* dst,
+                        const cdvs_image_desc* ddesc, int n, int32_t* flags, hipStream_t s);
 
 // Transform coding and ternary quantisation: eight code words per descriptor.
 constexpr int kTqWords = 8;

@@ -165,3 +165,23 @@ def test_scfv_noalloc_rejects_arguments_without_a_gpu():
     assert call(ctypes.byref(m), ctypes.c_void_p(4100), 1, 100) == cd.CDVS_ERR_ARG
     assert b"aligned" in L.cdvs_last_error(None)
     assert call(ctypes.byref(m), fake, 0, 100) == cd.CDVS_OK       # nothing to do, nothing enqueued
+
+
+def test_front_size_matches_oracle_rule():
+    """cdvs_front_size (host logic, no GPU) against the oracle's size rule on
+    seeded random sizes and the edges; sizes outside 1..8192 are refused."""
+    import numpy as np
+    import paper_1705_09776_amd as cd
+    from oracle import front as F
+    rng = np.random.default_rng(9)
+    cases = [(1, 1), (640, 640), (641, 641), (8192, 1), (1, 8192), (8192, 8192), (1281, 961)]
+    cases += [tuple(int(v) for v in rng.integers(1, 8193, 2)) for _ in range(2000)]
+    for w, h in cases:
+        assert cd.cdvs_front_size(w, h) == F.front_size(w, h), (w, h)
+    for w, h in ((0, 10), (10, 0), (8193, 10)):
+        try:
+            cd.cdvs_front_size(w, h)
+        except cd.CdvsError as e:
+            assert e.status == cd.CDVS_ERR_SHAPE
+        else:
+            raise AssertionError("accepted an invalid size")
