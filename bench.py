@@ -254,6 +254,9 @@ def sparse_leg(imgs, steps, contrast=4.0):
     return {"contrast": contrast, "tau": tau, "keypoints_per_image": round(sum(len(k) for k in plain_kp) / B, 1),
             "plain_images_per_s": round(B / t_plain, 1), "plain_eager_images_per_s": round(B / t_plain_eager, 1),
             "gated_images_per_s": round(B / t_gated, 1),
+            "gated_vs_plain_eager": round(t_plain_eager / t_gated, 4),
+            "net": ("loss: the gate's CNN costs more than the detection it skips" if t_gated > t_plain_eager
+                    else "gain"),
             "recall_top1000": round(hit / max(1, sum(len(a) for a in plain_kp)), 5),
             "active_cell_fraction": round(act / (5 * mask.size), 4),
             "timing": "plain: K graph replays (and K eager steps); gated: K eager steps"}
@@ -697,6 +700,11 @@ def main():
         plain_kp = [k.copy() for k in pipe.keypoints()]
         out["plain_eager_images_per_s"] = round(B / (eager_ms * 1e-3), 1)
         out["gated"] = gated_leg(pipe, args.steps, B, plain_kp)
+        g = out["gated"]
+        g["vs_plain_eager"] = round(g["value"] / out["plain_eager_images_per_s"], 4)
+        g["vs_plain_graph"] = round(g["value"] / out["value"], 4)
+        g["net"] = ("loss: the gate's CNN costs more than the detection it skips"
+                    if g["value"] < out["plain_eager_images_per_s"] else "gain")
     if not args.no_aggregate and os.path.exists(SCFV_MODEL):
         log("[bench] relevance, transform coding and SCFV on the plain pass's outputs")
         out["aggregate"] = aggregate_leg(pipe, args.steps, B)

@@ -38,6 +38,40 @@ __global__ __launch_bounds__(256) void k_front(const uint8_t* __restrict__ src,
         return;
     }
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    if (W == 2 * wo && H == 2 * ho && ((s.offset | s.pitch | d.offset | d.pitch) & 7) == 0) {
+        // An exact factor of 2 (e.g. 1280x960 -> 640x480): every overlap is
+        // a whole source pixel, so N = wo ho S for the 2x2 sum S, W H =
+        // 4 wo ho, and the rounded mean is (S + 2) / 4 -- the same integers
+        // as below.  Each lane takes 4 outputs from 8 bytes of both source
+        // rows (8-byte aligned: offsets and pitches are multiples of 8).
+        for (int y = part * 4 + wave; y < ho; y += kFrontParts * 4) {
+            const uint8_t* r0 = src + s.offset + (int64_t)(2 * y) * s.pitch;
+            const uint8_t* r1 = r0 + s.pitch;
+            uint8_t* orow = dst + d.offset + (int64_t)y * d.pitch;
+            for (int x4 = 4 * lane; x4 < wo; x4 += 256) {
+                if (x4 + 4 <= wo) {
+                    const uint2 a = *reinterpret_cast<const uint2*>(r0 + 2 * x4);
+                    const uint2 b = *reinterpret_cast<const uint2*>(r1 + 2 * x4);
+                    uint32_t o = 0;
+#pragma unroll
+                    for (int k = 0; k < 4; ++k) {
+                        const uint32_t wa = k < 2 ? a.x : a.y, wb = k < 2 ? b.x : b.y;
+                        const int sh = 16 * (k & 1);
+                        const uint32_t sum = ((wa >> sh) & 255u) + ((wa >> (sh + 8)) & 255u) +
+                                             ((wb >> sh) & 255u) + ((wb >> (sh + 8)) & 255u);
+                        o |= ((sum + 2u) >> 2) << (8 * k);
+                    }
+                    *reinterpret_cast<uint32_t*>(orow + x4) = o;
+                } else {
+                    for (int x = x4; x < wo; ++x) {
+                        const uint32_t sum = r0[2 * x] + r0[2 * x + 1] + r1[2 * x] + r1[2 * x + 1];
+                        orow[x] = (uint8_t)((sum + 2u) >> 2);
+                    }
+                }
+            }
+        }
+        return;
+    }
     const uint32_t WH = (uint32_t)W * (uint32_t)H;
     // 2 N + W H < 511 W H: 32-bit arithmetic while that stays below 2^32
     const bool narrow = (uint64_t)WH * 511u < (1ull << 32);

@@ -73,15 +73,31 @@ __global__ __launch_bounds__(256) void k_scfv_prep(const float* __restrict__ w, 
     }
 }
 
+// Reductions over each 32-lane half of the wave, the result in every lane:
+// within each 16-lane row by DPP (quad permutes [1,0,3,2] and [2,3,0,1],
+// then the half-row and row mirrors, each combining a lane group with the
+// other half of the next larger group), then across the half's two rows by
+// one swizzle (lane ^ 16 within 32-lane groups).
+template <int CTRL>
+__device__ __forceinline__ float dpp(float v) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, false));
+}
+__device__ __forceinline__ float xor16(float v) {
+    return __int_as_float(__builtin_amdgcn_ds_swizzle(__float_as_int(v), 0x401F));
+}
 __device__ __forceinline__ float half_max(float v) {
-#pragma unroll
-    for (int off = 16; off > 0; off >>= 1) v = fmaxf(v, __shfl_xor(v, off));
-    return v;
+    v = fmaxf(v, dpp<0xB1>(v));
+    v = fmaxf(v, dpp<0x4E>(v));
+    v = fmaxf(v, dpp<0x141>(v));
+    v = fmaxf(v, dpp<0x140>(v));
+    return fmaxf(v, xor16(v));
 }
 __device__ __forceinline__ float half_sum(float v) {
-#pragma unroll
-    for (int off = 16; off > 0; off >>= 1) v += __shfl_xor(v, off);
-    return v;
+    v += dpp<0xB1>(v);
+    v += dpp<0x4E>(v);
+    v += dpp<0x141>(v);
+    v += dpp<0x140>(v);
+    return v + xor16(v);
 }
 
 // Output stage of one image, shared by the one-workgroup-per-image kernel
@@ -199,25 +215,37 @@ __global__ __launch_bounds__(512) void k_scfv(const float* __restrict__ desc, co
     }
     float s0[2] = {0.f, 0.f};
 
+    // The descriptor tile is staged through registers: each thread holds
+    // two float4s (the same column group q of rows r and r + 16) and loads
+    // the next tile's while the current one is computed, so the global
+    // load's latency is hidden behind the tile's matrix work.
+    static_assert(TD * 32 == 2 * NW * 64, "two float4s per thread per tile");
+    const int q4 = tid & 31, r4 = tid >> 5;
+    const float4 mq = *reinterpret_cast<const float4*>(pca_mean + 4 * q4);
+    float4 pre[2];
+    auto fetch = [&](int t0) {
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+            const int r = r4 + 16 * j;
+            pre[j] = t0 + r < tend ? *reinterpret_cast<const float4*>(D + (int64_t)(t0 + r) * kDescDim + 4 * q4)
+                                   : make_float4(0.f, 0.f, 0.f, 0.f);
+        }
+    };
+    if (tbeg < tend) fetch(tbeg);
+
     for (int t0 = tbeg; t0 < tend; t0 += TD) {
         __syncthreads();   // the previous tile's readers are done
-        for (int e = tid; e < TD * 32; e += NW * 64) {
-            const int r = e >> 5, q = e & 31;
-            float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
-            if (t0 + r < tend) {
-                v = *reinterpret_cast<const float4*>(D + (int64_t)(t0 + r) * kDescDim + 4 * q);
-                const float4 m = *reinterpret_cast<const float4*>(pca_mean + 4 * q);
-                v.x -= m.x;
-                v.y -= m.y;
-                v.z -= m.z;
-                v.w -= m.w;
-            }
-            float* d = Dl + r * DSTR + 4 * q;
-            d[0] = v.x;
-            d[1] = v.y;
-            d[2] = v.z;
-            d[3] = v.w;
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+            const int r = r4 + 16 * j;
+            const bool live = t0 + r < tend;
+            float* d = Dl + r * DSTR + 4 * q4;
+            d[0] = live ? pre[j].x - mq.x : 0.f;
+            d[1] = live ? pre[j].y - mq.y : 0.f;
+            d[2] = live ? pre[j].z - mq.z : 0.f;
+            d[3] = live ? pre[j].w - mq.w : 0.f;
         }
+        if (t0 + TD < tend) fetch(t0 + TD);
         __syncthreads();
         if (wave < 4) {
             // X tile (rows 16 rt.., cols 16 ct..) = Dl . A^T over k = 0..127
