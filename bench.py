@@ -459,6 +459,40 @@ def aggregate_leg(pipe, steps, B):
     return out
 
 
+def bmlog_leg(pipe, steps, B):
+    """The BMLoG scale space (block frequency-domain Gaussians, Sec. III-A)
+    on the same batch against the spatial one, per-kernel events; and the
+    detector's keypoints on it against those on the spatial planes."""
+    import torch
+    import paper_1705_09776_amd as cd
+    cd.cdvs_pyramid_bmlog(pipe.ctx, pipe.d_images, pipe.d_pyr)
+    torch.cuda.synchronize()
+    cd.cdvs_profile_enable(pipe.ctx, True)
+    for _ in range(steps):
+        cd.cdvs_pyramid_bmlog(pipe.ctx, pipe.d_images, pipe.d_pyr)
+    for _ in range(steps):
+        pipe.pyramid()
+    torch.cuda.synchronize()
+    prof = cd.cdvs_profile_read(pipe.ctx)
+    cd.cdvs_profile_enable(pipe.ctx, False)
+    bm = prof["bmlog"][0] / steps
+    sp = (prof["preblur"][0] + prof["scales"][0]) / steps
+    # keypoints from the BMLoG planes against the spatial ones (the pipeline
+    # buffers hold the spatial pass again afterwards)
+    cd.cdvs_pyramid_bmlog(pipe.ctx, pipe.d_images, pipe.d_pyr)
+    pipe.detect()
+    kb = pipe.keypoints()
+    pipe.run()
+    torch.cuda.synchronize()
+    ks = pipe.keypoints()
+    key = lambda k: (int(k["octave"]), int(k["ix"]), int(k["iy"]))
+    same = sum(len({key(k) for k in a} & {key(k) for k in b}) for a, b in zip(kb, ks))
+    return {"bmlog_ms": round(bm, 4), "spatial_ms": round(sp, 4), "bmlog_over_spatial": round(bm / sp, 3),
+            "bmlog_images_per_s": round(B / (bm * 1e-3), 1),
+            "keypoints_shared_with_spatial": round(same / max(1, sum(len(a) for a in ks)), 4),
+            "timing": f"{steps} calls of each scale space on the batch, per-kernel events"}
+
+
 def front_leg(steps, n=256):
     """The front end on n images 1280x960 (the high-resolution recipe,
     rendered on the device) brought down to 640x480, then the plain pass:
@@ -569,6 +603,7 @@ def main():
     ap.add_argument("--stream-images", type=int, default=4096)
     ap.add_argument("--no-aggregate", action="store_true")
     ap.add_argument("--no-front", action="store_true")
+    ap.add_argument("--no-bmlog", action="store_true")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -708,6 +743,9 @@ def main():
     if not args.no_aggregate and os.path.exists(SCFV_MODEL):
         log("[bench] relevance, transform coding and SCFV on the plain pass's outputs")
         out["aggregate"] = aggregate_leg(pipe, args.steps, B)
+    if not args.no_bmlog:
+        log("[bench] BMLoG scale space against the spatial one")
+        out["bmlog"] = bmlog_leg(pipe, args.steps, B)
     if not args.no_front:
         log("[bench] front end (1280x960 -> 640x480) and plain pass")
         out["front"] = front_leg(args.steps)

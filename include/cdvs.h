@@ -247,6 +247,32 @@ int32_t cdvs_tune_get(const cdvs_ctx* ctx, int32_t kernel);
 cdvs_status cdvs_tune_set(cdvs_ctx* ctx, int32_t kernel, int32_t variant);
 
 /* ---------------------------------------------------------------------- */
+/* BMLoG scale space (Sec. III-A): the comparison variant of cdvs_pyramid   */
+/* ---------------------------------------------------------------------- */
+/* Writes the same planes as cdvs_pyramid, into the same layout, by the
+ * block-based mixture-domain filtering the paper compares: each octave image
+ * is cut into 128 x 128 blocks overlapping by 16 pixels on every side
+ * (block (bx, by) covers columns 96 bx - 16 .. 96 bx + 111 and rows likewise,
+ * pixels outside the image taken from the nearest edge pixel; a 640x480
+ * image has 35); every block is transformed once (2-D DFT), multiplied by
+ * the separable transfer function of each Gaussian (the DFT of its
+ * normalised taps, radius ceil(4 s), placed on the 128-periodic grid) and
+ * transformed back once per scale image, keeping its central 96 x 96
+ * pixels.  Octave 0 filters the u8 input with g0 (G_{0,0}) and with g0
+ * then g_k (G_{0,k}): one forward and five inverse transforms per block;
+ * octave o >= 1 filters G_{o,0} (G_{o-1,4} at even pixels) with g_1..g_4.
+ * The Laplacian stays in the spatial domain: cdvs_alp_detect runs on the
+ * result unchanged.  Where a kernel's radius is at most 16 (all but the
+ * octave-0 combined kernels, radius up to 19, whose wrapped tail is below
+ * 1e-6 of their mass) the kept pixels equal the spatial filter up to
+ * rounding; near the image border octave 0 differs from cdvs_pyramid's
+ * two clamped passes by the one clamped combined pass.  FP32 transforms:
+ * planes within about 1e-3 of the exact block result on the 0..255 scale.
+ * d_pyr: 256-byte aligned, cdvs_pyramid_bytes long.  One launch per octave;
+ * uses 134 KB of LDS per workgroup. */
+cdvs_status cdvs_pyramid_bmlog(cdvs_ctx* ctx, const uint8_t* d_images, float* d_pyr, void* stream);
+
+/* ---------------------------------------------------------------------- */
 /* Front end (Sec. III: inputs reduced to a longer side of at most 640)     */
 /* ---------------------------------------------------------------------- */
 #define CDVS_FRONT_LONG_SIDE 640
@@ -542,6 +568,7 @@ typedef enum {
     CDVS_KERNEL_ENCODE,       /* transform coding and ternary quantisation */
     CDVS_KERNEL_RELEVANCE,    /* relevance scores and per-image selection */
     CDVS_KERNEL_FRONT,        /* front-end downsampling to a longer side of 640 */
+    CDVS_KERNEL_BMLOG,        /* block frequency-domain scale images (one launch per octave) */
     CDVS_KERNEL_COUNT
 } cdvs_kernel_id;
 

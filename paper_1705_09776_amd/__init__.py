@@ -72,7 +72,7 @@ EXPORTS = ["cdvs_default_params", "cdvs_validate", "cdvs_ctx_create", "cdvs_ctx_
            "cdvs_graph_capture", "cdvs_graph_launch", "cdvs_profile_enable", "cdvs_profile_read",
            "cdvs_cnn_cells", "cdvs_cnn_cell_layout", "cdvs_cnn_forward", "cdvs_cnn_labels", "cdvs_cnn_backward",
            "cdvs_cnn_adam", "cdvs_autotune", "cdvs_tune_get", "cdvs_tune_set",
-           "cdvs_stream", "cdvs_standin_consume", "cdvs_scfv", "cdvs_scfv_noalloc", "cdvs_encode", "cdvs_front_size", "cdvs_front_end",
+           "cdvs_stream", "cdvs_standin_consume", "cdvs_scfv", "cdvs_scfv_noalloc", "cdvs_encode", "cdvs_front_size", "cdvs_front_end", "cdvs_pyramid_bmlog",
            "cdvs_relevance_select"]
 TUNE_VARIANTS = 4
 DETECT_VARIANTS = 2
@@ -80,7 +80,7 @@ DETECT_VARIANTS = 2
 KERNEL_SCALES = 1
 KERNEL_DETECT = 3
 KERNEL_NAMES = ["preblur", "scales", "clear", "detect", "finalize", "orient", "orient_compact", "describe",
-                "cnn_forward", "mask_count", "scfv", "encode", "relevance", "front"]
+                "cnn_forward", "mask_count", "scfv", "encode", "relevance", "front", "bmlog"]
 TQ_WORDS = 8
 SCFV_COMPONENTS = 512
 SCFV_DIM = 32
@@ -147,6 +147,7 @@ def lib():
         "cdvs_profile_enable": (i32, [vp, i32]),
         "cdvs_profile_read": (i32, [vp, vp, vp]),
         "cdvs_scfv": (i32, [vp, ctypes.POINTER(ScfvModel), vp, vp, vp, vp, vp, vp, vp, vp]),
+        "cdvs_pyramid_bmlog": (i32, [vp, vp, vp, vp]),
         "cdvs_front_size": (i32, [i32, i32, ctypes.POINTER(i32), ctypes.POINTER(i32)]),
         "cdvs_front_end": (i32, [vp, vp, vp, vp, vp]),
         "cdvs_scfv_noalloc": (i32, [ctypes.POINTER(ScfvModel), vp, vp, i32, i32, vp, vp, vp, vp, vp, vp]),
@@ -364,6 +365,12 @@ def cdvs_scfv(ctx, scfv: Scfv, d_desc, d_count, stream=None):
     _check(ctx, lib().cdvs_scfv(ctx, ctypes.byref(scfv.model), _ptr(d_desc), _ptr(d_count), _ptr(scfv.gm),
                                 _ptr(scfv.gv), _ptr(scfv.delta), _ptr(scfv.order), _ptr(scfv.bits),
                                 _stream(stream)))
+
+
+def cdvs_pyramid_bmlog(ctx, d_images, d_pyr, stream=None):
+    """The block frequency-domain (BMLoG) scale space into d_pyr (same
+    layout as cdvs_pyramid)."""
+    _check(ctx, lib().cdvs_pyramid_bmlog(ctx, _ptr(d_images), _ptr(d_pyr), _stream(stream)))
 
 
 def cdvs_front_size(width: int, height: int):

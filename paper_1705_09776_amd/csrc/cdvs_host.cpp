@@ -51,6 +51,12 @@ struct cdvs_ctx {
     float* d_scfv_prep = nullptr; // SCFV per-call model constants (kScfvPrepFloats)
     int32_t* d_wh = nullptr;      // per image: width, height
     cdvs_image_desc* d_img = nullptr;  // the image table (front-end output layout)
+    // BMLoG variant: per octave, (job, bx, by) of every block; transfer functions
+    std::vector<int32_t> bm_blocks;
+    int bm_start[kMaxOctaves] = {}, bm_count[kMaxOctaves] = {};
+    int32_t* d_bm_blocks = nullptr;
+    float* d_bm_H = nullptr;
+    float bm_H[kBmTransfers * kBmN] = {};
     // device
     OctJob* d_jobs = nullptr;
     std::vector<int32_t> blur_owner;           // [variant][octave][tile] -> job (relative to job_start[octave])
@@ -289,6 +295,8 @@ void cdvs_ctx_destroy(cdvs_ctx* ctx) {
     (void)hipFree(ctx->d_scfv_prep);
     (void)hipFree(ctx->d_wh);
     (void)hipFree(ctx->d_img);
+    (void)hipFree(ctx->d_bm_blocks);
+    (void)hipFree(ctx->d_bm_H);
     delete ctx;
 }
 
@@ -361,6 +369,22 @@ static cdvs_status build_layout(cdvs_ctx* c) {
                 for (int t = 0; t < nt; ++t) c->blur_owner.push_back((int32_t)j);
             }
         }
+    // BMLoG blocks: per octave, every job's grid of kBmStep-pixel block centres
+    c->bm_blocks.clear();
+    for (int o = 0; o < kMaxOctaves; ++o) {
+        c->bm_start[o] = (int)(c->bm_blocks.size() / 3);
+        for (size_t j = 0; j < per_oct[o].size(); ++j) {
+            const OctJob& jb = per_oct[o][j];
+            const int nbx = (jb.w + kBmStep - 1) / kBmStep, nby = (jb.h + kBmStep - 1) / kBmStep;
+            for (int by = 0; by < nby; ++by)
+                for (int bx = 0; bx < nbx; ++bx) {
+                    c->bm_blocks.push_back((int32_t)j);
+                    c->bm_blocks.push_back(bx);
+                    c->bm_blocks.push_back(by);
+                }
+        }
+        c->bm_count[o] = (int)(c->bm_blocks.size() / 3) - c->bm_start[o];
+    }
     // candidate capacity per image: kCandCap, or one slot per 64 base pixels
     // for larger images (noise extrema of the first octave alone come to
     // about one per 200 pixels at the default contrast)
@@ -456,6 +480,27 @@ static void build_constants(cdvs_ctx* c) {
         const double s = (k == 0) ? s0 : s0 * sqrt(pow(2.0, k / 2.0) - 1.0);
         make_taps(s, radii[k], c->taps.g[k]);
     }
+    // BMLoG transfer functions: the DFT over kBmN points of each tap set
+    // (taps in double, normalised), real for symmetric taps; then the
+    // products of the base blur's with each scale's
+    {
+        double Hd[kScales][kBmN];
+        for (int k = 0; k < kScales; ++k) {
+            const double sk = (k == 0) ? s0 : s0 * sqrt(pow(2.0, k / 2.0) - 1.0);
+            const int r = radii[k];
+            double t[2 * kMaxR + 1], sum = 0.0;
+            for (int p = -r; p <= r; ++p) sum += (t[p + r] = exp(-(double)(p * p) / (2.0 * sk * sk)));
+            for (int u = 0; u < kBmN; ++u) {
+                double a = t[r] / sum;
+                for (int p = 1; p <= r; ++p) a += 2.0 * t[r + p] / sum * cos(2.0 * M_PI * u * p / kBmN);
+                Hd[k][u] = a;
+            }
+        }
+        for (int u = 0; u < kBmN; ++u) {
+            for (int k = 0; k < kScales; ++k) c->bm_H[k * kBmN + u] = (float)Hd[k][u];
+            for (int k = 1; k < kScales; ++k) c->bm_H[(4 + k) * kBmN + u] = (float)(Hd[0][u] * Hd[k][u]);
+        }
+    }
     double sig[kScales];
     for (int k = 0; k < kScales; ++k) sig[k] = s0 * pow(2.0, k / 4.0);
     float beta[kScales][4];
@@ -527,6 +572,8 @@ cdvs_status cdvs_ctx_create(const cdvs_params* params, const cdvs_image_desc* im
     ALLOC(c->d_scfv_prep, sizeof(float) * kScfvPrepFloats);
     ALLOC(c->d_wh, sizeof(int32_t) * 2 * n);
     ALLOC(c->d_img, sizeof(cdvs_image_desc) * n);
+    ALLOC(c->d_bm_blocks, sizeof(int32_t) * std::max<size_t>(1, c->bm_blocks.size()));
+    ALLOC(c->d_bm_H, sizeof(float) * kBmTransfers * kBmN);
 #undef ALLOC
     std::vector<int32_t> wh(2 * n);
     for (size_t i = 0; i < n; ++i) {
@@ -544,6 +591,11 @@ cdvs_status cdvs_ctx_create(const cdvs_params* params, const cdvs_image_desc* im
         (e = hipMemcpy(c->d_cnn, c->cnn.data(), sizeof(CnnImage) * n, hipMemcpyHostToDevice)) != hipSuccess ||
         (e = hipMemcpy(c->d_wh, wh.data(), sizeof(int32_t) * 2 * n, hipMemcpyHostToDevice)) != hipSuccess ||
         (e = hipMemcpy(c->d_img, images, sizeof(cdvs_image_desc) * n, hipMemcpyHostToDevice)) != hipSuccess ||
+        (!c->bm_blocks.empty() &&
+         (e = hipMemcpy(c->d_bm_blocks, c->bm_blocks.data(), sizeof(int32_t) * c->bm_blocks.size(),
+                        hipMemcpyHostToDevice)) != hipSuccess) ||
+        (e = hipMemcpy(c->d_bm_H, c->bm_H, sizeof(float) * kBmTransfers * kBmN, hipMemcpyHostToDevice)) !=
+            hipSuccess ||
         (e = hipMemcpy(c->d_cand_off, c->cand_off.data(), sizeof(int64_t) * n, hipMemcpyHostToDevice)) != hipSuccess ||
         (e = hipMemcpy(c->d_cand_capv, c->cand_cap.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice)) !=
             hipSuccess ||
@@ -611,6 +663,20 @@ cdvs_status cdvs_pyramid(cdvs_ctx* ctx, const uint8_t* d_images, float* d_pyr, v
         HIP_OR_FAIL(ctx, launch_scales(d_pyr, ctx->d_jobs + ctx->job_start[o],
                                        ctx->d_blur_owner + ctx->blur_owner_start[v][o], ctx->blur_tiles[v][o], v,
                                        ctx->taps, s));
+    }
+    return CDVS_OK;
+}
+
+cdvs_status cdvs_pyramid_bmlog(cdvs_ctx* ctx, const uint8_t* d_images, float* d_pyr, void* stream) {
+    if (!ctx) return CDVS_ERR_STATE;
+    if (!d_images || !d_pyr) return fail(ctx, CDVS_ERR_ARG, "cdvs_pyramid_bmlog: null device pointer");
+    if (((uintptr_t)d_pyr & 255) != 0) return fail(ctx, CDVS_ERR_ARG, "cdvs_pyramid_bmlog: d_pyr not 256-byte aligned");
+    hipStream_t s = (hipStream_t)stream;
+    for (int o = 0; o < ctx->max_oct; ++o) {
+        Bracket b(ctx, CDVS_KERNEL_BMLOG, s);
+        HIP_OR_FAIL(ctx, launch_bmlog(d_images, d_pyr, ctx->d_jobs + ctx->job_start[o],
+                                      ctx->d_bm_blocks + 3 * (int64_t)ctx->bm_start[o], ctx->bm_count[o],
+                                      ctx->d_bm_H, o == 0, s));
     }
     return CDVS_OK;
 }

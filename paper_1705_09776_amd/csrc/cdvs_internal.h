@@ -234,6 +234,14 @@ hipError_t launch_relevance(const cdvs_keypoint* kp_in, const int32_t* count_in,
                             int kp_cap, const float* edges, const float* values, int n_keep, cdvs_keypoint* kp_out,
                             int32_t* count_out, float* score_out, hipStream_t s);
 
+// BMLoG scale space (the block frequency-domain variant): blocks of kBmN
+// pixels overlapping by kBmR on every side, one (job, bx, by) triple per
+// block; kBmTransfers rows of kBmN transfer-function values (g0, g1..g4,
+// then g0 g1 .. g0 g4).
+constexpr int kBmN = 128, kBmR = 16, kBmStep = kBmN - 2 * kBmR, kBmTransfers = 9;
+hipError_t launch_bmlog(const uint8_t* images, float* pyr, const OctJob* jobs, const int32_t* blocks, int nblocks,
+                        const float* H, bool octave0, hipStream_t stream);
+
 // Front end: longer side brought down to kFrontLongSide; the output size
 // (the longer side 640, the shorter rounded half up, at least 1; images
 // already within 640 unchanged).  Host and device share this rule.

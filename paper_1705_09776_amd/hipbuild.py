@@ -14,7 +14,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 OBJ = os.path.join(ROOT, "_build", "cdvs")
 LIB = os.path.join(PKG, "libcdvs.so")
-SOURCES = ["cdvs_host.cpp", "pyramid.hip", "detect.hip", "describe.hip", "cnn.hip", "scfv.hip", "tq.hip", "relevance.hip", "front.hip"]
+SOURCES = ["cdvs_host.cpp", "pyramid.hip", "detect.hip", "describe.hip", "cnn.hip", "scfv.hip", "tq.hip", "relevance.hip", "front.hip", "bmlog.hip"]
 ARCH = "gfx950"
 
 # Packed FP32 instructions are switched off for all device code.
