@@ -414,9 +414,10 @@ cdvs_status cdvs_scfv(cdvs_ctx* ctx, const cdvs_scfv_model* model, const float* 
  * model's derived constants (196 KB) and 64 blocks of per-part sums
  * (130 KB each).  Its device address is looked up on the first call on each
  * device.  Batches of at most 32 images are split into parts (as many as fit
- * in the 64 blocks, at most one per 32-descriptor tile of kp_capacity) whose
- * sums a second kernel adds up; larger batches take one workgroup per image
- * and use only the constants.  The outputs are those of cdvs_scfv (same
+ * in the 64 blocks, at most one per 32-descriptor tile of kp_capacity); 65
+ * workgroups per image add up the parts' sums and a third kernel completes
+ * the image; larger batches take one workgroup per image and use only the
+ * constants.  The outputs are those of cdvs_scfv (same
  * definitions, shapes and layouts; sums in another order, so equal up to
  * single-precision rounding).  d_desc is n_images x kp_capacity x 128 floats
  * (16-byte aligned), d_count n_images int32 (clamped to 0..kp_capacity).

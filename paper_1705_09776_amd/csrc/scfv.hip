@@ -352,8 +352,26 @@ __global__ __launch_bounds__(512) void k_scfv(const float* __restrict__ desc, co
     }
 }
 
-// Completes images aggregated in `splits` parts: adds up their partial
-// blocks (in part order) and writes the outputs as k_scfv does.
+// Adds up the partial blocks of images aggregated in `splits` parts, into
+// each image's first block (in part order): 512 floats per workgroup, so
+// the sums of one image are spread over 65 workgroups.
+__global__ __launch_bounds__(256) void k_scfv_reduce(float* __restrict__ partial, int splits) {
+    constexpr int kChunks = kScfvPartialFloats / 512;
+    static_assert(kScfvPartialFloats % 512 == 0, "whole chunks");
+    const int img = blockIdx.x / kChunks, chunk = blockIdx.x % kChunks;
+    float* P0 = partial + (int64_t)img * splits * kScfvPartialFloats + chunk * 512;
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+        const int e = threadIdx.x + 256 * j;
+        float a = P0[e];
+        for (int p = 1; p < splits; ++p) a += P0[(int64_t)p * kScfvPartialFloats + e];
+        P0[e] = a;
+    }
+}
+
+// Completes images aggregated in parts whose sums k_scfv_reduce has put in
+// each image's first partial block (blocks `splits` apart): writes the
+// outputs as k_scfv does.
 __global__ __launch_bounds__(512) void k_scfv_join(const float* __restrict__ partial, int splits,
                                                    const int32_t* __restrict__ count, int kp_cap,
                                                    const float* __restrict__ means, const float* __restrict__ vars,
@@ -367,23 +385,15 @@ __global__ __launch_bounds__(512) void k_scfv_join(const float* __restrict__ par
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, h = lane >> 5, c32 = lane & 31;
     const int K = min(max(count[img], 0), kp_cap);
     const float* P0 = partial + (int64_t)img * splits * kScfvPartialFloats;
-    float s = 0.f;
-    for (int p = 0; p < splits; ++p) s += P0[(int64_t)p * kScfvPartialFloats + tid];
-    s0s[tid] = s;
+    s0s[tid] = P0[tid];
     f16v acc1[2], acc2[2];
 #pragma unroll
     for (int t = 0; t < 2; ++t)
 #pragma unroll
         for (int i = 0; i < 16; ++i) {
             const int comp = CPW * wave + 32 * t + 8 * (i >> 2) + 4 * h + (i & 3);
-            float a = 0.f, b = 0.f;
-            for (int p = 0; p < splits; ++p) {
-                const float* P = P0 + (int64_t)p * kScfvPartialFloats + NC;
-                a += P[comp * PD + c32];
-                b += P[NC * PD + comp * PD + c32];
-            }
-            acc1[t][i] = a;
-            acc2[t][i] = b;
+            acc1[t][i] = P0[NC + comp * PD + c32];
+            acc2[t][i] = P0[NC + NC * PD + comp * PD + c32];
         }
     __syncthreads();
     scfv_output(img, K, wave, lane, s0s, acc1, acc2, means, vars, prep, gm_out, gv_out, delta_out, order_out,
@@ -455,6 +465,8 @@ hipError_t launch_scfv_static(float* scr, int splits, const float* desc, const i
         hipLaunchKernelGGL(k_scfv<true>, dim3(n_images * splits), dim3(NW * 64), 0, s, desc, count, kp_cap, splits,
                            per, pca_mean, pca_matrix, means, vars, prep, partial, nullptr, nullptr, nullptr, nullptr,
                            nullptr);
+        hipLaunchKernelGGL(k_scfv_reduce, dim3(n_images * (kScfvPartialFloats / 512)), dim3(256), 0, s, partial,
+                           splits);
         hipLaunchKernelGGL(k_scfv_join, dim3(n_images), dim3(NW * 64), 0, s, partial, splits, count, kp_cap, means,
                            vars, prep, gm, gv, delta, order, bits);
     }

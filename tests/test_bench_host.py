@@ -52,10 +52,21 @@ def test_traffic_requires_matching_source(tmp_path, monkeypatch):
     data = open(os.path.join(csrc, "pyramid.hip"), "rb").read() + open(os.path.join(csrc, "cdvs_internal.h"), "rb").read()
     good = hashlib.sha256(data).hexdigest()
     f = tmp_path / "traffic.md"
-    f.write_text(f"    traffic k_blur<scales> 1234 pyramid.hip {good}\n"
-                 f"    traffic k_describe 99 describe.hip {'0' * 64}\n")
+    f.write_text(f"    traffic k_blur<1,4,12,false,1> 1234 pyramid.hip {good}\n"
+                 f"    traffic k_describe 99 describe.hip {'0' * 64}\n"
+                 f"    valu k_blur<1,4,12,false,1> 777 pyramid.hip {good}\n")
     monkeypatch.setattr(bench, "TRAFFIC", str(f))
-    assert bench.measured_traffic("scales") == 1234
+    monkeypatch.setattr(bench, "SQ", str(f))
+    assert bench.measured_traffic("scales", 1) == 1234
+    assert bench.measured_traffic("scales", 2) is None      # another tile variant: not measured
     assert bench.measured_traffic("describe") is None      # stale: source changed since
     assert bench.measured_traffic("detect") is None        # no line
-    assert bench.measured_path_bytes() is None
+    assert bench.measured_path_bytes(1) is None
+    assert bench.measured_valu("scales", 1) == 777
+
+
+def test_committed_profiles_match_the_sources():
+    """The committed counter summaries were taken on the current kernels."""
+    for k in ("scales", "preblur", "detect", "finalize", "orient", "describe"):
+        assert bench.measured_traffic(k, 1) is not None, k
+        assert bench.measured_valu(k, 1) is not None, k

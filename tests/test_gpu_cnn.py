@@ -17,7 +17,7 @@ import os
 import oracle
 import synth
 from oracle import cnn
-from parity import assert_parity, check_images, summarize
+from parity import KP_RATE, assert_parity, check_images, oracle_stages, rates, summarize
 
 pytestmark = pytest.mark.gpu
 
@@ -272,3 +272,20 @@ def test_gated_detection_matches_oracle(O32, which):
     res = check_images(O32, imgs, pipe.keypoints(), pipe.oriented(), pipe.descriptors(), masks=masks,
                        fmax=pipe.params.mask_fmax)
     assert_parity(summarize(res), f"gated ({which} mask)")
+
+
+def test_gate_leaves_octaves_beyond_its_bits_dense(O32):
+    """A 2048x1536 image has octaves 0..6; the mask has bits for octaves 0..5
+    only, so octave 6 is always examined densely: an all-ones mask gives
+    exactly the plain keypoints, and an all-zeros mask gives the oracle's
+    gated detection under the same mask (every keypoint in octave 6)."""
+    img = synth.image(synth.SEED_HIRES, 11, 2048, 1536, nblobs=900, smax=40.0)
+    pipe, plain, gated, _ = _gated([img], lambda pp: np.full(pp.ncells, 0x3F, dtype=np.uint8), fmax=1.0)
+    assert pipe.num_octaves(0) == 7
+    np.testing.assert_array_equal(plain[0][_KEYS], gated[0][_KEYS])
+    pipe, plain, gated, m = _gated([img], lambda pp: np.zeros(pp.ncells, dtype=np.uint8), fmax=1.0)
+    g = gated[0]
+    assert len(g) > 0 and np.all(g["octave"] == 6)
+    ref, _, _, _ = oracle_stages(O32, img, topk=4096, mask=_image_masks(pipe, m)[0], fmax=1.0)
+    r_ref, r_got, _ = rates(ref, g)
+    assert r_ref >= KP_RATE and r_got >= KP_RATE
