@@ -315,6 +315,10 @@ def ragged_leg(steps, n=1024):
             "octave_px_per_image": round(npx / n, 1),
             "tile_variant": tune["variant"], "tile_variant_us": tune["us"],
             "detect_variant": tune["detect"], "detect_variant_us": tune["detect_us"], "autotune_s": round(t_tune, 3),
+            "launches_per_stage": {"pyramid": 1 + pipe.max_octaves(), "detect": 1, "finalize": 1, "orient": 2,
+                                   "describe": 1},
+            "persistent_detect": ("built and tested (same keypoints, and oracle parity), kept only when the "
+                                  "autotuner measures it faster: it is slower here (detect_variant_us[1])"),
             "timing": "K hipGraph replays of the whole plain pass over the packed ragged batch"}
 
 

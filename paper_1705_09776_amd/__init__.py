@@ -624,6 +624,10 @@ class Pipeline:
     def num_octaves(self, image):
         return int(lib().cdvs_num_octaves(self.ctx, image))
 
+    def max_octaves(self):
+        """The largest octave count of the batch (cdvs_pyramid's scale-kernel launches)."""
+        return max(self.num_octaves(i) for i in range(self.n))
+
     def candidate_capacity(self):
         return cdvs_candidate_capacity(self.ctx)
 

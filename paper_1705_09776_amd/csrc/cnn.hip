@@ -266,7 +266,16 @@ __global__ __launch_bounds__(FTHREADS, 2) void k_cnn_infer(const uint8_t* __rest
     for (int m = 0; m < kTapPairs; ++m) a[m] = fr[m * 64 + lane];
     __syncthreads();
 
-#pragma unroll 1
+    // The layers are unrolled, so each layer's output region is a constant
+    // and a cell index splits into (row, column) by constant division.  A
+    // lane's B operand of tap pair m is read at a per-lane base plus a
+    // constant offset: the base points at tap 0 of its cell (the cell at
+    // (-1, -1)), shifted for the lanes carrying the pair's second tap by
+    // that tap's distance from the first, which is one cell for pairs 0, 2
+    // and 3 and FFW - 2 cells for pair 1; pair 4's second tap is zero.  All
+    // ten loads of a step are issued before its MFMAs.
+    const int c8b = 2 * c8;                 // byte offset of this lane's 8 channels
+#pragma unroll
     for (int l = 0; l < kCnnLayers; ++l) {
         f4 bias;
 #pragma unroll
@@ -276,32 +285,43 @@ __global__ __launch_bounds__(FTHREADS, 2) void k_cnn_infer(const uint8_t* __rest
         const int ln = l + 1 < kCnnLayers ? l + 1 : l;
 #pragma unroll
         for (int m = 0; m < kTapPairs; ++m) an[m] = fr[(ln * kTapPairs + m) * 64 + lane];
-        const short* X = buf[l & 1];
+        const char* X = reinterpret_cast<const char*>(buf[l & 1]);
         short* Y = buf[(l + 1) & 1];
         const int lo = l + 1, C = FFW - 2 * lo, n = (FFH - 2 * lo) * C;
-        // two independent 16-cell blocks per wave step, so that consecutive
-        // MFMAs do not wait on each other's accumulator
+        constexpr int CB = FSTR * 2;        // bytes per cell
+        // tap t = 3 (dy + 1) + (dx + 1) at byte offset (dy + 1) FFW CB + (dx + 1) CB from tap 0
+        auto toff = [](int t) { return ((t / 3) * FFW + t % 3) * CB; };
         for (int q0 = wave * 32; q0 < n; q0 += 32 * (FTHREADS / 64)) {
             int fy[2], fx[2];
-            f4 acc[2] = {bias, bias};
+            const char* pa[2];
+            const char* pb[2];
 #pragma unroll
             for (int h = 0; h < 2; ++h) {
                 const int q = min(q0 + 16 * h + (lane & 15), n - 1);
                 fy[h] = lo + q / C;
                 fx[h] = lo + q % C;
+                const char* base = X + ((fy[h] - 1) * FFW + fx[h] - 1) * CB + c8b;
+                pa[h] = base + half * CB;
+                pb[h] = base + half * (FFW - 2) * CB;
             }
+            s8 b[kTapPairs][2];
 #pragma unroll
-            for (int m = 0; m < kTapPairs; ++m) {
-                const int t = 2 * m + half;
+            for (int h = 0; h < 2; ++h) {
+                b[0][h] = *reinterpret_cast<const s8*>(pa[h] + toff(0));
+                b[1][h] = *reinterpret_cast<const s8*>(pb[h] + toff(2));
+                b[2][h] = *reinterpret_cast<const s8*>(pa[h] + toff(4));
+                b[3][h] = *reinterpret_cast<const s8*>(pa[h] + toff(6));
+                b[4][h] = *reinterpret_cast<const s8*>(pa[h] - half * CB + toff(8));
+            }
+            f4 acc[2] = {bias, bias};
+#pragma unroll
+            for (int m = 0; m < kTapPairs; ++m)
 #pragma unroll
                 for (int h = 0; h < 2; ++h) {
-                    s8 b = {0, 0, 0, 0, 0, 0, 0, 0};
-                    if (t < 9)
-                        b = *reinterpret_cast<const s8*>(
-                            &X[((fy[h] + t / 3 - 1) * FFW + fx[h] + t % 3 - 1) * FSTR + c8]);
-                    acc[h] = mfma32(a[m], b, acc[h]);
+                    s8 bb = b[m][h];
+                    if (m == kTapPairs - 1 && half) bb = s8{0, 0, 0, 0, 0, 0, 0, 0};   // the tenth tap
+                    acc[h] = mfma32(a[m], bb, acc[h]);
                 }
-            }
 #pragma unroll
             for (int h = 0; h < 2; ++h) {
                 if (q0 + 16 * h + (lane & 15) < n) {

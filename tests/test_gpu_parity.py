@@ -446,6 +446,23 @@ def test_detect_launch_forms_identical(gated):
             np.testing.assert_array_equal(a[f], b[f])
 
 
+def test_persistent_detection_matches_oracle(O32):
+    """The persistent launch form on its own against the oracle (same bars as
+    the one-wave-per-strip form), on ragged sizes."""
+    imgs = [synth.image(synth.SEED_RAGGED, 20 + i, w, h, nblobs=120)
+            for i, (w, h) in enumerate([(640, 480), (333, 217), (480, 640)])]
+    pipe = cd.Pipeline([(im.shape[1], im.shape[0]) for im in imgs])
+    pipe.upload(imgs)
+    cd.cdvs_tune_set(pipe.ctx, cd.KERNEL_DETECT, 1)
+    pipe.run()
+    torch.cuda.synchronize()
+    assert pipe.sync_status() == cd.CDVS_OK
+    for im, got in zip(imgs, pipe.keypoints()):
+        sel, _, _, _ = _oracle_stages(O32, im)
+        r_ref, r_got, _ = rates(sel, got)
+        assert r_ref >= KP_RATE and r_got >= KP_RATE, (im.shape, r_ref, r_got)
+
+
 def test_keypoints_outside_the_histogram_bounds(single, single_oracle):
     """Caller-supplied records the histogram kernels cannot take (scale in
     octave units above 2 sigma0 -- the bound the fixed-point histograms are
