@@ -295,7 +295,9 @@ cdvs_status cdvs_front_size(int32_t width, int32_t height, int32_t* out_width, i
  * An image whose longer side is at most 640 is copied.  A source whose size
  * (by cdvs_front_size) is not the context's image size, or whose
  * descriptor is invalid, is skipped and latched: cdvs_sync_status returns
- * CDVS_ERR_SHAPE.  d_images must not alias d_src. */
+ * CDVS_ERR_SHAPE.  d_images must not alias d_src.  The source table is
+ * read on the device: the caller guarantees that every source it describes
+ * lies inside d_src (the library does not know that buffer's size). */
 cdvs_status cdvs_front_end(cdvs_ctx* ctx, const uint8_t* d_src, const cdvs_image_desc* d_src_desc,
                            uint8_t* d_images, void* stream);
 
