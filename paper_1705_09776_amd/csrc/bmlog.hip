@@ -4,22 +4,23 @@
 // detector -- built as an alternative to cdvs_pyramid with the same output
 // layout, to measure it against the spatial filters on this GPU.
 //
-// One 1024-lane workgroup per 128 x 128 block (blocks overlap by 16 pixels
+// One 512-lane workgroup per 128 x 128 block (blocks overlap by 16 pixels
 // on every side and keep their central 96 x 96; pixels outside the octave
-// image come from its nearest edge pixel).  Two LDS buffers of 128 rows x
-// 64 complex (row stride 65): S keeps the block's spectrum, W is the work
-// buffer.
+// image come from its nearest edge pixel), two workgroups per CU: one LDS
+// work buffer of 128 rows x 64 complex (row stride 65), the block's
+// spectrum held in registers (16 values per lane) across all its scales.
 //
 // Each 1-D transform is two passes of small DFTs held in registers, with
 // one LDS exchange between them (Cooley-Tukey, N = N1 N2: a pass of
 // N1-point DFTs along a stride, a twiddle, a pass of N2-point DFTs on
-// contiguous runs; every task writes back to the positions it read, so a
-// pass needs no second buffer and no barrier inside it):
+// contiguous runs):
 //   forward rows: the real rows as 64-point complex DFTs of the packed pairs
-//            (x[2n], x[2n+1]) (8 x 8), split into the spectra X[0..64] of
-//            the real rows, X[0] and X[64] (both real) packed as one complex
-//            value; then 128-point DFTs down the 64 columns (8 x 16), the
-//            packed column giving X[.][0] + i X[.][64] transformed;
+//            (x[2n], x[2n+1]) (8 x 8), split in place into the spectra
+//            X[0..64] of the real rows, X[0] and X[64] (both real) packed
+//            as one complex value; then 128-point DFTs down the 64 columns
+//            (8 x 16), the packed column giving X[.][0] + i X[.][64]
+//            transformed, each lane keeping one 16-frequency run of one
+//            column;
 //   per output scale: the spectrum times the separable real transfer
 //            function H(v) H(u) (the packed column takes H(0) and H(64)
 //            apart through the Hermitian pair P(v), P(128 - v)), 128-point
@@ -28,11 +29,14 @@
 //            DFTs (8 x 8) whose second pass writes the central 96 x 96
 //            pixels straight from registers, scaled by 1 / (128 * 64) (the
 //            last scale's even samples also to the next octave's base).
-// After a forward pass pair, frequency k1 + N1 k2 of a transform sits at
-// position N2 k1 + k2; the inverse passes take that order and return
-// natural order.  Lanes run over rows (or columns), so with the row stride
-// of 65 complex the LDS accesses of a wave are conflict-free or at the
-// two-cycle minimum of 64-bit accesses.
+// Passes write back to the positions they read (no barrier inside them),
+// except the forward rows' second pass, which reads, waits and writes its
+// output in natural order so that the split works in place.  After the
+// forward column passes frequency k1 + 8 k2 sits at position 16 k1 + k2;
+// the inverse passes take that order and return natural order.  Lanes run
+// over rows (or columns), so with the row stride of 65 complex the LDS
+// accesses of a wave are conflict-free or at the two-cycle minimum of
+// 64-bit accesses.
 #include "cdvs_internal.h"
 
 namespace cdvs {
@@ -44,7 +48,7 @@ constexpr int BR = kBmR;        // 16
 constexpr int BS = BN - 2 * BR; // 96
 constexpr int HN = BN / 2;      // 64 complex per row (packed pairs / half spectrum)
 constexpr int RS = HN + 1;      // LDS row stride, in complex values
-constexpr int NT = 1024;
+constexpr int NT = 512;
 static_assert(BN == 128 && BR == 16, "the pass plan is written for 128-point blocks");
 
 __device__ __forceinline__ float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
@@ -125,12 +129,12 @@ __device__ __forceinline__ void dft(float2 (&x)[N]) {
 // G_{0,0..4} through H rows 0 and 5..8), else input G_{o,0} and outputs
 // G_{o,1..4} through H rows 1..4.
 template <bool U8>
-__global__ __launch_bounds__(NT, 1) void k_bmlog(const uint8_t* __restrict__ images, float* __restrict__ pyr,
-                                                 const OctJob* __restrict__ jobs, const int32_t* __restrict__ blocks,
-                                                 const float* __restrict__ Ht) {
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_bmlog(const uint8_t* __restrict__ images, float* __restrict__ pyr,
+                                              const OctJob* __restrict__ jobs, const int32_t* __restrict__ blocks,
+                                              const float* __restrict__ Ht) {
     constexpr int NOUT = U8 ? 5 : 4;
-    __shared__ float2 S[BN * RS];   // spectrum
     __shared__ float2 W[BN * RS];   // work buffer
+    __shared__ float2 P0[BN];       // spectrum of the packed column, by storage row
     __shared__ float2 tw[BN];       // exp(-2 pi i j / 128)
     __shared__ float Hs[NOUT][BN];  // the transfer functions applied here
 
@@ -151,7 +155,7 @@ __global__ __launch_bounds__(NT, 1) void k_bmlog(const uint8_t* __restrict__ ima
         Hs[q][e % BN] = Ht[(U8 ? (q == 0 ? 0 : 4 + q) : 1 + q) * BN + e % BN];
     }
     // block pixels as packed pairs in natural order (coalesced along rows)
-#pragma unroll
+#pragma unroll 4
     for (int j = 0; j < BN * HN / NT; ++j) {
         const int e = t + j * NT, r = e / HN, n = e % HN;
         const int gy = min(max(y0 + r, 0), h - 1);
@@ -172,8 +176,9 @@ __global__ __launch_bounds__(NT, 1) void k_bmlog(const uint8_t* __restrict__ ima
 
     // forward rows, pass 1: task (row r, n2): z[n2 + 8 n1] -> 8-point DFT
     // over n1 -> times w64^(n2 k1) -> position n2 + 8 k1
-    {
-        const int r = t % BN, n2 = t / BN;
+#pragma unroll
+    for (int j = 0; j < BN * 8 / NT; ++j) {
+        const int e = t + j * NT, r = e % BN, n2 = e / BN;
         float2 x[8];
         float2* row = W + r * RS + n2;
 #pragma unroll
@@ -184,47 +189,58 @@ __global__ __launch_bounds__(NT, 1) void k_bmlog(const uint8_t* __restrict__ ima
     }
     __syncthreads();
     // pass 2: task (r, k1): positions 8 k1 .. 8 k1 + 7 -> 8-point DFT ->
-    // Z[k1 + 8 k2] at position 8 k1 + k2
+    // Z[k1 + 8 k2], written in natural order once every task has read
     {
-        const int r = t % BN, k1 = t / BN;
-        float2 x[8];
-        float2* run = W + r * RS + 8 * k1;
+        constexpr int NJ = BN * 8 / NT;
+        float2 x[NJ][8];
 #pragma unroll
-        for (int i = 0; i < 8; ++i) x[i] = run[i];
-        dft<8, false>(x);
+        for (int j = 0; j < NJ; ++j) {
+            const int e = t + j * NT, r = e % BN, k1 = e / BN;
+            const float2* run = W + r * RS + 8 * k1;
 #pragma unroll
-        for (int i = 0; i < 8; ++i) run[i] = x[i];
+            for (int i = 0; i < 8; ++i) x[j][i] = run[i];
+            dft<8, false>(x[j]);
+        }
+        __syncthreads();
+#pragma unroll
+        for (int j = 0; j < NJ; ++j) {
+            const int e = t + j * NT, r = e % BN, k1 = e / BN;
+            float2* row = W + r * RS + k1;
+#pragma unroll
+            for (int k2 = 0; k2 < 8; ++k2) row[8 * k2] = x[j][k2];
+        }
     }
     __syncthreads();
     // split each row's packed transform Z into the spectrum of the real row,
-    // into S in natural order: E = (Z[k] + conj Z[64-k]) / 2,
-    // O = (Z[k] - conj Z[64-k]) / 2i, X[k] = E + w^k O,
-    // X[64-k] = conj E - conj(w^k) conj O (w = exp(-2 pi i / 128));
-    // S[0] = X[0] + i X[64]
-#pragma unroll
+    // in place: E = (Z[k] + conj Z[64-k]) / 2, O = (Z[k] - conj Z[64-k]) / 2i,
+    // X[k] = E + w^k O, X[64-k] = conj E - conj(w^k) conj O
+    // (w = exp(-2 pi i / 128)); X[0] + i X[64] at position 0
+#pragma unroll 2
     for (int j = 0; j < BN * 32 / NT; ++j) {
         const int e = t + j * NT, r = e % BN, k = e / BN;   // k = 0 also does k = 32
-        const float2* Z = W + r * RS;
-        float2* X = S + r * RS;
-        const int kk = k == 0 ? 32 : k;
+        float2* X = W + r * RS;
         if (k == 0) {
-            const float2 z0 = Z[0];
+            const float2 z0 = X[0], z32 = X[32];
             X[0] = make_float2(z0.x + z0.y, z0.x - z0.y);
+            // k = 32 pairs with itself: E = Re z, O = Im z, w^32 = -i
+            X[32] = make_float2(z32.x, -z32.y);
+        } else {
+            const float2 zk = X[k], zm = X[HN - k];
+            const float2 E = make_float2(0.5f * (zk.x + zm.x), 0.5f * (zk.y - zm.y));
+            const float2 O = make_float2(0.5f * (zk.y + zm.y), -0.5f * (zk.x - zm.x));
+            const float2 wk = tw[k];
+            X[k] = cadd(E, cmul(wk, O));
+            X[HN - k] = csub(conjf2(E), cmul(conjf2(wk), conjf2(O)));
         }
-        const float2 zk = Z[8 * (kk & 7) + (kk >> 3)], zm = Z[8 * ((HN - kk) & 7) + ((HN - kk) >> 3)];
-        const float2 E = make_float2(0.5f * (zk.x + zm.x), 0.5f * (zk.y - zm.y));
-        const float2 O = make_float2(0.5f * (zk.y + zm.y), -0.5f * (zk.x - zm.x));
-        const float2 wk = tw[kk];
-        X[kk] = cadd(E, cmul(wk, O));
-        if (kk != 32) X[HN - kk] = csub(conjf2(E), cmul(conjf2(wk), conjf2(O)));
     }
     __syncthreads();
     // forward columns, pass 1: task (column u, n2): rows 16 n1 + n2 ->
     // 8-point DFT over n1 -> times w128^(n2 k1) -> rows 16 k1 + n2
-    {
-        const int u = t % HN, n2 = t / HN;
+#pragma unroll
+    for (int j = 0; j < HN * 16 / NT; ++j) {
+        const int e = t + j * NT, u = e % HN, n2 = e / HN;
         float2 x[8];
-        float2* col = S + n2 * RS + u;
+        float2* col = W + n2 * RS + u;
 #pragma unroll
         for (int i = 0; i < 8; ++i) x[i] = col[16 * i * RS];
         dft<8, false>(x);
@@ -232,17 +248,21 @@ __global__ __launch_bounds__(NT, 1) void k_bmlog(const uint8_t* __restrict__ ima
         for (int k1 = 0; k1 < 8; ++k1) col[16 * k1 * RS] = k1 == 0 ? x[0] : cmul(x[k1], tw[(n2 * k1) & (BN - 1)]);
     }
     __syncthreads();
-    // pass 2: task (u, k1): rows 16 k1 .. 16 k1 + 15 -> 16-point DFT ->
-    // frequency v = k1 + 8 k2 at row 16 k1 + k2
-    if (t < HN * 8) {
-        const int u = t % HN, k1 = t / HN;
-        float2 x[16];
-        float2* col = S + 16 * k1 * RS + u;
+    // pass 2: task (u, k1) = this thread: rows 16 k1 .. 16 k1 + 15 ->
+    // 16-point DFT -> frequencies v = k1 + 8 k2, kept in registers for every
+    // output scale (the packed column also in P0, for its Hermitian pairs)
+    static_assert(HN * 8 == NT, "one spectrum run per thread");
+    const int u = t % HN, k1 = t / HN;
+    float2 spec[16];
+    {
+        const float2* col = W + 16 * k1 * RS + u;
 #pragma unroll
-        for (int i = 0; i < 16; ++i) x[i] = col[i * RS];
-        dft<16, false>(x);
+        for (int i = 0; i < 16; ++i) spec[i] = col[i * RS];
+        dft<16, false>(spec);
+        if (u == 0) {
 #pragma unroll
-        for (int i = 0; i < 16; ++i) col[i * RS] = x[i];
+            for (int k2 = 0; k2 < 16; ++k2) P0[16 * k1 + k2] = spec[k2];
+        }
     }
     __syncthreads();
 
@@ -250,27 +270,27 @@ __global__ __launch_bounds__(NT, 1) void k_bmlog(const uint8_t* __restrict__ ima
     const float scale = 1.f / (float)(BN * HN);
     for (int q = 0; q < NOUT; ++q) {
         const float* H = Hs[q];
-        // inverse columns, pass A: task (u, k1): the filtered spectrum at
-        // rows 16 k1 + k2 (frequency v = k1 + 8 k2) -> 16-point inverse DFT
-        // over k2 -> rows 16 k1 + n2 of W.  The packed column holds
-        // P = F0 + i F64 (F0, F64 the Hermitian transforms of the real
-        // columns 0 and 64); filtered, it is H(v) (a P(v) + b conj P(128 - v)),
-        // a = (H(0) + H(64)) / 2, b = (H(0) - H(64)) / 2, P(128 - v) sitting
-        // at row 16 ((8 - k1) & 7) + ((16 - k2 - (k1 != 0)) & 15).
-        if (t < HN * 8) {
-            const int u = t % HN, k1 = t / HN;
+        // inverse columns, pass A: the filtered spectrum run (frequency
+        // v = k1 + 8 k2) -> 16-point inverse DFT over k2 -> rows 16 k1 + n2
+        // of W.  The packed column holds P = F0 + i F64 (F0, F64 the
+        // Hermitian transforms of the real columns 0 and 64); filtered, it is
+        // H(v) (a P(v) + b conj P(128 - v)), a = (H(0) + H(64)) / 2,
+        // b = (H(0) - H(64)) / 2, P(128 - v) sitting at storage row
+        // 16 ((8 - k1) & 7) + ((16 - k2 - (k1 != 0)) & 15), which is
+        // pb - k2 with pb = 16 ((8 - k1) & 7) + 15 + (k1 == 0), except row 0
+        // for k1 = k2 = 0.
+        {
             float2 x[16];
-            const float2* col = S + 16 * k1 * RS + u;
             if (u != 0) {
                 const float hu = H[u];
 #pragma unroll
-                for (int k2 = 0; k2 < 16; ++k2) x[k2] = cscale(col[k2 * RS], H[k1 + 8 * k2] * hu);
+                for (int k2 = 0; k2 < 16; ++k2) x[k2] = cscale(spec[k2], H[k1 + 8 * k2] * hu);
             } else {
                 const float a = 0.5f * (H[0] + H[HN]), b = 0.5f * (H[0] - H[HN]);
-                const int pk1 = (8 - k1) & 7, c = k1 != 0;
+                const int pb = 16 * ((8 - k1) & 7) + 15 + (k1 == 0);
 #pragma unroll
                 for (int k2 = 0; k2 < 16; ++k2) {
-                    const float2 p = col[k2 * RS], pm = S[(16 * pk1 + ((16 - k2 - c) & 15)) * RS];
+                    const float2 p = spec[k2], pm = P0[k2 == 0 && k1 == 0 ? 0 : pb - k2];
                     const float hv = H[k1 + 8 * k2];
                     x[k2] = make_float2(hv * (a * p.x + b * pm.x), hv * (a * p.y - b * pm.y));
                 }
@@ -283,13 +303,14 @@ __global__ __launch_bounds__(NT, 1) void k_bmlog(const uint8_t* __restrict__ ima
         __syncthreads();
         // pass B: task (u, n2): rows 16 k1 + n2 times conj w128^(n2 k1) ->
         // 8-point inverse DFT over k1 -> block row 16 n1 + n2
-        {
-            const int u = t % HN, n2 = t / HN;
+#pragma unroll 1
+        for (int j = 0; j < HN * 16 / NT; ++j) {
+            const int e = t + j * NT, uu = e % HN, n2 = e / HN;
             float2 x[8];
-            float2* col = W + n2 * RS + u;
+            float2* col = W + n2 * RS + uu;
 #pragma unroll
-            for (int k1 = 0; k1 < 8; ++k1)
-                x[k1] = k1 == 0 ? col[0] : cmulc(col[16 * k1 * RS], tw[(n2 * k1) & (BN - 1)]);
+            for (int kk = 0; kk < 8; ++kk)
+                x[kk] = kk == 0 ? col[0] : cmulc(col[16 * kk * RS], tw[(n2 * kk) & (BN - 1)]);
             dft<8, true>(x);
 #pragma unroll
             for (int n1 = 0; n1 < 8; ++n1) col[16 * n1 * RS] = x[n1];
@@ -298,8 +319,9 @@ __global__ __launch_bounds__(NT, 1) void k_bmlog(const uint8_t* __restrict__ ima
         // rebuild each kept row's packed transform (natural order) from its
         // half spectrum: E = (X[k] + conj X[64-k]) / 2,
         // O = (X[k] - conj X[64-k]) conj(w^k) / 2, Z[k] = E + i O
-        for (int e = t; e < BS * 32; e += NT) {
-            const int r = BR + e % BS, k = e / BS;   // k = 0 also does k = 32
+#pragma unroll 2
+        for (int j = 0; j < BS * 32 / NT; ++j) {
+            const int e = t + j * NT, r = BR + e % BS, k = e / BS;   // k = 0 also does k = 32
             float2* X = W + r * RS;
             if (k == 0) {
                 // X[0] = X[0].x and X[64] = X[0].y, both real (w^0 = 1);
@@ -323,8 +345,8 @@ __global__ __launch_bounds__(NT, 1) void k_bmlog(const uint8_t* __restrict__ ima
         __syncthreads();
         // inverse rows, pass 1: task (r, k2): positions 8 k1 + k2 -> 8-point
         // inverse DFT over k1 -> times conj w64^(n1 k2) -> position 8 n1 + k2
-        if (t < BS * 8) {
-            const int r = BR + t % BS, k2 = t / BS;
+        for (int e = t; e < BS * 8; e += NT) {
+            const int r = BR + e % BS, k2 = e / BS;
             float2 x[8];
             float2* row = W + r * RS + k2;
 #pragma unroll
@@ -339,14 +361,14 @@ __global__ __launch_bounds__(NT, 1) void k_bmlog(const uint8_t* __restrict__ ima
         // 8 n1 + 7 -> 8-point inverse DFT over k2 -> z[n1 + 8 n2] = the pixel
         // pair at block columns 2 n, 2 n + 1 (n = n1 + 8 n2); the kept
         // columns 16..111 are n2 = 1..6
-        if (t < BS * 8) {
-            const int n1 = t % 8, r = BR + t / 8;
+        const int plane = U8 ? q : q + 1;   // G_{o,plane}
+        for (int e = t; e < BS * 8; e += NT) {
+            const int n1 = e % 8, r = BR + e / 8;
             float2 x[8];
             const float2* run = W + r * RS + 8 * n1;
 #pragma unroll
             for (int i = 0; i < 8; ++i) x[i] = run[i];
             dft<8, true>(x);
-            const int plane = U8 ? q : q + 1;   // G_{o,plane}
             const int gy = y0 + r;
             const bool down = job.next0 >= 0 && q == NOUT - 1 && (gy & 1) == 0;
             if (gy < h) {
