@@ -23,6 +23,8 @@ typedef short s4 __attribute__((ext_vector_type(4)));
 typedef short s8 __attribute__((ext_vector_type(8)));
 typedef __bf16 b8 __attribute__((ext_vector_type(8)));
 typedef float f4 __attribute__((ext_vector_type(4)));
+typedef float f2v __attribute__((ext_vector_type(2)));
+typedef __bf16 bf2v __attribute__((ext_vector_type(2)));
 
 // Forward 3x3 convolutions use v_mfma_f32_16x16x32_bf16, two taps per
 // instruction: lane l holds A[l%16][8(l/16)+j] and B[8(l/16)+j][l%16] for
@@ -46,6 +48,13 @@ __device__ __forceinline__ short f2bf(float f) {
     return (short)(u >> 16);
 }
 __device__ __forceinline__ float bf2f(short h) { return __uint_as_float(((uint32_t)(uint16_t)h) << 16); }
+// max(x, 0) as one median (x is finite)
+__device__ __forceinline__ float relu(float x) { return __builtin_amdgcn_fmed3f(x, 0.f, 3.402823466e38f); }
+// Two floats -> two bf16 in one word (low half: a), by the hardware
+// conversion, which rounds to nearest even as f2bf does (finite inputs).
+__device__ __forceinline__ uint32_t f2bf2(float a, float b) {
+    return __builtin_bit_cast(uint32_t, __builtin_convertvector((f2v){a, b}, bf2v));
+}
 
 __device__ __forceinline__ int find_cnn_image(const CnnImage* im, int n, int tile) {
     int lo = 0, hi = n - 1;
@@ -219,6 +228,7 @@ __global__ __launch_bounds__(FTHREADS, 2) void k_cnn_infer(const uint8_t* __rest
     const int ty0 = (lt / g.ftiles_x) * FTH, tx0 = (lt % g.ftiles_x) * FTW;
     const int oy = ty0 - FHALO, ox = tx0 - FHALO;   // image cell of frame (0, 0)
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, kb = lane >> 4;
+    const int H4 = g.H4, W4 = g.W4;   // read once (the layer loops test every cell against them)
 
     // u8 -> bf16(u / 255) table (the same expression as s2d_frag)
     if (threadIdx.x < 256) lut[threadIdx.x] = f2bf((float)threadIdx.x / 255.f);
@@ -233,7 +243,7 @@ __global__ __launch_bounds__(FTHREADS, 2) void k_cnn_infer(const uint8_t* __rest
         const int fx = it % FFW, r4 = (it / FFW) & 3, fy = it / (FFW * 4);
         const int cy = oy + fy, cx = ox + fx;
         px[k] = 0;
-        if (it < FFH * FFW * 4 && cy >= 0 && cy < g.H4 && cx >= 0 && cx < g.W4) {
+        if (it < FFH * FFW * 4 && cy >= 0 && cy < H4 && cx >= 0 && cx < W4) {
             const int y = min(4 * cy + r4, g.H - 1);
             const uint8_t* row = images + g.src + (int64_t)y * g.src_pitch;
             const int x0 = 4 * cx;
@@ -253,7 +263,7 @@ __global__ __launch_bounds__(FTHREADS, 2) void k_cnn_infer(const uint8_t* __rest
         const int fx = it % FFW, r4 = (it / FFW) & 3, fy = it / (FFW * 4);
         const int cy = oy + fy, cx = ox + fx;
         s4 v = {0, 0, 0, 0};
-        if (cy >= 0 && cy < g.H4 && cx >= 0 && cx < g.W4) {
+        if (cy >= 0 && cy < H4 && cx >= 0 && cx < W4) {
 #pragma unroll
             for (int j = 0; j < 4; ++j) v[j] = lut[(px[k] >> (8 * j)) & 255u];
         }
@@ -318,20 +328,24 @@ __global__ __launch_bounds__(FTHREADS, 2) void k_cnn_infer(const uint8_t* __rest
             for (int m = 0; m < kTapPairs; ++m)
 #pragma unroll
                 for (int h = 0; h < 2; ++h) {
-                    s8 bb = b[m][h];
-                    if (m == kTapPairs - 1 && half) bb = s8{0, 0, 0, 0, 0, 0, 0, 0};   // the tenth tap
-                    acc[h] = mfma32(a[m], bb, acc[h]);
+                    // (the tenth tap's lanes read tap 8's cell again: its A
+                    // fragment is zero and every activation is finite and
+                    // non-negative, so those products add exact zeros)
+                    acc[h] = mfma32(a[m], b[m][h], acc[h]);
                 }
+            // relu, bf16, zero outside the image: computed for every lane and
+            // selected (no branch per element), one 8-byte store per cell
 #pragma unroll
             for (int h = 0; h < 2; ++h) {
-                if (q0 + 16 * h + (lane & 15) < n) {
-                    const int cy = oy + fy[h], cx = ox + fx[h];
-                    const bool in = cy >= 0 && cy < g.H4 && cx >= 0 && cx < g.W4;
-                    s4 o;
-#pragma unroll
-                    for (int r = 0; r < 4; ++r) o[r] = in ? f2bf(fmaxf(acc[h][r], 0.f)) : (short)0;
-                    *reinterpret_cast<s4*>(&Y[(fy[h] * FFW + fx[h]) * FSTR + 4 * kb]) = o;
-                }
+                const int cy = oy + fy[h], cx = ox + fx[h];
+                const bool in = (unsigned)cy < (unsigned)H4 && (unsigned)cx < (unsigned)W4;
+                uint2 o;
+                o.x = f2bf2(relu(acc[h][0]), relu(acc[h][1]));
+                o.y = f2bf2(relu(acc[h][2]), relu(acc[h][3]));
+                o.x = in ? o.x : 0u;
+                o.y = in ? o.y : 0u;
+                if (q0 + 16 * h + (lane & 15) < n)
+                    *reinterpret_cast<uint2*>(&Y[(fy[h] * FFW + fx[h]) * FSTR + 4 * kb]) = o;
             }
         }
 #pragma unroll
@@ -343,12 +357,12 @@ __global__ __launch_bounds__(FTHREADS, 2) void k_cnn_infer(const uint8_t* __rest
     const short* X4 = buf[kCnnLayers & 1];
     for (int q = threadIdx.x; q < FTH * FTW; q += blockDim.x) {
         const int cy = ty0 + q / FTW, cx = tx0 + q % FTW;
-        if (cy >= g.H4 || cx >= g.W4) continue;
+        if (cy >= H4 || cx >= W4) continue;
         const short* xs = &X4[((FHALO + q / FTW) * FFW + FHALO + q % FTW) * FSTR];
         float x[CC];
 #pragma unroll
         for (int ch = 0; ch < CC; ++ch) x[ch] = bf2f(xs[ch]);
-        const int64_t c = g.cell0 + (int64_t)cy * g.W4 + cx;
+        const int64_t c = g.cell0 + (int64_t)cy * W4 + cx;
         uint32_t bits = 0;
 #pragma unroll
         for (int o = 0; o < NHD; ++o) {
