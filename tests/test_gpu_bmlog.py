@@ -100,3 +100,18 @@ def test_close_to_spatial_inside():
                 continue
             inner = (slice(m, a.shape[0] - m), slice(m, a.shape[1] - m))
             assert np.abs(a[inner] - b[inner]).max() <= 5e-3, (o, k)
+
+
+def test_bench_batch_sampled():
+    """The benchmark's launch configuration: the BMLoG scale space of the
+    256-image 640x480 batch in one launch per octave; sampled images (first,
+    last and two between) against the float64 oracle on every plane."""
+    imgs = synth.fixed_batch(synth.SEED_BATCH, 256)
+    pipe = _bmlog(list(imgs))
+    for i in (0, 37, 128, 255):
+        ref = B.pyramid(imgs[i])
+        assert pipe.num_octaves(i) == len(ref)
+        for o, P in enumerate(ref):
+            for k in range(5):
+                d = np.abs(pipe.plane(i, o, k).astype(np.float64) - P[k]).max()
+                assert d <= TOL, (i, o, k, d)

@@ -93,3 +93,23 @@ def test_detector_on_front_end_output():
         np.testing.assert_array_equal(a, b)
     for a, b in zip(desc_a, ref.descriptors()):
         np.testing.assert_array_equal(a, b)
+
+
+def test_bench_configuration_every_image():
+    """The benchmark's launch configuration: 256 high-resolution scenes of
+    1280x960 rendered on the device, brought to 640x480 in one launch; every
+    output image bit-exact against the oracle on its source."""
+    W, H, n = 1280, 960, 256
+    src = synth.device_batch(synth.SEED_HIRES, n, W, H, 400, 1200, smax=40.0)
+    d_sd = cd.descs_to_device([cd.ImageDesc(i * W * H, W, H, W, 0) for i in range(n)])
+    wo, ho = cd.cdvs_front_size(W, H)
+    pipe = cd.Pipeline([(wo, ho)] * n)
+    pipe.front_end(src, d_sd)
+    torch.cuda.synchronize()
+    assert pipe.sync_status() == cd.CDVS_OK
+    host = pipe.d_images.cpu().numpy()
+    srch = src.cpu().numpy()
+    for i, d in enumerate(pipe.descs):
+        out = host[d.offset:d.offset + d.pitch * d.height].reshape(d.height, d.pitch)[:, :d.width]
+        ref = F.front(srch[i * W * H:(i + 1) * W * H].reshape(H, W))
+        np.testing.assert_array_equal(out, ref, err_msg=f"image {i}")

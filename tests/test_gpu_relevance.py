@@ -117,3 +117,29 @@ def test_end_to_end_selection(model, O32):
         hit += len(pairs)
     print(f"relevance selection end to end: {hit / tot:.4f} of the oracle's 300 per image found")
     assert hit / tot >= 0.97
+
+
+def test_bench_configuration_every_image(model):
+    """The benchmark's launch configuration: the plain pass on the 256-image
+    640x480 batch, then 300 of each image's 1000 keypoints selected in one
+    launch; on the GPU's own records the oracle's selection and scores must
+    come out identical for every image."""
+    imgs = synth.fixed_batch(synth.SEED_BATCH, 256)
+    pipe = cd.Pipeline([(640, 480)] * len(imgs))
+    pipe.upload(list(imgs))
+    pipe.run()
+    torch.cuda.synchronize()
+    assert pipe.sync_status() == cd.CDVS_OK
+    kps = pipe.keypoints()
+    score = torch.zeros((len(imgs), pipe.kp_capacity), dtype=torch.float32, device="cuda")
+    cd.cdvs_relevance_select(pipe.ctx, cd.Relevance(model), pipe.d_kp, pipe.d_count, 300, pipe.d_kp_ori,
+                             pipe.d_count_ori, score)
+    torch.cuda.synchronize()
+    got = pipe.oriented()
+    sc = score.cpu().numpy()
+    for i, k in enumerate(kps):
+        idx, r = relevance.select(k, 640, 480, model, 300)
+        assert len(got[i]) == len(idx) == min(300, len(k)), i
+        for f in ("ix", "iy", "octave"):
+            np.testing.assert_array_equal(got[i][f], k[f][idx], err_msg=f"image {i}")
+        np.testing.assert_array_equal(sc[i, :len(idx)].view(np.uint32), r[idx].view(np.uint32), err_msg=f"image {i}")

@@ -100,3 +100,24 @@ def test_end_to_end_symbols(model, O32):
     print(f"{close.sum()} descriptor pairs within 1e-3; {sure.mean():.4f} of their symbols away from a threshold")
     assert close.sum() >= 0.85 * len(pairs)
     np.testing.assert_array_equal(gq[jb[close]][sure], rq[sure])
+
+
+def test_bench_configuration_every_image(model):
+    """The benchmark's launch configuration: all 128 elements of the 1000
+    descriptors of each of the 256 images of the plain pass coded in one
+    launch; on the GPU's own descriptors the oracle's codes must come out
+    identical for every descriptor."""
+    imgs = synth.fixed_batch(synth.SEED_BATCH, 256)
+    pipe = cd.Pipeline([(640, 480)] * len(imgs))
+    pipe.upload(list(imgs))
+    pipe.run()
+    codes = torch.full((len(imgs), pipe.kp_capacity, cd.TQ_WORDS), -1, dtype=torch.int32, device="cuda")
+    cd.cdvs_encode(pipe.ctx, cd.Tq(model), 128, pipe.d_desc, pipe.d_count_ori, codes)
+    torch.cuda.synchronize()
+    assert pipe.sync_status() == cd.CDVS_OK
+    got = codes.cpu().numpy().view(np.uint32)
+    desc = pipe.d_desc.cpu().numpy()
+    cnt = pipe.d_count_ori.cpu().numpy()
+    assert cnt.min() > 0
+    for i in range(len(imgs)):
+        np.testing.assert_array_equal(got[i, :cnt[i]], tq.encode(desc[i, :cnt[i]], model, 128), err_msg=f"image {i}")
