@@ -274,6 +274,28 @@ def test_gated_detection_matches_oracle(O32, which):
     assert_parity(summarize(res), f"gated ({which} mask)")
 
 
+def test_gated_bench_configuration_every_image(O32):
+    """The benchmark's gated launch configuration: the trained 640x480
+    network's mask at its stored threshold over the 256-image batch, then
+    the gated pass; every image against the oracle's gated detection under
+    the GPU's mask, to the plain path's bars."""
+    from paper_1705_09776_amd import surrogate
+    imgs = list(synth.fixed_batch(synth.SEED_BATCH, 256))
+    pipe = cd.Pipeline([(640, 480)] * len(imgs))
+    pipe.upload(imgs)
+    pipe.cnn_buffers()
+    w = os.path.join(_ROOT, "paper_1705_09776_amd", "weights", "surrogate_640x480.npz")
+    tau = float(json.load(open(os.path.splitext(w)[0] + ".json"))["tau"])
+    params = torch.from_numpy(surrogate.load_checkpoint(w)["params"]).cuda()
+    pipe.run_gated(params, tau)
+    torch.cuda.synchronize()
+    assert pipe.sync_status() == cd.CDVS_OK
+    masks = _image_masks(pipe, pipe.d_mask.cpu().numpy())
+    res = check_images(O32, imgs, pipe.keypoints(), pipe.oriented(), pipe.descriptors(), masks=masks,
+                       fmax=pipe.params.mask_fmax)
+    assert_parity(summarize(res), "gated (trained mask, 256-image batch)")
+
+
 def test_gate_leaves_octaves_beyond_its_bits_dense(O32):
     """A 2048x1536 image has octaves 0..6; the mask has bits for octaves 0..5
     only, so octave 6 is always examined densely: an all-ones mask gives
