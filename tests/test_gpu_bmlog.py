@@ -115,3 +115,26 @@ def test_bench_batch_sampled():
             for k in range(5):
                 d = np.abs(pipe.plane(i, o, k).astype(np.float64) - P[k]).max()
                 assert d <= TOL, (i, o, k, d)
+
+
+def test_edge_shapes():
+    """The smallest side allowed (16), odd sides, a side shorter than one
+    block's kept 96 pixels next to one spanning many blocks, and a flat
+    image (exactly the constant after every transform, up to rounding)."""
+    rng = np.random.default_rng(4)
+    imgs = [rng.integers(0, 256, size=(16, 16), dtype=np.uint8),
+            synth.image(21, 1, 97, 61, nblobs=10),
+            synth.image(21, 2, 1000, 33, nblobs=40),
+            synth.image(21, 3, 17, 611, nblobs=20),
+            np.full((64, 80), 117, dtype=np.uint8)]
+    pipe = _bmlog(imgs)
+    for i, im in enumerate(imgs):
+        ref = B.pyramid(im)
+        assert pipe.num_octaves(i) == len(ref)
+        for o, P in enumerate(ref):
+            for k in range(5):
+                d = np.abs(pipe.plane(i, o, k).astype(np.float64) - P[k]).max()
+                assert d <= TOL, (im.shape, o, k, d)
+    for o in range(pipe.num_octaves(4)):
+        for k in range(5):
+            assert np.abs(pipe.plane(4, o, k) - 117.0).max() <= TOL
