@@ -11,7 +11,7 @@
  * computes, following "Fast MPEG-CDVS Encoder with GPU-CPU Hybrid Computing"
  * (Duan et al.), in the order the paper gives:
  *   - Sec. III-A, Eq. (1): Gaussian scale space by separable filters, then a
- *     3x3 Laplacian, scale-normalised ("normalized derivatives").
+ *     3x3 Laplacian, scale-normalised (times sigma^2).
  *   - Sec. III-A, Eqs. (2)-(3): the ALP cubic in sigma per pixel, its
  *     extremal scale from p'(sigma) = 0, then the 8-neighbour comparison.
  *   - Sec. IV-A, Algorithm 1: per octave, stage A (filtering + ALP test),

@@ -4,7 +4,7 @@ integer arithmetic).
 Only the test suite, the smoke check and the benchmark's CPU-baseline leg
 may import this module; the GPU path shares nothing with it.
 
-What it computes (Sec. III, the opening of "CDVS Revisit for Speedup": the
+What it computes (the opening of Sec. III: the
 encoder first brings every input image down to a low resolution whose
 longer side is at most 640 pixels).  The paper names neither the output
 size rule nor the filter; the readings taken here are:
