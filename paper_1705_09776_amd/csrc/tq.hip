@@ -28,7 +28,10 @@ __global__ __launch_bounds__(256) void k_tq_encode(const float* __restrict__ des
                                                    int n_elem, uint32_t* __restrict__ codes) {
     __shared__ float slo[kDescDim], shi[kDescDim];
     __shared__ int sord[kDescDim];
-    __shared__ uint8_t sym[kTqDesc][kDescDim];
+    // symbol rows padded to 136 bytes: a cell's eight symbols go out as one
+    // 8-byte store, and the four descriptors of a wave start on different banks
+    constexpr int kSymStride = kDescDim + 8;
+    __shared__ __align__(8) uint8_t sym[kTqDesc][kSymStride];
     const int tid = threadIdx.x, cell = tid & 15, dl = tid >> 4;
     if (tid < kDescDim) {
         slo[tid] = lo[tid];
@@ -63,11 +66,15 @@ __global__ __launch_bounds__(256) void k_tq_encode(const float* __restrict__ des
             v[6] = ((h1 + h5) - (h3 + h7)) / 4.f;
             v[7] = ((h0 + h1 + h2 + h3) - (h4 + h5 + h6 + h7)) / 8.f;
         }
+        uint32_t s0 = 0u, s1 = 0u;
 #pragma unroll
         for (int k = 0; k < 8; ++k) {
             const int e = cell * 8 + k;
-            sym[dl][e] = v[k] > shi[e] ? 1 : (v[k] < slo[e] ? 2 : 0);
+            const uint32_t c = v[k] > shi[e] ? 1u : (v[k] < slo[e] ? 2u : 0u);
+            if (k < 4) s0 |= c << (8 * k);
+            else s1 |= c << (8 * (k - 4));
         }
+        *reinterpret_cast<uint2*>(&sym[dl][cell * 8]) = make_uint2(s0, s1);
     }
     __syncthreads();
     if (active && cell < 8) {
