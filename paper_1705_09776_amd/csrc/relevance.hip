@@ -10,6 +10,10 @@
 // then (r, input index) pairs are sorted in LDS by a bitonic sort on 64-bit
 // keys -- the complement of r's bits (r >= 0, so its bits order like its
 // value) over the index -- and the first n_keep records are copied out.
+// The sort's exchanges at distances below 128 stay inside one 128-key
+// chunk, which one wave holds in registers (two keys per lane) and
+// exchanges by lane shuffles; only the longer distances go through LDS
+// with a workgroup barrier each.
 #include "cdvs_internal.h"
 
 namespace cdvs {
@@ -31,6 +35,65 @@ __device__ __forceinline__ int bin_of(const float* edges, float v) {
     return b;
 }
 
+// One compare-exchange of a bitonic stage of block size `size` at distance
+// `stride` < 64, for the key k of element i held by this lane, whose
+// partner (i ^ stride) is in lane ^ stride: the lower index keeps the
+// smaller key in an ascending block, the larger in a descending one.
+__device__ __forceinline__ unsigned long long bitonic_lane_step(unsigned long long k, int i, int size, int stride) {
+    const unsigned long long o = __shfl_xor(k, stride);
+    const bool asc = (i & size) == 0, lower = (i & stride) == 0;
+    return (lower == asc) ? (o < k ? o : k) : (o > k ? o : k);
+}
+
+// The steps at distances below 128 of bitonic block sizes first..last, on
+// the 128-key chunks of key[0 .. npow): each wave takes whole chunks, two
+// keys per lane (elements c*128 + lane and c*128 + 64 + lane).
+__device__ __forceinline__ void bitonic_chunk_steps(unsigned long long* key, int npow, int first, int last) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    for (int c = wave; c < npow / 128; c += nw) {
+        const int i0 = 128 * c + lane, i1 = i0 + 64;
+        unsigned long long k0 = key[i0], k1 = key[i1];
+        for (int size = first; size <= last; size <<= 1) {
+            if (size >= 128) {   // distance 64: the lane's own pair, one direction for both
+                const bool asc = (i0 & size) == 0;
+                const unsigned long long lo = k0 < k1 ? k0 : k1, hi = k0 < k1 ? k1 : k0;
+                k0 = asc ? lo : hi;
+                k1 = asc ? hi : lo;
+            }
+            for (int stride = (size >> 1) < 32 ? (size >> 1) : 32; stride > 0; stride >>= 1) {
+                k0 = bitonic_lane_step(k0, i0, size, stride);
+                k1 = bitonic_lane_step(k1, i1, size, stride);
+            }
+        }
+        key[i0] = k0;
+        key[i1] = k1;
+    }
+}
+
+// Ascending bitonic sort of key[0 .. npow) (npow a power of two, at least
+// 128) by the whole workgroup: block sizes up to 128 entirely in
+// registers, then for each larger size its distances of 128 and more
+// through LDS (a barrier each) and the rest in registers.
+__device__ void bitonic_sort_keys(unsigned long long* key, int npow) {
+    bitonic_chunk_steps(key, npow, 2, 128);
+    __syncthreads();
+    for (int size = 256; size <= npow; size <<= 1) {
+        for (int stride = size >> 1; stride >= 128; stride >>= 1) {
+            for (int t = threadIdx.x; t < npow / 2; t += blockDim.x) {
+                const int lo = 2 * t - (t & (stride - 1)), hi = lo + stride;
+                const unsigned long long a = key[lo], b = key[hi];
+                if ((a > b) == ((lo & size) == 0)) {
+                    key[lo] = b;
+                    key[hi] = a;
+                }
+            }
+            __syncthreads();
+        }
+        bitonic_chunk_steps(key, npow, size, size);
+        __syncthreads();
+    }
+}
+
 __global__ __launch_bounds__(kRelThreads) void k_relevance(const cdvs_keypoint* __restrict__ kp_in,
                                                            const int32_t* __restrict__ count_in,
                                                            const int32_t* __restrict__ wh, int kp_cap,
@@ -46,7 +109,7 @@ __global__ __launch_bounds__(kRelThreads) void k_relevance(const cdvs_keypoint* 
     if (tid < kRelFeatures * kRelBins) sv[tid] = values[tid];
     __syncthreads();
     const int n = min(max(count_in[img], 0), kp_cap);
-    int npow = 1;
+    int npow = 128;   // the sort works on whole 128-key chunks (padding sorts last)
     while (npow < n) npow <<= 1;
     const float hx = 0.5f * (float)(wh[2 * img] - 1), hy = 0.5f * (float)(wh[2 * img + 1] - 1);
     const cdvs_keypoint* in = kp_in + (int64_t)img * kp_cap;
@@ -63,21 +126,7 @@ __global__ __launch_bounds__(kRelThreads) void k_relevance(const cdvs_keypoint* 
         key[i] = k;
     }
     __syncthreads();
-    for (int size = 2; size <= npow; size <<= 1)
-        for (int stride = size >> 1; stride > 0; stride >>= 1) {
-            for (int i = tid; i < npow; i += kRelThreads) {
-                const int j = i ^ stride;
-                if (j > i) {
-                    const unsigned long long a = key[i], b = key[j];
-                    const bool up = (i & size) == 0;
-                    if ((a > b) == up) {
-                        key[i] = b;
-                        key[j] = a;
-                    }
-                }
-            }
-            __syncthreads();
-        }
+    bitonic_sort_keys(key, npow);
     const int m = min(n, n_keep);
     for (int i = tid; i < m; i += kRelThreads) {
         const unsigned long long k = key[i];
