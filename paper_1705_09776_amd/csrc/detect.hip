@@ -497,11 +497,64 @@ __global__ __launch_bounds__(FIN_THREADS) void k_select(const cdvs_keypoint* __r
     }
 }
 
-// Ascending bitonic sort of npow (a power of two) 64-bit keys with 16-bit
-// payloads in LDS by the whole workgroup.
-__device__ __forceinline__ void bitonic_sort(unsigned long long* key, unsigned short* idx, int npow) {
-    for (int size = 2; size <= npow; size <<= 1) {
-        for (int stride = size >> 1; stride > 0; stride >>= 1) {
+// One compare-exchange of a bitonic stage of block size `size` at distance
+// `stride` < 64 for the (key, payload) of element i held by this lane, whose
+// partner (i ^ stride) is in lane ^ stride: the lower index keeps the
+// smaller key in an ascending block, the larger in a descending one (equal
+// keys stay where they are).
+__device__ __forceinline__ void bitonic_lane_step(unsigned long long& k, int& p, int i, int size, int stride) {
+    const unsigned long long o = __shfl_xor(k, stride);
+    const int op = __shfl_xor(p, stride);
+    const bool asc = (i & size) == 0, lower = (i & stride) == 0;
+    const bool take = (lower == asc) ? (o < k) : (o > k);
+    k = take ? o : k;
+    p = take ? op : p;
+}
+
+// The steps at distances below 128 of bitonic block sizes first..last on
+// the 128-entry chunks of [0, npow): each wave takes whole chunks, two
+// entries per lane (c*128 + lane and c*128 + 64 + lane) in registers.
+__device__ __forceinline__ void bitonic_chunk_steps(unsigned long long* key, unsigned short* idx, int npow, int first,
+                                                    int last) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    for (int c = wave; c < npow / 128; c += nw) {
+        const int i0 = 128 * c + lane, i1 = i0 + 64;
+        unsigned long long k0 = key[i0], k1 = key[i1];
+        int p0 = idx[i0], p1 = idx[i1];
+        for (int size = first; size <= last; size <<= 1) {
+            if (size >= 128) {   // distance 64: the lane's own pair, one direction for both
+                const bool asc = (i0 & size) == 0;
+                if (asc ? (k0 > k1) : (k0 < k1)) {
+                    const unsigned long long tk = k0;
+                    k0 = k1;
+                    k1 = tk;
+                    const int tp = p0;
+                    p0 = p1;
+                    p1 = tp;
+                }
+            }
+            for (int stride = (size >> 1) < 32 ? (size >> 1) : 32; stride > 0; stride >>= 1) {
+                bitonic_lane_step(k0, p0, i0, size, stride);
+                bitonic_lane_step(k1, p1, i1, size, stride);
+            }
+        }
+        key[i0] = k0;
+        key[i1] = k1;
+        idx[i0] = (unsigned short)p0;
+        idx[i1] = (unsigned short)p1;
+    }
+}
+
+// Ascending bitonic sort of npow (a power of two, at least 128) 64-bit keys
+// with 16-bit payloads in LDS by the whole workgroup: block sizes up to 128
+// entirely in registers (lane shuffles), then for each larger size its
+// distances of 128 and more through LDS with a barrier each, the rest in
+// registers.
+__device__ void bitonic_sort(unsigned long long* key, unsigned short* idx, int npow) {
+    bitonic_chunk_steps(key, idx, npow, 2, 128);
+    __syncthreads();
+    for (int size = 256; size <= npow; size <<= 1) {
+        for (int stride = size >> 1; stride >= 128; stride >>= 1) {
             for (int t = threadIdx.x; t < npow / 2; t += blockDim.x) {
                 const int lo = 2 * t - (t & (stride - 1));
                 const int hi = lo + stride;
@@ -517,6 +570,8 @@ __device__ __forceinline__ void bitonic_sort(unsigned long long* key, unsigned s
             }
             __syncthreads();
         }
+        bitonic_chunk_steps(key, idx, npow, size, size);
+        __syncthreads();
     }
 }
 
@@ -553,7 +608,7 @@ __global__ __launch_bounds__(FIN_THREADS) void k_finalize(const cdvs_keypoint* _
     const cdvs_keypoint* c = n_all > kCandCap ? sel + (int64_t)img * kCandCap : cand + cand_off[img];
     const int n = min(n_all, kCandCap);
     const int tid = threadIdx.x;
-    int npow = 1;
+    int npow = 128;   // the sort works on whole 128-entry chunks (padding sorts last)
     while (npow < n) npow <<= 1;
 
     if (tid < kMaxOctaves + 2) seg[tid] = n;
