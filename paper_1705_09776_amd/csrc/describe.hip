@@ -280,36 +280,52 @@ __global__ __launch_bounds__(64 * kKpWaves) void k_orient(const float* __restric
 }
 
 // Expand the per-keypoint orientation records of one image in input order
-// and cut at `limit`.
-__global__ __launch_bounds__(256) void k_orient_compact(const cdvs_keypoint* __restrict__ ori,
-                                                        const int32_t* __restrict__ ori_cnt,
-                                                        const int32_t* __restrict__ count_in, int kp_cap, int limit,
-                                                        cdvs_keypoint* __restrict__ out,
-                                                        int32_t* __restrict__ count_out) {
-    __shared__ int part[256];
-    const int img = blockIdx.x, tid = threadIdx.x;
+// and cut at `limit`.  One 1024-lane workgroup per image: each lane takes a
+// contiguous run of keypoints (one while the image has at most 1024), the
+// runs' record counts are prefix-summed by wave scans and one scan of the
+// wave totals, and each lane then copies its run's records.
+constexpr int kCompactThreads = 1024;
+
+__global__ __launch_bounds__(kCompactThreads) void k_orient_compact(const cdvs_keypoint* __restrict__ ori,
+                                                                    const int32_t* __restrict__ ori_cnt,
+                                                                    const int32_t* __restrict__ count_in, int kp_cap,
+                                                                    int limit, cdvs_keypoint* __restrict__ out,
+                                                                    int32_t* __restrict__ count_out) {
+    __shared__ int wsum[kCompactThreads / 64];
+    const int img = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int n = min(max(count_in[img], 0), kp_cap);
-    const int chunk = (n + 255) / 256;
+    const int chunk = (n + kCompactThreads - 1) / kCompactThreads;
     const int beg = min(tid * chunk, n), end = min(beg + chunk, n);
     const int32_t* cnt = ori_cnt + (int64_t)img * kp_cap;
     int sum = 0;
     for (int i = beg; i < end; ++i) sum += cnt[i];
-    part[tid] = sum;
-    __syncthreads();
-    for (int off = 1; off < 256; off <<= 1) {
-        const int v = tid >= off ? part[tid - off] : 0;
-        __syncthreads();
-        part[tid] += v;
-        __syncthreads();
+    // inclusive scan within the wave
+    int incl = sum;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const int v = __shfl_up(incl, off);
+        if (lane >= off) incl += v;
     }
-    int pos = part[tid] - sum;  // exclusive prefix
+    if (lane == 63) wsum[wave] = incl;
+    __syncthreads();
+    if (wave == 0) {
+        int w = lane < kCompactThreads / 64 ? wsum[lane] : 0;
+#pragma unroll
+        for (int off = 1; off < kCompactThreads / 64; off <<= 1) {
+            const int v = __shfl_up(w, off);
+            if (lane >= off) w += v;
+        }
+        if (lane < kCompactThreads / 64) wsum[lane] = w;   // inclusive over waves
+    }
+    __syncthreads();
+    int pos = incl - sum + (wave > 0 ? wsum[wave - 1] : 0);   // exclusive prefix
     for (int i = beg; i < end && pos < limit; ++i) {
         const int c = cnt[i];
         for (int j = 0; j < c && pos + j < limit; ++j)
             out[(int64_t)img * kp_cap + pos + j] = ori[((int64_t)img * kp_cap + i) * kMaxOri + j];
         pos += c;
     }
-    if (tid == 255) count_out[img] = min(part[255], limit);
+    if (tid == kCompactThreads - 1) count_out[img] = min(wsum[kCompactThreads / 64 - 1], limit);
 }
 
 __global__ __launch_bounds__(64 * kKpWaves) void k_describe(const float* __restrict__ pyr, const OctGeom* __restrict__ geom,
@@ -451,8 +467,8 @@ hipError_t launch_orient_compact(const cdvs_keypoint* ori, const int32_t* ori_cn
                                  hipStream_t stream) {
     if (n_images <= 0) return hipSuccess;
     const int limit = min(topk > 0 ? topk : kp_cap, kp_cap);
-    hipLaunchKernelGGL(k_orient_compact, dim3(n_images), dim3(256), 0, stream, ori, ori_cnt, count_in, kp_cap, limit,
-                       out, count_out);
+    hipLaunchKernelGGL(k_orient_compact, dim3(n_images), dim3(kCompactThreads), 0, stream, ori, ori_cnt, count_in, kp_cap,
+                       limit, out, count_out);
     return hipGetLastError();
 }
 
