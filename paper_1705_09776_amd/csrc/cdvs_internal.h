@@ -83,7 +83,9 @@ struct DetParams {
 struct OriParams {
     float radius, wsigma, peak;
     float sigma0;
-    float fix;  // fixed-point scale of the LDS histogram
+    float fix;      // fixed-point scale of the LDS histogram (a power of two)
+    float inv_fix;  // 1 / fix, exact
+    float lfix;     // log2(fix), an integer
     int32_t max_ori;
     int32_t kp_cap;
 };
@@ -91,7 +93,9 @@ struct OriParams {
 struct DescParams {
     float cell, radius, wsigma, clamp;
     float sigma0;
-    float fix;  // fixed-point scale of the LDS histogram
+    float fix;      // fixed-point scale of the LDS histogram (a power of two)
+    float inv_fix;  // 1 / fix, exact
+    float lfix;     // log2(fix), an integer
     int32_t kp_cap;
 };
 

@@ -21,10 +21,37 @@ __device__ __forceinline__ float wave_sum(float v) {
     return v;
 }
 
-__device__ __forceinline__ float wave_max(float v) {
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v = fmaxf(v, __shfl_xor(v, off));
-    return v;
+// Maximum over the wave, by row operations (DPP) within each 16-lane row,
+// a swizzle across row pairs and the two halves' first lanes.
+__device__ __forceinline__ float wave_max_dpp(float v) {
+    v = fmaxf(v, __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0xB1, 0xf, 0xf, false)));  // xor 1
+    v = fmaxf(v, __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x4E, 0xf, 0xf, false)));  // xor 2
+    v = fmaxf(v, __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x141, 0xf, 0xf, false))); // half mirror
+    v = fmaxf(v, __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x140, 0xf, 0xf, false))); // mirror
+    v = fmaxf(v, __int_as_float(__builtin_amdgcn_ds_swizzle(__float_as_int(v), 0x401F)));                    // xor 16
+    const float a = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 0));
+    const float b = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 32));
+    return fmaxf(a, b);
+}
+
+// q = n / d and r = n - q d for 0 <= n < 2^31, d >= 1: a single-precision
+// estimate from the hardware reciprocal, refined once from the remainder
+// (which leaves it at most one off) and corrected (products in unsigned
+// arithmetic, so n - q d cannot overflow).
+__device__ __forceinline__ void divmod_est(int n, int d, int& q, int& r) {
+    const float inv = __builtin_amdgcn_rcpf((float)d);
+    q = (int)((float)n * inv);
+    r = (int)((unsigned)n - (unsigned)q * (unsigned)d);
+    q += (int)((float)r * inv);
+    r = (int)((unsigned)n - (unsigned)q * (unsigned)d);
+    while (r < 0) {
+        --q;
+        r += d;
+    }
+    while (r >= d) {
+        ++q;
+        r -= d;
+    }
 }
 
 // A keypoint the histogram kernels can take: octave in range, finite
@@ -53,10 +80,15 @@ struct KpGeom {
     float cx, cy, s;     // octave pixels
 };
 
-__device__ __forceinline__ KpGeom keypoint_geometry(const float* pyr, const OctGeom* geom, int img,
-                                                    const cdvs_keypoint& k, float sigma0) {
+// og: this lane's entry of the keypoint's image's octave table (octave
+// lane % 16), loaded beside the keypoint record; the keypoint's octave is
+// the same in every lane, so its entry is read from that lane.
+__device__ __forceinline__ int og_field(int v, int o) { return __builtin_amdgcn_readlane(v, o); }
+
+__device__ __forceinline__ KpGeom keypoint_geometry(const float* pyr, const OctGeom& og, const cdvs_keypoint& k,
+                                                    float sigma0) {
     KpGeom g;
-    const OctGeom og = geom[img * kMaxOctaves + k.octave];
+    const int o = __builtin_amdgcn_readfirstlane(k.octave);
     const float sc = 1.0f / (float)(1 << k.octave);
     g.cx = k.x * sc;
     g.cy = k.y * sc;
@@ -66,13 +98,15 @@ __device__ __forceinline__ KpGeom keypoint_geometry(const float* pyr, const OctG
     // one keypoint per wave: the plane pointer and pitch are the same in
     // every lane, and kept in scalar registers so that pixel addresses are
     // a 32-bit offset from them
-    const uint64_t po = (uint64_t)(og.plane0 + (int64_t)ks * og.plane_stride);
+    const int64_t plane0 = (int64_t)(((uint64_t)(uint32_t)og_field((int)(og.plane0 >> 32), o) << 32) |
+                                     (uint32_t)og_field((int)og.plane0, o));
+    const uint64_t po = (uint64_t)(plane0 + (int64_t)__builtin_amdgcn_readfirstlane(ks) * og_field(og.plane_stride, o));
     const uint32_t plo = __builtin_amdgcn_readfirstlane((uint32_t)po);
     const uint32_t phi = __builtin_amdgcn_readfirstlane((uint32_t)(po >> 32));
     g.plane = pyr + (int64_t)(((uint64_t)phi << 32) | plo);
-    g.w = og.w;
-    g.h = og.h;
-    g.pitch = __builtin_amdgcn_readfirstlane(og.pitch);
+    g.w = og_field(og.w, o);
+    g.h = og_field(og.h, o);
+    g.pitch = og_field(og.pitch, o);
     return g;
 }
 
@@ -177,10 +211,11 @@ constexpr int kDescStride = 16 * kDescCellBins + 1;
 struct BoxWalk {
     int u, v, du, dv, u1;
     __device__ __forceinline__ BoxWalk(int lane, int u0, int v0, int bw) {
-        u = u0 + lane % bw;
-        v = v0 + lane / bw;
-        du = 64 % bw;
-        dv = 64 / bw;
+        int q, r;
+        divmod_est(lane, bw, q, r);
+        u = u0 + r;
+        v = v0 + q;
+        divmod_est(64, bw, dv, du);
         u1 = u0 + bw - 1;
     }
     __device__ __forceinline__ void next(int bw) {
@@ -199,10 +234,16 @@ __global__ __launch_bounds__(64 * kKpWaves) void k_orient(const float* __restric
                                                 cdvs_keypoint* __restrict__ ori, int32_t* __restrict__ ori_cnt) {
     __shared__ uint32_t hist[kKpWaves][kCopies * kOriStride];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int64_t slot = (int64_t)xcd_remap(blockIdx.x, gridDim.x) * kKpWaves + wave;
-    const int img = (int)(slot / op.kp_cap), i = (int)(slot % op.kp_cap);
-    if (img >= n_images || i >= count[img]) return;   // uniform over the wave
+    const int slot = xcd_remap(blockIdx.x, gridDim.x) * kKpWaves + wave;
+    int img, i;
+    divmod_est(slot, op.kp_cap, img, i);
+    if (img >= n_images) return;   // uniform over the wave
+    // the count, the record and the image's octave table (one octave per
+    // lane) load together: one memory round trip before the walk
+    const int cnt = count[img];
     const cdvs_keypoint k = kp[(int64_t)img * op.kp_cap + i];
+    const OctGeom og = geom[img * kMaxOctaves + (lane & (kMaxOctaves - 1))];
+    if (i >= cnt) return;   // uniform over the wave
     if (!keypoint_ok(k, op.sigma0)) {
         if (lane == 0) ori_cnt[(int64_t)img * op.kp_cap + i] = 0;
         return;
@@ -212,13 +253,13 @@ __global__ __launch_bounds__(64 * kKpWaves) void k_orient(const float* __restric
 
     {
         uint32_t* hc = &hist[wave][(lane & (kCopies - 1)) * kOriStride];
-        const KpGeom g = keypoint_geometry(pyr, geom, img, k, op.sigma0);
+        const KpGeom g = keypoint_geometry(pyr, og, k, op.sigma0);
         const float R = op.radius * g.s;
         const float R2 = R * R;
         const float ws = op.wsigma * g.s;
         // Gaussian weight in fixed-point units: fix exp(-d^2 / (2 ws^2)) =
         // 2^(d^2 nid + log2 fix), fix being a power of two
-        const float nid = -1.4426950408889634f / (2.f * ws * ws), lfix = log2f(op.fix);
+        const float nid = -1.4426950408889634f / (2.f * ws * ws), lfix = op.lfix;
         const int u0 = max((int)ceilf(g.cx - R), 1), u1 = min((int)floorf(g.cx + R), g.w - 2);
         const int v0 = max((int)ceilf(g.cy - R), 1), v1 = min((int)floorf(g.cy + R), g.h - 2);
         const int bw = u1 - u0 + 1, bh = v1 - v0 + 1;
@@ -249,14 +290,14 @@ __global__ __launch_bounds__(64 * kKpWaves) void k_orient(const float* __restric
 #pragma unroll
         for (int c = 0; c < kCopies; ++c)
             t += hist[wave][c * kOriStride + b] + (b < 2 ? hist[wave][c * kOriStride + kOriBins + b] : 0u);
-        return (float)t / op.fix;
+        return (float)t * op.inv_fix;
     };
     // every lane reads its bin and both neighbours from the summed copies
     const float hsum = lane < kOriBins ? bin(lane) : 0.f;
     const float hb = hsum;
     const float hl = __shfl(hsum, lane == 0 ? kOriBins - 1 : lane - 1);
     const float hr = __shfl(hsum, lane == kOriBins - 1 ? 0 : lane + 1);
-    const float mx = wave_max(hb);
+    const float mx = wave_max_dpp(hb);
     const bool pk = lane < kOriBins && hb > hl && hb > hr && hb > op.peak * mx;
     const uint64_t pm = __ballot(pk);
     int rank = 0;
@@ -334,10 +375,16 @@ __global__ __launch_bounds__(64 * kKpWaves) void k_describe(const float* __restr
                                                   float* __restrict__ desc) {
     __shared__ uint32_t hist[kKpWaves][kCopies * kDescStride];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int64_t slot = (int64_t)xcd_remap(blockIdx.x, gridDim.x) * kKpWaves + wave;
-    const int img = (int)(slot / dp.kp_cap), i = (int)(slot % dp.kp_cap);
-    if (img >= n_images || i >= count[img]) return;   // uniform over the wave
+    const int slot = xcd_remap(blockIdx.x, gridDim.x) * kKpWaves + wave;
+    int img, i;
+    divmod_est(slot, dp.kp_cap, img, i);
+    if (img >= n_images) return;   // uniform over the wave
+    // the count, the record and the image's octave table (one octave per
+    // lane) load together: one memory round trip before the walk
+    const int cnt = count[img];
     const cdvs_keypoint k = kp[(int64_t)img * dp.kp_cap + i];
+    const OctGeom og = geom[img * kMaxOctaves + (lane & (kMaxOctaves - 1))];
+    if (i >= cnt) return;   // uniform over the wave
     if (!keypoint_ok(k, dp.sigma0)) {
         float* out = desc + (((int64_t)img * dp.kp_cap + i) * kDescDim);
         out[lane] = 0.f;
@@ -349,7 +396,7 @@ __global__ __launch_bounds__(64 * kKpWaves) void k_describe(const float* __restr
 
     {
         uint32_t* hc = &hist[wave][(lane & (kCopies - 1)) * kDescStride];
-        const KpGeom g = keypoint_geometry(pyr, geom, img, k, dp.sigma0);
+        const KpGeom g = keypoint_geometry(pyr, og, k, dp.sigma0);
         const float th = k.theta;
         // hardware sine and cosine: theta is in [0, 2 pi), where they are
         // accurate to ~1e-6, far below what the cell weights can resolve
@@ -365,7 +412,7 @@ __global__ __launch_bounds__(64 * kKpWaves) void k_describe(const float* __restr
         const float ws = dp.wsigma * g.s;
         // Gaussian weight in fixed-point units: fix exp(-d^2 / (2 ws^2)) =
         // 2^(d^2 nid + log2 fix), fix being a power of two
-        const float nid = -1.4426950408889634f / (2.f * ws * ws), lfix = log2f(dp.fix);
+        const float nid = -1.4426950408889634f / (2.f * ws * ws), lfix = dp.lfix;
         const int u0 = max((int)ceilf(g.cx - R), 1), u1 = min((int)floorf(g.cx + R), g.w - 2);
         const int v0 = max((int)ceilf(g.cy - R), 1), v1 = min((int)floorf(g.cy + R), g.h - 2);
         const int bw = u1 - u0 + 1, bh = v1 - v0 + 1;
@@ -431,7 +478,7 @@ __global__ __launch_bounds__(64 * kKpWaves) void k_describe(const float* __restr
         i0 += h[e0] + (wrap ? h[e0 + 8] : 0u);
         i1 += h[e1] + (wrap ? h[e1 + 8] : 0u);
     }
-    const float h0 = (float)i0 / dp.fix, h1 = (float)i1 / dp.fix;
+    const float h0 = (float)i0 * dp.inv_fix, h1 = (float)i1 * dp.inv_fix;
     float* out = desc + (((int64_t)img * dp.kp_cap + i) * kDescDim);
     const float n2 = wave_sum(h0 * h0 + h1 * h1);
     if (!(n2 > 0.f)) {
