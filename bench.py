@@ -84,7 +84,7 @@ SQ = os.path.join(ROOT, "profiles", "sq_counters_plain_batch256_640x480.md")
 SIMDS, CLOCK_HZ = 1024, 2.4e9      # 256 CUs x 4 SIMDs; a wave64 VALU instruction takes 4 cycles of a SIMD
 # kernel names in the profile summaries (the scale kernel's carries its tile variant)
 _PROFILE_NAME = {"detect": "k_detect_strip<false,false>", "describe": "k_describe", "scales": "k_blur<1,4,12,false,{v}>",
-                 "orient": "k_orient", "finalize": "k_finalize", "preblur": "k_blur<0,1,7,true,0>",
+                 "orient": "k_orient", "finalize": "k_finalize", "preblur": "k_blur<0,1,7,true,4>",
                  "orient_compact": "k_orient_compact"}
 
 

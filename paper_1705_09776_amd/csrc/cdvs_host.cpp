@@ -30,7 +30,7 @@ struct cdvs_ctx {
     std::vector<OctJob> jobs;                  // grouped by octave
     int max_oct = 0;
     int job_start[kMaxOctaves + 1] = {};
-    int blur_tiles[kBlurVariants][kMaxOctaves] = {};
+    int blur_tiles[kBlurTilings][kMaxOctaves] = {};
     int blur_variant = 1;    // scale-plane tile variant (cdvs_autotune; 128 x 16 measured best untuned)
     int detect_variant = 0;  // detection launch form (cdvs_autotune)
     int64_t pyr_floats = 0;
@@ -60,7 +60,7 @@ struct cdvs_ctx {
     // device
     OctJob* d_jobs = nullptr;
     std::vector<int32_t> blur_owner;           // [variant][octave][tile] -> job (relative to job_start[octave])
-    int blur_owner_start[kBlurVariants][kMaxOctaves] = {};
+    int blur_owner_start[kBlurTilings][kMaxOctaves] = {};
     int32_t* d_blur_owner = nullptr;
     std::vector<int32_t> cnn_owner;            // fused CNN tile -> image
     int32_t* d_cnn_owner = nullptr;
@@ -341,7 +341,7 @@ static cdvs_status build_layout(cdvs_ctx* c) {
             j.src_pitch = d.pitch;
             j.image = i;
             j.octave = o;
-            for (int v = 0; v < kBlurVariants; ++v) j.tiles_x_blur[v] = (ws[o] + blur_tw(v) - 1) / blur_tw(v);
+            for (int v = 0; v < kBlurTilings; ++v) j.tiles_x_blur[v] = (ws[o] + blur_tw(v) - 1) / blur_tw(v);
             per_oct[o].push_back(j);
         }
     }
@@ -349,18 +349,18 @@ static cdvs_status build_layout(cdvs_ctx* c) {
     c->jobs.clear();
     for (int o = 0; o < kMaxOctaves; ++o) {
         c->job_start[o] = (int)c->jobs.size();
-        int tb[kBlurVariants] = {};
+        int tb[kBlurTilings] = {};
         for (OctJob& j : per_oct[o]) {
-            for (int v = 0; v < kBlurVariants; ++v) {
+            for (int v = 0; v < kBlurTilings; ++v) {
                 j.tile0_blur[v] = tb[v];
                 tb[v] += j.tiles_x_blur[v] * ((j.h + blur_th(v) - 1) / blur_th(v));
             }
             c->jobs.push_back(j);
         }
-        for (int v = 0; v < kBlurVariants; ++v) c->blur_tiles[v][o] = tb[v];
+        for (int v = 0; v < kBlurTilings; ++v) c->blur_tiles[v][o] = tb[v];
     }
     c->blur_owner.clear();
-    for (int v = 0; v < kBlurVariants; ++v)
+    for (int v = 0; v < kBlurTilings; ++v)
         for (int o = 0; o < kMaxOctaves; ++o) {
             c->blur_owner_start[v][o] = (int)c->blur_owner.size();
             for (size_t j = 0; j < per_oct[o].size(); ++j) {

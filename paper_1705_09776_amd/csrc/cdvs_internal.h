@@ -45,7 +45,7 @@ struct OctJob {
     int32_t src_pitch;  // bytes
     int32_t image;
     int32_t octave;
-    int32_t tiles_x_blur[4], tile0_blur[4];  // tiling of the blur kernels, per tile variant
+    int32_t tiles_x_blur[5], tile0_blur[5];  // tiling of the blur kernels, per tile shape (kBlurTilings)
 };
 
 // One detection strip: everything the detection kernel needs to load and
@@ -142,14 +142,17 @@ struct GateParams {
     float fmax;              // fraction of active cells above which detection is dense
 };
 
-// Kernel tile shapes.
-// Scale-plane kernel tile variants (width x height, autotuned); the
-// pre-blur always uses kPreblurVariant (64 x 32, measured faster than 64 x 16).
+// Kernel tile shapes (width x height).  Shapes 0..3 are the scale-plane
+// kernel's variants (autotuned); shape 4 is the pre-blur's own, 128 x 32
+// (measured against 64 x 32, 80 x 32, 160 x 16 and 160 x 32: its column
+// windows and row groups fill the workgroup's lanes best).
 constexpr int kBlurVariants = 4;
+constexpr int kPreblurVariant = 4;
+constexpr int kBlurTilings = 5;
 constexpr int kBlurV = 8;
-constexpr int kPreblurVariant = 0;
-__host__ __device__ constexpr int blur_tw(int v) { return v == 1 ? 128 : v == 2 ? 32 : 64; }
-__host__ __device__ constexpr int blur_th(int v) { return v == 0 ? 32 : v == 1 ? 16 : v == 2 ? 32 : 16; }
+__host__ __device__ constexpr int blur_tw(int v) { return v == 1 || v == 4 ? 128 : v == 2 ? 32 : 64; }
+__host__ __device__ constexpr int blur_th(int v) { return v == 1 || v == 3 ? 16 : 32; }
+static_assert(sizeof(OctJob::tiles_x_blur) / sizeof(int32_t) == kBlurTilings, "one tiling per blur tile shape");
 
 // Launchers (each enqueues on `stream`, returns the launch error).
 hipError_t launch_preblur(const uint8_t* images, float* pyr, const OctJob* jobs, const int32_t* owner, int ntiles,
