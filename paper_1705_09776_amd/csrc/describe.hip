@@ -15,10 +15,17 @@ namespace {
 
 constexpr float kTwoPi = 6.283185307179586f;
 
+// Sum over the wave, by the same row operations, swizzle and first-lane
+// reads as the maximum below; every lane gets the same value.
 __device__ __forceinline__ float wave_sum(float v) {
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
-    return v;
+    v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0xB1, 0xf, 0xf, false));    // xor 1
+    v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x4E, 0xf, 0xf, false));    // xor 2
+    v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x141, 0xf, 0xf, false));   // half mirror
+    v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x140, 0xf, 0xf, false));   // mirror
+    v += __int_as_float(__builtin_amdgcn_ds_swizzle(__float_as_int(v), 0x401F));                     // xor 16
+    const float a = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 0));
+    const float b = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 32));
+    return a + b;
 }
 
 // Maximum over the wave, by row operations (DPP) within each 16-lane row,
@@ -61,7 +68,7 @@ __device__ __forceinline__ void divmod_est(int n, int d, int& q, int& r) {
 // wrap.  Others get no orientation and an all-zero descriptor.
 __device__ __forceinline__ bool keypoint_ok(const cdvs_keypoint& k, float sigma0) {
     if (k.octave < 0 || k.octave >= kMaxOctaves) return false;
-    const float s = k.sigma * (1.0f / (float)(1 << k.octave));
+    const float s = k.sigma * __builtin_amdgcn_ldexpf(1.0f, -k.octave);   // 2^-octave, exact
     return isfinite(k.x) && isfinite(k.y) && s > 0.f && s <= 2.f * sigma0;
 }
 
@@ -80,6 +87,15 @@ struct KpGeom {
     float cx, cy, s;     // octave pixels
 };
 
+// An empty statement that takes the keypoint count, record and octave-table
+// entry as inputs: their loads are then all issued before it and waited for
+// once, instead of each being sunk behind the branch that first uses it
+// (three memory round trips in a row before the walk).
+__device__ __forceinline__ void settle(int cnt, const cdvs_keypoint& k, const OctGeom& og) {
+    asm volatile("" ::"v"(cnt), "v"(k.x), "v"(k.y), "v"(k.sigma), "v"(k.theta), "v"(k.octave), "v"(og.plane0),
+                 "v"(og.w), "v"(og.h), "v"(og.pitch), "v"(og.plane_stride));
+}
+
 // og: this lane's entry of the keypoint's image's octave table (octave
 // lane % 16), loaded beside the keypoint record; the keypoint's octave is
 // the same in every lane, so its entry is read from that lane.
@@ -89,7 +105,7 @@ __device__ __forceinline__ KpGeom keypoint_geometry(const float* pyr, const OctG
                                                     float sigma0) {
     KpGeom g;
     const int o = __builtin_amdgcn_readfirstlane(k.octave);
-    const float sc = 1.0f / (float)(1 << k.octave);
+    const float sc = __builtin_amdgcn_ldexpf(1.0f, -k.octave);   // 2^-octave, exact
     g.cx = k.x * sc;
     g.cy = k.y * sc;
     g.s = k.sigma * sc;
@@ -205,6 +221,19 @@ constexpr int kOriStride = kOriBins + 2;
 constexpr int kDescCellBins = 9;
 constexpr int kDescStride = 16 * kDescCellBins + 1;
 
+// Zeroes the N words (a multiple of 4) of a 16-byte-aligned LDS histogram
+// with the wave's 64 lanes, 16 bytes per lane and store, fully unrolled.
+template <int N>
+__device__ __forceinline__ void wave_zero(uint32_t* h, int lane) {
+    static_assert(N % 4 == 0, "whole 16-byte groups");
+    uint4* q = reinterpret_cast<uint4*>(h);
+#pragma unroll
+    for (int r = 0; r < (N / 4 + 63) / 64; ++r) {
+        const int j = lane + 64 * r;
+        if (N / 4 % 64 == 0 || j < N / 4) q[j] = make_uint4(0u, 0u, 0u, 0u);
+    }
+}
+
 // Walks the bounding box [u0, u0+bw) x [v0, ...) in row-major order, 64
 // pixels per step, without integer division in the loop; a lane is past the
 // box's last row exactly when its pixel index is past the box.
@@ -232,7 +261,7 @@ __global__ __launch_bounds__(64 * kKpWaves) void k_orient(const float* __restric
                                                 const cdvs_keypoint* __restrict__ kp,
                                                 const int32_t* __restrict__ count, int n_images, OriParams op,
                                                 cdvs_keypoint* __restrict__ ori, int32_t* __restrict__ ori_cnt) {
-    __shared__ uint32_t hist[kKpWaves][kCopies * kOriStride];
+    __shared__ __align__(16) uint32_t hist[kKpWaves][kCopies * kOriStride];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int slot = xcd_remap(blockIdx.x, gridDim.x) * kKpWaves + wave;
     int img, i;
@@ -243,12 +272,13 @@ __global__ __launch_bounds__(64 * kKpWaves) void k_orient(const float* __restric
     const int cnt = count[img];
     const cdvs_keypoint k = kp[(int64_t)img * op.kp_cap + i];
     const OctGeom og = geom[img * kMaxOctaves + (lane & (kMaxOctaves - 1))];
+    settle(cnt, k, og);
     if (i >= cnt) return;   // uniform over the wave
     if (!keypoint_ok(k, op.sigma0)) {
         if (lane == 0) ori_cnt[(int64_t)img * op.kp_cap + i] = 0;
         return;
     }
-    for (int j = lane; j < kCopies * kOriStride; j += 64) hist[wave][j] = 0u;
+    wave_zero<kCopies * kOriStride>(hist[wave], lane);
     wave_sync();
 
     {
@@ -259,7 +289,9 @@ __global__ __launch_bounds__(64 * kKpWaves) void k_orient(const float* __restric
         const float ws = op.wsigma * g.s;
         // Gaussian weight in fixed-point units: fix exp(-d^2 / (2 ws^2)) =
         // 2^(d^2 nid + log2 fix), fix being a power of two
-        const float nid = -1.4426950408889634f / (2.f * ws * ws), lfix = op.lfix;
+        // (the hardware reciprocal, 1 ulp: these per-keypoint constants need
+        // no correctly rounded division)
+        const float nid = -1.4426950408889634f * __builtin_amdgcn_rcpf(2.f * ws * ws), lfix = op.lfix;
         const int u0 = max((int)ceilf(g.cx - R), 1), u1 = min((int)floorf(g.cx + R), g.w - 2);
         const int v0 = max((int)ceilf(g.cy - R), 1), v1 = min((int)floorf(g.cy + R), g.h - 2);
         const int bw = u1 - u0 + 1, bh = v1 - v0 + 1;
@@ -303,12 +335,14 @@ __global__ __launch_bounds__(64 * kKpWaves) void k_orient(const float* __restric
     int rank = 0;
     for (uint64_t m = pm; m; m &= m - 1) {
         const int j = __ffsll((unsigned long long)m) - 1;
-        const float hj = __shfl(hb, j);
+        const float hj = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(hb), j));   // j is uniform
         if (hj > hb || (hj == hb && j < lane)) ++rank;
     }
     const int64_t base = ((int64_t)img * op.kp_cap + i);
     if (pk && rank < op.max_ori) {
-        const float off = 0.5f * (hl - hr) / (hl - 2.f * hb + hr);
+        // a peak's parabola has hl - 2 hb + hr < 0; the hardware reciprocal
+        // (1 ulp) moves the offset by far less than the angle tolerance
+        const float off = 0.5f * (hl - hr) * __builtin_amdgcn_rcpf(hl - 2.f * hb + hr);
         float t = ((float)lane + off) * kTwoPi / (float)kOriBins;
         if (t < 0.f) t += kTwoPi;
         if (t >= kTwoPi) t -= kTwoPi;
@@ -373,7 +407,7 @@ __global__ __launch_bounds__(64 * kKpWaves) void k_describe(const float* __restr
                                                   const cdvs_keypoint* __restrict__ kp,
                                                   const int32_t* __restrict__ count, int n_images, DescParams dp,
                                                   float* __restrict__ desc) {
-    __shared__ uint32_t hist[kKpWaves][kCopies * kDescStride];
+    __shared__ __align__(16) uint32_t hist[kKpWaves][kCopies * kDescStride];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int slot = xcd_remap(blockIdx.x, gridDim.x) * kKpWaves + wave;
     int img, i;
@@ -384,6 +418,7 @@ __global__ __launch_bounds__(64 * kKpWaves) void k_describe(const float* __restr
     const int cnt = count[img];
     const cdvs_keypoint k = kp[(int64_t)img * dp.kp_cap + i];
     const OctGeom og = geom[img * kMaxOctaves + (lane & (kMaxOctaves - 1))];
+    settle(cnt, k, og);
     if (i >= cnt) return;   // uniform over the wave
     if (!keypoint_ok(k, dp.sigma0)) {
         float* out = desc + (((int64_t)img * dp.kp_cap + i) * kDescDim);
@@ -391,7 +426,7 @@ __global__ __launch_bounds__(64 * kKpWaves) void k_describe(const float* __restr
         out[lane + 64] = 0.f;
         return;
     }
-    for (int j = lane; j < kCopies * kDescStride; j += 64) hist[wave][j] = 0u;
+    wave_zero<kCopies * kDescStride>(hist[wave], lane);
     wave_sync();
 
     {
@@ -403,7 +438,9 @@ __global__ __launch_bounds__(64 * kKpWaves) void k_describe(const float* __restr
         const float ct = __cosf(th), st = __sinf(th);
         const float R = dp.radius * g.s;
         const float R2 = R * R;
-        const float icw = 1.f / (dp.cell * g.s);    // cell units
+        // cell units (the per-keypoint constants below use the hardware
+        // reciprocal, 1 ulp, instead of correctly rounded divisions)
+        const float icw = __builtin_amdgcn_rcpf(dp.cell * g.s);
         // rotation by -theta and the scale to cell units in one 2 x 2 matrix,
         // the cell-grid centre (1.5, 1.5) added by the same multiply-adds
         const float cti = ct * icw, sti = st * icw;
@@ -412,7 +449,7 @@ __global__ __launch_bounds__(64 * kKpWaves) void k_describe(const float* __restr
         const float ws = dp.wsigma * g.s;
         // Gaussian weight in fixed-point units: fix exp(-d^2 / (2 ws^2)) =
         // 2^(d^2 nid + log2 fix), fix being a power of two
-        const float nid = -1.4426950408889634f / (2.f * ws * ws), lfix = dp.lfix;
+        const float nid = -1.4426950408889634f * __builtin_amdgcn_rcpf(2.f * ws * ws), lfix = dp.lfix;
         const int u0 = max((int)ceilf(g.cx - R), 1), u1 = min((int)floorf(g.cx + R), g.w - 2);
         const int v0 = max((int)ceilf(g.cy - R), 1), v1 = min((int)floorf(g.cy + R), g.h - 2);
         const int bw = u1 - u0 + 1, bh = v1 - v0 + 1;
@@ -486,9 +523,10 @@ __global__ __launch_bounds__(64 * kKpWaves) void k_describe(const float* __restr
         out[lane + 64] = 0.f;
         return;
     }
-    const float inv = 1.f / sqrtf(n2);
+    // hardware reciprocal square roots (1 ulp; n2 > 0 and far from denormal)
+    const float inv = __builtin_amdgcn_rsqf(n2);
     const float t0 = fminf(h0 * inv, dp.clamp), t1 = fminf(h1 * inv, dp.clamp);
-    const float inv2 = 1.f / sqrtf(wave_sum(t0 * t0 + t1 * t1));
+    const float inv2 = __builtin_amdgcn_rsqf(wave_sum(t0 * t0 + t1 * t1));
     out[lane] = t0 * inv2;
     out[lane + 64] = t1 * inv2;
 }
