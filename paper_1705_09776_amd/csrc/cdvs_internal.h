@@ -111,6 +111,23 @@ __device__ __forceinline__ int xcd_remap(int b, int n) {
     return x * per + min(x, rem) + i;
 }
 
+// The value held by lane ^ S of the wave, for a compile-time S < 64: row
+// operations (DPP) for S = 1, 2, the swizzle's bit-mask mode (within 32
+// lanes) for S = 4, 8, 16, and a lane permute for 32.  Every lane must be
+// active.
+template <int S>
+__device__ __forceinline__ uint32_t lane_xor(uint32_t v) {
+    static_assert(S > 0 && S < 64 && (S & (S - 1)) == 0, "a power of two below 64");
+    if constexpr (S == 1) return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0xB1, 0xf, 0xf, false);
+    else if constexpr (S == 2) return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x4E, 0xf, 0xf, false);
+    else if constexpr (S <= 16) return (uint32_t)__builtin_amdgcn_ds_swizzle((int)v, (S << 10) | 0x1F);
+    else return (uint32_t)__shfl_xor((int)v, S);
+}
+template <int S>
+__device__ __forceinline__ unsigned long long lane_xor64(unsigned long long v) {
+    return ((unsigned long long)lane_xor<S>((uint32_t)(v >> 32)) << 32) | lane_xor<S>((uint32_t)v);
+}
+
 // Bits of the device status word.
 constexpr int kFlagCandOverflow = 1;
 constexpr int kFlagSelectInexact = 2;   // a reduced image's top-k reached its selection threshold

@@ -498,17 +498,33 @@ __global__ __launch_bounds__(FIN_THREADS) void k_select(const cdvs_keypoint* __r
 }
 
 // One compare-exchange of a bitonic stage of block size `size` at distance
-// `stride` < 64 for the (key, payload) of element i held by this lane, whose
-// partner (i ^ stride) is in lane ^ stride: the lower index keeps the
-// smaller key in an ascending block, the larger in a descending one (equal
-// keys stay where they are).
-__device__ __forceinline__ void bitonic_lane_step(unsigned long long& k, int& p, int i, int size, int stride) {
-    const unsigned long long o = __shfl_xor(k, stride);
-    const int op = __shfl_xor(p, stride);
-    const bool asc = (i & size) == 0, lower = (i & stride) == 0;
-    const bool take = (lower == asc) ? (o < k) : (o > k);
+// S < 64 for the (key, payload) of element i held by this lane, whose
+// partner (i ^ S) is in lane ^ S: the lower index keeps the smaller key in
+// an ascending block, the larger in a descending one (equal keys stay where
+// they are).  Both comparisons are made and one is selected, so no lane
+// branches.
+template <int S>
+__device__ __forceinline__ void bitonic_lane_step(unsigned long long& k, int& p, int i, int size) {
+    const unsigned long long o = lane_xor64<S>(k);
+    const int op = (int)lane_xor<S>((uint32_t)p);
+    const bool want_min = ((i & size) == 0) == ((i & S) == 0);
+    const bool lt = o < k, gt = k < o;
+    const bool take = (want_min & lt) | (!want_min & gt);
     k = take ? o : k;
     p = take ? op : p;
+}
+
+// The distances 32, 16, .., 1 (those below `size`) of one bitonic stage
+// for both of the lane's elements.
+__device__ __forceinline__ void bitonic_lane_steps(unsigned long long& k0, int& p0, int i0, unsigned long long& k1,
+                                                   int& p1, int i1, int size) {
+#define CDVS_STEP(S)                                   \
+    if (size > S) {                                    \
+        bitonic_lane_step<S>(k0, p0, i0, size);        \
+        bitonic_lane_step<S>(k1, p1, i1, size);        \
+    }
+    CDVS_STEP(32) CDVS_STEP(16) CDVS_STEP(8) CDVS_STEP(4) CDVS_STEP(2) CDVS_STEP(1)
+#undef CDVS_STEP
 }
 
 // The steps at distances below 128 of bitonic block sizes first..last on
@@ -533,10 +549,7 @@ __device__ __forceinline__ void bitonic_chunk_steps(unsigned long long* key, uns
                     p1 = tp;
                 }
             }
-            for (int stride = (size >> 1) < 32 ? (size >> 1) : 32; stride > 0; stride >>= 1) {
-                bitonic_lane_step(k0, p0, i0, size, stride);
-                bitonic_lane_step(k1, p1, i1, size, stride);
-            }
+            bitonic_lane_steps(k0, p0, i0, k1, p1, i1, size);
         }
         key[i0] = k0;
         key[i1] = k1;

@@ -36,13 +36,15 @@ __device__ __forceinline__ int bin_of(const float* edges, float v) {
 }
 
 // One compare-exchange of a bitonic stage of block size `size` at distance
-// `stride` < 64, for the key k of element i held by this lane, whose
-// partner (i ^ stride) is in lane ^ stride: the lower index keeps the
-// smaller key in an ascending block, the larger in a descending one.
-__device__ __forceinline__ unsigned long long bitonic_lane_step(unsigned long long k, int i, int size, int stride) {
-    const unsigned long long o = __shfl_xor(k, stride);
-    const bool asc = (i & size) == 0, lower = (i & stride) == 0;
-    return (lower == asc) ? (o < k ? o : k) : (o > k ? o : k);
+// S < 64, for the key k of element i held by this lane, whose partner
+// (i ^ S) is in lane ^ S: the lower index keeps the smaller key in an
+// ascending block, the larger in a descending one (by selects, no branch).
+template <int S>
+__device__ __forceinline__ unsigned long long bitonic_lane_step(unsigned long long k, int i, int size) {
+    const unsigned long long o = lane_xor64<S>(k);
+    const bool want_min = ((i & size) == 0) == ((i & S) == 0);
+    const unsigned long long mn = o < k ? o : k, mx = o < k ? k : o;
+    return want_min ? mn : mx;
 }
 
 // The steps at distances below 128 of bitonic block sizes first..last, on
@@ -60,10 +62,13 @@ __device__ __forceinline__ void bitonic_chunk_steps(unsigned long long* key, int
                 k0 = asc ? lo : hi;
                 k1 = asc ? hi : lo;
             }
-            for (int stride = (size >> 1) < 32 ? (size >> 1) : 32; stride > 0; stride >>= 1) {
-                k0 = bitonic_lane_step(k0, i0, size, stride);
-                k1 = bitonic_lane_step(k1, i1, size, stride);
-            }
+#define CDVS_STEP(S)                                 \
+    if (size > S) {                                  \
+        k0 = bitonic_lane_step<S>(k0, i0, size);     \
+        k1 = bitonic_lane_step<S>(k1, i1, size);     \
+    }
+            CDVS_STEP(32) CDVS_STEP(16) CDVS_STEP(8) CDVS_STEP(4) CDVS_STEP(2) CDVS_STEP(1)
+#undef CDVS_STEP
         }
         key[i0] = k0;
         key[i1] = k1;
