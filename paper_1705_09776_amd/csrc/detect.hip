@@ -85,7 +85,9 @@ struct Cand {
 // Strict extremum of the centre value p = v[4] against the eight
 // neighbours' cubics v[] evaluated at the centre's scale (Algorithm 1 stage A).
 // (All eight below p for a maximum, above it for a minimum: compared through
-// their max and min, without branches; the values are finite.)
+// their max and min, without branches; mn > p is tested as -mn < -p = |p|,
+// so one float select and one comparison decide both cases exactly; the
+// values are finite.)
 __device__ __forceinline__ bool strict_extremum(const float (&v)[9], float p) {
     float mx = v[0], mn = v[0];
 #pragma unroll
@@ -94,7 +96,7 @@ __device__ __forceinline__ bool strict_extremum(const float (&v)[9], float p) {
             mx = fmaxf(mx, v[i]);
             mn = fminf(mn, v[i]);
         }
-    return p > 0.f ? (mx < p) : (mn > p);
+    return (p > 0.f ? mx : -mn) < fabsf(p);
 }
 
 // One quadratic refinement step on the 3x3 values v[] (row-major, centre
@@ -184,10 +186,10 @@ constexpr int kQFlush = kQCap - 60;
 constexpr int kQFields = 12;           // the eight neighbour values, s, p, pss, (x | y << 16)
 
 __device__ __forceinline__ float lane_from_left(float v) {   // lane l gets lane l-1's value (lane 0: 0)
-    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x138, 0xf, 0xf, false));
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x138, 0xf, 0xf, true));
 }
 __device__ __forceinline__ float lane_from_right(float v) {  // lane l gets lane l+1's value (lane 63: 0)
-    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x130, 0xf, 0xf, false));
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x130, 0xf, 0xf, true));
 }
 
 struct StripRow {
@@ -295,7 +297,7 @@ __device__ __forceinline__ void strip_centres(const float4& aU, const float4& aM
     v[1] = horner(aU, s);
     v[4] = p;
     v[7] = horner(aD, s);
-    const bool keep = pass && strict_extremum(v, p);
+    const bool keep = pass & strict_extremum(v, p);   // both evaluated: no branch
     const uint64_t m = __ballot(keep);
     if (!m) return;
     const int lane = threadIdx.x & 63;
