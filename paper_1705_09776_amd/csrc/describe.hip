@@ -132,12 +132,14 @@ __device__ __forceinline__ KpGeom keypoint_geometry(const float* pyr, const OctG
 // the arctangent reduce the argument to t = min(|x|, |y|) / max(|x|, |y|)
 // in [0, 1] (its rounding, under 2 ulp, moves the angle by less than
 // 1e-7 rad), where
-// atan(t) is an odd polynomial t P(t^2) of degree 15 whose coefficients are
+// atan(t) is an odd polynomial t P(t^2) of degree 11 whose coefficients are
 // a minimax fit (Lawson's reweighted least squares on Chebyshev nodes of
 // [0, 1], written by fit_atan_poly.py beside this file); its error is
-// 6.7e-8 rad, below 2e-7 rad in fp32, and the reflections add at
-// most about one fp32 ulp of 2 pi (4.8e-7), well inside what the histograms
-// can resolve.  (0, 0) gives 0.
+// 1.7e-6 rad (2e-6 of a descriptor bin, 1e-5 of an orientation bin, whose
+// linear split makes every pixel's contribution continuous in the angle),
+// and the reflections add at most about one fp32 ulp of 2 pi (4.8e-7).
+// (Degree 15 reached 6.7e-8 rad for two more multiply-adds per pixel.)
+// (0, 0) gives 0.
 __device__ __forceinline__ float angle_2pi(float y, float x) {
     const float ax = fabsf(x), ay = fabsf(y);
     // mx is kept at least the smallest normal float, so (0, 0) gives
@@ -147,14 +149,12 @@ __device__ __forceinline__ float angle_2pi(float y, float x) {
     // division is a full IEEE sequence on this target, several times longer
     const float t = mn * __builtin_amdgcn_rcpf(mx);
     const float s = t * t;
-    float p = -0.004054567310959101f;
-    p = fmaf(p, s, 0.021862957626581192f);
-    p = fmaf(p, s, -0.0559123270213604f);
-    p = fmaf(p, s, 0.0964219719171524f);
-    p = fmaf(p, s, -0.1390862911939621f);
-    p = fmaf(p, s, 0.19946566224098206f);
-    p = fmaf(p, s, -0.33329859375953674f);
-    p = fmaf(p, s, 0.9999993443489075f);
+    float p = -0.01171913556754589f;
+    p = fmaf(p, s, 0.05264734849333763f);
+    p = fmaf(p, s, -0.116426482796669f);
+    p = fmaf(p, s, 0.19354037940502167f);
+    p = fmaf(p, s, -0.33262282609939575f);
+    p = fmaf(p, s, 0.9999772310256958f);
     float r = p * t;                                   // atan(t), in [0, pi/4]
     if (ay > ax) r = 1.5707963267948966f - r;          // first quadrant
     if (x < 0.f) r = 3.141592653589793f - r;           // upper half plane

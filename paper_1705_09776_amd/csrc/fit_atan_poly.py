@@ -1,7 +1,7 @@
 """Fits the arctangent polynomial of describe.hip's angle_2pi().
 
 atan(t) on [0, 1] is approximated by the odd polynomial t P(t^2), P of
-degree 7 (8 coefficients, degree 15 in t), with the smallest largest
+degree 5 (6 coefficients, degree 11 in t), with the smallest largest
 absolute error: Lawson's iteratively reweighted least squares (C. L. Lawson,
 "Contributions to the theory of linear least maximum approximation", 1961)
 on 4001 Chebyshev nodes of [0, 1], in float64, then rounded to float32.
@@ -14,13 +14,13 @@ from __future__ import annotations
 
 import numpy as np
 
-DEGREE = 7          # of P in s = t^2
+DEGREE = 5          # of P in s = t^2
 NODES = 4001
 ITERATIONS = 400
 
 
 def fit() -> np.ndarray:
-    """float32 coefficients c[0] (of s^7) .. c[7] (of s^0)."""
+    """float32 coefficients c[0] (of s^DEGREE) .. c[DEGREE] (of s^0)."""
     k = np.arange(NODES)
     t = 0.5 - 0.5 * np.cos(np.pi * (k + 0.5) / NODES)      # Chebyshev nodes of [0, 1]
     A = t[:, None] * (t * t)[:, None] ** np.arange(DEGREE, -1, -1)[None, :]

@@ -41,10 +41,10 @@ def _angle(y, x):
 
 def test_polynomial_on_unit_interval():
     c = _coeffs()
-    assert len(c) == 8
+    assert len(c) == 6
     t = np.linspace(0, 1, 100001)
     p = np.polyval(np.array(c, dtype=np.float64), t * t) * t   # c runs from the highest power down
-    assert np.abs(p - np.arctan(t)).max() < 1e-7
+    assert np.abs(p - np.arctan(t)).max() < 2e-6
 
 
 def test_angle_all_quadrants():
@@ -57,8 +57,9 @@ def test_angle_all_quadrants():
     ref = np.mod(np.arctan2(y.astype(np.float64), x.astype(np.float64)), 2 * np.pi)
     d = np.abs(got - ref)
     d = np.minimum(d, 2 * np.pi - d)
-    # one fp32 ulp at 2 pi is 4.8e-7: the reflections add about that much
-    assert d.max() < 8e-7
+    # the polynomial's 1.7e-6, plus one fp32 ulp at 2 pi (4.8e-7) from the
+    # reflections
+    assert d.max() < 2.5e-6
     # 2 pi itself only by rounding (the histograms take it as bin 0)
     assert np.all((got >= 0) & (got <= np.float32(2 * np.pi)))
     assert _angle(np.float32([0]), np.float32([0]))[0] == 0
@@ -77,4 +78,4 @@ def test_coefficients_reproduced_by_the_fit_script():
     src = np.array(_coeffs(), dtype=np.float32)
     assert fitted.shape == src.shape
     assert np.all(np.abs(fitted - src) <= np.spacing(np.abs(src)))
-    assert mod.max_error(src) < 1e-7
+    assert mod.max_error(src) < 2e-6
