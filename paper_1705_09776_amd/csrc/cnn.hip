@@ -586,19 +586,41 @@ __global__ void k_labels(const cdvs_keypoint* __restrict__ kp, const int32_t* __
 }
 
 // Active-cell count per (image, octave) of a mask, for the dense fallback.
-__global__ __launch_bounds__(256) void k_mask_count(const uint8_t* __restrict__ mask, const CnnImage* __restrict__ imgs,
-                                                    int32_t* __restrict__ active) {
+// Active cells per (image, octave) of a mask, one 1024-lane workgroup per
+// image: the image's cell bytes are read 16 at a time from the first
+// 16-byte boundary (the bytes before it and after the last whole group one
+// at a time), and octave o's count of a 4-byte word is the population count
+// of bit o of its four bytes.
+constexpr int kCountThreads = 1024;
+
+__device__ __forceinline__ void count_word(uint32_t x, int (&loc)[NHD]) {
+#pragma unroll
+    for (int o = 0; o < NHD; ++o) loc[o] += __popc(x & (0x01010101u << o));
+}
+
+__global__ __launch_bounds__(kCountThreads) void k_mask_count(const uint8_t* __restrict__ mask,
+                                                             const CnnImage* __restrict__ imgs,
+                                                             int32_t* __restrict__ active) {
     __shared__ int cnt[NHD];
     const CnnImage& g = imgs[blockIdx.x];
     if (threadIdx.x < NHD) cnt[threadIdx.x] = 0;
     __syncthreads();
     int loc[NHD] = {0, 0, 0, 0, 0, 0};
     const int64_t n = (int64_t)g.H4 * g.W4;
-    for (int64_t c = threadIdx.x; c < n; c += blockDim.x) {
-        const uint32_t b = mask[g.cell0 + c];
-#pragma unroll
-        for (int o = 0; o < NHD; ++o) loc[o] += (b >> o) & 1u;
+    const uint8_t* m = mask + g.cell0;
+    const int64_t head = min(n, (int64_t)((16u - ((uint32_t)(uintptr_t)m & 15u)) & 15u));
+    const int64_t ng = (n - head) / 16;   // whole 16-byte groups
+    const uint4* q = reinterpret_cast<const uint4*>(m + head);
+    for (int64_t c = threadIdx.x; c < ng; c += blockDim.x) {
+        const uint4 v = q[c];
+        count_word(v.x, loc);
+        count_word(v.y, loc);
+        count_word(v.z, loc);
+        count_word(v.w, loc);
     }
+    // the bytes before the first group and after the last
+    const int64_t tail0 = head + 16 * ng, rest = head + (n - tail0);
+    for (int64_t j = threadIdx.x; j < rest; j += blockDim.x) count_word(m[j < head ? j : tail0 + (j - head)], loc);
 #pragma unroll
     for (int o = 0; o < NHD; ++o)
         if (loc[o]) atomicAdd(&cnt[o], loc[o]);
@@ -693,7 +715,7 @@ hipError_t launch_cnn_labels(const cdvs_keypoint* kp, const int32_t* count, int 
 }
 
 hipError_t launch_mask_count(const uint8_t* mask, const CnnImage* imgs, int nimg, int32_t* active, hipStream_t s) {
-    hipLaunchKernelGGL(k_mask_count, dim3(nimg), dim3(256), 0, s, mask, imgs, active);
+    hipLaunchKernelGGL(k_mask_count, dim3(nimg), dim3(kCountThreads), 0, s, mask, imgs, active);
     return hipGetLastError();
 }
 
