@@ -517,10 +517,11 @@ static void build_constants(cdvs_ctx* c) {
     // the fixed-point scales are powers of two: their inverses and base-2
     // logarithms are exact
     const float ofix = fixed_scale(p.ori_radius, p.sigma0), dfix = fixed_scale(p.desc_radius, p.sigma0);
+    const KpDiv kd = make_kp_div((uint32_t)c->kp_cap);
     c->ori = OriParams{p.ori_radius, p.ori_wsigma, p.ori_peak, p.sigma0, ofix, 1.f / ofix, (float)ilogb(ofix),
-                       p.max_ori, c->kp_cap};
+                       p.max_ori, c->kp_cap, kd};
     c->desc = DescParams{p.desc_cell, p.desc_radius, p.desc_wsigma, p.desc_clamp, p.sigma0,
-                         dfix, 1.f / dfix, (float)ilogb(dfix), c->kp_cap};
+                         dfix, 1.f / dfix, (float)ilogb(dfix), c->kp_cap, kd};
 }
 
 cdvs_status cdvs_ctx_create(const cdvs_params* params, const cdvs_image_desc* images, int32_t n_images,

@@ -80,6 +80,35 @@ struct DetParams {
     int32_t border;
 };
 
+// Division of an unsigned 32-bit n by a fixed d >= 1 as a multiply-high and
+// shifts (the round-up method of Granlund and Montgomery, "Division by
+// invariant integers using multiplication", 1994): with l = ceil(log2 d),
+// m = floor(2^32 (2^l - d) / d) + 1 and t = mulhi(m, n), the quotient is
+// (t + ((n - t) >> 1)) >> (l - 1) for every n < 2^32 (d = 1: n itself).
+// The keypoint kernels take their (image, keypoint) slot apart with it in
+// scalar registers.
+struct KpDiv {
+    uint32_t d, m;
+    int32_t sh;   // l - 1; unused when d = 1
+};
+
+inline KpDiv make_kp_div(uint32_t d) {
+    KpDiv v{d, 0u, 0};
+    if (d > 1) {
+        int l = 0;
+        while ((1ull << l) < d) ++l;
+        v.m = (uint32_t)(((1ull << 32) * ((1ull << l) - d)) / d + 1ull);
+        v.sh = l - 1;
+    }
+    return v;
+}
+
+__device__ __forceinline__ uint32_t kp_div_q(uint32_t n, const KpDiv& v) {
+    if (v.d == 1u) return n;
+    const uint32_t t = __umulhi(v.m, n);
+    return (t + ((n - t) >> 1)) >> v.sh;
+}
+
 struct OriParams {
     float radius, wsigma, peak;
     float sigma0;
@@ -88,6 +117,7 @@ struct OriParams {
     float lfix;     // log2(fix), an integer
     int32_t max_ori;
     int32_t kp_cap;
+    KpDiv kp_div;   // division of a keypoint slot by kp_cap
 };
 
 struct DescParams {
@@ -97,6 +127,7 @@ struct DescParams {
     float inv_fix;  // 1 / fix, exact
     float lfix;     // log2(fix), an integer
     int32_t kp_cap;
+    KpDiv kp_div;
 };
 
 // Workgroups are dealt to the 8 XCDs of an MI355X round-robin by block

@@ -263,9 +263,10 @@ __global__ __launch_bounds__(64 * kKpWaves) void k_orient(const float* __restric
                                                 cdvs_keypoint* __restrict__ ori, int32_t* __restrict__ ori_cnt) {
     __shared__ __align__(16) uint32_t hist[kKpWaves][kCopies * kOriStride];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int slot = xcd_remap(blockIdx.x, gridDim.x) * kKpWaves + wave;
-    int img, i;
-    divmod_est(slot, op.kp_cap, img, i);
+    // the slot is the same in every lane: taken apart in scalar registers
+    const uint32_t slot = (uint32_t)__builtin_amdgcn_readfirstlane(xcd_remap(blockIdx.x, gridDim.x) * kKpWaves + wave);
+    const uint32_t qimg = kp_div_q(slot, op.kp_div);
+    const int img = (int)qimg, i = (int)(slot - qimg * (uint32_t)op.kp_cap);
     if (img >= n_images) return;   // uniform over the wave
     // the count, the record and the image's octave table (one octave per
     // lane) load together: one memory round trip before the walk
@@ -409,9 +410,10 @@ __global__ __launch_bounds__(64 * kKpWaves) void k_describe(const float* __restr
                                                   float* __restrict__ desc) {
     __shared__ __align__(16) uint32_t hist[kKpWaves][kCopies * kDescStride];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int slot = xcd_remap(blockIdx.x, gridDim.x) * kKpWaves + wave;
-    int img, i;
-    divmod_est(slot, dp.kp_cap, img, i);
+    // the slot is the same in every lane: taken apart in scalar registers
+    const uint32_t slot = (uint32_t)__builtin_amdgcn_readfirstlane(xcd_remap(blockIdx.x, gridDim.x) * kKpWaves + wave);
+    const uint32_t qimg = kp_div_q(slot, dp.kp_div);
+    const int img = (int)qimg, i = (int)(slot - qimg * (uint32_t)dp.kp_cap);
     if (img >= n_images) return;   // uniform over the wave
     // the count, the record and the image's octave table (one octave per
     // lane) load together: one memory round trip before the walk
