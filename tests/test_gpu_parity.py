@@ -215,6 +215,27 @@ def test_small_topk(O32):
     assert [tuple(r) for r in sel[["octave", "ix", "iy"]]] == [tuple(r) for r in got[["octave", "ix", "iy"]]]
 
 
+@pytest.mark.parametrize("cap", [1, 7])
+def test_small_capacities_per_image(O32, cap):
+    """Keypoint capacities of 1 (the slot divider's identity case) and 7 (a
+    general divisor) over a batch of three images: each image's top-k
+    matches the oracle's, and its oriented records and descriptors are
+    those of the same image run alone, so no slot lands in another image."""
+    p = cd.default_params()
+    p.topk = cap
+    imgs = list(synth.fixed_batch(synth.SEED_BATCH, 3))
+    pipe = _run(imgs, params=p, kp_capacity=cap)
+    for i, img in enumerate(imgs):
+        got = pipe.keypoints()[i]
+        sel, _, _, _ = _oracle_stages(O32, img, topk=cap)
+        assert [tuple(r) for r in sel[["octave", "ix", "iy"]]] == [tuple(r) for r in got[["octave", "ix", "iy"]]]
+        alone = _run([img], params=p, kp_capacity=cap)
+        fields = [f for f in cd.KP_DTYPE.names if f != "image"]   # the batch index differs
+        np.testing.assert_array_equal(pipe.oriented()[i][fields], alone.oriented()[0][fields])
+        assert np.all(pipe.oriented()[i]["image"] == i)
+        np.testing.assert_array_equal(pipe.descriptors()[i], alone.descriptors()[0])
+
+
 def test_repeatable(single):
     img, _ = single
     pipe = _run([img])
