@@ -377,13 +377,12 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_
                 for (int n2 = 1; n2 < 7; ++n2) {
                     const int gx = x0 + 2 * (n1 + 8 * n2);
                     if (gx >= w) continue;
-                    // non-temporal, as the spatial pyramid writes its planes
+                    // (plain stores: this kernel's 8-byte stores cover half
+                    // lines, which non-temporal stores wrote back 1.47x over)
                     const float a = x[n2].x * scale, b = x[n2].y * scale;
-                    typedef float f32x2 __attribute__((ext_vector_type(2)));
-                    const f32x2 ab = {a, b};
-                    if (gx + 1 < w) __builtin_nontemporal_store(ab, reinterpret_cast<f32x2*>(out + gx));
-                    else __builtin_nontemporal_store(a, out + gx);
-                    if (down) __builtin_nontemporal_store(a, pyr + job.next0 + (int64_t)(gy >> 1) * job.next_pitch + (gx >> 1));
+                    if (gx + 1 < w) *reinterpret_cast<float2*>(out + gx) = make_float2(a, b);
+                    else out[gx] = a;
+                    if (down) pyr[job.next0 + (int64_t)(gy >> 1) * job.next_pitch + (gx >> 1)] = a;
                 }
             }
         }
