@@ -220,6 +220,15 @@ int32_t cdvs_candidate_capacity(const cdvs_ctx* ctx);
  * kernel nodes (counters are cleared by a kernel, never by a memset). */
 cdvs_status cdvs_graph_capture(cdvs_ctx* ctx, const uint8_t* d_images, float* d_pyr, cdvs_keypoint* d_kp,
                                int32_t* d_count, cdvs_keypoint* d_kp_ori, int32_t* d_count_ori, float* d_desc);
+/* The same for the gated pass (the learned candidate mask, a15):
+ * cdvs_cnn_forward with the fused inference kernel (d_mask: the caller's
+ * buffer of cdvs_cnn_cells bytes, bits at threshold tau in (0, 1); d_params:
+ * CDVS_CNN_PARAMS fp32), then the four calls above with d_mask passed to
+ * cdvs_alp_detect.  Arguments are checked before anything is recorded; the
+ * errors are those of cdvs_graph_capture and cdvs_cnn_forward. */
+cdvs_status cdvs_graph_capture_gated(cdvs_ctx* ctx, const uint8_t* d_images, const float* d_params, float tau,
+                                     uint8_t* d_mask, float* d_pyr, cdvs_keypoint* d_kp, int32_t* d_count,
+                                     cdvs_keypoint* d_kp_ori, int32_t* d_count_ori, float* d_desc);
 cdvs_status cdvs_graph_launch(cdvs_ctx* ctx, void* stream);
 
 /* Autotuning of two kernels on the context's batch.  CDVS_KERNEL_SCALES has

@@ -69,7 +69,8 @@ assert KP_DTYPE.itemsize == 48
 EXPORTS = ["cdvs_default_params", "cdvs_validate", "cdvs_ctx_create", "cdvs_ctx_destroy", "cdvs_last_error",
            "cdvs_pyramid_bytes", "cdvs_num_octaves", "cdvs_plane_layout", "cdvs_pyramid", "cdvs_alp_detect",
            "cdvs_orient", "cdvs_describe", "cdvs_sync_status", "cdvs_candidate_capacity",
-           "cdvs_graph_capture", "cdvs_graph_launch", "cdvs_profile_enable", "cdvs_profile_read",
+           "cdvs_graph_capture", "cdvs_graph_capture_gated", "cdvs_graph_launch", "cdvs_profile_enable",
+           "cdvs_profile_read",
            "cdvs_cnn_cells", "cdvs_cnn_cell_layout", "cdvs_cnn_forward", "cdvs_cnn_labels", "cdvs_cnn_backward",
            "cdvs_cnn_adam", "cdvs_autotune", "cdvs_tune_get", "cdvs_tune_set",
            "cdvs_stream", "cdvs_standin_consume", "cdvs_scfv", "cdvs_scfv_noalloc", "cdvs_encode", "cdvs_front_size", "cdvs_front_end", "cdvs_pyramid_bmlog",
@@ -143,6 +144,7 @@ def lib():
         "cdvs_cnn_adam": (i32, [vp, vp, vp, vp, vp, i32, ctypes.c_float, ctypes.c_float, ctypes.c_float,
                                 ctypes.c_float, vp]),
         "cdvs_graph_capture": (i32, [vp, vp, vp, vp, vp, vp, vp, vp]),
+        "cdvs_graph_capture_gated": (i32, [vp, vp, vp, ctypes.c_float, vp, vp, vp, vp, vp, vp, vp]),
         "cdvs_graph_launch": (i32, [vp, vp]),
         "cdvs_profile_enable": (i32, [vp, i32]),
         "cdvs_profile_read": (i32, [vp, vp, vp]),
@@ -278,6 +280,13 @@ def cdvs_cnn_adam(ctx, d_params, d_grad, d_m, d_v, step, lr=1e-3, beta1=0.9, bet
 def cdvs_graph_capture(ctx, d_images, d_pyr, d_kp, d_count, d_kp_ori, d_count_ori, d_desc):
     _check(ctx, lib().cdvs_graph_capture(ctx, _ptr(d_images), _ptr(d_pyr), _ptr(d_kp), _ptr(d_count),
                                          _ptr(d_kp_ori), _ptr(d_count_ori), _ptr(d_desc)))
+
+
+def cdvs_graph_capture_gated(ctx, d_images, d_params, tau, d_mask, d_pyr, d_kp, d_count, d_kp_ori, d_count_ori,
+                             d_desc):
+    _check(ctx, lib().cdvs_graph_capture_gated(ctx, _ptr(d_images), _ptr(d_params), float(tau), _ptr(d_mask),
+                                               _ptr(d_pyr), _ptr(d_kp), _ptr(d_count), _ptr(d_kp_ori),
+                                               _ptr(d_count_ori), _ptr(d_desc)))
 
 
 def cdvs_graph_launch(ctx, stream=None):
@@ -608,6 +617,13 @@ class Pipeline:
         """Capture the whole pass on this pipeline's buffers into a HIP graph."""
         cdvs_graph_capture(self.ctx, self.d_images, self.d_pyr, self.d_kp, self.d_count, self.d_kp_ori,
                            self.d_count_ori, self.d_desc)
+
+    def capture_gated(self, params, tau):
+        """Capture the whole gated pass (fused CNN mask, pyramid, gated
+        detection, orientation, descriptors) into the context's graph."""
+        self.cnn_buffers()
+        cdvs_graph_capture_gated(self.ctx, self.d_images, params, tau, self.d_mask, self.d_pyr, self.d_kp,
+                                 self.d_count, self.d_kp_ori, self.d_count_ori, self.d_desc)
 
     def replay(self, stream=None):
         cdvs_graph_launch(self.ctx, stream)

@@ -10,6 +10,7 @@
 #include <condition_variable>
 #include <deque>
 #include <fstream>
+#include <functional>
 #include <mutex>
 #include <thread>
 #include <sstream>
@@ -953,12 +954,9 @@ cdvs_status cdvs_cnn_adam(cdvs_ctx* ctx, float* d_params, const float* d_grad, f
     return CDVS_OK;
 }
 
-cdvs_status cdvs_graph_capture(cdvs_ctx* ctx, const uint8_t* d_images, float* d_pyr, cdvs_keypoint* d_kp,
-                               int32_t* d_count, cdvs_keypoint* d_kp_ori, int32_t* d_count_ori, float* d_desc) {
-    if (!ctx) return CDVS_ERR_STATE;
-    if (ctx->prof) return fail(ctx, CDVS_ERR_STATE, "cdvs_graph_capture: disable event timing first");
-    if (!d_images || !d_pyr || !d_kp || !d_count || !d_kp_ori || !d_count_ori || !d_desc)
-        return fail(ctx, CDVS_ERR_ARG, "cdvs_graph_capture: null device pointer");
+// Records what `pass` enqueues on the context's capture stream into the
+// context's graph, replacing any previous one.
+static cdvs_status capture_into(cdvs_ctx* ctx, const std::function<cdvs_status(void*)>& pass) {
     if (!ctx->cap_stream) HIP_OR_FAIL(ctx, hipStreamCreateWithFlags(&ctx->cap_stream, hipStreamNonBlocking));
     if (ctx->graph_exec) {
         (void)hipGraphExecDestroy(ctx->graph_exec);
@@ -968,12 +966,8 @@ cdvs_status cdvs_graph_capture(cdvs_ctx* ctx, const uint8_t* d_images, float* d_
         (void)hipGraphDestroy(ctx->graph);
         ctx->graph = nullptr;
     }
-    void* s = (void*)ctx->cap_stream;
     HIP_OR_FAIL(ctx, hipStreamBeginCapture(ctx->cap_stream, hipStreamCaptureModeThreadLocal));
-    cdvs_status st = cdvs_pyramid(ctx, d_images, d_pyr, s);
-    if (st == CDVS_OK) st = cdvs_alp_detect(ctx, d_pyr, nullptr, d_kp, d_count, s);
-    if (st == CDVS_OK) st = cdvs_orient(ctx, d_pyr, d_kp, d_count, d_kp_ori, d_count_ori, s);
-    if (st == CDVS_OK) st = cdvs_describe(ctx, d_pyr, d_kp_ori, d_count_ori, d_desc, s);
+    const cdvs_status st = pass((void*)ctx->cap_stream);
     hipGraph_t g = nullptr;
     hipError_t e = hipStreamEndCapture(ctx->cap_stream, &g);
     if (st != CDVS_OK) {
@@ -984,6 +978,39 @@ cdvs_status cdvs_graph_capture(cdvs_ctx* ctx, const uint8_t* d_images, float* d_
     ctx->graph = g;
     HIP_OR_FAIL(ctx, hipGraphInstantiate(&ctx->graph_exec, g, nullptr, nullptr, 0));
     return CDVS_OK;
+}
+
+cdvs_status cdvs_graph_capture(cdvs_ctx* ctx, const uint8_t* d_images, float* d_pyr, cdvs_keypoint* d_kp,
+                               int32_t* d_count, cdvs_keypoint* d_kp_ori, int32_t* d_count_ori, float* d_desc) {
+    if (!ctx) return CDVS_ERR_STATE;
+    if (ctx->prof) return fail(ctx, CDVS_ERR_STATE, "cdvs_graph_capture: disable event timing first");
+    if (!d_images || !d_pyr || !d_kp || !d_count || !d_kp_ori || !d_count_ori || !d_desc)
+        return fail(ctx, CDVS_ERR_ARG, "cdvs_graph_capture: null device pointer");
+    return capture_into(ctx, [&](void* s) {
+        cdvs_status st = cdvs_pyramid(ctx, d_images, d_pyr, s);
+        if (st == CDVS_OK) st = cdvs_alp_detect(ctx, d_pyr, nullptr, d_kp, d_count, s);
+        if (st == CDVS_OK) st = cdvs_orient(ctx, d_pyr, d_kp, d_count, d_kp_ori, d_count_ori, s);
+        if (st == CDVS_OK) st = cdvs_describe(ctx, d_pyr, d_kp_ori, d_count_ori, d_desc, s);
+        return st;
+    });
+}
+
+cdvs_status cdvs_graph_capture_gated(cdvs_ctx* ctx, const uint8_t* d_images, const float* d_params, float tau,
+                                     uint8_t* d_mask, float* d_pyr, cdvs_keypoint* d_kp, int32_t* d_count,
+                                     cdvs_keypoint* d_kp_ori, int32_t* d_count_ori, float* d_desc) {
+    if (!ctx) return CDVS_ERR_STATE;
+    if (ctx->prof) return fail(ctx, CDVS_ERR_STATE, "cdvs_graph_capture_gated: disable event timing first");
+    if (!d_images || !d_params || !d_mask || !d_pyr || !d_kp || !d_count || !d_kp_ori || !d_count_ori || !d_desc)
+        return fail(ctx, CDVS_ERR_ARG, "cdvs_graph_capture_gated: null device pointer");
+    if (!(tau > 0.f && tau < 1.f)) return fail(ctx, CDVS_ERR_ARG, "cdvs_graph_capture_gated: tau must be in (0, 1)");
+    return capture_into(ctx, [&](void* s) {
+        cdvs_status st = cdvs_cnn_forward(ctx, d_images, d_params, nullptr, nullptr, d_mask, tau, s);
+        if (st == CDVS_OK) st = cdvs_pyramid(ctx, d_images, d_pyr, s);
+        if (st == CDVS_OK) st = cdvs_alp_detect(ctx, d_pyr, d_mask, d_kp, d_count, s);
+        if (st == CDVS_OK) st = cdvs_orient(ctx, d_pyr, d_kp, d_count, d_kp_ori, d_count_ori, s);
+        if (st == CDVS_OK) st = cdvs_describe(ctx, d_pyr, d_kp_ori, d_count_ori, d_desc, s);
+        return st;
+    });
 }
 
 cdvs_status cdvs_graph_launch(cdvs_ctx* ctx, void* stream) {

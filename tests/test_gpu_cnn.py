@@ -296,6 +296,45 @@ def test_gated_bench_configuration_every_image(O32):
     assert_parity(summarize(res), "gated (trained mask, 256-image batch)")
 
 
+def test_gated_graph_replay_equals_eager():
+    """The captured gated pass (fused CNN mask, pyramid, gated detection,
+    orientation, descriptors) replayed several times, with the outputs and
+    the mask cleared and an eager gated pass on the same buffers in between,
+    reproduces the eager gated run: the mask bit for bit, keypoints and
+    descriptors to the plain pass's replay bars."""
+    from paper_1705_09776_amd import surrogate
+    imgs = list(synth.fixed_batch(synth.SEED_BATCH, 4))
+    pipe = cd.Pipeline([(640, 480)] * len(imgs))
+    pipe.upload(imgs)
+    pipe.cnn_buffers()
+    w = os.path.join(_ROOT, "paper_1705_09776_amd", "weights", "surrogate_640x480.npz")
+    tau = float(json.load(open(os.path.splitext(w)[0] + ".json"))["tau"])
+    params = torch.from_numpy(surrogate.load_checkpoint(w)["params"]).cuda()
+    pipe.run_gated(params, tau)
+    torch.cuda.synchronize()
+    assert pipe.sync_status() == cd.CDVS_OK
+    m0 = pipe.d_mask.cpu().numpy().copy()
+    k0 = [k.copy() for k in pipe.oriented()]
+    d0 = [d.copy() for d in pipe.descriptors()]
+    pipe.capture_gated(params, tau)
+    for r in range(3):
+        for t in (pipe.d_mask, pipe.d_kp, pipe.d_count, pipe.d_kp_ori, pipe.d_count_ori, pipe.d_desc, pipe.d_pyr):
+            t.zero_()
+        torch.cuda.synchronize()
+        pipe.replay()
+        torch.cuda.synchronize()
+        assert pipe.sync_status() == cd.CDVS_OK
+        np.testing.assert_array_equal(pipe.d_mask.cpu().numpy(), m0)
+        k1, d1 = pipe.oriented(), pipe.descriptors()
+        for i in range(len(imgs)):
+            np.testing.assert_array_equal(k1[i][["x", "y", "sigma", "p", "octave", "ix", "iy"]],
+                                          k0[i][["x", "y", "sigma", "p", "octave", "ix", "iy"]])
+            np.testing.assert_allclose(k1[i]["theta"], k0[i]["theta"], atol=1e-5)
+            np.testing.assert_allclose(d1[i], d0[i], atol=1e-5)
+        pipe.run_gated(params, tau)   # eager pass between replays
+        torch.cuda.synchronize()
+
+
 def test_gate_leaves_octaves_beyond_its_bits_dense(O32):
     """A 2048x1536 image has octaves 0..6; the mask has bits for octaves 0..5
     only, so octave 6 is always examined densely: an all-ones mask gives
