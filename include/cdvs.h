@@ -216,16 +216,20 @@ int32_t cdvs_candidate_capacity(const cdvs_ctx* ctx);
  * buffers into a graph owned by the context (capturing on a stream of its
  * own; nothing runs), replacing any previous one.  cdvs_graph_launch enqueues
  * one replay on `stream`; the buffers must stay valid while the graph exists.
- * Capture is refused while event timing is enabled.  The graph holds only
- * kernel nodes (counters are cleared by a kernel, never by a memset). */
+ * Capture is refused while event timing is enabled (CDVS_ERR_STATE) and for
+ * a null pointer (CDVS_ERR_ARG), keeping any previous graph; an argument
+ * that one of the recorded calls refuses (a misaligned pyramid) ends the
+ * capture with that call's error, and the context then holds no graph.
+ * The graph holds only kernel nodes (counters are cleared by a kernel,
+ * never by a memset). */
 cdvs_status cdvs_graph_capture(cdvs_ctx* ctx, const uint8_t* d_images, float* d_pyr, cdvs_keypoint* d_kp,
                                int32_t* d_count, cdvs_keypoint* d_kp_ori, int32_t* d_count_ori, float* d_desc);
-/* The same for the gated pass (the learned candidate mask, a15):
+/* The same for the gated pass (detection gated by the learned candidate mask):
  * cdvs_cnn_forward with the fused inference kernel (d_mask: the caller's
  * buffer of cdvs_cnn_cells bytes, bits at threshold tau in (0, 1); d_params:
  * CDVS_CNN_PARAMS fp32), then the four calls above with d_mask passed to
- * cdvs_alp_detect.  Arguments are checked before anything is recorded; the
- * errors are those of cdvs_graph_capture and cdvs_cnn_forward. */
+ * cdvs_alp_detect.  A tau outside (0, 1) is refused like a null pointer,
+ * before the capture begins; otherwise the errors are as above. */
 cdvs_status cdvs_graph_capture_gated(cdvs_ctx* ctx, const uint8_t* d_images, const float* d_params, float tau,
                                      uint8_t* d_mask, float* d_pyr, cdvs_keypoint* d_kp, int32_t* d_count,
                                      cdvs_keypoint* d_kp_ori, int32_t* d_count_ori, float* d_desc);

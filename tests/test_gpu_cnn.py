@@ -335,6 +335,50 @@ def test_gated_graph_replay_equals_eager():
         torch.cuda.synchronize()
 
 
+def test_gated_capture_arguments_rejected():
+    """Capturing the gated pass refuses a threshold outside (0, 1), a null
+    buffer and enabled event timing before the capture begins, keeping the
+    graph captured earlier; a misaligned pyramid is refused by the recorded
+    pyramid call, which ends the capture and leaves no graph."""
+    imgs = list(synth.fixed_batch(synth.SEED_BATCH, 1))
+    pipe = cd.Pipeline([(640, 480)])
+    pipe.upload(imgs)
+    pipe.cnn_buffers()
+    params = torch.zeros(cd.CNN_PARAMS, dtype=torch.float32, device="cuda")
+    pipe.run()
+    pipe.capture()
+    args = [pipe.d_images, params, 0.5, pipe.d_mask, pipe.d_pyr, pipe.d_kp, pipe.d_count, pipe.d_kp_ori,
+            pipe.d_count_ori, pipe.d_desc]
+    cases = [(2, 0.0), (2, 1.0), (2, float("nan")), (3, None), (1, None)]
+    for idx, val in cases:
+        a = list(args)
+        a[idx] = val
+        with pytest.raises(cd.CdvsError) as e:
+            cd.cdvs_graph_capture_gated(pipe.ctx, *a)
+        assert e.value.status == cd.CDVS_ERR_ARG, (idx, val)
+    cd.cdvs_profile_enable(pipe.ctx, True)
+    with pytest.raises(cd.CdvsError) as e:
+        cd.cdvs_graph_capture_gated(pipe.ctx, *args)
+    assert e.value.status == cd.CDVS_ERR_STATE
+    cd.cdvs_profile_enable(pipe.ctx, False)
+    # the plain graph captured above is still there and still runs
+    k0 = [k.copy() for k in pipe.keypoints()]
+    pipe.d_count.zero_()
+    pipe.replay()
+    torch.cuda.synchronize()
+    assert pipe.sync_status() == cd.CDVS_OK
+    for a, b in zip(pipe.keypoints(), k0):
+        np.testing.assert_array_equal(a, b)
+    a = list(args)
+    a[4] = pipe.d_pyr[1:]
+    with pytest.raises(cd.CdvsError) as e:
+        cd.cdvs_graph_capture_gated(pipe.ctx, *a)
+    assert e.value.status == cd.CDVS_ERR_ARG
+    with pytest.raises(cd.CdvsError) as e:
+        pipe.replay()
+    assert e.value.status == cd.CDVS_ERR_STATE
+
+
 def test_gate_leaves_octaves_beyond_its_bits_dense(O32):
     """A 2048x1536 image has octaves 0..6; the mask has bits for octaves 0..5
     only, so octave 6 is always examined densely: an all-ones mask gives
